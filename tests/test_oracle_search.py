@@ -1,0 +1,122 @@
+"""Pins of the oracle's outer layer: reflected-force algebra, the rotation
+retraction, the climb to an index-1 saddle (closed-form Stoner-Wohlfarth
+saddle, exact inertia count) and the two-sided descent.  CPU."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_26269_amd import synth as S
+from tests import closed_forms as CF
+
+
+def _ham(p):
+    return O.Ham(**p.asdict())
+
+
+def test_reflected_force_is_a_reflection():
+    rng = np.random.default_rng(0)
+    m = S.random_texture(64, rng)
+    F, v = S.random_tangent(m, 2, rng)
+    v = v / np.linalg.norm(v)
+    Fm = O.reflected_force(F, v[None])
+    assert np.linalg.norm(Fm) == pytest.approx(np.linalg.norm(F), rel=1e-14)
+    assert float((Fm * v).sum()) == pytest.approx(-float((F * v).sum()), rel=1e-13)
+    assert np.allclose(O.reflected_force(F, -v[None]), Fm, atol=1e-15)
+    # component orthogonal to v unchanged
+    perp = F - float((F * v).sum()) * v
+    assert np.allclose(Fm - float((Fm * v).sum()) * v, perp, atol=1e-14)
+
+
+def test_rotation_retraction():
+    rng = np.random.default_rng(1)
+    m = S.random_texture(128, rng)
+    d = S.random_tangent(m, 1, rng)[0] * 0.3
+    r = O.rotate(m, d)
+    assert np.abs(np.linalg.norm(r, axis=0) - 1).max() < 1e-15
+    # exact angle: the rotation by d_i turns m_i by |d_i|
+    ang = np.arccos(np.clip((r * m).sum(0), -1, 1))
+    assert np.allclose(ang, np.linalg.norm(d, axis=0), atol=1e-7)
+    # first order: R(h d) = m + h d + O(h^2)
+    h = 1e-6
+    assert np.abs((O.rotate(m, h * d) - m) / h - d).max() < 1e-5
+
+
+def test_step_cap_and_fixed_step():
+    rng = np.random.default_rng(2)
+    m = S.random_texture(32, rng)
+    G = S.random_tangent(m, 1, rng)[0]
+    opt = O.LBFGS(O.StepRule(kind="fixed", theta_max=0.05), alpha0=10.0)
+    d = opt.direction(m, G)
+    assert np.linalg.norm(d, axis=0).max() == pytest.approx(0.05, rel=1e-12)
+    assert float((d * G).sum()) < 0
+
+
+def test_stoner_wohlfarth_saddle_and_minima_closed_form():
+    """Uniform m = x with B = b x, easy axis z, D = 0, 0 < b < 2K: the
+    coherent-rotation saddle (lambda_1 = b - 2K, lambda_2 = b) and minima
+    (h, 0, +-sqrt(1 - h^2)), h = b / 2K, barrier N K (1 - h)^2."""
+    p = S.ham_sw(8)
+    h = _ham(p)
+    b, K = p.B[0], p.K
+    m0 = S.add_tilt_noise(S.uniform(h.N, (1, 0, 0)), 0.02, np.random.default_rng(0))
+    r = O.saddle_search(h, m0, tau_F=1e-8)
+    assert r.status == O.SADDLE
+    assert np.abs(r.m - S.uniform(h.N, (1, 0, 0))).max() < 1e-6
+    assert r.evals[0] == pytest.approx(b - 2 * K, abs=1e-8)
+    assert r.evals[1] == pytest.approx(b, abs=1e-8)
+    mp, mm = CF.sw_minima(b, K)
+    seen = []
+    for sgn in (+1, -1):
+        d = O.descend(h, r.m, r.V[0], sgn, tau_F=1e-8)
+        assert d.converged and d.lam1 > 0
+        assert r.E - d.E == pytest.approx(CF.sw_barrier(h.N, b, K), rel=1e-9)
+        dev = min(np.abs(d.m - mp[:, None]).max(), np.abs(d.m - mm[:, None]).max())
+        assert dev < 1e-6
+        seen.append(np.sign(d.m[2, 0]))
+    assert sorted(seen) == [-1, 1]  # the two sides reach the two distinct minima
+
+
+@pytest.mark.parametrize("seed", [0])
+def test_collapse_saddle_is_index_one_by_exact_inertia(seed):
+    """NN model 16x16, radius-1 start: the climb reaches a saddle whose dense
+    tangent Hessian has exactly one negative eigenvalue; both descents go
+    downhill, one of them to the skyrmion (Q = 1)."""
+    p = S.ham_nn(16)
+    h = _ham(p)
+    m0 = S.add_tilt_noise(S.skyrmion(16, 16, 1.0), 0.05, np.random.default_rng(seed))
+    r = O.saddle_search(h, m0, tau_F=1e-6)
+    assert r.status == O.SADDLE
+    w = np.linalg.eigvalsh(O.dense_tangent_hessian(h, r.m))
+    tau = 1e-6 * h.h_est()
+    assert int((w < -tau).sum()) == 1
+    assert np.allclose(r.evals, w[:2], atol=1e-8)
+    Es = []
+    Qs = []
+    for sgn in (+1, -1):
+        d = O.descend(h, r.m, r.V[0], sgn, tau_F=1e-6)
+        assert d.converged
+        assert d.lam1 >= -tau
+        Es.append(d.E)
+        Qs.append(round(d.Q))
+    assert r.E > max(Es)
+    assert 1 in Qs
+
+
+def test_literal_start_is_degenerate_goldstone_point():
+    """NN model 16x16, radius-3 start: the climb stalls at the translated
+    relaxed skyrmion, a point with two near-zero (Goldstone) modes."""
+    p = S.ham_nn(16)
+    h = _ham(p)
+    r = O.saddle_search(h, S.nn_start(0), tau_F=1e-6)
+    assert r.status == O.DEGENERATE
+    assert np.all(np.abs(r.evals) < 1e-6 * h.h_est())
+    assert abs(O.topological_charge(h, r.m) - 1) < 1e-6
+
+
+def test_dedupe_metric():
+    rng = np.random.default_rng(3)
+    m = S.random_texture(50, rng)
+    assert O.max_site_angle(m, m) < 1e-7
+    d = S.random_tangent(m, 1, rng)[0]
+    d = 0.01 * d / np.linalg.norm(d, axis=0).max()
+    assert O.max_site_angle(m, O.rotate(m, d)) == pytest.approx(0.01, rel=1e-6)
