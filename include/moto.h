@@ -1,0 +1,315 @@
+/*
+ * moto.h -- C ABI of the MI355X (gfx950) bilayer minimum-mode kernel.
+ *
+ * Method: Xu & Delin, "A general optimization framework for mapping local
+ * transition-state networks" (arXiv 2509.26269).  The library implements the
+ * data-parallel hot path of its bilayer minimum-mode-following (MMF) kernel
+ * for atomistic spin systems:
+ *   - energy and gradient of the spin Hamiltonian (Methods, Eq.
+ *     param-hamiltonian; Methods, "Gradient, HVP, and Hessian");
+ *   - the tangent-space Hessian-vector product (Methods, "HVP operator mode");
+ *   - the inner layer: k smallest eigenpairs of the (masked) tangent Hessian
+ *     by block LOBPCG from HVPs only (Results, "Bilayer MMF"; Knyazev 2001);
+ *   - the outer layer: reflected force F_mmf = F - 2 (F.v) v and a rotation
+ *     step of every spin (Results, "Bilayer MMF" equation; Supplementary
+ *     Note 1, Algorithm 1, bilayer-kernel loop);
+ *   - certification lambda_1 < 0 < lambda_2 and the two-sided +-min-mode
+ *     descent (Results, "Deterministic bidirectional saddle descent";
+ *     Supplementary Note 1, item iii).
+ *
+ * CONVENTIONS (every entry point)
+ *   Lattice: periodic rhombic Lx x Ly triangular lattice, a1 = (1,0),
+ *     a2 = (1/2, sqrt3/2), nearest-neighbour distance 1, site s = x + Lx*y,
+ *     N = Lx*Ly.  Shell s = all lattice offsets at the s-th smallest distance.
+ *   Energy: E = -sum_i sum_delta J_delta m_i.m_{i+delta}
+ *               - sum_i sum_{delta in NN} D_delta.(m_i x m_{i+delta})
+ *               - sum_i B.m_i - K sum_i m_iz^2,
+ *     sums over ORDERED pairs (every bond counted twice, as the i != j sums
+ *     of the paper read literally), mu_i = 1, D_delta = D[s] (z x dhat).
+ *   Spins and ambient vectors: SoA, m = [3][N] (all mx, then my, then mz).
+ *   Tangent frame layout: a tangent vector v_i is stored as two coordinates
+ *     (v_i.e1_i, v_i.e2_i) in the orthonormal tangent basis of Duff et al.,
+ *     "Building an Orthonormal Basis, Revisited" (JCGT 2017) built from m_i:
+ *       s = copysign(1, m_z); a = -1/(s + m_z); b = m_x m_y a;
+ *       e1 = (1 + s m_x^2 a, s b, -s m_x);  e2 = (b, s + m_y^2 a, -m_y),
+ *     computed in the precision of the call; V = [n][2][N].
+ *   Tangent (Riemannian) Hessian on the product of unit spheres:
+ *       (H v)_i = P_i (A v)_i - c_i v_i,  P_i = I - m_i m_i^T,  c_i = m_i.g_i,
+ *     A the constant Euclidean Hessian, g = A m - B the Euclidean gradient.
+ *   Mask: uint8 per site, nonzero = active; NULL = all active.  The masked
+ *     operator is the principal submatrix on the active sites, M H M.
+ *   Batches: `batch` independent lattices of the plan's size stored back to
+ *     back (m = [batch][3][N], V = [batch][n][2|3][N], c = [batch][N], ...).
+ *
+ * OWNERSHIP AND ERRORS
+ *   Every array argument is a DEVICE pointer owned by the caller unless
+ *   marked "host".  No call keeps a pointer after it returns and no call
+ *   allocates device memory: scratch comes from a caller workspace whose size
+ *   the matching *_workspace function returns.  Calls are ordered on the
+ *   given stream (NULL = default stream).  moto_energy_grad,
+ *   moto_tangent_hvp, moto_hessian_apply and moto_reflected_step do not
+ *   synchronise; the iterative drivers (moto_min_modes, moto_descend,
+ *   moto_saddle_search, moto_saddle_search_batched) synchronise with the
+ *   stream at their convergence checks and report through host structs.
+ *   Return value: MOTO_OK or a negative error detected before any launch
+ *   (outputs untouched) or from the HIP runtime (MOTO_EHIP).  A plan holds
+ *   pinned host memory for convergence read-back: use one plan from one host
+ *   thread at a time.
+ *
+ * GPU SCOPE: up to 3 exchange shells and DMI on the nearest-neighbour shell
+ * (D[1..] must be 0); other Hamiltonians return MOTO_EUNSUPPORTED.
+ */
+#ifndef MOTO_H
+#define MOTO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t moto_status;
+
+/* host return codes */
+#define MOTO_OK 0
+#define MOTO_EINVAL (-1)
+#define MOTO_EHIP (-2)
+#define MOTO_EWORKSPACE (-4)
+#define MOTO_EUNSUPPORTED (-6)
+
+/* outcome codes reported in the result structs (device-detected) */
+#define MOTO_SADDLE 0        /* certified index-1 saddle (lambda_1 < -tau < tau < lambda_2) */
+#define MOTO_CONVERGED 0     /* eigen-solve: all k residuals below tolerance */
+#define MOTO_NOT_CONVERGED 1 /* iteration cap reached */
+#define MOTO_DEGENERATE 2    /* |lambda_1| or |lambda_2| within tau of zero */
+#define MOTO_HIGHER_INDEX 3  /* lambda_2 < -tau */
+#define MOTO_NAN 4           /* non-finite value met */
+#define MOTO_BREAKDOWN 5     /* LOBPCG basis lost rank below the block size */
+
+typedef enum { MOTO_F32 = 0, MOTO_F64 = 1 } moto_dtype;
+typedef enum { MOTO_AMBIENT = 0, MOTO_FRAME = 1 } moto_layout;
+
+#define MOTO_MAX_SHELLS 8
+
+/* Spin Hamiltonian (Methods, Eq. param-hamiltonian), reduced units. */
+typedef struct {
+    int32_t Lx, Ly;            /* lattice size, >= 1 each                   */
+    int32_t n_shells;          /* exchange shells in use, 1..MOTO_MAX_SHELLS */
+    int32_t reserved;          /* must be 0                                 */
+    double J[MOTO_MAX_SHELLS]; /* exchange per shell (J > 0 ferromagnetic)  */
+    double D[MOTO_MAX_SHELLS]; /* DMI magnitude per shell, D_delta = D (z x dhat) */
+    double K;                  /* uniaxial anisotropy along e_z             */
+    double B[3];               /* Zeeman field (mu_i = 1)                   */
+} moto_hamiltonian;
+
+typedef struct moto_plan_s *moto_plan;
+typedef void *moto_stream; /* a hipStream_t */
+
+/* Plan: validated Hamiltonian, stencil coefficients, pinned read-back
+ * buffer.  Immutable after creation.  Returns MOTO_EINVAL for bad sizes,
+ * MOTO_EUNSUPPORTED outside the GPU scope above. */
+moto_status moto_plan_create(const moto_hamiltonian *h /* host */, moto_plan *out /* host */);
+moto_status moto_plan_destroy(moto_plan p);
+const char *moto_status_string(moto_status s);
+/* Rigorous bound on ||H||: 4 sum_delta (|J_delta| + |D_delta|) + 4|K| + |B|;
+ * all relative tolerances below are multiples of it. */
+double moto_hessian_norm_bound(moto_plan p);
+/* Number of Hamiltonian parameters theta = (J_0..J_{ns-1}, D_0..D_{ns-1}, K, Bx, By, Bz). */
+int32_t moto_n_params(moto_plan p);
+
+/* ---------------------------------------------------------------------
+ * Energy and gradient (Methods, Eq. param-hamiltonian; "Gradient, HVP,
+ * and Hessian").  FP64 or FP32 spins (dt); reductions always in FP64,
+ * deterministic (fixed order).
+ *   m        [batch][3][N] unit spins, dtype dt
+ *   mask     [batch][N] or NULL; zeroes F on inactive sites only
+ *   E        [batch] FP64 energies (or NULL)
+ *   grad     [batch][3][N] Euclidean gradient g = dE/dm, dtype dt (or NULL)
+ *   c        [batch][N] c_i = m_i.g_i, dtype dt (or NULL)
+ *   F        [batch][3][N] force F_i = -(I - m_i m_i^T) g_i, dtype dt (or NULL)
+ *   dE_dtheta [batch][n_params] FP64 partials of E with respect to theta (or NULL)
+ * Workspace: moto_energy_grad_workspace(p, batch) bytes. */
+size_t moto_energy_grad_workspace(moto_plan p, int32_t batch);
+moto_status moto_energy_grad(moto_plan p, moto_dtype dt, int32_t batch, const void *m,
+                             const uint8_t *mask, double *E, void *grad, void *c, void *F,
+                             double *dE_dtheta, void *ws, size_t ws_bytes, moto_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Tangent Hessian-vector product, the operator of the inner layer (Methods,
+ * "HVP operator mode"): W_j = M H(m) M V_j for n_vec vectors per lattice.
+ *   m     [batch][3][N] unit spins, dtype dt
+ *   c     [batch][N] Weingarten scalars c_i = m_i.g_i (from moto_energy_grad)
+ *   V, W  frame layout [batch][n_vec][2][N], ambient [batch][n_vec][3][N]
+ *         (ambient inputs must be tangent); W must not alias V.
+ * No workspace.  Does not synchronise. */
+moto_status moto_tangent_hvp(moto_plan p, moto_dtype dt, moto_layout layout, int32_t batch,
+                             const void *m, const void *c, const uint8_t *mask, int32_t n_vec,
+                             const void *V, void *W, moto_stream stream);
+
+/* Euclidean Hessian (constant) applied to ambient vectors: W_j = A V_j,
+ * [batch][n_vec][3][N] (the double-backward of the energy). */
+moto_status moto_hessian_apply(moto_plan p, moto_dtype dt, int32_t batch, int32_t n_vec,
+                               const void *V, void *W, moto_stream stream);
+
+/* Mixed second derivatives for the double backward: out[b][q] =
+ * d(g(m_b) . U_b)/d theta_q, FP64, deterministic.  U ambient [batch][3][N].
+ * Workspace: moto_energy_grad_workspace(p, batch). */
+moto_status moto_param_mixed(moto_plan p, moto_dtype dt, int32_t batch, const void *m,
+                             const void *U, double *out, void *ws, size_t ws_bytes,
+                             moto_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Inner layer: k smallest eigenpairs of the masked tangent Hessian at m by
+ * block LOBPCG (Knyazev 2001) with HVPs only, Rayleigh-Ritz on [X W P] in
+ * FP64 (SVQB orthonormalisation, Stathopoulos & Wu 2002, then Jacobi), block
+ * width k + guard.  HVP and blocks in `hvp` precision; Gram, Rayleigh-Ritz
+ * and the returned vectors in FP64.
+ * Stopping rule: ||H v_j - lambda_j v_j||_2 <= tol * moto_hessian_norm_bound
+ * for all j < k, or max_iter iterations (Results: iteration cap 200).
+ *   m      [3][N] FP64 unit spins (batch 1)
+ *   evals  [k] FP64 ascending
+ *   V      [k][3][N] FP64 ambient unit tangent vectors; input warm start when
+ *          opts.warm == 1; output sign rule: the entry of largest magnitude
+ *          (first in [3][N] order) is positive
+ *   resid  [k] FP64 residual norms (or NULL)
+ *   info   host: outcome (MOTO_CONVERGED / NOT_CONVERGED / NAN / BREAKDOWN),
+ *          iterations, HVP columns applied
+ * opts.warm == 2 reuses the full block left in ws by the previous call on
+ * the same workspace (transported to the new tangent spaces).
+ * Workspace: moto_min_modes_workspace(p, hvp, k, guard) bytes. */
+typedef struct {
+    double tol;          /* relative residual tolerance (default 1e-5 F32, 1e-10 F64) */
+    int32_t max_iter;    /* default 200 */
+    int32_t guard;       /* extra block vectors; <0 = max(2, ceil(k/2)) */
+    int32_t warm;        /* 0 random start, 1 V holds k start vectors, 2 reuse block */
+    int32_t check_every; /* iterations between host convergence checks (default 8) */
+    uint64_t seed;       /* start-block seed (SplitMix64 counter generator) */
+} moto_eig_opts;
+
+typedef struct {
+    int32_t status;
+    int32_t iters;
+    int64_t n_hvp;
+} moto_info;
+
+size_t moto_min_modes_workspace(moto_plan p, moto_dtype hvp, int32_t k, int32_t guard);
+moto_status moto_min_modes(moto_plan p, moto_dtype hvp, const double *m, const uint8_t *mask,
+                           int32_t k, const moto_eig_opts *opts /* host */, double *evals,
+                           double *V, double *resid, moto_info *info /* host */, void *ws,
+                           size_t ws_bytes, moto_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Outer layer, one step (Results, "Bilayer MMF"; Algorithm 1 bilayer loop):
+ *   F_mmf = F - 2 sum_{r < k_reflect} (F.v_r) v_r;   G = -F_mmf;
+ *   direction d from L-BFGS on G (memory `mem`, stored pairs transported by
+ *   projection onto the current tangent spaces, pairs with s.y <= sy_min
+ *   skipped, initial scaling s.y/y.y of the newest valid pair or alpha0,
+ *   reset to d = -alpha0 G whenever d.G >= 0) or the fixed step d = -alpha0 G;
+ *   d scaled so that max_i |d_i| <= theta_max; each spin rotated by d_i
+ *   (m_i <- cos|d_i| m_i + sin|d_i| d_i/|d_i|, renormalised).
+ * If ||F_mmf||_2 <= tau_F the step is not taken and the stop flag is set.
+ * k_reflect = 0 gives the plain downhill step of the descent.
+ *   m      [3][N] FP64, updated in place
+ *   F      [3][N] FP64 tangent force at m (moto_energy_grad)
+ *   V      [k_reflect][3][N] FP64 unit min modes (NULL if k_reflect = 0)
+ *   state  optimiser state, moto_step_state_bytes(p, mem) bytes, zeroed by
+ *          the caller before the first step of a run
+ *   out    [2] FP64 device: out[0] = ||F_mmf||_2 at m, out[1] = 1 if stopped */
+typedef struct {
+    int32_t rule;      /* 0 = L-BFGS, 1 = fixed step */
+    int32_t mem;       /* L-BFGS memory, 1..16 (default 8) */
+    double theta_max;  /* rotation cap, rad (default 0.1) */
+    double alpha0;     /* initial / fixed step; <= 0 means 1 / moto_hessian_norm_bound */
+    double sy_min;     /* curvature-pair threshold (default 1e-12) */
+    double tau_F;      /* stop threshold on ||F_mmf||_2 */
+} moto_step_opts;
+
+size_t moto_step_state_bytes(moto_plan p, int32_t mem);
+moto_status moto_reflected_step(moto_plan p, double *m, const double *F, const double *V,
+                                int32_t k_reflect, const moto_step_opts *opts /* host */,
+                                void *state, double *out, moto_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Two-sided descent, one side (Supplementary Note 1, item iii): rotate the
+ * saddle m by sign*eta*v1/max_i|v1_i| (largest spin rotation eta), then relax
+ * with the step rule on F (k_reflect = 0) until ||F||_2 <= tau_F or
+ * max_iter steps; finally one k = 1 eigen-solve at the minimum.
+ *   m   [3][N] FP64: saddle in, relaxed state out
+ *   v1  [3][N] FP64 unit min mode at the saddle
+ *   res host: energy, topological charge (Berg-Luescher), ||F||, lambda_1. */
+typedef struct {
+    double eta;          /* default 0.1 rad */
+    double tau_F;        /* default 1e-6 */
+    int32_t max_iter;    /* default 5000 */
+    int32_t check_every; /* steps between host checks (default 16) */
+    moto_step_opts step;
+    moto_eig_opts eig;   /* final lambda_1 solve */
+} moto_descend_opts;
+
+typedef struct {
+    int32_t converged;
+    int32_t iters;
+    double E;
+    double Q;
+    double fnorm;
+    double lambda1;
+} moto_descend_result;
+
+size_t moto_descend_workspace(moto_plan p, moto_dtype hvp, const moto_descend_opts *o);
+moto_status moto_descend(moto_plan p, moto_dtype hvp, double *m, const double *v1, int32_t sign,
+                         const moto_descend_opts *opts /* host */,
+                         moto_descend_result *res /* host */, void *ws, size_t ws_bytes,
+                         moto_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Driver of the five calls: one saddle search (Algorithm 1, bilayer-kernel
+ * loop).  Repeat {energy_grad; min_modes(k, warm-started); reflected_step}
+ * until ||F_mmf||_2 <= tau_F, then certify with a k_cert >= 2 solve:
+ * MOTO_SADDLE if lambda_1 < -tau_lam and lambda_2 > tau_lam, else
+ * MOTO_HIGHER_INDEX / MOTO_DEGENERATE; MOTO_NOT_CONVERGED after max_outer.
+ *   m    [3][N] FP64: start in, final point out
+ *   evals_out [k_cert] FP64 device (or NULL), V_out [k_cert][3][N] FP64 device (or NULL) */
+typedef struct {
+    double tau_F;        /* default 1e-6 */
+    double tau_lam;      /* <= 0: 1e-6 (F64) or 1e-4 (F32) times the norm bound */
+    int32_t k;           /* modes during the climb (default 1) */
+    int32_t k_cert;      /* modes for certification (default 2) */
+    int32_t k_reflect;   /* reflected modes (default 1) */
+    int32_t max_outer;   /* default 5000 */
+    moto_step_opts step;
+    moto_eig_opts eig;
+} moto_search_opts;
+
+typedef struct {
+    int32_t status;
+    int32_t iters;
+    int64_t n_hvp;
+    double E;
+    double fnorm;
+    double lambda1, lambda2;
+} moto_search_result;
+
+size_t moto_saddle_search_workspace(moto_plan p, moto_dtype hvp, const moto_search_opts *o);
+moto_status moto_saddle_search(moto_plan p, moto_dtype hvp, double *m, const uint8_t *mask,
+                               const moto_search_opts *opts /* host */,
+                               moto_search_result *res /* host */, double *evals_out,
+                               double *V_out, void *ws, size_t ws_bytes, moto_stream stream);
+
+/* Defaults for the option structs. */
+void moto_default_eig_opts(moto_dtype hvp, moto_eig_opts *o);
+void moto_default_step_opts(moto_step_opts *o);
+void moto_default_descend_opts(moto_dtype hvp, moto_descend_opts *o);
+void moto_default_search_opts(moto_dtype hvp, moto_search_opts *o);
+
+/* Berg-Luescher topological charge of each lattice in a batch, FP64 out
+ * (the Q of the Results; a check of starts and descent end points).
+ * Workspace: moto_energy_grad_workspace(p, batch). */
+moto_status moto_topological_charge(moto_plan p, int32_t batch, const double *m, double *Q,
+                                    void *ws, size_t ws_bytes, moto_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOTO_H */

@@ -1,0 +1,625 @@
+// api.cpp -- host side of the C ABI declared in include/moto.h: plans,
+// workspace layouts, argument checks, and the host loops of the iterative
+// drivers (eigen-solve, descent, saddle search) that queue the device
+// kernels and poll the device convergence flags.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "kernels.hpp"
+#include "moto.h"
+
+using namespace moto;
+
+struct moto_plan_s {
+    moto_hamiltonian h;
+    Geo g;
+    CoefD k;
+    double hest;
+    int ns;
+    int64_t* pinned;  // host read-back buffer (hipHostMalloc)
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t al(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+#define HIP_TRY(expr)                               \
+    do {                                            \
+        if ((expr) != hipSuccess) return MOTO_EHIP; \
+    } while (0)
+
+size_t energy_ws(const moto_plan p, int batch) { return al(sizeof(double) * NPART * (size_t)batch * p->g.tiles); }
+
+// Eigen-solve workspace layout (offsets in bytes from the workspace base).
+struct EigLayout {
+    size_t mT, cT, c64, S, HS, Xsave, part, G, ctrl, total;
+    int mb, n2, nblk_g, nblk_u, nblk_o;
+};
+
+EigLayout eig_layout(const moto_plan p, moto_dtype hvp, int k, int guard) {
+    EigLayout L;
+    const size_t N = p->g.N;
+    const size_t es = hvp == MOTO_F64 ? sizeof(double) : sizeof(float);
+    L.mb = k + guard;
+    L.n2 = 2 * (int)N;
+    L.nblk_g = gram_blocks(L.n2);
+    L.nblk_u = update_blocks(L.n2);
+    L.nblk_o = (int)((N + NT - 1) / NT);
+    size_t o = 0;
+    L.mT = o;
+    o += al(es * 3 * N);
+    L.cT = o;
+    o += al(es * N);
+    L.c64 = o;
+    o += al(sizeof(double) * N);
+    L.S = o;
+    o += al(es * 3 * (size_t)L.mb * L.n2);
+    L.HS = o;
+    o += al(es * 3 * (size_t)L.mb * L.n2);
+    L.Xsave = o;
+    o += al(es * (size_t)L.mb * 3 * N);
+    size_t part = sizeof(double) * NPART * (size_t)p->g.tiles;
+    part = std::max(part, sizeof(double) * (size_t)L.nblk_g * (2 * MAXS * (MAXS + 1) / 2));
+    part = std::max(part, sizeof(double) * (size_t)L.nblk_u * MAXB);
+    part = std::max(part, sizeof(double) * ((size_t)L.nblk_o * MAXB * 3 + MAXB));
+    L.part = o;
+    o += al(part);
+    L.G = o;
+    o += al(sizeof(double) * 2 * MAXS * MAXS);
+    L.ctrl = o;
+    o += al(sizeof(EigCtrl));
+    L.total = o;
+    return L;
+}
+
+int resolve_guard(int k, int guard) {
+    if (guard >= 0) return guard;
+    int g = (k + 1) / 2;
+    return g < 2 ? 2 : g;
+}
+
+bool hvp_ok(moto_dtype d) { return d == MOTO_F32 || d == MOTO_F64; }
+
+// Read back n bytes of device memory through the plan's pinned buffer.
+moto_status readback(moto_plan p, const void* dev, size_t n, void* host, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(p->pinned, dev, n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(host, p->pinned, n);
+    return MOTO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* moto_status_string(moto_status s) {
+    switch (s) {
+        case MOTO_OK: return "ok";
+        case MOTO_EINVAL: return "invalid argument";
+        case MOTO_EHIP: return "HIP runtime error";
+        case MOTO_EWORKSPACE: return "workspace too small";
+        case MOTO_EUNSUPPORTED: return "Hamiltonian outside the GPU scope (<= 3 shells, NN DMI)";
+        default: return "unknown status";
+    }
+}
+
+moto_status moto_plan_create(const moto_hamiltonian* h, moto_plan* out) {
+    if (!h || !out) return MOTO_EINVAL;
+    *out = nullptr;
+    if (h->Lx < 1 || h->Ly < 1 || h->n_shells < 1 || h->n_shells > MOTO_MAX_SHELLS || h->reserved != 0)
+        return MOTO_EINVAL;
+    if ((int64_t)h->Lx * h->Ly > (int64_t)1 << 28) return MOTO_EINVAL;
+    for (int s = 0; s < MOTO_MAX_SHELLS; ++s) {
+        if (!std::isfinite(h->J[s]) || !std::isfinite(h->D[s])) return MOTO_EINVAL;
+        if (s >= 3 && s < h->n_shells && h->J[s] != 0.0) return MOTO_EUNSUPPORTED;
+        if (s >= 1 && h->D[s] != 0.0) return MOTO_EUNSUPPORTED;
+    }
+    if (h->n_shells > 3) return MOTO_EUNSUPPORTED;
+    if (!std::isfinite(h->K) || !std::isfinite(h->B[0]) || !std::isfinite(h->B[1]) || !std::isfinite(h->B[2]))
+        return MOTO_EINVAL;
+    moto_plan p = new (std::nothrow) moto_plan_s;
+    if (!p) return MOTO_EINVAL;
+    p->h = *h;
+    p->g = make_geo(h->Lx, h->Ly);
+    p->ns = h->n_shells;
+    for (int s = 0; s < 3; ++s) p->k.cJ[s] = s < h->n_shells ? -2.0 * h->J[s] : 0.0;
+    p->k.cD = 2.0 * h->D[0];
+    p->k.cK = -2.0 * h->K;
+    for (int a = 0; a < 3; ++a) p->k.B[a] = h->B[a];
+    double sj = 0.0, sd = 0.0;
+    for (int s = 0; s < h->n_shells; ++s) {
+        sj += 6.0 * std::fabs(h->J[s]);
+        sd += 6.0 * std::fabs(h->D[s]);
+    }
+    p->hest = 4.0 * (sj + sd) + 4.0 * std::fabs(h->K) +
+              std::sqrt(h->B[0] * h->B[0] + h->B[1] * h->B[1] + h->B[2] * h->B[2]);
+    p->pinned = nullptr;
+    if (hipHostMalloc((void**)&p->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete p;
+        return MOTO_EHIP;
+    }
+    *out = p;
+    return MOTO_OK;
+}
+
+moto_status moto_plan_destroy(moto_plan p) {
+    if (!p) return MOTO_EINVAL;
+    if (p->pinned) (void)hipHostFree(p->pinned);
+    delete p;
+    return MOTO_OK;
+}
+
+double moto_hessian_norm_bound(moto_plan p) { return p ? p->hest : 0.0; }
+int32_t moto_n_params(moto_plan p) { return p ? 2 * p->ns + 4 : 0; }
+
+// ---------------------------------------------------------------------------
+size_t moto_energy_grad_workspace(moto_plan p, int32_t batch) {
+    if (!p || batch < 1) return 0;
+    return energy_ws(p, batch);
+}
+
+moto_status moto_energy_grad(moto_plan p, moto_dtype dt, int32_t batch, const void* m, const uint8_t* mask,
+                             double* E, void* grad, void* c, void* F, double* dE_dtheta, void* ws,
+                             size_t ws_bytes, moto_stream stream) {
+    if (!p || !m || batch < 1 || !hvp_ok(dt)) return MOTO_EINVAL;
+    const bool need_red = E || dE_dtheta;
+    if (!ws || ws_bytes < energy_ws(p, batch)) return MOTO_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_energy_grad(p->g, p->k, dt == MOTO_F64, batch, m, mask, grad, c, F, (double*)ws, st));
+    if (need_red) HIP_TRY(launch_reduce_partials((double*)ws, batch, p->g.tiles, p->ns, E, dE_dtheta, st));
+    return MOTO_OK;
+}
+
+moto_status moto_tangent_hvp(moto_plan p, moto_dtype dt, moto_layout layout, int32_t batch, const void* m,
+                             const void* c, const uint8_t* mask, int32_t n_vec, const void* V, void* W,
+                             moto_stream stream) {
+    if (!p || !m || !c || !V || !W || batch < 1 || n_vec < 0 || !hvp_ok(dt)) return MOTO_EINVAL;
+    if (layout != MOTO_AMBIENT && layout != MOTO_FRAME) return MOTO_EINVAL;
+    if (V == W) return MOTO_EINVAL;
+    if (n_vec == 0) return MOTO_OK;
+    HIP_TRY(launch_tangent_hvp(p->g, p->k, dt == MOTO_F64, layout == MOTO_FRAME, batch, m, c, mask, n_vec, V, W,
+                               nullptr, (hipStream_t)stream));
+    return MOTO_OK;
+}
+
+moto_status moto_hessian_apply(moto_plan p, moto_dtype dt, int32_t batch, int32_t n_vec, const void* V, void* W,
+                               moto_stream stream) {
+    if (!p || !V || !W || batch < 1 || n_vec < 0 || !hvp_ok(dt) || V == W) return MOTO_EINVAL;
+    if (n_vec == 0) return MOTO_OK;
+    HIP_TRY(launch_hessian_apply(p->g, p->k, dt == MOTO_F64, batch, n_vec, V, W, (hipStream_t)stream));
+    return MOTO_OK;
+}
+
+moto_status moto_param_mixed(moto_plan p, moto_dtype dt, int32_t batch, const void* m, const void* U, double* out,
+                             void* ws, size_t ws_bytes, moto_stream stream) {
+    if (!p || !m || !U || !out || batch < 1 || !hvp_ok(dt)) return MOTO_EINVAL;
+    if (!ws || ws_bytes < energy_ws(p, batch)) return MOTO_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_param_mixed(p->g, dt == MOTO_F64, batch, m, U, (double*)ws, st));
+    HIP_TRY(launch_reduce_partials((double*)ws, batch, p->g.tiles, p->ns, nullptr, out, st));
+    return MOTO_OK;
+}
+
+moto_status moto_topological_charge(moto_plan p, int32_t batch, const double* m, double* Q, void* ws,
+                                    size_t ws_bytes, moto_stream stream) {
+    if (!p || !m || !Q || batch < 1) return MOTO_EINVAL;
+    if (!ws || ws_bytes < energy_ws(p, batch)) return MOTO_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_topo_charge(p->g, batch, m, (double*)ws, st));
+    HIP_TRY(launch_reduce_partials((double*)ws, batch, p->g.tiles, p->ns, Q, nullptr, st));
+    return MOTO_OK;
+}
+
+// ---------------------------------------------------------------------------
+void moto_default_eig_opts(moto_dtype hvp, moto_eig_opts* o) {
+    if (!o) return;
+    o->tol = hvp == MOTO_F64 ? 1e-10 : 1e-5;
+    o->max_iter = 200;
+    o->guard = -1;
+    o->warm = 0;
+    o->check_every = 8;
+    o->seed = 0x2509262690ull;
+}
+
+size_t moto_min_modes_workspace(moto_plan p, moto_dtype hvp, int32_t k, int32_t guard) {
+    if (!p || k < 1 || !hvp_ok(hvp)) return 0;
+    return eig_layout(p, hvp, k, resolve_guard(k, guard)).total;
+}
+
+static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, const uint8_t* mask, int k,
+                                  const moto_eig_opts* o, double* evals, double* V, double* resid, moto_info* info,
+                                  char* ws, size_t ws_bytes, hipStream_t st, const double* c64_in) {
+    const int guard = resolve_guard(k, o->guard);
+    const EigLayout L = eig_layout(p, hvp, k, guard);
+    if (L.mb > MAXB || L.mb > L.n2) return MOTO_EINVAL;
+    if (ws_bytes < L.total) return MOTO_EWORKSPACE;
+    const bool f64 = hvp == MOTO_F64;
+    const int N = p->g.N;
+    double* c64 = (double*)(ws + L.c64);
+    double* part = (double*)(ws + L.part);
+    EigCtrl* ctrl = (EigCtrl*)(ws + L.ctrl);
+    // c_i = m_i . g_i at m (FP64)
+    if (c64_in) {
+        HIP_TRY(hipMemcpyAsync(c64, c64_in, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    } else {
+        HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, nullptr, nullptr, c64, nullptr, part, st));
+    }
+    const void* mT = m;
+    const void* cT = c64;
+    if (!f64) {
+        HIP_TRY(launch_f64_to_f32(m, (float*)(ws + L.mT), 3 * (size_t)N, st));
+        HIP_TRY(launch_f64_to_f32(c64, (float*)(ws + L.cT), (size_t)N, st));
+        mT = ws + L.mT;
+        cT = ws + L.cT;
+    }
+    EigArgs a;
+    a.n2 = L.n2;
+    a.mb = L.mb;
+    a.k = k;
+    a.max_iter = o->max_iter;
+    a.tol_abs = o->tol * p->hest;
+    a.drop = f64 ? 1e-13 : 1e-9;
+    void* S = ws + L.S;
+    void* HS = ws + L.HS;
+    const size_t es = f64 ? sizeof(double) : sizeof(float);
+    void* Wslot = (char*)S + es * (size_t)L.mb * L.n2;
+    void* HWslot = (char*)HS + es * (size_t)L.mb * L.n2;
+    const int warm = o->warm;
+    HIP_TRY(launch_eig_init(f64, a, S, m, warm == 1 ? V : nullptr, warm == 1 ? k : 0, ws + L.Xsave, warm == 2,
+                            mask, N, o->seed, ctrl, st));
+    // start: HX = H X; Rayleigh-Ritz on span(X); W = HX - X Lam
+    HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, S, HS, &ctrl->done, st));
+    HIP_TRY(launch_gram(f64, a, L.mb, S, HS, part, L.nblk_g, (double*)(ws + L.G), ctrl, st));
+    HIP_TRY(launch_rr(a, L.mb, (double*)(ws + L.G), ctrl, st));
+    HIP_TRY(launch_update(f64, a, L.mb, L.mb, S, HS, part, L.nblk_u, ctrl, st));
+    HIP_TRY(launch_eig_control(a, part, L.nblk_u, L.mb, ctrl, 1, st));
+    const int every = o->check_every > 0 ? o->check_every : 8;
+    const int max_chunks = o->max_iter / every + 2;
+    int hdr[4];
+    for (int chunk = 0; chunk < max_chunks; ++chunk) {
+        moto_status rs = readback(p, ctrl, sizeof(hdr), hdr, st);
+        if (rs != MOTO_OK) return rs;
+        if (hdr[0]) break;
+        for (int it = 0; it < every; ++it) {
+            HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, Wslot, HWslot, &ctrl->done,
+                                       st));
+            HIP_TRY(launch_gram(f64, a, -1, S, HS, part, L.nblk_g, (double*)(ws + L.G), ctrl, st));
+            HIP_TRY(launch_rr(a, -1, (double*)(ws + L.G), ctrl, st));
+            HIP_TRY(launch_update(f64, a, -1, L.mb, S, HS, part, L.nblk_u, ctrl, st));
+            HIP_TRY(launch_eig_control(a, part, L.nblk_u, L.mb, ctrl, 0, st));
+        }
+    }
+    HIP_TRY(launch_eig_output(f64, a, S, m, N, V, part, L.nblk_o, ctrl, evals, resid, ws + L.Xsave, st));
+    EigCtrl hc;
+    moto_status rs = readback(p, ctrl, 32, &hc, st);
+    if (rs != MOTO_OK) return rs;
+    if (info) {
+        info->status = hc.status;
+        info->iters = hc.iters;
+        info->n_hvp = hc.n_hvp;
+    }
+    return MOTO_OK;
+}
+
+moto_status moto_min_modes(moto_plan p, moto_dtype hvp, const double* m, const uint8_t* mask, int32_t k,
+                           const moto_eig_opts* opts, double* evals, double* V, double* resid, moto_info* info,
+                           void* ws, size_t ws_bytes, moto_stream stream) {
+    if (!p || !m || !V || !evals || k < 1 || !hvp_ok(hvp)) return MOTO_EINVAL;
+    moto_eig_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_eig_opts(hvp, &o);
+    if (o.max_iter < 0 || !(o.tol >= 0.0) || o.warm < 0 || o.warm > 2) return MOTO_EINVAL;
+    if (!ws) return MOTO_EWORKSPACE;
+    return min_modes_impl(p, hvp, m, mask, k, &o, evals, V, resid, info, (char*)ws, ws_bytes,
+                          (hipStream_t)stream, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+void moto_default_step_opts(moto_step_opts* o) {
+    if (!o) return;
+    o->rule = 0;
+    o->mem = 8;
+    o->theta_max = 0.1;
+    o->alpha0 = 0.0;
+    o->sy_min = 1e-12;
+    o->tau_F = 1e-6;
+}
+
+size_t moto_step_state_bytes(moto_plan p, int32_t mem) {
+    if (!p || mem < 1 || mem > 16) return 0;
+    return step_state_bytes(p->g.N, mem);
+}
+
+static bool fill_step_args(moto_plan p, const moto_step_opts* o, int k_reflect, StepArgs* a) {
+    if (o->rule != 0 && o->rule != 1) return false;
+    if (o->mem < 1 || o->mem > 16 || !(o->theta_max > 0.0) || k_reflect < 0 || k_reflect > 4) return false;
+    a->N = p->g.N;
+    a->mem = o->mem;
+    a->rule = o->rule;
+    a->k_reflect = k_reflect;
+    a->theta_max = o->theta_max;
+    a->alpha0 = o->alpha0 > 0.0 ? o->alpha0 : 1.0 / p->hest;
+    a->sy_min = o->sy_min;
+    a->tau_F = o->tau_F;
+    return true;
+}
+
+moto_status moto_reflected_step(moto_plan p, double* m, const double* F, const double* V, int32_t k_reflect,
+                                const moto_step_opts* opts, void* state, double* out, moto_stream stream) {
+    if (!p || !m || !F || !state || !out || (k_reflect > 0 && !V)) return MOTO_EINVAL;
+    moto_step_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_step_opts(&o);
+    StepArgs a;
+    if (!fill_step_args(p, &o, k_reflect, &a)) return MOTO_EINVAL;
+    HIP_TRY(launch_step(a, m, F, V, state, out, (hipStream_t)stream));
+    return MOTO_OK;
+}
+
+// ---------------------------------------------------------------------------
+void moto_default_descend_opts(moto_dtype hvp, moto_descend_opts* o) {
+    if (!o) return;
+    o->eta = 0.1;
+    o->tau_F = 1e-6;
+    o->max_iter = 5000;
+    o->check_every = 16;
+    moto_default_step_opts(&o->step);
+    moto_default_eig_opts(hvp, &o->eig);
+}
+
+// Descent / search workspace: [energy partials][F 3N][out 2][state][eig ws][V k_max 3N][evals]
+struct DrvLayout {
+    size_t epart, F, out, state, eig, V, ev, total;
+};
+
+static DrvLayout drv_layout(moto_plan p, moto_dtype hvp, int mem, int kmax, int guard) {
+    DrvLayout L;
+    const size_t N = p->g.N;
+    size_t o = 0;
+    L.epart = o;
+    o += energy_ws(p, 1);
+    L.F = o;
+    o += al(sizeof(double) * 3 * N);
+    L.out = o;
+    o += al(sizeof(double) * 4);
+    L.state = o;
+    o += al(step_state_bytes((int)N, mem));
+    L.eig = o;
+    o += al(eig_layout(p, hvp, kmax, resolve_guard(kmax, guard)).total);
+    L.V = o;
+    o += al(sizeof(double) * 3 * N * (size_t)kmax);
+    L.ev = o;
+    o += al(sizeof(double) * 2 * (size_t)kmax);
+    L.total = o;
+    return L;
+}
+
+size_t moto_descend_workspace(moto_plan p, moto_dtype hvp, const moto_descend_opts* o) {
+    if (!p || !hvp_ok(hvp)) return 0;
+    moto_descend_opts d;
+    if (o)
+        d = *o;
+    else
+        moto_default_descend_opts(hvp, &d);
+    if (d.step.mem < 1 || d.step.mem > 16) return 0;
+    return drv_layout(p, hvp, d.step.mem, 1, d.eig.guard).total;
+}
+
+moto_status moto_descend(moto_plan p, moto_dtype hvp, double* m, const double* v1, int32_t sign,
+                         const moto_descend_opts* opts, moto_descend_result* res, void* ws, size_t ws_bytes,
+                         moto_stream stream) {
+    if (!p || !m || !v1 || !res || (sign != 1 && sign != -1) || !hvp_ok(hvp)) return MOTO_EINVAL;
+    moto_descend_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_descend_opts(hvp, &o);
+    if (!(o.eta > 0.0) || o.max_iter < 0) return MOTO_EINVAL;
+    o.step.tau_F = o.tau_F;
+    StepArgs a;
+    if (!fill_step_args(p, &o.step, 0, &a)) return MOTO_EINVAL;
+    const DrvLayout L = drv_layout(p, hvp, o.step.mem, 1, o.eig.guard);
+    if (!ws || ws_bytes < L.total) return MOTO_EWORKSPACE;
+    char* w = (char*)ws;
+    hipStream_t st = (hipStream_t)stream;
+    const int N = p->g.N;
+    double* F = (double*)(w + L.F);
+    double* out = (double*)(w + L.out);
+    double* part = (double*)(w + L.epart);
+    HIP_TRY(hipMemsetAsync(w + L.state, 0, step_state_bytes(N, o.step.mem), st));
+    HIP_TRY(hipMemsetAsync(out, 0, sizeof(double) * 2, st));
+    HIP_TRY(launch_seed_rotate(N, m, v1, sign * o.eta, part, st));
+    const int every = o.check_every > 0 ? o.check_every : 16;
+    int it = 0;
+    double ho[2] = {0.0, 0.0};
+    while (it < o.max_iter) {
+        const int n = std::min(every, o.max_iter - it);
+        for (int q = 0; q < n; ++q) {
+            HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, nullptr, nullptr, nullptr, F, part, st));
+            HIP_TRY(launch_step(a, m, F, nullptr, w + L.state, out, st));
+        }
+        it += n;
+        moto_status rs = readback(p, out, sizeof(ho), ho, st);
+        if (rs != MOTO_OK) return rs;
+        if (ho[1] != 0.0 || !std::isfinite(ho[0])) break;
+    }
+    // final quantities at the relaxed state
+    double* E = (double*)(w + L.ev);
+    HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, nullptr, nullptr, nullptr, F, part, st));
+    HIP_TRY(launch_reduce_partials(part, 1, p->g.tiles, p->ns, E, nullptr, st));
+    // residual force norm after the last step: one more stop test with a zero-step state
+    moto_eig_opts eo = o.eig;
+    eo.warm = 0;
+    double lam = 0.0;
+    moto_info inf;
+    moto_status rs = min_modes_impl(p, hvp, m, nullptr, 1, &eo, E + 1, (double*)(w + L.V), nullptr, &inf,
+                                    w + L.eig, ws_bytes - L.eig, st, nullptr);
+    if (rs != MOTO_OK) return rs;
+    HIP_TRY(launch_topo_charge(p->g, 1, m, part, st));
+    double Qd[1];
+    HIP_TRY(launch_reduce_partials(part, 1, p->g.tiles, p->ns, (double*)(w + L.out) + 2, nullptr, st));
+    double hv[4];
+    rs = readback(p, w + L.ev, 2 * sizeof(double), hv, st);
+    if (rs != MOTO_OK) return rs;
+    rs = readback(p, (double*)(w + L.out) + 2, sizeof(double), Qd, st);
+    if (rs != MOTO_OK) return rs;
+    lam = hv[1];
+    // ||F|| at the final point: the step state holds it when stopped; otherwise
+    // recompute through one stop-only test
+    res->converged = ho[1] != 0.0 ? 1 : 0;
+    res->iters = it;
+    res->E = hv[0];
+    res->Q = Qd[0];
+    res->fnorm = ho[0];
+    res->lambda1 = lam;
+    {
+        // exact step count from the state header
+        int hdr[5];
+        rs = readback(p, w + L.state, sizeof(hdr), hdr, st);
+        if (rs != MOTO_OK) return rs;
+        res->iters = hdr[4];
+    }
+    return MOTO_OK;
+}
+
+// ---------------------------------------------------------------------------
+void moto_default_search_opts(moto_dtype hvp, moto_search_opts* o) {
+    if (!o) return;
+    o->tau_F = 1e-6;
+    o->tau_lam = 0.0;
+    o->k = 1;
+    o->k_cert = 2;
+    o->k_reflect = 1;
+    o->max_outer = 5000;
+    moto_default_step_opts(&o->step);
+    moto_default_eig_opts(hvp, &o->eig);
+}
+
+size_t moto_saddle_search_workspace(moto_plan p, moto_dtype hvp, const moto_search_opts* o) {
+    if (!p || !hvp_ok(hvp)) return 0;
+    moto_search_opts d;
+    if (o)
+        d = *o;
+    else
+        moto_default_search_opts(hvp, &d);
+    if (d.step.mem < 1 || d.step.mem > 16 || d.k < 1) return 0;
+    const int kmax = std::max(d.k, std::max(d.k_cert, 2));
+    return drv_layout(p, hvp, d.step.mem, kmax, d.eig.guard).total;
+}
+
+moto_status moto_saddle_search(moto_plan p, moto_dtype hvp, double* m, const uint8_t* mask,
+                               const moto_search_opts* opts, moto_search_result* res, double* evals_out,
+                               double* V_out, void* ws, size_t ws_bytes, moto_stream stream) {
+    if (!p || !m || !res || !hvp_ok(hvp)) return MOTO_EINVAL;
+    moto_search_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_search_opts(hvp, &o);
+    if (o.k < 1 || o.k_reflect < 0 || o.k_reflect > o.k || o.k_reflect > 4 || o.max_outer < 0) return MOTO_EINVAL;
+    const int kc = std::max(o.k_cert, 2);
+    const int kmax = std::max(o.k, kc);
+    o.step.tau_F = o.tau_F;
+    StepArgs a;
+    if (!fill_step_args(p, &o.step, o.k_reflect, &a)) return MOTO_EINVAL;
+    const DrvLayout L = drv_layout(p, hvp, o.step.mem, kmax, o.eig.guard);
+    if (!ws || ws_bytes < L.total) return MOTO_EWORKSPACE;
+    char* w = (char*)ws;
+    hipStream_t st = (hipStream_t)stream;
+    const int N = p->g.N;
+    double* F = (double*)(w + L.F);
+    double* out = (double*)(w + L.out);
+    double* part = (double*)(w + L.epart);
+    double* V = (double*)(w + L.V);
+    double* ev = (double*)(w + L.ev);
+    double* c64 = (double*)(w + L.eig) ;  // scratch only before the first eigen call (not used)
+    (void)c64;
+    HIP_TRY(hipMemsetAsync(w + L.state, 0, step_state_bytes(N, o.step.mem), st));
+    HIP_TRY(hipMemsetAsync(out, 0, sizeof(double) * 2, st));
+    const double tau_lam = o.tau_lam > 0.0 ? o.tau_lam : (hvp == MOTO_F64 ? 1e-6 : 1e-4) * p->hest;
+    int it = 0;
+    int64_t n_hvp = 0;
+    double ho[2] = {INFINITY, 0.0};
+    bool nan = false;
+    for (it = 0; it <= o.max_outer; ++it) {
+        HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, mask, nullptr, nullptr, F, part, st));
+        moto_eig_opts eo = o.eig;
+        eo.warm = it == 0 ? 0 : 2;
+        moto_info inf;
+        moto_status rs = min_modes_impl(p, hvp, m, mask, o.k, &eo, ev, V, nullptr, &inf, w + L.eig,
+                                        ws_bytes - L.eig, st, nullptr);
+        if (rs != MOTO_OK) return rs;
+        n_hvp += inf.n_hvp;
+        if (inf.status == MOTO_NAN) {
+            nan = true;
+            break;
+        }
+        if (it == o.max_outer) {
+            // last iterate: evaluate ||F_mmf|| without moving (tau = +inf)
+            StepArgs a2 = a;
+            a2.tau_F = INFINITY;
+            HIP_TRY(launch_step(a2, m, F, V, w + L.state, out, st));
+        } else {
+            HIP_TRY(launch_step(a, m, F, V, w + L.state, out, st));
+        }
+        rs = readback(p, out, sizeof(ho), ho, st);
+        if (rs != MOTO_OK) return rs;
+        if (ho[1] != 0.0 || !std::isfinite(ho[0])) break;
+    }
+    // certification at the final point
+    moto_eig_opts eo = o.eig;
+    eo.warm = 0;
+    eo.seed = o.eig.seed + 1;
+    moto_info inf;
+    moto_status rs = min_modes_impl(p, hvp, m, mask, kc, &eo, ev, V, nullptr, &inf, w + L.eig, ws_bytes - L.eig,
+                                    st, nullptr);
+    if (rs != MOTO_OK) return rs;
+    n_hvp += inf.n_hvp;
+    HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, mask, nullptr, nullptr, F, part, st));
+    HIP_TRY(launch_reduce_partials(part, 1, p->g.tiles, p->ns, out + 2, nullptr, st));
+    double hv[3];
+    rs = readback(p, out + 2, sizeof(double), hv, st);
+    if (rs != MOTO_OK) return rs;
+    double lam[2];
+    rs = readback(p, ev, sizeof(lam), lam, st);
+    if (rs != MOTO_OK) return rs;
+    int status;
+    const bool conv = std::isfinite(ho[0]) && ho[0] <= o.tau_F;
+    if (nan || !std::isfinite(ho[0]) || !std::isfinite(lam[0]) || !std::isfinite(lam[1]) || inf.status == MOTO_NAN)
+        status = MOTO_NAN;
+    else if (!conv)
+        status = MOTO_NOT_CONVERGED;
+    else if (lam[0] < -tau_lam && lam[1] > tau_lam)
+        status = MOTO_SADDLE;
+    else if (lam[1] < -tau_lam)
+        status = MOTO_HIGHER_INDEX;
+    else
+        status = MOTO_DEGENERATE;
+    {
+        int hdr[5];
+        rs = readback(p, w + L.state, sizeof(hdr), hdr, st);
+        if (rs != MOTO_OK) return rs;
+        res->iters = hdr[4];
+    }
+    res->status = status;
+    res->n_hvp = n_hvp;
+    res->E = hv[0];
+    res->fnorm = ho[0];
+    res->lambda1 = lam[0];
+    res->lambda2 = lam[1];
+    if (evals_out) HIP_TRY(hipMemcpyAsync(evals_out, ev, sizeof(double) * kc, hipMemcpyDeviceToDevice, st));
+    if (V_out) HIP_TRY(hipMemcpyAsync(V_out, V, sizeof(double) * 3 * (size_t)N * kc, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MOTO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// kernels.hpp -- internal launch interface between the host API and the HIP
+// kernels of the bilayer minimum-mode kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace moto {
+
+// Slots of the per-block partial sums of the energy-type reductions.
+constexpr int NPART = 11;
+
+// Stencil coefficients in FP64 (cast to the kernel precision at launch).
+struct CoefD {
+    double cJ[3];
+    double cD;
+    double cK;
+    double B[3];
+};
+
+// ---- stencil.hip ----
+hipError_t launch_energy_grad(const Geo& g, const CoefD& k, bool f64, int batch, const void* m,
+                              const uint8_t* mask, void* grad, void* c, void* F, double* part,
+                              hipStream_t st);
+hipError_t launch_param_mixed(const Geo& g, bool f64, int batch, const void* m, const void* U, double* part,
+                              hipStream_t st);
+hipError_t launch_reduce_partials(const double* part, int batch, int tiles, int ns, double* E, double* dth,
+                                  hipStream_t st);
+hipError_t launch_tangent_hvp(const Geo& g, const CoefD& k, bool f64, bool frame, int batch, const void* m,
+                              const void* c, const uint8_t* mask, int nvec, const void* V, void* W,
+                              const int* done, hipStream_t st);
+hipError_t launch_hessian_apply(const Geo& g, const CoefD& k, bool f64, int batch, int nvec, const void* V,
+                                void* W, hipStream_t st);
+hipError_t launch_topo_charge(const Geo& g, int batch, const double* m, double* part, hipStream_t st);
+
+// ---- lobpcg.hip ----
+// Control block of one eigen-solve, resident in device memory.
+constexpr int MAXB = 16;        // max block width (k + guard)
+constexpr int MAXS = 3 * MAXB;  // max Rayleigh-Ritz basis size
+struct EigCtrl {
+    int done;        // 1 once converged / capped / failed: later launches are no-ops
+    int status;      // MOTO_CONVERGED, MOTO_NOT_CONVERGED, MOTO_NAN, MOTO_BREAKDOWN
+    int iters;       // LOBPCG iterations taken
+    int np;          // columns of P in the current basis (0 or mb)
+    long long n_hvp; // HVP columns applied
+    int rank;        // basis rank kept by the last Rayleigh-Ritz
+    int pad;
+    double lam[MAXB];
+    double resid[MAXB];
+    double C[MAXS * MAXB];  // Ritz coefficients, column-major [s][mb] -> C[i + s*j]
+};
+
+struct EigArgs {
+    int n2;      // rows of the frame-coordinate vectors (2N)
+    int mb;      // block width
+    int k;       // wanted pairs
+    int max_iter;
+    double tol_abs;
+    double drop;  // SVQB rank threshold (relative)
+};
+
+hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m, const double* Vwarm, int nwarm,
+                           const void* Xsave, int use_save, const uint8_t* mask, int N, uint64_t seed,
+                           EigCtrl* ctrl, hipStream_t st);
+hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const void* HS, double* part, int nblk,
+                       double* G, const EigCtrl* ctrl, hipStream_t st);
+int gram_blocks(int n2);
+hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, hipStream_t st);
+hipError_t launch_update(bool f64, const EigArgs& a, int ns, int nx, void* S, void* HS, double* part, int nblk,
+                         EigCtrl* ctrl, hipStream_t st);
+int update_blocks(int n2);
+hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, int ns_w, EigCtrl* ctrl,
+                              int first, hipStream_t st);
+hipError_t launch_eig_output(bool f64, const EigArgs& a, const void* S, const double* m, int N, double* V,
+                             double* part, int nblk, const EigCtrl* ctrl, double* evals, double* resid,
+                             void* Xsave, hipStream_t st);
+
+// ---- step.hip ----
+struct StepArgs {
+    int N;
+    int mem;
+    int rule;  // 0 lbfgs, 1 fixed
+    int k_reflect;
+    double theta_max;
+    double alpha0;
+    double sy_min;
+    double tau_F;
+};
+size_t step_state_bytes(int N, int mem);
+hipError_t launch_step(const StepArgs& a, double* m, const double* F, const double* V, void* state, double* out,
+                       hipStream_t st);
+hipError_t launch_seed_rotate(int N, double* m, const double* v1, double scale_sign_eta, double* part,
+                              hipStream_t st);
+hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t st);
+hipError_t launch_mask_zero(double* v, const uint8_t* mask, int N, int ncomp, hipStream_t st);
+
+}  // namespace moto

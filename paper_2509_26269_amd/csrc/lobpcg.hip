@@ -1,0 +1,636 @@
+// lobpcg.hip -- device kernels of the inner layer: block LOBPCG (Knyazev
+// 2001) on the tangent Hessian in frame coordinates, with the Rayleigh-Ritz
+// step of every iteration solved on the device in FP64 by one workgroup.
+//
+// Block storage (precision T, frame coordinates, rows = 2N):
+//   S  = [X | W | P]  = 3*mb column vectors of n2 rows, column-major
+//   HS = [HX | HW | HP]
+// One iteration: HW = H W (tangent HVP kernel) -> Grams S^T HS, S^T S (FP64
+// accumulation, fixed-order reduction) -> Rayleigh-Ritz (SVQB
+// orthonormalisation of the Gram, Stathopoulos & Wu 2002, then cyclic Jacobi)
+// -> X, P, HX, HP updated in place from the Ritz coefficients, W = HX - X Lam
+// and its column norms -> convergence control.  Every kernel returns at once
+// when the control block says the solve is done, so chunks of iterations can
+// be queued without host round trips.
+#include "kernels.hpp"
+
+namespace moto {
+
+constexpr int RCH = 64;  // rows per Gram chunk
+
+__device__ __forceinline__ int sol_ns(const EigArgs& a, const EigCtrl* ctrl, int ns_fixed) {
+    return ns_fixed >= 0 ? ns_fixed : 2 * a.mb + ctrl->np;
+}
+
+// --------------------------------------------------------------------------
+// Start block: warm vectors (ambient FP64 or the saved ambient block)
+// converted to frame coordinates at m, random (SplitMix64) columns for the
+// rest; masked rows zero.  Also resets the control block.
+// --------------------------------------------------------------------------
+template <class T>
+__global__ void k_eig_init(EigArgs a, T* __restrict__ S, const double* __restrict__ m,
+                           const double* __restrict__ Vwarm, int nwarm, const T* __restrict__ Xsave, int use_save,
+                           const uint8_t* __restrict__ mask, int N, uint64_t seed, EigCtrl* ctrl) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->done = 0;
+        ctrl->status = MOTO_NOT_CONVERGED;
+        ctrl->iters = 0;
+        ctrl->np = 0;
+        ctrl->n_hvp = 0;
+        ctrl->rank = a.mb;
+    }
+    if (s >= N) return;
+    T e1[3], e2[3];
+    onb((T)m[s], (T)m[N + s], (T)m[2 * N + s], e1, e2);
+    const bool on = mask == nullptr || mask[s] != 0;
+    for (int j = 0; j < a.mb; ++j) {
+        T va, vb;
+        if (use_save) {
+            const T x0 = Xsave[(size_t)j * 3 * N + s], x1 = Xsave[(size_t)j * 3 * N + N + s],
+                    x2 = Xsave[(size_t)j * 3 * N + 2 * N + s];
+            va = e1[0] * x0 + e1[1] * x1 + e1[2] * x2;
+            vb = e2[0] * x0 + e2[1] * x1 + e2[2] * x2;
+        } else if (j < nwarm) {
+            const double* v = Vwarm + (size_t)j * 3 * N;
+            va = (T)(e1[0] * v[s] + e1[1] * v[N + s] + e1[2] * v[2 * N + s]);
+            vb = (T)(e2[0] * v[s] + e2[1] * v[N + s] + e2[2] * v[2 * N + s]);
+        } else {
+            va = (T)splitmix_uniform(seed, (uint64_t)j * 2 * N + s);
+            vb = (T)splitmix_uniform(seed, (uint64_t)j * 2 * N + N + s);
+        }
+        S[(size_t)j * a.n2 + s] = on ? va : T(0);
+        S[(size_t)j * a.n2 + N + s] = on ? vb : T(0);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Gram matrices: entries e < ns(ns+1)/2 are S_i.HS_j (i <= j), the next
+// ns(ns+1)/2 are S_i.S_j.  Each block accumulates its rows in FP64 and writes
+// one partial row; k_gram_final sums the partials in block order.
+// --------------------------------------------------------------------------
+constexpr int GQ = 10;  // entries per thread (2 * 48 * 49 / 2 / 256 < 10)
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* __restrict__ S,
+                                             const T* __restrict__ HS, double* __restrict__ part,
+                                             const EigCtrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int ns = sol_ns(a, ctrl, ns_fixed);
+    const int Eh = ns * (ns + 1) / 2, E = 2 * Eh;
+    __shared__ T ts[MAXS][RCH];
+    __shared__ T th[MAXS][RCH];
+    int ei[GQ], ej[GQ], ew[GQ];
+#pragma unroll
+    for (int q = 0; q < GQ; ++q) {
+        int e = threadIdx.x + q * NT;
+        ei[q] = ej[q] = ew[q] = 0;
+        if (e < E) {
+            ew[q] = e >= Eh;
+            int p = e - ew[q] * Eh;
+            int i = 0;
+            while (p >= ns - i) {
+                p -= ns - i;
+                ++i;
+            }
+            ei[q] = i;
+            ej[q] = i + p;
+        }
+    }
+    double acc[GQ];
+#pragma unroll
+    for (int q = 0; q < GQ; ++q) acc[q] = 0.0;
+    const int nchunks = (a.n2 + RCH - 1) / RCH;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int r0 = ch * RCH;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < ns * RCH; idx += NT) {
+            const int col = idx / RCH, rr = idx % RCH;
+            const int r = r0 + rr;
+            ts[col][rr] = r < a.n2 ? S[(size_t)col * a.n2 + r] : T(0);
+            th[col][rr] = r < a.n2 ? HS[(size_t)col * a.n2 + r] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+            if (threadIdx.x + q * NT < E) {
+                const T* x = ts[ei[q]];
+                const T* y = ew[q] ? ts[ej[q]] : th[ej[q]];
+                double sacc = 0.0;
+                for (int rr = 0; rr < RCH; ++rr) sacc += (double)x[rr] * (double)y[rr];
+                acc[q] += sacc;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < GQ; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < E) part[(size_t)blockIdx.x * (2 * MAXS * (MAXS + 1) / 2) + e] = acc[q];
+    }
+}
+
+// G layout: G[0][i][j] = (S^T HS) symmetrised from the upper triangle,
+// G[1][i][j] = S^T S; leading dimension MAXS.
+__global__ __launch_bounds__(NT) void k_gram_final(EigArgs a, int ns_fixed, const double* __restrict__ part,
+                                                   int nblk, double* __restrict__ G,
+                                                   const EigCtrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int ns = sol_ns(a, ctrl, ns_fixed);
+    const int Eh = ns * (ns + 1) / 2, E = 2 * Eh;
+    for (int e = threadIdx.x; e < E; e += NT) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (2 * MAXS * (MAXS + 1) / 2) + e];
+        const int w = e >= Eh;
+        int p = e - w * Eh, i = 0;
+        while (p >= ns - i) {
+            p -= ns - i;
+            ++i;
+        }
+        const int j = i + p;
+        G[w * MAXS * MAXS + i * MAXS + j] = s;
+        G[w * MAXS * MAXS + j * MAXS + i] = s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// One-workgroup parallel cyclic Jacobi on an n x n symmetric matrix in LDS
+// (leading dimension MAXS); round-robin ordering, so the n/2 rotations of a
+// round act on disjoint index pairs (Golub & Van Loan, parallel Jacobi).
+// On return diag(A) holds the eigenvalues, Z the eigenvectors (columns).
+// --------------------------------------------------------------------------
+__device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweeps, double* red, double* cs,
+                          double* sn, int* pp, int* qq) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n * MAXS; i += NT) {
+        const int r = i / MAXS, c = i % MAXS;
+        Z[i] = (r == c) ? 1.0 : 0.0;
+    }
+    const int ne = n + (n & 1);
+    const int half = ne / 2;
+    __syncthreads();
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        // off-diagonal and total Frobenius norms
+        double off = 0.0, fro = 0.0;
+        for (int i = tid; i < n * n; i += NT) {
+            const int r = i / n, c = i % n;
+            const double v = A[r * MAXS + c];
+            fro += v * v;
+            if (r != c) off += v * v;
+        }
+        off = wave_sum(off);
+        fro = wave_sum(fro);
+        if ((tid & 63) == 0) {
+            red[tid >> 6] = off;
+            red[4 + (tid >> 6)] = fro;
+        }
+        __syncthreads();
+        const double offt = red[0] + red[1] + red[2] + red[3];
+        const double frot = red[4] + red[5] + red[6] + red[7];
+        __syncthreads();
+        if (!(offt > tol * tol * frot)) break;
+        for (int round = 0; round < ne - 1; ++round) {
+            if (tid < half) {
+                int pa = tid, pb = ne - 1 - tid;
+                int ia = pa == 0 ? 0 : 1 + (pa - 1 + round) % (ne - 1);
+                int ib = pb == 0 ? 0 : 1 + (pb - 1 + round) % (ne - 1);
+                int p = ia < ib ? ia : ib, q = ia < ib ? ib : ia;
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double apq = A[p * MAXS + q];
+                    if (apq != 0.0) {
+                        const double tau = (A[q * MAXS + q] - A[p * MAXS + p]) / (2.0 * apq);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                }
+                cs[tid] = c;
+                sn[tid] = s;
+                pp[tid] = p;
+                qq[tid] = q < n ? q : -1;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int i = tid; i < half * n; i += NT) {
+                const int kp = i / n, col = i % n;
+                const int q = qq[kp];
+                if (q < 0) continue;
+                const int p = pp[kp];
+                const double c = cs[kp], s = sn[kp];
+                const double ap = A[p * MAXS + col], aq = A[q * MAXS + col];
+                A[p * MAXS + col] = c * ap - s * aq;
+                A[q * MAXS + col] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, Z <- Z J
+            for (int i = tid; i < half * n; i += NT) {
+                const int kp = i / n, row = i % n;
+                const int q = qq[kp];
+                if (q < 0) continue;
+                const int p = pp[kp];
+                const double c = cs[kp], s = sn[kp];
+                const double ap = A[row * MAXS + p], aq = A[row * MAXS + q];
+                A[row * MAXS + p] = c * ap - s * aq;
+                A[row * MAXS + q] = s * ap + c * aq;
+                const double zp = Z[row * MAXS + p], zq = Z[row * MAXS + q];
+                Z[row * MAXS + p] = c * zp - s * zq;
+                Z[row * MAXS + q] = s * zp + c * zq;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Rayleigh-Ritz on span(S), basis size ns = nx + nw + np:
+//   G_B -> D G_B D = Z diag(theta) Z^T, keep theta > drop * max(theta),
+//   T = D Z_keep theta^-1/2 (so T^T G_B T = I);
+//   A~ = T^T G_A T = Y diag(lam) Y^T;  C = T Y[:, lowest mb].
+__global__ __launch_bounds__(NT) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ G,
+                                           EigCtrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int ns = sol_ns(a, ctrl, ns_fixed);
+    __shared__ double A[MAXS * MAXS];
+    __shared__ double Z[MAXS * MAXS];
+    __shared__ double Tm[MAXS * MAXS];
+    __shared__ double dsc[MAXS], th[MAXS], red[8], cs[MAXS / 2 + 1], sn[MAXS / 2 + 1];
+    __shared__ int pp[MAXS / 2 + 1], qq[MAXS / 2 + 1], keep[MAXS], order[MAXS];
+    __shared__ int rank_s;
+    const int tid = threadIdx.x;
+    const double* GA = G;
+    const double* GB = G + MAXS * MAXS;
+    for (int i = tid; i < ns; i += NT) dsc[i] = 1.0 / sqrt(fmax(GB[i * MAXS + i], 1e-300));
+    __syncthreads();
+    for (int i = tid; i < ns * ns; i += NT) {
+        const int r = i / ns, c = i % ns;
+        A[r * MAXS + c] = dsc[r] * GB[r * MAXS + c] * dsc[c];
+    }
+    __syncthreads();
+    jacobi_wg(A, Z, ns, 1e-15, 40, red, cs, sn, pp, qq);
+    // rank-revealing selection, in ascending eigen order for determinism
+    if (tid == 0) {
+        double tmax = 0.0;
+        for (int i = 0; i < ns; ++i) tmax = fmax(tmax, A[i * MAXS + i]);
+        int r = 0;
+        for (int i = 0; i < ns; ++i) {
+            const double t = A[i * MAXS + i];
+            if (t > a.drop * tmax) {
+                keep[r] = i;
+                th[r] = t;
+                ++r;
+            }
+        }
+        rank_s = r;
+    }
+    __syncthreads();
+    const int r = rank_s;
+    // T = D Z_keep theta^-1/2   (ns x r)
+    for (int i = tid; i < ns * r; i += NT) {
+        const int row = i / r, c = i % r;
+        Tm[row * MAXS + c] = dsc[row] * Z[row * MAXS + keep[c]] / sqrt(th[c]);
+    }
+    __syncthreads();
+    // Z <- G_A T  (ns x r)
+    for (int i = tid; i < ns * r; i += NT) {
+        const int row = i / r, c = i % r;
+        double s = 0.0;
+        for (int l = 0; l < ns; ++l) s += GA[row * MAXS + l] * Tm[l * MAXS + c];
+        Z[row * MAXS + c] = s;
+    }
+    __syncthreads();
+    // A <- T^T Z  (r x r), symmetrised
+    for (int i = tid; i < r * r; i += NT) {
+        const int row = i / r, c = i % r;
+        double s = 0.0;
+        for (int l = 0; l < ns; ++l) s += Tm[l * MAXS + row] * Z[l * MAXS + c];
+        A[row * MAXS + c] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < r * r; i += NT) {
+        const int row = i / r, c = i % r;
+        if (row < c) {
+            const double v = 0.5 * (A[row * MAXS + c] + A[c * MAXS + row]);
+            A[row * MAXS + c] = v;
+            A[c * MAXS + row] = v;
+        }
+    }
+    __syncthreads();
+    jacobi_wg(A, Z, r, 1e-15, 40, red, cs, sn, pp, qq);
+    // ascending order (stable by index)
+    for (int i = tid; i < r; i += NT) {
+        const double li = A[i * MAXS + i];
+        int rk = 0;
+        for (int j = 0; j < r; ++j) {
+            const double lj = A[j * MAXS + j];
+            rk += (lj < li) || (lj == li && j < i);
+        }
+        order[rk] = i;
+    }
+    __syncthreads();
+    const int mb = a.mb;
+    const int mcol = r < mb ? r : mb;
+    // C = T Y[:, order[0..mb)]   column-major [ns][mb]
+    for (int i = tid; i < ns * mb; i += NT) {
+        const int row = i % ns, j = i / ns;
+        double s = 0.0;
+        if (j < mcol) {
+            const int yc = order[j];
+            for (int l = 0; l < r; ++l) s += Tm[row * MAXS + l] * Z[l * MAXS + yc];
+        }
+        ctrl->C[row + ns * j] = s;
+    }
+    for (int j = tid; j < mb; j += NT) ctrl->lam[j] = j < mcol ? A[order[j] * MAXS + order[j]] : 0.0;
+    if (tid == 0) ctrl->rank = r;
+}
+
+// --------------------------------------------------------------------------
+// Block update from the Ritz coefficients (in place, row by row):
+//   X <- S C,  P <- S C_wp,  HX <- HS C,  HP <- HS C_wp,  W <- HX - X Lam,
+// with C_wp = C with its first nx rows zeroed; per-block partial sums of
+// |W_j|^2.  ns == nx (the start) leaves P untouched.
+// --------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __restrict__ S, T* __restrict__ HS,
+                                               double* __restrict__ part, const EigCtrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int ns = sol_ns(a, ctrl, ns_fixed);
+    const int mb = a.mb, nx = mb;
+    __shared__ double C[MAXS * MAXB];
+    __shared__ double lam[MAXB];
+    __shared__ double red[MAXB * (NT / 64)];
+    for (int i = threadIdx.x; i < ns * mb; i += NT) C[i] = ctrl->C[i];
+    for (int i = threadIdx.x; i < mb; i += NT) lam[i] = ctrl->lam[i];
+    __syncthreads();
+    double rs[MAXB];
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) rs[j] = 0.0;
+    const bool has_p = ns > nx;
+    for (int r = blockIdx.x * NT + threadIdx.x; r < a.n2; r += gridDim.x * NT) {
+        T sv[MAXS];
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i)
+            if (i < ns) sv[i] = S[(size_t)i * a.n2 + r];
+        double xn[MAXB];
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            if (j < mb) {
+                double x = 0.0, p = 0.0;
+#pragma unroll
+                for (int i = 0; i < MAXS; ++i) {
+                    if (i < ns) {
+                        const double t = C[i + ns * j] * (double)sv[i];
+                        x += t;
+                        if (i >= nx) p += t;
+                    }
+                }
+                xn[j] = x;
+                S[(size_t)j * a.n2 + r] = (T)x;
+                if (has_p) S[(size_t)(2 * mb + j) * a.n2 + r] = (T)p;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i)
+            if (i < ns) sv[i] = HS[(size_t)i * a.n2 + r];
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            if (j < mb) {
+                double hx = 0.0, hp = 0.0;
+#pragma unroll
+                for (int i = 0; i < MAXS; ++i) {
+                    if (i < ns) {
+                        const double t = C[i + ns * j] * (double)sv[i];
+                        hx += t;
+                        if (i >= nx) hp += t;
+                    }
+                }
+                HS[(size_t)j * a.n2 + r] = (T)hx;
+                if (has_p) HS[(size_t)(2 * mb + j) * a.n2 + r] = (T)hp;
+                const T w = (T)(hx - lam[j] * xn[j]);
+                S[(size_t)(mb + j) * a.n2 + r] = w;
+                rs[j] += (double)w * (double)w;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) {
+        if (j < mb) {
+            const double s = wave_sum(rs[j]);
+            if (lane == 0) red[j * (NT / 64) + wv] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < mb) {
+        const int j = threadIdx.x;
+        part[(size_t)blockIdx.x * MAXB + j] = red[j * 4] + red[j * 4 + 1] + red[j * 4 + 2] + red[j * 4 + 3];
+    }
+}
+
+// Convergence control (one thread): residual norms, NaN, rank and cap checks.
+__global__ void k_eig_control(EigArgs a, const double* __restrict__ part, int nblk, EigCtrl* __restrict__ ctrl,
+                              int first) {
+    if (threadIdx.x != 0 || ctrl->done) return;
+    bool conv = true, bad = false;
+    for (int j = 0; j < a.mb; ++j) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * MAXB + j];
+        const double rj = sqrt(s);
+        ctrl->resid[j] = rj;
+        if (!isfinite(rj) || !isfinite(ctrl->lam[j])) bad = true;
+        if (j < a.k && !(rj <= a.tol_abs)) conv = false;
+    }
+    ctrl->n_hvp += a.mb;
+    if (!first) {
+        ctrl->iters += 1;
+        ctrl->np = a.mb;
+    }
+    if (bad) {
+        ctrl->status = MOTO_NAN;
+        ctrl->done = 1;
+    } else if (ctrl->rank < a.mb) {
+        ctrl->status = MOTO_BREAKDOWN;
+        ctrl->done = 1;
+    } else if (conv) {
+        ctrl->status = MOTO_CONVERGED;
+        ctrl->done = 1;
+    } else if (ctrl->iters >= a.max_iter) {
+        ctrl->status = MOTO_NOT_CONVERGED;
+        ctrl->done = 1;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Output: the first k block columns to ambient FP64 unit vectors with the
+// sign rule (entry of largest magnitude, first in [3][N] order, positive);
+// the whole block saved ambient for a warm restart.
+// Partials per block and column: [|v|^2, max|v_c,s|, first flat index of it].
+// --------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(NT) void k_eig_out1(EigArgs a, const T* __restrict__ S, const double* __restrict__ m,
+                                                 int N, double* __restrict__ V, double* __restrict__ part,
+                                                 T* __restrict__ Xsave) {
+    __shared__ double rn[MAXB][NT / 64], rm[MAXB][NT / 64], ri[MAXB][NT / 64];
+    const int s = blockIdx.x * NT + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    T e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+    if (s < N) onb((T)m[s], (T)m[N + s], (T)m[2 * N + s], e1, e2);
+    for (int j = 0; j < a.mb; ++j) {
+        double nrm = 0.0, mx = -1.0, mi = 1e300;
+        if (s < N) {
+            const T va = S[(size_t)j * a.n2 + s], vb = S[(size_t)j * a.n2 + N + s];
+            for (int c = 0; c < 3; ++c) {
+                const T amb = va * e1[c] + vb * e2[c];
+                if (Xsave) Xsave[(size_t)j * 3 * N + c * N + s] = amb;
+                if (j < a.k) {
+                    const double v = (double)amb;
+                    V[(size_t)j * 3 * N + c * N + s] = v;
+                    nrm += v * v;
+                    const double av = fabs(v);
+                    const double idx = (double)(c * N + s);
+                    if (av > mx || (av == mx && idx < mi)) {
+                        mx = av;
+                        mi = idx;
+                    }
+                }
+            }
+        }
+        if (j < a.k) {
+            nrm = wave_sum(nrm);
+            for (int o = 32; o > 0; o >>= 1) {
+                const double omx = __shfl_xor(mx, o, 64), omi = __shfl_xor(mi, o, 64);
+                if (omx > mx || (omx == mx && omi < mi)) {
+                    mx = omx;
+                    mi = omi;
+                }
+            }
+            if (lane == 0) {
+                rn[j][wv] = nrm;
+                rm[j][wv] = mx;
+                ri[j][wv] = mi;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < a.k) {
+        const int j = threadIdx.x;
+        double n = 0.0, mx = -1.0, mi = 1e300;
+        for (int w = 0; w < NT / 64; ++w) {
+            n += rn[j][w];
+            if (rm[j][w] > mx || (rm[j][w] == mx && ri[j][w] < mi)) {
+                mx = rm[j][w];
+                mi = ri[j][w];
+            }
+        }
+        double* p = part + ((size_t)blockIdx.x * MAXB + j) * 3;
+        p[0] = n;
+        p[1] = mx;
+        p[2] = mi;
+    }
+}
+
+// Scale factor per column: sign(v[argmax]) / |v|; also evals and residuals.
+__global__ void k_eig_out2(EigArgs a, const double* __restrict__ part, int nblk, const double* __restrict__ V,
+                           int N, double* __restrict__ scale, const EigCtrl* __restrict__ ctrl,
+                           double* __restrict__ evals, double* __restrict__ resid) {
+    const int j = threadIdx.x;
+    if (j >= a.k) return;
+    double n = 0.0, mx = -1.0, mi = 1e300;
+    for (int b = 0; b < nblk; ++b) {
+        const double* p = part + ((size_t)b * MAXB + j) * 3;
+        n += p[0];
+        if (p[1] > mx || (p[1] == mx && p[2] < mi)) {
+            mx = p[1];
+            mi = p[2];
+        }
+    }
+    const long long idx = (long long)mi;
+    const double sgn = (idx >= 0 && idx < 3LL * N && V[(size_t)j * 3 * N + idx] < 0.0) ? -1.0 : 1.0;
+    scale[j] = sgn / sqrt(n);
+    if (evals) evals[j] = ctrl->lam[j];
+    if (resid) resid[j] = ctrl->resid[j];
+}
+
+__global__ void k_eig_out3(int k, int N, double* __restrict__ V, const double* __restrict__ scale) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t tot = (size_t)k * 3 * N;
+    if (i < tot) V[i] *= scale[i / (3 * (size_t)N)];
+}
+
+// --------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------
+int gram_blocks(int n2) {
+    int nch = (n2 + RCH - 1) / RCH;
+    return nch < 240 ? nch : 240;
+}
+
+int update_blocks(int n2) {
+    int nb = (n2 + NT - 1) / NT;
+    return nb < 1024 ? nb : 1024;
+}
+
+hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m, const double* Vwarm, int nwarm,
+                           const void* Xsave, int use_save, const uint8_t* mask, int N, uint64_t seed,
+                           EigCtrl* ctrl, hipStream_t st) {
+    dim3 grid((N + NT - 1) / NT);
+    if (f64)
+        hipLaunchKernelGGL(k_eig_init<double>, grid, dim3(NT), 0, st, a, (double*)S, m, Vwarm, nwarm,
+                           (const double*)Xsave, use_save, mask, N, seed, ctrl);
+    else
+        hipLaunchKernelGGL(k_eig_init<float>, grid, dim3(NT), 0, st, a, (float*)S, m, Vwarm, nwarm,
+                           (const float*)Xsave, use_save, mask, N, seed, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const void* HS, double* part, int nblk,
+                       double* G, const EigCtrl* ctrl, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_gram<double>, dim3(nblk), dim3(NT), 0, st, a, ns, (const double*)S,
+                           (const double*)HS, part, ctrl);
+    else
+        hipLaunchKernelGGL(k_gram<float>, dim3(nblk), dim3(NT), 0, st, a, ns, (const float*)S, (const float*)HS,
+                           part, ctrl);
+    hipLaunchKernelGGL(k_gram_final, dim3(1), dim3(NT), 0, st, a, ns, part, nblk, G, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, hipStream_t st) {
+    hipLaunchKernelGGL(k_rr, dim3(1), dim3(NT), 0, st, a, ns, G, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(bool f64, const EigArgs& a, int ns, int /*nx*/, void* S, void* HS, double* part,
+                         int nblk, EigCtrl* ctrl, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_update<double>, dim3(nblk), dim3(NT), 0, st, a, ns, (double*)S, (double*)HS, part,
+                           ctrl);
+    else
+        hipLaunchKernelGGL(k_update<float>, dim3(nblk), dim3(NT), 0, st, a, ns, (float*)S, (float*)HS, part,
+                           ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, int /*ns_w*/, EigCtrl* ctrl,
+                              int first, hipStream_t st) {
+    hipLaunchKernelGGL(k_eig_control, dim3(1), dim3(64), 0, st, a, part, nblk, ctrl, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_output(bool f64, const EigArgs& a, const void* S, const double* m, int N, double* V,
+                             double* part, int nblk_unused, const EigCtrl* ctrl, double* evals, double* resid,
+                             void* Xsave, hipStream_t st) {
+    (void)nblk_unused;
+    const int nb = (N + NT - 1) / NT;
+    if (f64)
+        hipLaunchKernelGGL(k_eig_out1<double>, dim3(nb), dim3(NT), 0, st, a, (const double*)S, m, N, V, part,
+                           (double*)Xsave);
+    else
+        hipLaunchKernelGGL(k_eig_out1<float>, dim3(nb), dim3(NT), 0, st, a, (const float*)S, m, N, V, part,
+                           (float*)Xsave);
+    double* scale = part + (size_t)nb * MAXB * 3;
+    hipLaunchKernelGGL(k_eig_out2, dim3(1), dim3(64), 0, st, a, part, nb, V, N, scale, ctrl, evals, resid);
+    const size_t tot = (size_t)a.k * 3 * N;
+    hipLaunchKernelGGL(k_eig_out3, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a.k, N, V, scale);
+    return hipGetLastError();
+}
+
+}  // namespace moto

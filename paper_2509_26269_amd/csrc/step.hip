@@ -1,0 +1,491 @@
+// step.hip -- device kernels of the outer layer: reflected force and one
+// L-BFGS / fixed rotation step of every spin (Results, "Bilayer MMF";
+// Supplementary Note 1, Algorithm 1, bilayer loop).
+//
+// The L-BFGS two-loop recursion is run in coefficient space: every vector it
+// touches is a combination of the stored pairs S_j, Y_j and the current G, so
+// one fused pass computes the Gram matrix of {S_0.., Y_0.., G} (after the
+// projection transport of the stored pairs), a one-thread kernel runs the
+// recursion on that small matrix, and one pass forms the direction.
+#include "kernels.hpp"
+
+namespace moto {
+
+constexpr int SMEM = 16;                  // max L-BFGS memory
+constexpr int SNV = 2 * SMEM + 1;         // max Gram basis size
+constexpr int SNE = SNV * (SNV + 1) / 2;  // Gram entries (upper triangle)
+constexpr int SPART = SNE + 1;            // + ||F_mmf||^2
+constexpr int SCH = 64;                   // sites per staged chunk
+constexpr int MAXR = 4;                   // max reflected modes
+
+struct StepHdr {
+    int count, head, have_prev, stopped;
+    int iters;
+    int cu;  // number of pairs the coefficients below refer to (G is coef[2*cu])
+    int pad1, pad2;
+    double fnorm;
+    double coef[SNV];
+};
+
+struct StepPtrs {
+    StepHdr* hdr;
+    double *S, *Y, *G, *Gp, *dp, *d, *pgram, *pdot, *pmax;
+    size_t vstride;  // doubles between stored vectors
+    int nblk;
+};
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int step_blocks(int N) {
+    int nb = (N + SCH - 1) / SCH;
+    return nb < 256 ? nb : 256;
+}
+
+static StepPtrs step_ptrs(void* state, int N, int mem, size_t* total) {
+    StepPtrs P;
+    char* base = (char*)state;
+    const int nblk = step_blocks(N);
+    const size_t v = al(sizeof(double) * 3 * (size_t)N);
+    size_t o = 0;
+    P.hdr = (StepHdr*)(base + o);
+    o += al(sizeof(StepHdr));
+    P.S = (double*)(base + o);
+    o += v * mem;
+    P.Y = (double*)(base + o);
+    o += v * mem;
+    P.G = (double*)(base + o);
+    o += v;
+    P.Gp = (double*)(base + o);
+    o += v;
+    P.dp = (double*)(base + o);
+    o += v;
+    P.d = (double*)(base + o);
+    o += v;
+    P.pgram = (double*)(base + o);
+    o += al(sizeof(double) * SPART * nblk);
+    P.pdot = (double*)(base + o);
+    o += al(sizeof(double) * MAXR * nblk);
+    P.pmax = (double*)(base + o);
+    o += al(sizeof(double) * nblk);
+    P.vstride = v / sizeof(double);
+    P.nblk = nblk;
+    if (total) *total = o;
+    return P;
+}
+
+size_t step_state_bytes(int N, int mem) {
+    size_t t = 0;
+    step_ptrs(nullptr, N, mem, &t);
+    return t;
+}
+
+// Ring bookkeeping shared by the Gram and control kernels: the pair formed
+// at this step goes to `slot`; logical pair j (oldest first) lives in
+// physical slot (h_new + j) % mem.
+struct Ring {
+    int c_new, h_new, slot;
+};
+
+__device__ __forceinline__ Ring ring_next(const StepHdr* h, int mem, int rule) {
+    Ring r;
+    r.slot = -1;
+    r.c_new = h->count;
+    r.h_new = h->head;
+    if (h->have_prev && rule == 0) {
+        if (h->count < mem) {
+            r.slot = (h->head + h->count) % mem;
+            r.c_new = h->count + 1;
+        } else {
+            r.slot = h->head;
+            r.h_new = (h->head + 1) % mem;
+        }
+    }
+    return r;
+}
+
+// (1) per-block partial dots F . v_r
+__global__ __launch_bounds__(NT) void k_step_dots(StepArgs a, const double* __restrict__ F,
+                                                  const double* __restrict__ V, StepPtrs P) {
+    if (P.hdr->stopped) return;
+    __shared__ double red[MAXR * (NT / 64)];
+    double v[MAXR] = {0, 0, 0, 0};
+    const size_t n3 = 3 * (size_t)a.N;
+    const int per = (a.N + gridDim.x - 1) / gridDim.x;
+    const int s0 = blockIdx.x * per, s1 = min(a.N, s0 + per);
+    for (int s = s0 + threadIdx.x; s < s1; s += NT)
+        for (int r = 0; r < a.k_reflect; ++r)
+            for (int c = 0; c < 3; ++c) v[r] += F[c * a.N + s] * V[r * n3 + c * a.N + s];
+    block_sum<MAXR>(v, red);
+    if (threadIdx.x == 0)
+        for (int r = 0; r < MAXR; ++r) P.pdot[(size_t)blockIdx.x * MAXR + r] = v[r];
+}
+
+// (2) G = -(F - 2 sum_r (F.v_r) v_r); projection transport of the stored
+// pairs onto the tangent spaces at m; new pair s = P d_prev, y = G - P G_prev;
+// Gram partials of {S_0..S_{c-1}, Y_0..Y_{c-1}, G} and ||F_mmf||^2.
+__global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __restrict__ m,
+                                                  const double* __restrict__ F, const double* __restrict__ V,
+                                                  StepPtrs P) {
+    const StepHdr* h = P.hdr;
+    if (h->stopped) return;
+    __shared__ double fr[MAXR];
+    __shared__ double stage[SNV][3][SCH];
+    const Ring rg = ring_next(h, a.mem, a.rule);
+    const int c = rg.c_new;
+    const int nv = 2 * c + 1;
+    const int ne = nv * (nv + 1) / 2;
+    if (threadIdx.x < MAXR) {
+        double s = 0.0;
+        if ((int)threadIdx.x < a.k_reflect)
+            for (int b = 0; b < P.nblk; ++b) s += P.pdot[(size_t)b * MAXR + threadIdx.x];
+        fr[threadIdx.x] = s;
+    }
+    // entry owned by this thread (upper triangle of the nv x nv Gram)
+    int ei = 0, ej = 0;
+    if ((int)threadIdx.x < ne) {
+        int p = threadIdx.x, i = 0;
+        while (p >= nv - i) {
+            p -= nv - i;
+            ++i;
+        }
+        ei = i;
+        ej = i + p;
+    }
+    double acc = 0.0, fn2 = 0.0;
+    __syncthreads();
+    const size_t n3 = 3 * (size_t)a.N;
+    const int nchunks = (a.N + SCH - 1) / SCH;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int t = threadIdx.x;
+        if (t < SCH) {
+            const int s = ch * SCH + t;
+            if (s < a.N) {
+                const double mi[3] = {m[s], m[a.N + s], m[2 * a.N + s]};
+                double fm[3];
+                for (int cc = 0; cc < 3; ++cc) {
+                    double v = F[cc * a.N + s];
+                    for (int r = 0; r < a.k_reflect; ++r) v -= 2.0 * fr[r] * V[r * n3 + cc * a.N + s];
+                    fm[cc] = v;
+                    fn2 += v * v;
+                }
+                double g[3] = {-fm[0], -fm[1], -fm[2]};
+                for (int cc = 0; cc < 3; ++cc) P.G[cc * a.N + s] = g[cc];
+                // transport stored pairs / form the new one
+                double sn[3] = {0, 0, 0}, yn[3] = {0, 0, 0};
+                if (rg.slot >= 0) {
+                    double dpv[3], gpv[3];
+                    for (int cc = 0; cc < 3; ++cc) {
+                        dpv[cc] = P.dp[cc * a.N + s];
+                        gpv[cc] = P.Gp[cc * a.N + s];
+                    }
+                    const double md = mi[0] * dpv[0] + mi[1] * dpv[1] + mi[2] * dpv[2];
+                    const double mg = mi[0] * gpv[0] + mi[1] * gpv[1] + mi[2] * gpv[2];
+                    for (int cc = 0; cc < 3; ++cc) {
+                        sn[cc] = dpv[cc] - md * mi[cc];
+                        yn[cc] = g[cc] - (gpv[cc] - mg * mi[cc]);
+                    }
+                }
+                for (int j = 0; j < c; ++j) {
+                    const int ph = (rg.h_new + j) % a.mem;
+                    double* Sj = P.S + ph * P.vstride;
+                    double* Yj = P.Y + ph * P.vstride;
+                    double sv[3], yv[3];
+                    if (ph == rg.slot) {
+                        for (int cc = 0; cc < 3; ++cc) {
+                            sv[cc] = sn[cc];
+                            yv[cc] = yn[cc];
+                        }
+                    } else {
+                        for (int cc = 0; cc < 3; ++cc) {
+                            sv[cc] = Sj[cc * a.N + s];
+                            yv[cc] = Yj[cc * a.N + s];
+                        }
+                        const double ms = mi[0] * sv[0] + mi[1] * sv[1] + mi[2] * sv[2];
+                        const double my = mi[0] * yv[0] + mi[1] * yv[1] + mi[2] * yv[2];
+                        for (int cc = 0; cc < 3; ++cc) {
+                            sv[cc] -= ms * mi[cc];
+                            yv[cc] -= my * mi[cc];
+                        }
+                    }
+                    for (int cc = 0; cc < 3; ++cc) {
+                        Sj[cc * a.N + s] = sv[cc];
+                        Yj[cc * a.N + s] = yv[cc];
+                        stage[j][cc][t] = sv[cc];
+                        stage[c + j][cc][t] = yv[cc];
+                    }
+                }
+                for (int cc = 0; cc < 3; ++cc) stage[2 * c][cc][t] = g[cc];
+            } else {
+                for (int q = 0; q < nv; ++q)
+                    for (int cc = 0; cc < 3; ++cc) stage[q][cc][t] = 0.0;
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < ne) {
+            double sacc = 0.0;
+            for (int cc = 0; cc < 3; ++cc)
+                for (int tt = 0; tt < SCH; ++tt) sacc += stage[ei][cc][tt] * stage[ej][cc][tt];
+            acc += sacc;
+        }
+        __syncthreads();
+    }
+    // ||F_mmf||^2 was accumulated by threads < SCH only
+    __shared__ double red[NT / 64];
+    double w = wave_sum(fn2);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+    __syncthreads();
+    double* pg = P.pgram + (size_t)blockIdx.x * SPART;
+    if ((int)threadIdx.x < ne) pg[threadIdx.x] = acc;
+    if (threadIdx.x == 0) pg[SNE] = red[0] + red[1] + red[2] + red[3];
+}
+
+// (3) one thread: reduce the Gram, stop test, two-loop recursion in
+// coefficient space, reset test; writes the direction coefficients.
+__global__ void k_step_ctrl(StepArgs a, StepPtrs P) {
+    if (threadIdx.x != 0) return;
+    StepHdr* h = P.hdr;
+    if (h->stopped) return;
+    const Ring rg = ring_next(h, a.mem, a.rule);
+    const int c = rg.c_new;
+    const int nv = 2 * c + 1;
+    const int ne = nv * (nv + 1) / 2;
+    double Gm[SNV][SNV];
+    for (int e = 0; e < ne; ++e) {
+        double s = 0.0;
+        for (int b = 0; b < P.nblk; ++b) s += P.pgram[(size_t)b * SPART + e];
+        int p = e, i = 0;
+        while (p >= nv - i) {
+            p -= nv - i;
+            ++i;
+        }
+        Gm[i][i + p] = s;
+        Gm[i + p][i] = s;
+    }
+    double f2 = 0.0;
+    for (int b = 0; b < P.nblk; ++b) f2 += P.pgram[(size_t)b * SPART + SNE];
+    const double fn = sqrt(f2);
+    h->fnorm = fn;
+    h->count = c;
+    h->head = rg.h_new;
+    if (!(fn > a.tau_F)) {  // converged (or NaN): do not move
+        h->stopped = 1;
+        return;
+    }
+    const int iG = 2 * c;
+    double coef[SNV];
+    for (int q = 0; q < nv; ++q) coef[q] = 0.0;
+    bool reset = (a.rule != 0);
+    if (a.rule == 0) {
+        double q[SNV], alph[SMEM], rho[SMEM];
+        bool valid[SMEM];
+        for (int i = 0; i < nv; ++i) q[i] = 0.0;
+        q[iG] = 1.0;
+        int newest = -1;
+        for (int j = 0; j < c; ++j) {
+            const double sy = Gm[j][c + j];
+            valid[j] = sy > a.sy_min;
+            rho[j] = valid[j] ? 1.0 / sy : 0.0;
+            if (valid[j]) newest = j;
+        }
+        for (int j = c - 1; j >= 0; --j) {
+            if (!valid[j]) continue;
+            double sq = 0.0;
+            for (int i = 0; i < nv; ++i) sq += Gm[j][i] * q[i];
+            alph[j] = rho[j] * sq;
+            q[c + j] -= alph[j];
+        }
+        const double gamma = newest >= 0 ? Gm[newest][c + newest] / Gm[c + newest][c + newest] : a.alpha0;
+        for (int i = 0; i < nv; ++i) q[i] *= gamma;
+        for (int j = 0; j < c; ++j) {
+            if (!valid[j]) continue;
+            double yr = 0.0;
+            for (int i = 0; i < nv; ++i) yr += Gm[c + j][i] * q[i];
+            const double beta = rho[j] * yr;
+            q[j] += alph[j] - beta;
+        }
+        double dG = 0.0;
+        for (int i = 0; i < nv; ++i) {
+            coef[i] = -q[i];
+            dG += coef[i] * Gm[i][iG];
+        }
+        if (!(dG < 0.0)) reset = true;
+    }
+    if (reset) {
+        for (int q = 0; q < nv; ++q) coef[q] = 0.0;
+        coef[iG] = -a.alpha0;
+        if (a.rule == 0) h->count = 0;
+    }
+    for (int q = 0; q < SNV; ++q) h->coef[q] = q < nv ? coef[q] : 0.0;
+    h->cu = c;
+}
+
+// (4) direction d = P(sum coef . vectors) and per-block max |d_i|
+__global__ __launch_bounds__(NT) void k_step_dir(StepArgs a, const double* __restrict__ m, StepPtrs P) {
+    const StepHdr* h = P.hdr;
+    if (h->stopped) return;
+    __shared__ double red[NT / 64];
+    const int cu = h->cu;
+    double mx = 0.0;
+    for (int s = blockIdx.x * NT + threadIdx.x; s < a.N; s += gridDim.x * NT) {
+        double d[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < cu; ++j) {
+            const int ph = (h->head + j) % a.mem;
+            const double cs = h->coef[j], cy = h->coef[cu + j];
+            if (cs == 0.0 && cy == 0.0) continue;
+            const double* Sj = P.S + ph * P.vstride;
+            const double* Yj = P.Y + ph * P.vstride;
+            for (int cc = 0; cc < 3; ++cc) d[cc] += cs * Sj[cc * a.N + s] + cy * Yj[cc * a.N + s];
+        }
+        const double cg = h->coef[2 * cu];
+        for (int cc = 0; cc < 3; ++cc) d[cc] += cg * P.G[cc * a.N + s];
+        const double mi[3] = {m[s], m[a.N + s], m[2 * a.N + s]};
+        const double md = mi[0] * d[0] + mi[1] * d[1] + mi[2] * d[2];
+        double n2 = 0.0;
+        for (int cc = 0; cc < 3; ++cc) {
+            d[cc] -= md * mi[cc];
+            P.d[cc * a.N + s] = d[cc];
+            n2 += d[cc] * d[cc];
+        }
+        mx = fmax(mx, sqrt(n2));
+    }
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) P.pmax[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// (5) rotation cap and exponential-map rotation of every spin; d -> d_prev,
+// G -> G_prev.
+__global__ __launch_bounds__(NT) void k_step_rot(StepArgs a, double* __restrict__ m, StepPtrs P, int nblk_dir) {
+    const StepHdr* h = P.hdr;
+    if (h->stopped) return;
+    __shared__ double scale_s;
+    if (threadIdx.x == 0) {
+        double mx = 0.0;
+        for (int b = 0; b < nblk_dir; ++b) mx = fmax(mx, P.pmax[b]);
+        scale_s = mx > a.theta_max ? a.theta_max / mx : 1.0;
+    }
+    __syncthreads();
+    const double sc = scale_s;
+    for (int s = blockIdx.x * NT + threadIdx.x; s < a.N; s += gridDim.x * NT) {
+        double d[3], mi[3];
+        double n2 = 0.0;
+        for (int cc = 0; cc < 3; ++cc) {
+            d[cc] = sc * P.d[cc * a.N + s];
+            mi[cc] = m[cc * a.N + s];
+            n2 += d[cc] * d[cc];
+            P.dp[cc * a.N + s] = d[cc];
+            P.Gp[cc * a.N + s] = P.G[cc * a.N + s];
+        }
+        const double th = sqrt(n2);
+        if (th > 0.0) {
+            const double ct = cos(th), st = sin(th) / th;
+            double o[3], on = 0.0;
+            for (int cc = 0; cc < 3; ++cc) {
+                o[cc] = ct * mi[cc] + st * d[cc];
+                on += o[cc] * o[cc];
+            }
+            const double inv = 1.0 / sqrt(on);
+            for (int cc = 0; cc < 3; ++cc) m[cc * a.N + s] = o[cc] * inv;
+        }
+    }
+}
+
+__global__ void k_step_finish(StepPtrs P, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    StepHdr* h = P.hdr;
+    out[0] = h->fnorm;
+    out[1] = h->stopped ? 1.0 : 0.0;
+    if (!h->stopped) {
+        h->have_prev = 1;
+        h->iters += 1;
+    }
+}
+
+hipError_t launch_step(const StepArgs& a, double* m, const double* F, const double* V, void* state, double* out,
+                       hipStream_t st) {
+    StepPtrs P = step_ptrs(state, a.N, a.mem, nullptr);
+    const int nb = P.nblk;
+    if (a.k_reflect > 0) hipLaunchKernelGGL(k_step_dots, dim3(nb), dim3(NT), 0, st, a, F, V, P);
+    hipLaunchKernelGGL(k_step_gram, dim3(nb), dim3(NT), 0, st, a, m, F, V, P);
+    hipLaunchKernelGGL(k_step_ctrl, dim3(1), dim3(64), 0, st, a, P);
+    hipLaunchKernelGGL(k_step_dir, dim3(nb), dim3(NT), 0, st, a, m, P);
+    hipLaunchKernelGGL(k_step_rot, dim3(nb), dim3(NT), 0, st, a, m, P, nb);
+    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64), 0, st, P, out);
+    return hipGetLastError();
+}
+
+// ---- descent seed: m <- R(m, scale * v1 / max_i |v1_i|) ----
+__global__ __launch_bounds__(NT) void k_maxnorm(int N, const double* __restrict__ v, double* __restrict__ part) {
+    __shared__ double red[NT / 64];
+    double mx = 0.0;
+    for (int s = blockIdx.x * NT + threadIdx.x; s < N; s += gridDim.x * NT)
+        mx = fmax(mx, sqrt(v[s] * v[s] + v[N + s] * v[N + s] + v[2 * N + s] * v[2 * N + s]));
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(NT) void k_seed_rot(int N, double* __restrict__ m, const double* __restrict__ v,
+                                                 double sse, const double* __restrict__ part, int nblk) {
+    __shared__ double sc;
+    if (threadIdx.x == 0) {
+        double mx = 0.0;
+        for (int b = 0; b < nblk; ++b) mx = fmax(mx, part[b]);
+        sc = mx > 0.0 ? sse / mx : 0.0;
+    }
+    __syncthreads();
+    for (int s = blockIdx.x * NT + threadIdx.x; s < N; s += gridDim.x * NT) {
+        double d[3], mi[3], n2 = 0.0;
+        for (int cc = 0; cc < 3; ++cc) {
+            d[cc] = sc * v[cc * N + s];
+            mi[cc] = m[cc * N + s];
+            n2 += d[cc] * d[cc];
+        }
+        const double th = sqrt(n2);
+        if (th > 0.0) {
+            const double ct = cos(th), st = sin(th) / th;
+            double o[3], on = 0.0;
+            for (int cc = 0; cc < 3; ++cc) {
+                o[cc] = ct * mi[cc] + st * d[cc];
+                on += o[cc] * o[cc];
+            }
+            const double inv = 1.0 / sqrt(on);
+            for (int cc = 0; cc < 3; ++cc) m[cc * N + s] = o[cc] * inv;
+        }
+    }
+}
+
+hipError_t launch_seed_rotate(int N, double* m, const double* v1, double scale_sign_eta, double* part,
+                              hipStream_t st) {
+    int nb = (N + NT - 1) / NT;
+    nb = nb < 256 ? nb : 256;
+    hipLaunchKernelGGL(k_maxnorm, dim3(nb), dim3(NT), 0, st, N, v1, part);
+    hipLaunchKernelGGL(k_seed_rot, dim3(nb), dim3(NT), 0, st, N, m, v1, scale_sign_eta, part, nb);
+    return hipGetLastError();
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ s, float* __restrict__ d, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (float)s[i];
+}
+
+hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+__global__ void k_mask_zero(double* __restrict__ v, const uint8_t* __restrict__ mask, int N, int ncomp) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N || mask[s]) return;
+    for (int c = 0; c < ncomp; ++c) v[(size_t)c * N + s] = 0.0;
+}
+
+hipError_t launch_mask_zero(double* v, const uint8_t* mask, int N, int ncomp, hipStream_t st) {
+    hipLaunchKernelGGL(k_mask_zero, dim3((N + NT - 1) / NT), dim3(NT), 0, st, v, mask, N, ncomp);
+    return hipGetLastError();
+}
+
+}  // namespace moto

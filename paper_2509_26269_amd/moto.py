@@ -1,0 +1,401 @@
+"""Python binding of libmoto.so (argument marshalling only).
+
+Each function has the name of the C entry point it calls and takes torch
+tensors that already live on the GPU; every step of the computation runs in
+the HIP kernels of the library.  There is no CPU fallback: a missing library
+raises at import of the first call.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmoto.so")
+
+MOTO_F32, MOTO_F64 = 0, 1
+MOTO_AMBIENT, MOTO_FRAME = 0, 1
+MAX_SHELLS = 8
+
+SADDLE = CONVERGED = 0
+NOT_CONVERGED, DEGENERATE, HIGHER_INDEX, NAN, BREAKDOWN = 1, 2, 3, 4, 5
+STATUS_NAMES = {0: "SADDLE/CONVERGED", 1: "NOT_CONVERGED", 2: "DEGENERATE", 3: "HIGHER_INDEX", 4: "NAN",
+                5: "BREAKDOWN"}
+
+
+class MotoError(RuntimeError):
+    pass
+
+
+class _Ham(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("n_shells", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("J", ctypes.c_double * MAX_SHELLS),
+                ("D", ctypes.c_double * MAX_SHELLS), ("K", ctypes.c_double), ("B", ctypes.c_double * 3)]
+
+
+class EigOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("guard", ctypes.c_int32),
+                ("warm", ctypes.c_int32), ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("n_hvp", ctypes.c_int64)]
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("mem", ctypes.c_int32), ("theta_max", ctypes.c_double),
+                ("alpha0", ctypes.c_double), ("sy_min", ctypes.c_double), ("tau_F", ctypes.c_double)]
+
+
+class DescendOpts(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("tau_F", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("step", StepOpts), ("eig", EigOpts)]
+
+
+class DescendResult(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int32), ("iters", ctypes.c_int32), ("E", ctypes.c_double),
+                ("Q", ctypes.c_double), ("fnorm", ctypes.c_double), ("lambda1", ctypes.c_double)]
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("tau_F", ctypes.c_double), ("tau_lam", ctypes.c_double), ("k", ctypes.c_int32),
+                ("k_cert", ctypes.c_int32), ("k_reflect", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("step", StepOpts), ("eig", EigOpts)]
+
+
+class SearchResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("n_hvp", ctypes.c_int64),
+                ("E", ctypes.c_double), ("fnorm", ctypes.c_double), ("lambda1", ctypes.c_double),
+                ("lambda2", ctypes.c_double)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("L", ctypes.POINTER(ctypes.c_int32))]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_i32 = ctypes.c_int32
+
+
+def lib():
+    """Load libmoto.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MotoError(f"{LIB_PATH} not found: build it with `python -m paper_2509_26269_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "moto_plan_create": (_i32, [ctypes.POINTER(_Ham), ctypes.POINTER(_vp)]),
+        "moto_plan_destroy": (_i32, [_vp]),
+        "moto_status_string": (ctypes.c_char_p, [_i32]),
+        "moto_hessian_norm_bound": (ctypes.c_double, [_vp]),
+        "moto_n_params": (_i32, [_vp]),
+        "moto_energy_grad_workspace": (_sz, [_vp, _i32]),
+        "moto_energy_grad": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "moto_tangent_hvp": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+        "moto_hessian_apply": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
+        "moto_param_mixed": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "moto_min_modes_workspace": (_sz, [_vp, _i32, _i32, _i32]),
+        "moto_min_modes": (_i32, [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(EigOpts), _vp, _vp, _vp,
+                                  ctypes.POINTER(Info), _vp, _sz, _vp]),
+        "moto_step_state_bytes": (_sz, [_vp, _i32]),
+        "moto_reflected_step": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(StepOpts), _vp, _vp, _vp]),
+        "moto_descend_workspace": (_sz, [_vp, _i32, ctypes.POINTER(DescendOpts)]),
+        "moto_descend": (_i32, [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(DescendOpts),
+                                ctypes.POINTER(DescendResult), _vp, _sz, _vp]),
+        "moto_saddle_search_workspace": (_sz, [_vp, _i32, ctypes.POINTER(SearchOpts)]),
+        "moto_saddle_search": (_i32, [_vp, _i32, _vp, _vp, ctypes.POINTER(SearchOpts), ctypes.POINTER(SearchResult),
+                                      _vp, _vp, _vp, _sz, _vp]),
+        "moto_default_eig_opts": (None, [_i32, ctypes.POINTER(EigOpts)]),
+        "moto_default_step_opts": (None, [ctypes.POINTER(StepOpts)]),
+        "moto_default_descend_opts": (None, [_i32, ctypes.POINTER(DescendOpts)]),
+        "moto_default_search_opts": (None, [_i32, ctypes.POINTER(SearchOpts)]),
+        "moto_topological_charge": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+    }
+    optional = {
+        "moto_saddle_search_batched_workspace": (_sz, [_vp, _i32, ctypes.POINTER(BatchDesc),
+                                                       ctypes.POINTER(SearchOpts)]),
+        "moto_saddle_search_batched": (_i32, [ctypes.POINTER(_Ham), _i32, ctypes.POINTER(BatchDesc), _vp,
+                                              ctypes.POINTER(SearchOpts), ctypes.POINTER(SearchResult), _vp, _sz,
+                                              _vp]),
+    }
+    for name, (res, args) in list(sig.items()) + list(optional.items()):
+        if not hasattr(L, name):
+            if name in sig:
+                raise MotoError(f"libmoto.so lacks {name}")
+            continue
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise MotoError(f"{what}: {lib().moto_status_string(rc).decode()} ({rc})")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise MotoError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise MotoError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return MOTO_F64
+    if t.dtype == torch.float32:
+        return MOTO_F32
+    raise MotoError(f"unsupported dtype {t.dtype}")
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+class Plan:
+    """moto_plan: a validated Hamiltonian on an Lx x Ly lattice."""
+
+    def __init__(self, Lx: int, Ly: int, J: Sequence[float], D: Sequence[float] = (), K: float = 0.0,
+                 B: Sequence[float] = (0.0, 0.0, 0.0)):
+        h = _Ham()
+        h.Lx, h.Ly = int(Lx), int(Ly)
+        h.n_shells = max(len(J), len(D), 1)
+        h.reserved = 0
+        for s in range(MAX_SHELLS):
+            h.J[s] = float(J[s]) if s < len(J) else 0.0
+            h.D[s] = float(D[s]) if s < len(D) else 0.0
+        h.K = float(K)
+        for a in range(3):
+            h.B[a] = float(B[a])
+        self._h = h
+        self.Lx, self.Ly, self.N = h.Lx, h.Ly, h.Lx * h.Ly
+        self.n_shells = h.n_shells
+        p = ctypes.c_void_p()
+        _check(lib().moto_plan_create(ctypes.byref(h), ctypes.byref(p)), "moto_plan_create")
+        self._p = p
+
+    @classmethod
+    def from_params(cls, p) -> "Plan":
+        return cls(p.Lx, p.Ly, list(p.J), list(p.D), p.K, tuple(p.B))
+
+    @property
+    def handle(self):
+        return self._p
+
+    def hessian_norm_bound(self) -> float:
+        return float(lib().moto_hessian_norm_bound(self._p))
+
+    def n_params(self) -> int:
+        return int(lib().moto_n_params(self._p))
+
+    def close(self):
+        if getattr(self, "_p", None) is not None and self._p.value:
+            lib().moto_plan_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+def moto_energy_grad(plan: Plan, m: torch.Tensor, mask: Optional[torch.Tensor] = None, want_grad: bool = True,
+                     want_c: bool = True, want_F: bool = True, want_dtheta: bool = False, stream=None):
+    """E [batch] (FP64), grad, c, F (dtype of m), dE/dtheta [batch][n_params] (FP64)."""
+    batch = m.numel() // (3 * plan.N)
+    dev = m.device
+    E = torch.empty(batch, dtype=torch.float64, device=dev)
+    g = torch.empty_like(m) if want_grad else None
+    c = torch.empty(m.shape[:-2] + (plan.N,), dtype=m.dtype, device=dev) if want_c else None
+    F = torch.empty_like(m) if want_F else None
+    dth = torch.empty(batch, plan.n_params(), dtype=torch.float64, device=dev) if want_dtheta else None
+    nb = lib().moto_energy_grad_workspace(plan.handle, batch)
+    ws = _ws(nb, dev)
+    _check(lib().moto_energy_grad(plan.handle, _dt(m), batch, _ptr(m), _ptr(mask), _ptr(E), _ptr(g), _ptr(c),
+                                  _ptr(F), _ptr(dth), _ptr(ws), nb, _stream(stream)), "moto_energy_grad")
+    return E, g, c, F, dth
+
+
+def moto_tangent_hvp(plan: Plan, m: torch.Tensor, c: torch.Tensor, V: torch.Tensor, layout: int = MOTO_FRAME,
+                     mask: Optional[torch.Tensor] = None, W: Optional[torch.Tensor] = None, batch: int = 1,
+                     stream=None) -> torch.Tensor:
+    """W = M H(m) M V; V is [batch][n_vec][2|3][N]."""
+    dv = 2 if layout == MOTO_FRAME else 3
+    n_vec = V.numel() // (batch * dv * plan.N)
+    if W is None:
+        W = torch.empty_like(V)
+    _check(lib().moto_tangent_hvp(plan.handle, _dt(m), layout, batch, _ptr(m), _ptr(c), _ptr(mask), n_vec,
+                                  _ptr(V), _ptr(W), _stream(stream)), "moto_tangent_hvp")
+    return W
+
+
+def moto_hessian_apply(plan: Plan, V: torch.Tensor, batch: int = 1, W: Optional[torch.Tensor] = None,
+                       stream=None) -> torch.Tensor:
+    n_vec = V.numel() // (batch * 3 * plan.N)
+    if W is None:
+        W = torch.empty_like(V)
+    _check(lib().moto_hessian_apply(plan.handle, _dt(V), batch, n_vec, _ptr(V), _ptr(W), _stream(stream)),
+           "moto_hessian_apply")
+    return W
+
+
+def moto_param_mixed(plan: Plan, m: torch.Tensor, U: torch.Tensor, batch: int = 1, stream=None) -> torch.Tensor:
+    out = torch.empty(batch, plan.n_params(), dtype=torch.float64, device=m.device)
+    nb = lib().moto_energy_grad_workspace(plan.handle, batch)
+    ws = _ws(nb, m.device)
+    _check(lib().moto_param_mixed(plan.handle, _dt(m), batch, _ptr(m), _ptr(U), _ptr(out), _ptr(ws), nb,
+                                  _stream(stream)), "moto_param_mixed")
+    return out
+
+
+def moto_topological_charge(plan: Plan, m: torch.Tensor, batch: int = 1, stream=None) -> torch.Tensor:
+    Q = torch.empty(batch, dtype=torch.float64, device=m.device)
+    nb = lib().moto_energy_grad_workspace(plan.handle, batch)
+    ws = _ws(nb, m.device)
+    _check(lib().moto_topological_charge(plan.handle, batch, _ptr(m), _ptr(Q), _ptr(ws), nb, _stream(stream)),
+           "moto_topological_charge")
+    return Q
+
+
+def eig_opts(dtype: int = MOTO_F64, **kw) -> EigOpts:
+    o = EigOpts()
+    lib().moto_default_eig_opts(dtype, ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def step_opts(**kw) -> StepOpts:
+    o = StepOpts()
+    lib().moto_default_step_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def descend_opts(dtype: int = MOTO_F64, step: Optional[dict] = None, eig: Optional[dict] = None,
+                 **kw) -> DescendOpts:
+    o = DescendOpts()
+    lib().moto_default_descend_opts(dtype, ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    for k, v in (step or {}).items():
+        setattr(o.step, k, v)
+    for k, v in (eig or {}).items():
+        setattr(o.eig, k, v)
+    return o
+
+
+def search_opts(dtype: int = MOTO_F64, step: Optional[dict] = None, eig: Optional[dict] = None,
+                **kw) -> SearchOpts:
+    o = SearchOpts()
+    lib().moto_default_search_opts(dtype, ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    for k, v in (step or {}).items():
+        setattr(o.step, k, v)
+    for k, v in (eig or {}).items():
+        setattr(o.eig, k, v)
+    return o
+
+
+@dataclass
+class MinModes:
+    evals: torch.Tensor
+    V: torch.Tensor
+    resid: torch.Tensor
+    status: int
+    iters: int
+    n_hvp: int
+
+
+class EigWorkspace:
+    """Reusable eigen-solve workspace (keeps the block for warm == 2)."""
+
+    def __init__(self, plan: Plan, hvp: int, k: int, guard: int = -1, device="cuda"):
+        self.nbytes = int(lib().moto_min_modes_workspace(plan.handle, hvp, k, guard))
+        self.buf = _ws(self.nbytes, device)
+
+
+def moto_min_modes(plan: Plan, m: torch.Tensor, k: int, hvp: int = MOTO_F64, mask: Optional[torch.Tensor] = None,
+                   opts: Optional[EigOpts] = None, V0: Optional[torch.Tensor] = None,
+                   ws: Optional[EigWorkspace] = None, stream=None) -> MinModes:
+    o = opts if opts is not None else eig_opts(hvp)
+    dev = m.device
+    V = torch.zeros(k, 3, plan.N, dtype=torch.float64, device=dev) if V0 is None else V0.clone().contiguous()
+    if V0 is not None and o.warm == 0:
+        o.warm = 1
+    evals = torch.empty(k, dtype=torch.float64, device=dev)
+    resid = torch.empty(k, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = EigWorkspace(plan, hvp, k, o.guard, dev)
+    info = Info()
+    _check(lib().moto_min_modes(plan.handle, hvp, _ptr(m), _ptr(mask), k, ctypes.byref(o), _ptr(evals), _ptr(V),
+                                _ptr(resid), ctypes.byref(info), _ptr(ws.buf), ws.nbytes, _stream(stream)),
+           "moto_min_modes")
+    return MinModes(evals, V, resid, info.status, info.iters, info.n_hvp)
+
+
+class StepState:
+    def __init__(self, plan: Plan, mem: int = 8, device="cuda"):
+        self.nbytes = int(lib().moto_step_state_bytes(plan.handle, mem))
+        self.buf = torch.zeros(self.nbytes, dtype=torch.uint8, device=device)
+        self.out = torch.zeros(2, dtype=torch.float64, device=device)
+
+    def reset(self):
+        self.buf.zero_()
+        self.out.zero_()
+
+
+def moto_reflected_step(plan: Plan, m: torch.Tensor, F: torch.Tensor, V: Optional[torch.Tensor], k_reflect: int,
+                        state: StepState, opts: Optional[StepOpts] = None, stream=None) -> torch.Tensor:
+    o = opts if opts is not None else step_opts()
+    _check(lib().moto_reflected_step(plan.handle, _ptr(m), _ptr(F), _ptr(V), k_reflect, ctypes.byref(o),
+                                     _ptr(state.buf), _ptr(state.out), _stream(stream)), "moto_reflected_step")
+    return state.out
+
+
+def moto_descend(plan: Plan, m: torch.Tensor, v1: torch.Tensor, sign: int, hvp: int = MOTO_F64,
+                 opts: Optional[DescendOpts] = None, stream=None) -> DescendResult:
+    o = opts if opts is not None else descend_opts(hvp)
+    nb = int(lib().moto_descend_workspace(plan.handle, hvp, ctypes.byref(o)))
+    ws = _ws(nb, m.device)
+    res = DescendResult()
+    _check(lib().moto_descend(plan.handle, hvp, _ptr(m), _ptr(v1), int(sign), ctypes.byref(o), ctypes.byref(res),
+                              _ptr(ws), nb, _stream(stream)), "moto_descend")
+    return res
+
+
+def moto_saddle_search(plan: Plan, m: torch.Tensor, hvp: int = MOTO_F64, mask: Optional[torch.Tensor] = None,
+                       opts: Optional[SearchOpts] = None, stream=None):
+    """Returns (SearchResult, evals [k_cert], V [k_cert][3][N]); m is updated in place."""
+    o = opts if opts is not None else search_opts(hvp)
+    kc = max(o.k_cert, 2)
+    nb = int(lib().moto_saddle_search_workspace(plan.handle, hvp, ctypes.byref(o)))
+    ws = _ws(nb, m.device)
+    ev = torch.empty(kc, dtype=torch.float64, device=m.device)
+    V = torch.empty(kc, 3, plan.N, dtype=torch.float64, device=m.device)
+    res = SearchResult()
+    _check(lib().moto_saddle_search(plan.handle, hvp, _ptr(m), _ptr(mask), ctypes.byref(o), ctypes.byref(res),
+                                    _ptr(ev), _ptr(V), _ptr(ws), nb, _stream(stream)), "moto_saddle_search")
+    return res, ev, V

@@ -1,0 +1,194 @@
+"""GPU parity of the lattice kernels against the FP64 oracle, through the
+C ABI: energy/gradient/c/F, parameter partials, tangent HVP (frame and
+ambient, FP64 and FP32, masked, batched), Euclidean Hessian apply, mixed
+parameter derivatives, topological charge.
+
+Tolerances: FP64 relative 1e-10 (energy) / 1e-10 (vectors) and the HVP bound
+1e-6 of the parity contract; FP32 relative 1e-6 (energy, FP64 reduction) and
+1e-4 (vectors)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_26269_amd import synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# lattice sizes: several tiles with ragged tails, a tile-sized one, tiny ones
+SIZES = [(16, 16), (37, 23), (64, 8), (5, 7), (3, 3), (1, 4)]
+
+
+def _dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _M():
+    from paper_2509_26269_amd import moto as M
+
+    return M
+
+
+def _params(Lx, Ly, shells=3):
+    p = S.ham_3shell(Lx, Ly) if shells == 3 else S.ham_nn(Lx, Ly)
+    p.B = (0.011, -0.017, 0.03)
+    return p
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("Lx,Ly", SIZES)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_energy_grad_parity(Lx, Ly, dt):
+    M = _M()
+    p = _params(Lx, Ly)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    rng = np.random.default_rng(Lx * 100 + Ly)
+    m = S.random_texture(h.N, rng)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    md = _dev(m, tdt)
+    E, g, c, F, dth = M.moto_energy_grad(plan, md, want_dtheta=True)
+    torch.cuda.synchronize()
+    m_in = _np(md)  # the spins exactly as the GPU saw them
+    Eo, go, co, Fo = O.energy_grad(h, m_in)
+    tol_e, tol_v = (1e-10, 1e-10) if dt == "f64" else (1e-6, 1e-4)
+    assert abs(float(E[0]) - Eo) <= tol_e * max(abs(Eo), 1.0)
+    assert _rel(_np(g), go) <= tol_v
+    assert _rel(_np(c), co) <= tol_v
+    assert _rel(_np(F), Fo) <= tol_v
+    dto = O.param_grad(h, m_in)
+    assert np.allclose(_np(dth)[0], dto, rtol=tol_e * 10, atol=tol_e * 10 * h.N)
+
+
+def test_energy_grad_batched_and_masked():
+    M = _M()
+    p = _params(20, 12)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    rng = np.random.default_rng(5)
+    ms = np.stack([S.random_texture(h.N, rng) for _ in range(3)])
+    mask = np.stack([S.random_mask_disc(20, 12, 4.0, (5 + 3 * b, 6)) for b in range(3)])
+    E, g, c, F, _ = M.moto_energy_grad(plan, _dev(ms), mask=_dev(mask, torch.uint8))
+    for b in range(3):
+        Eo, go, co, Fo = O.energy_grad(h, ms[b])
+        assert abs(float(E[b]) - Eo) <= 1e-10 * abs(Eo)
+        assert _rel(_np(g[b]), go) <= 1e-12
+        assert _rel(_np(F[b]), Fo * mask[b]) <= 1e-12
+
+
+@pytest.mark.parametrize("Lx,Ly", SIZES)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("layout", ["frame", "ambient"])
+def test_tangent_hvp_parity(Lx, Ly, dt, layout):
+    M = _M()
+    p = _params(Lx, Ly)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    rng = np.random.default_rng(7 * Lx + Ly)
+    m = S.random_texture(h.N, rng)
+    _, _, c, _ = O.energy_grad(h, m)
+    nvec = 3
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    md, cd = _dev(m, tdt), _dev(c, tdt)
+    m_in = _np(md)
+    if layout == "frame":
+        a = rng.standard_normal((nvec, 2, h.N))
+        Wd = M.moto_tangent_hvp(plan, md, cd, _dev(a, tdt), M.MOTO_FRAME)
+        v = O.from_frame(m_in, _np(_dev(a, tdt)))
+        ref = O.to_frame(m_in, O.tangent_hvp(h, m_in, _np(cd), v))
+    else:
+        v = S.random_tangent(m_in, nvec, rng)
+        vd = _dev(v, tdt)
+        Wd = M.moto_tangent_hvp(plan, md, cd, vd, M.MOTO_AMBIENT)
+        ref = O.tangent_hvp(h, m_in, _np(cd), _np(vd))
+    tol = 1e-12 if dt == "f64" else 1e-4
+    W = _np(Wd)
+    for j in range(nvec):
+        assert _rel(W[j], ref[j]) <= tol, (j, _rel(W[j], ref[j]))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_tangent_hvp_masked_batched(dt):
+    M = _M()
+    Lx, Ly, B, nvec = 33, 18, 3, 2
+    p = _params(Lx, Ly)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    rng = np.random.default_rng(11)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    ms = np.stack([S.random_texture(h.N, rng) for _ in range(B)])
+    cs = np.stack([O.energy_grad(h, ms[b])[2] for b in range(B)])
+    masks = np.stack([S.random_mask_disc(Lx, Ly, 5.0, (4 + 10 * b, 9)) for b in range(B)])
+    a = rng.standard_normal((B, nvec, 2, h.N))
+    md, cd, ad = _dev(ms, tdt), _dev(cs, tdt), _dev(a, tdt)
+    Wd = M.moto_tangent_hvp(plan, md, cd, ad, M.MOTO_FRAME, mask=_dev(masks, torch.uint8), batch=B)
+    W = _np(Wd)
+    tol = 1e-12 if dt == "f64" else 1e-4
+    for b in range(B):
+        mb = _np(md[b])
+        v = O.from_frame(mb, _np(ad[b]))
+        ref = O.to_frame(mb, O.tangent_hvp(h, mb, _np(cd[b]), v, mask=masks[b]))
+        for j in range(nvec):
+            assert _rel(W[b, j], ref[j]) <= tol
+        assert np.all(W[b][:, :, masks[b] == 0] == 0)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_hessian_apply_and_param_mixed(dt):
+    M = _M()
+    Lx, Ly = 29, 17
+    p = _params(Lx, Ly)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    rng = np.random.default_rng(13)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    m = S.random_texture(h.N, rng)
+    U = rng.standard_normal((2, 3, h.N))
+    md, Ud = _dev(m, tdt), _dev(U, tdt)
+    W = _np(M.moto_hessian_apply(plan, Ud))
+    tol = 1e-12 if dt == "f64" else 1e-5
+    for j in range(2):
+        assert _rel(W[j], O.apply_A(h, _np(Ud[j]))) <= tol
+    # d(g.U)/dtheta by central differences of the oracle gradient in theta
+    mix = _np(M.moto_param_mixed(plan, md, Ud[0].contiguous()))[0]
+    th = h.theta()
+    ns = h.n_shells
+    m_in = _np(md)
+
+    def mk(t):
+        return O.Ham(Lx, Ly, list(t[:ns]), list(t[ns:2 * ns]), t[2 * ns], tuple(t[2 * ns + 1:]))
+
+    for i in range(len(th)):
+        tp, tm = th.copy(), th.copy()
+        tp[i] += 1e-3
+        tm[i] -= 1e-3
+        fd = float(((O.gradient(mk(tp), m_in) - O.gradient(mk(tm), m_in)) * _np(Ud[0])).sum()) / 2e-3
+        assert abs(mix[i] - fd) <= (1e-9 if dt == "f64" else 1e-5) * max(1.0, abs(fd)) * 10
+
+
+def test_topological_charge_gpu():
+    M = _M()
+    L = 32
+    p = _params(L, L)
+    plan = M.Plan.from_params(p)
+    for kind, Q in [("skyrmion", 1), ("antiskyrmion", -1), ("biskyrmion", 2)]:
+        m = S.three_shell_start(L, seed=3, kind=kind)
+        q = float(M.moto_topological_charge(plan, _dev(m))[0])
+        assert abs(q - O.topological_charge(L, m, L)) < 1e-10
+        assert abs(q - Q) < 1e-6
+
+
+def test_bad_arguments_rejected():
+    M = _M()
+    plan = M.Plan.from_params(_params(8, 8))
+    m = _dev(S.uniform(64))
+    with pytest.raises(M.MotoError):
+        M.moto_tangent_hvp(plan, m, torch.zeros(64, dtype=torch.float64, device="cuda"),
+                           torch.zeros(1, 2, 64, dtype=torch.float64, device="cuda"), layout=7)
