@@ -1,0 +1,241 @@
+"""Benchmark of the bilayer minimum-mode kernel on one MI355X.
+
+Headline (the 128x128 three-shell workload, FP32 HVP):
+  * tangent HVP throughput, G site-vectors/s, on a batch of B = 1024
+    independent 128x128 lattices x 4 vectors in the FP32 frame layout (the
+    footprint, 1.3 GB, is several times the 256 MB Infinity Cache, so the
+    kernel streams from HBM); one step = one batched HVP launch;
+  * the roofline of that kernel (algorithmic bytes 12 + 16 n_vec per site);
+  * wall time of the k = 4 eigen-solve (residual 1e-5) on one 128x128 state;
+  * saddle searches/s on 128x128 lattices (k = 2, FP32 HVP, tau_F = 1e-5);
+  * the FP64 CPU oracle timed on a bounded sample of the same HVP workload.
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tangent HVP Gsite/s (GB/s vs HBM peak) + saddle searches/s, 128² lattice"
+HBM_PEAK_GBS = 8000.0
+
+
+def hvp_inputs(M, S, torch, plan, L, B, nvec, n_distinct=32, seed=2025):
+    """B states tiled from n_distinct seeded skyrmion/antiskyrmion starts;
+    c from moto_energy_grad; random frame-coordinate vectors."""
+    kinds = ["skyrmion", "antiskyrmion"]
+    base = np.stack([S.three_shell_start(L, seed=seed + i, kind=kinds[i % 2]) for i in range(n_distinct)])
+    base_t = torch.as_tensor(base, dtype=torch.float32, device="cuda")
+    reps = (B + n_distinct - 1) // n_distinct
+    m = base_t.repeat(reps, 1, 1)[:B].contiguous()
+    _, _, c, _, _ = M.moto_energy_grad(plan, m, want_grad=False, want_F=False)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    V = torch.randn(B, nvec, 2, L * L, dtype=torch.float32, device="cuda", generator=gen)
+    W = torch.empty_like(V)
+    return m, c.contiguous(), V, W, base
+
+
+def time_hvp(M, torch, plan, m, c, V, W, B, steps, warmup):
+    for _ in range(warmup):
+        M.moto_tangent_hvp(plan, m, c, V, M.MOTO_FRAME, W=W, batch=B)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for i in range(steps):
+        ev[i][0].record()
+        M.moto_tangent_hvp(plan, m, c, V, M.MOTO_FRAME, W=W, batch=B)
+        ev[i][1].record()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    per = [a.elapsed_time(b) for a, b in ev]
+    return t0.elapsed_time(t1), per, wall
+
+
+def cpu_baseline(O, S, p, base, nvec, budget_s=12.0):
+    """FP64 oracle HVP (frame coordinates in and out) on a bounded sample of
+    the workload: distinct states x nvec vectors, until the time budget."""
+    h = O.Ham(**p.asdict())
+    rng = np.random.default_rng(7)
+    n_done = 0
+    t0 = time.perf_counter()
+    i = 0
+    while time.perf_counter() - t0 < budget_s and i < len(base):
+        m = base[i].astype(np.float64)
+        m = m / np.linalg.norm(m, axis=0)
+        _, _, c, _ = O.energy_grad(h, m)
+        a = rng.standard_normal((nvec, 2, h.N))
+        t1 = time.perf_counter()
+        v = O.from_frame(m, a)
+        w = O.tangent_hvp(h, m, c, v)
+        _ = O.to_frame(m, w)
+        n_done += nvec
+        i += 1
+        del t1
+    el = time.perf_counter() - t0
+    return n_done, el
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--nvec", type=int, default=4)
+    ap.add_argument("--L", type=int, default=128)
+    ap.add_argument("--searches", type=int, default=8, help="one-at-a-time GPU searches timed")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-search", action="store_true")
+    ap.add_argument("--hvp-only", action="store_true", help="only the HVP leg (for profilers)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (byte-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+              "(the path would shard by independent lattices, see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2509_26269_amd import moto as M
+    from paper_2509_26269_amd import synth as S
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    L, B, nvec = args.L, args.batch, args.nvec
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.calib_copy_mib} MiB done", file=sys.stderr, flush=True)
+        del src, dst
+    p = S.ham_3shell(L)
+    plan = M.Plan.from_params(p)
+    N = L * L
+    print(f"[bench] inputs: {B} x {L}x{L}, n_vec={nvec}", file=sys.stderr, flush=True)
+    m, c, V, W, base = hvp_inputs(M, S, torch, plan, L, B, nvec)
+    torch.cuda.synchronize()
+    print("[bench] timing batched tangent HVP", file=sys.stderr, flush=True)
+    total_ms, per, wall = time_hvp(M, torch, plan, m, c, V, W, B, args.steps, args.warmup)
+    ms_per_step = total_ms / args.steps
+    avg_launch_ms = float(np.mean(per))
+    site_vecs = B * N * nvec
+    gsites = site_vecs / (ms_per_step * 1e-3) / 1e9
+    alg_bytes = (12 + 16 * nvec) * N * B
+    achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(gsites, 3),
+        "unit": "Gsite/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"tangent HVP, frame layout, batch of {B} periodic {L}x{L} triangular lattices "
+                        f"x {nvec} vectors, 3 exchange shells + NN DMI + K + B (J2,J3 seeded), "
+                        "seeded skyrmion/antiskyrmion states",
+            "lattice": f"{L}x{L}", "batch": B, "n_vec": nvec, "hvp": "f32",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "k_tangent_hvp<float, frame>",
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": round(avg_launch_ms, 5),
+        },
+    }
+    del W, V, m, c
+    torch.cuda.empty_cache()
+
+    extra = {}
+    if not args.hvp_only:
+        # eigen-solve wall time on one 128x128 state (k = 4, residual 1e-5)
+        print("[bench] 128x128 k=4 FP32 eigen-solve", file=sys.stderr, flush=True)
+        m1 = torch.as_tensor(base[0].astype(np.float64), device="cuda")
+        m1 = m1 / m1.norm(dim=0, keepdim=True)
+        ws = M.EigWorkspace(plan, M.MOTO_F32, 4)
+        o = M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=400)
+        r = M.moto_min_modes(plan, m1, 4, M.MOTO_F32, opts=o, ws=ws)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            r = M.moto_min_modes(plan, m1, 4, M.MOTO_F32, opts=o, ws=ws)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        extra["min_modes_128_k4_ms"] = round(1e3 * float(np.median(times)), 3)
+        extra["min_modes_128_k4_iters"] = r.iters
+        extra["min_modes_128_k4_n_hvp"] = int(r.n_hvp)
+        extra["min_modes_128_k4_status"] = M.STATUS_NAMES[r.status]
+        extra["min_modes_workspace_bytes"] = ws.nbytes
+        extra["dense_hessian_bytes_avoided"] = (2 * N) ** 2 * 8
+
+    if not args.hvp_only and not args.no_search and args.searches > 0:
+        print(f"[bench] {args.searches} saddle searches on {L}x{L} one at a time", file=sys.stderr, flush=True)
+        so = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, k_cert=2, max_outer=3000,
+                           eig={"tol": 1e-5, "max_iter": 200})
+        kinds = ["skyrmion", "antiskyrmion", "biskyrmion"]
+        rng = np.random.default_rng(128)
+        stats = {}
+        t0 = time.perf_counter()
+        n_iter = 0
+        for i in range(args.searches):
+            m0 = S.three_shell_start(L, seed=int(rng.integers(1 << 30)), kind=kinds[i % 3],
+                                     R=float(rng.uniform(1.0, 3.0)))
+            md = torch.as_tensor(m0, device="cuda")
+            res, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, opts=so)
+            stats[M.STATUS_NAMES[res.status]] = stats.get(M.STATUS_NAMES[res.status], 0) + 1
+            n_iter += res.iters
+            print(f"[bench]   search {i}: {M.STATUS_NAMES[res.status]} iters={res.iters}", file=sys.stderr,
+                  flush=True)
+        el = time.perf_counter() - t0
+        extra["searches_per_s_one_at_a_time"] = round(args.searches / el, 4)
+        extra["search_status"] = stats
+        extra["search_mean_outer_iters"] = round(n_iter / args.searches, 1)
+
+    if not args.hvp_only and not args.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        import oracle as O
+
+        n_done, el = cpu_baseline(O, S, p, base, nvec)
+        out["cpu_baseline"] = {
+            "value": round(n_done * N / el / 1e9, 6),
+            "unit": "Gsite/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_done} FP64 oracle HVPs ({n_done // nvec} distinct {L}x{L} states x {nvec} vectors, "
+                      f"frame coordinates in/out) in {el:.1f} s",
+        }
+    out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

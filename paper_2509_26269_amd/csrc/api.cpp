@@ -70,7 +70,7 @@ EigLayout eig_layout(const moto_plan p, moto_dtype hvp, int k, int guard) {
     L.part = o;
     o += al(part);
     L.G = o;
-    o += al(sizeof(double) * 2 * MAXS * MAXS);
+    o += al(sizeof(double) * 2 * MAXS * (MAXS + 1) / 2);
     L.ctrl = o;
     o += al(sizeof(EigCtrl));
     L.total = o;
@@ -270,14 +270,16 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
     void* Wslot = (char*)S + es * (size_t)L.mb * L.n2;
     void* HWslot = (char*)HS + es * (size_t)L.mb * L.n2;
     const int warm = o->warm;
+    double* G = (double*)(ws + L.G);
     HIP_TRY(launch_eig_init(f64, a, S, m, warm == 1 ? V : nullptr, warm == 1 ? k : 0, ws + L.Xsave, warm == 2,
                             mask, N, o->seed, ctrl, st));
-    // start: HX = H X; Rayleigh-Ritz on span(X); W = HX - X Lam
+    // start: orthonormal X; HX = H X; Rayleigh-Ritz on span(X); W = HX - X Lam
+    for (int pass = 0; pass < 2; ++pass) HIP_TRY(launch_orth(f64, a, 0, S, part, L.nblk_g, G, ctrl, st));
     HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, S, HS, &ctrl->done, st));
-    HIP_TRY(launch_gram(f64, a, L.mb, S, HS, part, L.nblk_g, (double*)(ws + L.G), ctrl, st));
-    HIP_TRY(launch_rr(a, L.mb, (double*)(ws + L.G), ctrl, st));
-    HIP_TRY(launch_update(f64, a, L.mb, L.mb, S, HS, part, L.nblk_u, ctrl, st));
-    HIP_TRY(launch_eig_control(a, part, L.nblk_u, L.mb, ctrl, 1, st));
+    HIP_TRY(launch_gram(f64, a, L.mb, S, HS, part, L.nblk_g, G, ctrl, st));
+    HIP_TRY(launch_rr(a, L.mb, G, ctrl, st));
+    HIP_TRY(launch_update(f64, a, L.mb, S, HS, part, L.nblk_u, ctrl, st));
+    HIP_TRY(launch_eig_control(a, part, L.nblk_u, ctrl, 1, st));
     const int every = o->check_every > 0 ? o->check_every : 8;
     const int max_chunks = o->max_iter / every + 2;
     int hdr[4];
@@ -286,15 +288,16 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
         if (rs != MOTO_OK) return rs;
         if (hdr[0]) break;
         for (int it = 0; it < every; ++it) {
+            for (int pass = 0; pass < 2; ++pass) HIP_TRY(launch_orth(f64, a, 1, S, part, L.nblk_g, G, ctrl, st));
             HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, Wslot, HWslot, &ctrl->done,
                                        st));
-            HIP_TRY(launch_gram(f64, a, -1, S, HS, part, L.nblk_g, (double*)(ws + L.G), ctrl, st));
-            HIP_TRY(launch_rr(a, -1, (double*)(ws + L.G), ctrl, st));
-            HIP_TRY(launch_update(f64, a, -1, L.mb, S, HS, part, L.nblk_u, ctrl, st));
-            HIP_TRY(launch_eig_control(a, part, L.nblk_u, L.mb, ctrl, 0, st));
+            HIP_TRY(launch_gram(f64, a, -1, S, HS, part, L.nblk_g, G, ctrl, st));
+            HIP_TRY(launch_rr(a, -1, G, ctrl, st));
+            HIP_TRY(launch_update(f64, a, -1, S, HS, part, L.nblk_u, ctrl, st));
+            HIP_TRY(launch_eig_control(a, part, L.nblk_u, ctrl, 0, st));
         }
     }
-    HIP_TRY(launch_eig_output(f64, a, S, m, N, V, part, L.nblk_o, ctrl, evals, resid, ws + L.Xsave, st));
+    HIP_TRY(launch_eig_output(f64, a, S, m, N, V, part, ctrl, evals, resid, ws + L.Xsave, st));
     EigCtrl hc;
     moto_status rs = readback(p, ctrl, 32, &hc, st);
     if (rs != MOTO_OK) return rs;

@@ -40,42 +40,49 @@ hipError_t launch_topo_charge(const Geo& g, int batch, const double* m, double* 
 constexpr int MAXB = 16;        // max block width (k + guard)
 constexpr int MAXS = 3 * MAXB;  // max Rayleigh-Ritz basis size
 struct EigCtrl {
-    int done;        // 1 once converged / capped / failed: later launches are no-ops
-    int status;      // MOTO_CONVERGED, MOTO_NOT_CONVERGED, MOTO_NAN, MOTO_BREAKDOWN
-    int iters;       // LOBPCG iterations taken
-    int np;          // columns of P in the current basis (0 or mb)
-    long long n_hvp; // HVP columns applied
-    int rank;        // basis rank kept by the last Rayleigh-Ritz
+    int done;         // 1 once converged / capped / failed: later launches are no-ops
+    int status;       // MOTO_CONVERGED, MOTO_NOT_CONVERGED, MOTO_NAN, MOTO_BREAKDOWN
+    int iters;        // LOBPCG iterations taken
+    int np;           // columns of P in the current basis (0 or mb)
+    long long n_hvp;  // HVP columns applied
+    int rank;         // basis rank kept by the last Rayleigh-Ritz
     int pad;
     double lam[MAXB];
     double resid[MAXB];
-    double C[MAXS * MAXB];  // Ritz coefficients, column-major [s][mb] -> C[i + s*j]
+    double C[MAXS * MAXB];       // Ritz coefficients of X, column-major [ns][mb]
+    double Cp[MAXS * MAXB];      // orthonormal complement spanning the new P, [ns][mb]
+    double Bw[2 * MAXB * MAXB];  // [X P]^T W projection coefficients, [2mb][mb]
+    double Tw[MAXB * MAXB];      // orthonormalising transform of the projected block, [mb][mb]
 };
 
 struct EigArgs {
-    int n2;      // rows of the frame-coordinate vectors (2N)
-    int mb;      // block width
-    int k;       // wanted pairs
+    int n2;        // rows of the frame-coordinate vectors (2N)
+    int mb;        // block width
+    int k;         // wanted pairs
     int max_iter;
     double tol_abs;
-    double drop;  // SVQB rank threshold (relative)
+    double drop;   // rank threshold of the orthonormalisations (relative)
 };
 
 hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m, const double* Vwarm, int nwarm,
                            const void* Xsave, int use_save, const uint8_t* mask, int N, uint64_t seed,
                            EigCtrl* ctrl, hipStream_t st);
+// Orthonormalise the X block (target 0, start) or the W block against [X P]
+// and itself (target 1), in place.
+hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* part, int nblk, double* G,
+                       EigCtrl* ctrl, hipStream_t st);
 hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const void* HS, double* part, int nblk,
                        double* G, const EigCtrl* ctrl, hipStream_t st);
 int gram_blocks(int n2);
 hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, hipStream_t st);
-hipError_t launch_update(bool f64, const EigArgs& a, int ns, int nx, void* S, void* HS, double* part, int nblk,
+hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, double* part, int nblk,
                          EigCtrl* ctrl, hipStream_t st);
 int update_blocks(int n2);
-hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, int ns_w, EigCtrl* ctrl,
-                              int first, hipStream_t st);
+hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, EigCtrl* ctrl, int first,
+                              hipStream_t st);
 hipError_t launch_eig_output(bool f64, const EigArgs& a, const void* S, const double* m, int N, double* V,
-                             double* part, int nblk, const EigCtrl* ctrl, double* evals, double* resid,
-                             void* Xsave, hipStream_t st);
+                             double* part, const EigCtrl* ctrl, double* evals, double* resid, void* Xsave,
+                             hipStream_t st);
 
 // ---- step.hip ----
 struct StepArgs {

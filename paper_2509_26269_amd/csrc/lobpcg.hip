@@ -1,22 +1,34 @@
 // lobpcg.hip -- device kernels of the inner layer: block LOBPCG (Knyazev
-// 2001) on the tangent Hessian in frame coordinates, with the Rayleigh-Ritz
-// step of every iteration solved on the device in FP64 by one workgroup.
+// 2001) on the tangent Hessian in frame coordinates, with every small dense
+// step solved on the device in FP64 by one workgroup.
 //
-// Block storage (precision T, frame coordinates, rows = 2N):
-//   S  = [X | W | P]  = 3*mb column vectors of n2 rows, column-major
+// Block storage (precision T, frame coordinates, rows n2 = 2N):
+//   S  = [X | W | P]  = 3*mb column vectors, column-major
 //   HS = [HX | HW | HP]
-// One iteration: HW = H W (tangent HVP kernel) -> Grams S^T HS, S^T S (FP64
-// accumulation, fixed-order reduction) -> Rayleigh-Ritz (SVQB
-// orthonormalisation of the Gram, Stathopoulos & Wu 2002, then cyclic Jacobi)
-// -> X, P, HX, HP updated in place from the Ritz coefficients, W = HX - X Lam
-// and its column norms -> convergence control.  Every kernel returns at once
-// when the control block says the solve is done, so chunks of iterations can
-// be queued without host round trips.
+// The basis is kept orthonormal so that no large coefficient ever multiplies
+// FP32 data (the recurrences HX <- HS C stay consistent with H X):
+//   * W (the residual block) is orthonormalised against [X P] and itself,
+//     twice, BEFORE its HVP (so HW is exact for the basis actually used);
+//   * the new P is an orthonormal basis of the complement of the new X in
+//     span(X_new, W/P part of the Ritz vectors), built in coefficient space
+//     (the orthogonal-P construction of Duersch, Shao, Yang & Gu, SISC 2018);
+//   * Rayleigh-Ritz still orthonormalises the Gram (SVQB, Stathopoulos & Wu
+//     2002) and drops dependent directions before the eigen-solve.
+// One iteration: orth(W) x2 -> HW = H W -> Grams S^T HS, S^T S (FP64,
+// fixed-order reduction) -> Rayleigh-Ritz (cyclic Jacobi) -> block update
+// X, P, HX, HP, W = HX - X Lam -> convergence control.  Every kernel returns
+// at once when the control block says the solve is done, so chunks of
+// iterations can be queued without host round trips.
 #include "kernels.hpp"
 
 namespace moto {
 
-constexpr int RCH = 64;  // rows per Gram chunk
+constexpr int RCH = 64;                              // rows per staged chunk
+constexpr int GENT = 2 * MAXS * (MAXS + 1) / 2;      // Gram entries (upper triangles of 2 matrices)
+constexpr int GQ = (GENT + NT - 1) / NT;             // entries per thread
+constexpr int OENT = MAXS * MAXB;                    // orthonormalisation Gram entries
+constexpr int OQ = (OENT + NT - 1) / NT;
+constexpr int PSTRIDE = GENT;                        // doubles per block partial row
 
 __device__ __forceinline__ int sol_ns(const EigArgs& a, const EigCtrl* ctrl, int ns_fixed) {
     return ns_fixed >= 0 ? ns_fixed : 2 * a.mb + ctrl->np;
@@ -24,8 +36,8 @@ __device__ __forceinline__ int sol_ns(const EigArgs& a, const EigCtrl* ctrl, int
 
 // --------------------------------------------------------------------------
 // Start block: warm vectors (ambient FP64 or the saved ambient block)
-// converted to frame coordinates at m, random (SplitMix64) columns for the
-// rest; masked rows zero.  Also resets the control block.
+// converted to frame coordinates at m, SplitMix64 columns for the rest;
+// masked rows zero.  Resets the control block.
 // --------------------------------------------------------------------------
 template <class T>
 __global__ void k_eig_init(EigArgs a, T* __restrict__ S, const double* __restrict__ m,
@@ -65,11 +77,197 @@ __global__ void k_eig_init(EigArgs a, T* __restrict__ S, const double* __restric
 }
 
 // --------------------------------------------------------------------------
-// Gram matrices: entries e < ns(ns+1)/2 are S_i.HS_j (i <= j), the next
-// ns(ns+1)/2 are S_i.S_j.  Each block accumulates its rows in FP64 and writes
-// one partial row; k_gram_final sums the partials in block order.
+// Orthonormalisation of a target block Y (X at the start, W afterwards)
+// against the projection set Q = [X P] (empty at the start):
+//   B = Q^T Y,  M = Y^T Y - B^T B  (= (Y - Q B)^T (Y - Q B) for orthonormal Q),
+//   M -> D M D = Z diag(theta) Z^T,  Tw = D Z_keep theta^-1/2 (zero-padded),
+//   Y <- (Y - Q B) Tw.
+// Columns whose projected norm is negligible are zeroed (and so dropped by
+// the Rayleigh-Ritz rank test).
 // --------------------------------------------------------------------------
-constexpr int GQ = 10;  // entries per thread (2 * 48 * 49 / 2 / 256 < 10)
+struct OrthCols {
+    int nq;       // projection columns
+    int qcol[MAXS];
+    int t0;       // first target column
+};
+
+__device__ __forceinline__ void orth_cols(const EigArgs& a, int target, const EigCtrl* ctrl, OrthCols& oc) {
+    oc.nq = 0;
+    oc.t0 = target == 0 ? 0 : a.mb;
+    if (target == 1) {
+        for (int i = 0; i < a.mb; ++i) oc.qcol[oc.nq++] = i;                    // X
+        for (int i = 0; i < ctrl->np; ++i) oc.qcol[oc.nq++] = 2 * a.mb + i;     // P
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_orth_gram(EigArgs a, int target, const T* __restrict__ S,
+                                                  double* __restrict__ part, const EigCtrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ OrthCols oc;
+    __shared__ T ts[MAXS][RCH];
+    if (threadIdx.x == 0) orth_cols(a, target, ctrl, oc);
+    __syncthreads();
+    const int nrow = oc.nq + a.mb;  // staged columns: Q then Y
+    const int E = nrow * a.mb;      // entry e = j * nrow + i : (stage col i) . (Y col j)
+    double acc[OQ];
+#pragma unroll
+    for (int q = 0; q < OQ; ++q) acc[q] = 0.0;
+    const int nchunks = (a.n2 + RCH - 1) / RCH;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int r0 = ch * RCH;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < nrow * RCH; idx += NT) {
+            const int c = idx / RCH, rr = idx % RCH, r = r0 + rr;
+            const int col = c < oc.nq ? oc.qcol[c] : oc.t0 + (c - oc.nq);
+            ts[c][rr] = r < a.n2 ? S[(size_t)col * a.n2 + r] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < OQ; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < E) {
+                const int j = e / nrow, i = e % nrow;
+                const T* x = ts[i];
+                const T* y = ts[oc.nq + j];
+                double s = 0.0;
+                for (int rr = 0; rr < RCH; ++rr) s += (double)x[rr] * (double)y[rr];
+                acc[q] += s;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < OQ; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < E) part[(size_t)blockIdx.x * PSTRIDE + e] = acc[q];
+    }
+}
+
+// Multi-block fixed-order reduction of per-block partial rows: G[e] = sum_b part[b][e].
+__global__ __launch_bounds__(NT) void k_reduce_rows(const double* __restrict__ part, int nblk, int E,
+                                                    double* __restrict__ G, const EigCtrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int e = blockIdx.x * NT + threadIdx.x;
+    if (e >= E) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * PSTRIDE + e];
+    G[e] = s;
+}
+
+__device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweeps, double* red, double* cs,
+                          double* sn, int* pp, int* qq);
+
+__global__ __launch_bounds__(NT) void k_orth_small(EigArgs a, int target, const double* __restrict__ G,
+                                                   EigCtrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ OrthCols oc;
+    __shared__ double A[MAXS * MAXS];
+    __shared__ double Z[MAXS * MAXS];
+    __shared__ double dsc[MAXB], th[MAXB], red[8], cs[MAXS / 2 + 1], sn[MAXS / 2 + 1];
+    __shared__ int pp[MAXS / 2 + 1], qq[MAXS / 2 + 1], keep[MAXB];
+    __shared__ int nkeep;
+    const int tid = threadIdx.x;
+    if (tid == 0) orth_cols(a, target, ctrl, oc);
+    __syncthreads();
+    const int mb = a.mb, nq = oc.nq, nrow = nq + mb;
+    // B = Q^T Y -> ctrl->Bw ([2mb][mb], rows in projection order)
+    for (int i = tid; i < nq * mb; i += NT) {
+        const int r = i % nq, j = i / nq;
+        ctrl->Bw[r + 2 * MAXB * j] = G[j * nrow + r];
+    }
+    // M = Y^T Y - B^T B
+    for (int i = tid; i < mb * mb; i += NT) {
+        const int r = i % mb, c = i / mb;
+        double v = G[c * nrow + nq + r];
+        for (int l = 0; l < nq; ++l) v -= G[r * nrow + l] * G[c * nrow + l];
+        A[r * MAXS + c] = v;
+    }
+    __syncthreads();
+    for (int j = tid; j < mb; j += NT) {
+        const double full = G[j * nrow + nq + j];
+        const double proj = A[j * MAXS + j];
+        // negligible after projection (relative to the column itself): drop
+        dsc[j] = (proj > a.drop * full && proj > 0.0) ? 1.0 / sqrt(proj) : 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < mb * mb; i += NT) {
+        const int r = i % mb, c = i / mb;
+        A[r * MAXS + c] *= dsc[r] * dsc[c];
+    }
+    __syncthreads();
+    jacobi_wg(A, Z, mb, 1e-15, 40, red, cs, sn, pp, qq);
+    if (tid == 0) {
+        int r = 0;
+        for (int i = 0; i < mb; ++i) {
+            const double t = A[i * MAXS + i];
+            if (t > a.drop) {
+                keep[r] = i;
+                th[r] = t;
+                ++r;
+            }
+        }
+        nkeep = r;
+    }
+    __syncthreads();
+    for (int i = tid; i < mb * mb; i += NT) {
+        const int row = i % mb, c = i / mb;
+        ctrl->Tw[row + mb * c] = c < nkeep ? dsc[row] * Z[row * MAXS + keep[c]] / sqrt(th[c]) : 0.0;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_orth_apply(EigArgs a, int target, T* __restrict__ S,
+                                                   const EigCtrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ OrthCols oc;
+    __shared__ double B[2 * MAXB * MAXB];
+    __shared__ double Tw[MAXB * MAXB];
+    if (threadIdx.x == 0) orth_cols(a, target, ctrl, oc);
+    for (int i = threadIdx.x; i < 2 * MAXB * MAXB; i += NT) B[i] = ctrl->Bw[i];
+    for (int i = threadIdx.x; i < MAXB * MAXB; i += NT) Tw[i] = ctrl->Tw[i];
+    __syncthreads();
+    const int mb = a.mb, nq = oc.nq;
+    for (int r = blockIdx.x * NT + threadIdx.x; r < a.n2; r += gridDim.x * NT) {
+        double q[MAXS], u[MAXB];
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i)
+            if (i < nq) q[i] = (double)S[(size_t)oc.qcol[i] * a.n2 + r];
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            if (j < mb) {
+                double v = (double)S[(size_t)(oc.t0 + j) * a.n2 + r];
+#pragma unroll
+                for (int i = 0; i < MAXS; ++i)
+                    if (i < nq) v -= B[i + 2 * MAXB * j] * q[i];
+                u[j] = v;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            if (j < mb) {
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l < MAXB; ++l)
+                    if (l < mb) v += u[l] * Tw[l + mb * j];
+                S[(size_t)(oc.t0 + j) * a.n2 + r] = (T)v;
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Rayleigh-Ritz Grams: entries e < ns(ns+1)/2 are S_i.HS_j (i <= j), the next
+// ns(ns+1)/2 are S_i.S_j.  Per-block FP64 partial rows, then k_reduce_rows.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void tri_index(int p, int ns, int& i, int& j) {
+    int ii = 0;
+    while (p >= ns - ii) {
+        p -= ns - ii;
+        ++ii;
+    }
+    i = ii;
+    j = ii + p;
+}
 
 template <class T>
 __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* __restrict__ S,
@@ -83,18 +281,11 @@ __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* _
     int ei[GQ], ej[GQ], ew[GQ];
 #pragma unroll
     for (int q = 0; q < GQ; ++q) {
-        int e = threadIdx.x + q * NT;
+        const int e = threadIdx.x + q * NT;
         ei[q] = ej[q] = ew[q] = 0;
         if (e < E) {
             ew[q] = e >= Eh;
-            int p = e - ew[q] * Eh;
-            int i = 0;
-            while (p >= ns - i) {
-                p -= ns - i;
-                ++i;
-            }
-            ei[q] = i;
-            ej[q] = i + p;
+            tri_index(e - ew[q] * Eh, ns, ei[q], ej[q]);
         }
     }
     double acc[GQ];
@@ -125,30 +316,7 @@ __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* _
 #pragma unroll
     for (int q = 0; q < GQ; ++q) {
         const int e = threadIdx.x + q * NT;
-        if (e < E) part[(size_t)blockIdx.x * (2 * MAXS * (MAXS + 1) / 2) + e] = acc[q];
-    }
-}
-
-// G layout: G[0][i][j] = (S^T HS) symmetrised from the upper triangle,
-// G[1][i][j] = S^T S; leading dimension MAXS.
-__global__ __launch_bounds__(NT) void k_gram_final(EigArgs a, int ns_fixed, const double* __restrict__ part,
-                                                   int nblk, double* __restrict__ G,
-                                                   const EigCtrl* __restrict__ ctrl) {
-    if (ctrl->done) return;
-    const int ns = sol_ns(a, ctrl, ns_fixed);
-    const int Eh = ns * (ns + 1) / 2, E = 2 * Eh;
-    for (int e = threadIdx.x; e < E; e += NT) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (2 * MAXS * (MAXS + 1) / 2) + e];
-        const int w = e >= Eh;
-        int p = e - w * Eh, i = 0;
-        while (p >= ns - i) {
-            p -= ns - i;
-            ++i;
-        }
-        const int j = i + p;
-        G[w * MAXS * MAXS + i * MAXS + j] = s;
-        G[w * MAXS * MAXS + j * MAXS + i] = s;
+        if (e < E) part[(size_t)blockIdx.x * PSTRIDE + e] = acc[q];
     }
 }
 
@@ -169,7 +337,6 @@ __device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweep
     const int half = ne / 2;
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        // off-diagonal and total Frobenius norms
         double off = 0.0, fro = 0.0;
         for (int i = tid; i < n * n; i += NT) {
             const int r = i / n, c = i % n;
@@ -190,10 +357,10 @@ __device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweep
         if (!(offt > tol * tol * frot)) break;
         for (int round = 0; round < ne - 1; ++round) {
             if (tid < half) {
-                int pa = tid, pb = ne - 1 - tid;
-                int ia = pa == 0 ? 0 : 1 + (pa - 1 + round) % (ne - 1);
-                int ib = pb == 0 ? 0 : 1 + (pb - 1 + round) % (ne - 1);
-                int p = ia < ib ? ia : ib, q = ia < ib ? ib : ia;
+                const int pa = tid, pb = ne - 1 - tid;
+                const int ia = pa == 0 ? 0 : 1 + (pa - 1 + round) % (ne - 1);
+                const int ib = pb == 0 ? 0 : 1 + (pb - 1 + round) % (ne - 1);
+                const int p = ia < ib ? ia : ib, q = ia < ib ? ib : ia;
                 double c = 1.0, s = 0.0;
                 if (q < n) {
                     const double apq = A[p * MAXS + q];
@@ -210,8 +377,7 @@ __device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweep
                 qq[tid] = q < n ? q : -1;
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int i = tid; i < half * n; i += NT) {
+            for (int i = tid; i < half * n; i += NT) {  // rows: A <- J^T A
                 const int kp = i / n, col = i % n;
                 const int q = qq[kp];
                 if (q < 0) continue;
@@ -222,8 +388,7 @@ __device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweep
                 A[q * MAXS + col] = s * ap + c * aq;
             }
             __syncthreads();
-            // columns: A <- A J, Z <- Z J
-            for (int i = tid; i < half * n; i += NT) {
+            for (int i = tid; i < half * n; i += NT) {  // columns: A <- A J, Z <- Z J
                 const int kp = i / n, row = i % n;
                 const int q = qq[kp];
                 if (q < 0) continue;
@@ -241,32 +406,50 @@ __device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweep
     }
 }
 
-// Rayleigh-Ritz on span(S), basis size ns = nx + nw + np:
+// --------------------------------------------------------------------------
+// Rayleigh-Ritz on span(S), basis size ns:
 //   G_B -> D G_B D = Z diag(theta) Z^T, keep theta > drop * max(theta),
-//   T = D Z_keep theta^-1/2 (so T^T G_B T = I);
-//   A~ = T^T G_A T = Y diag(lam) Y^T;  C = T Y[:, lowest mb].
-__global__ __launch_bounds__(NT) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ G,
+//   T = D Z_keep theta^-1/2  (T^T G_B T = I);
+//   T^T G_A T = Y diag(lam) Y^T;   C = T Y[:, lowest mb]   (X_new = S C);
+//   C_wp = C with its X rows zeroed, made G_B-orthogonal to C (twice) and
+//   G_B-orthonormalised with rank dropping -> Cp  (P_new = S Cp).
+// G layout: G[e] for the upper triangles of S^T HS then S^T S (row-major).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ Gtri,
                                            EigCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     const int ns = sol_ns(a, ctrl, ns_fixed);
+    const int mb = a.mb;
     __shared__ double A[MAXS * MAXS];
     __shared__ double Z[MAXS * MAXS];
     __shared__ double Tm[MAXS * MAXS];
-    __shared__ double dsc[MAXS], th[MAXS], red[8], cs[MAXS / 2 + 1], sn[MAXS / 2 + 1];
+    __shared__ double dsc[MAXS], th[MAXS], ev[MAXS], red[8], cs[MAXS / 2 + 1], sn[MAXS / 2 + 1];
+    __shared__ double h1[MAXB * MAXB];
     __shared__ int pp[MAXS / 2 + 1], qq[MAXS / 2 + 1], keep[MAXS], order[MAXS];
     __shared__ int rank_s;
     const int tid = threadIdx.x;
-    const double* GA = G;
-    const double* GB = G + MAXS * MAXS;
-    for (int i = tid; i < ns; i += NT) dsc[i] = 1.0 / sqrt(fmax(GB[i * MAXS + i], 1e-300));
+    const int Eh = ns * (ns + 1) / 2;
+    auto GA = [&](int i, int j) {
+        const int r = i < j ? i : j, c = i < j ? j : i;
+        return Gtri[r * ns - r * (r - 1) / 2 + (c - r)];
+    };
+    auto GB = [&](int i, int j) {
+        const int r = i < j ? i : j, c = i < j ? j : i;
+        return Gtri[Eh + r * ns - r * (r - 1) / 2 + (c - r)];
+    };
+    double gbmax = 0.0;
+    for (int i = 0; i < ns; ++i) gbmax = fmax(gbmax, GB(i, i));
+    for (int i = tid; i < ns; i += NT) {
+        const double gii = GB(i, i);
+        dsc[i] = gii > 1e-24 * gbmax ? 1.0 / sqrt(gii) : 0.0;
+    }
     __syncthreads();
     for (int i = tid; i < ns * ns; i += NT) {
         const int r = i / ns, c = i % ns;
-        A[r * MAXS + c] = dsc[r] * GB[r * MAXS + c] * dsc[c];
+        A[r * MAXS + c] = dsc[r] * GB(r, c) * dsc[c];
     }
     __syncthreads();
     jacobi_wg(A, Z, ns, 1e-15, 40, red, cs, sn, pp, qq);
-    // rank-revealing selection, in ascending eigen order for determinism
     if (tid == 0) {
         double tmax = 0.0;
         for (int i = 0; i < ns; ++i) tmax = fmax(tmax, A[i * MAXS + i]);
@@ -283,22 +466,19 @@ __global__ __launch_bounds__(NT) void k_rr(EigArgs a, int ns_fixed, const double
     }
     __syncthreads();
     const int r = rank_s;
-    // T = D Z_keep theta^-1/2   (ns x r)
-    for (int i = tid; i < ns * r; i += NT) {
+    for (int i = tid; i < ns * r; i += NT) {  // T (ns x r)
         const int row = i / r, c = i % r;
         Tm[row * MAXS + c] = dsc[row] * Z[row * MAXS + keep[c]] / sqrt(th[c]);
     }
     __syncthreads();
-    // Z <- G_A T  (ns x r)
-    for (int i = tid; i < ns * r; i += NT) {
+    for (int i = tid; i < ns * r; i += NT) {  // Z <- G_A T
         const int row = i / r, c = i % r;
         double s = 0.0;
-        for (int l = 0; l < ns; ++l) s += GA[row * MAXS + l] * Tm[l * MAXS + c];
+        for (int l = 0; l < ns; ++l) s += GA(row, l) * Tm[l * MAXS + c];
         Z[row * MAXS + c] = s;
     }
     __syncthreads();
-    // A <- T^T Z  (r x r), symmetrised
-    for (int i = tid; i < r * r; i += NT) {
+    for (int i = tid; i < r * r; i += NT) {  // A <- T^T Z
         const int row = i / r, c = i % r;
         double s = 0.0;
         for (int l = 0; l < ns; ++l) s += Tm[l * MAXS + row] * Z[l * MAXS + c];
@@ -315,20 +495,17 @@ __global__ __launch_bounds__(NT) void k_rr(EigArgs a, int ns_fixed, const double
     }
     __syncthreads();
     jacobi_wg(A, Z, r, 1e-15, 40, red, cs, sn, pp, qq);
-    // ascending order (stable by index)
+    for (int i = tid; i < r; i += NT) ev[i] = A[i * MAXS + i];
+    __syncthreads();
     for (int i = tid; i < r; i += NT) {
-        const double li = A[i * MAXS + i];
+        const double li = ev[i];
         int rk = 0;
-        for (int j = 0; j < r; ++j) {
-            const double lj = A[j * MAXS + j];
-            rk += (lj < li) || (lj == li && j < i);
-        }
+        for (int j = 0; j < r; ++j) rk += (ev[j] < li) || (ev[j] == li && j < i);
         order[rk] = i;
     }
     __syncthreads();
-    const int mb = a.mb;
     const int mcol = r < mb ? r : mb;
-    // C = T Y[:, order[0..mb)]   column-major [ns][mb]
+    // C = T Y[:, order[0..mb)] -> A region (ld MAXB) and ctrl->C
     for (int i = tid; i < ns * mb; i += NT) {
         const int row = i % ns, j = i / ns;
         double s = 0.0;
@@ -336,34 +513,120 @@ __global__ __launch_bounds__(NT) void k_rr(EigArgs a, int ns_fixed, const double
             const int yc = order[j];
             for (int l = 0; l < r; ++l) s += Tm[row * MAXS + l] * Z[l * MAXS + yc];
         }
+        A[row * MAXB + j] = s;
         ctrl->C[row + ns * j] = s;
     }
-    for (int j = tid; j < mb; j += NT) ctrl->lam[j] = j < mcol ? A[order[j] * MAXS + order[j]] : 0.0;
+    for (int j = tid; j < mb; j += NT) ctrl->lam[j] = j < mcol ? ev[order[j]] : 0.0;
     if (tid == 0) ctrl->rank = r;
+    __syncthreads();
+    // ---- P complement: Cwp (Tm region, ld MAXB) ----
+    const int nx = mb;
+    for (int i = tid; i < ns * mb; i += NT) {
+        const int row = i % ns, j = i / ns;
+        Tm[row * MAXB + j] = row < nx ? 0.0 : A[row * MAXB + j];
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = tid; i < ns * mb; i += NT) {  // Z <- G_B Cwp
+            const int row = i % ns, j = i / ns;
+            double s = 0.0;
+            for (int l = 0; l < ns; ++l) s += GB(row, l) * Tm[l * MAXB + j];
+            Z[row * MAXB + j] = s;
+        }
+        __syncthreads();
+        for (int i = tid; i < mb * mb; i += NT) {  // h1 <- C^T G_B Cwp
+            const int p = i % mb, j = i / mb;
+            double s = 0.0;
+            for (int l = 0; l < ns; ++l) s += A[l * MAXB + p] * Z[l * MAXB + j];
+            h1[p + MAXB * j] = s;
+        }
+        __syncthreads();
+        for (int i = tid; i < ns * mb; i += NT) {  // Cwp <- Cwp - C h1
+            const int row = i % ns, j = i / ns;
+            double s = Tm[row * MAXB + j];
+            for (int p = 0; p < mb; ++p) s -= A[row * MAXB + p] * h1[p + MAXB * j];
+            Tm[row * MAXB + j] = s;
+        }
+        __syncthreads();
+    }
+    // Mp = Cwp^T G_B Cwp  (mb x mb) -> Z region (ld MAXS) after the product
+    for (int i = tid; i < ns * mb; i += NT) {
+        const int row = i % ns, j = i / ns;
+        double s = 0.0;
+        for (int l = 0; l < ns; ++l) s += GB(row, l) * Tm[l * MAXB + j];
+        A[row * MAXB + j] = s;  // C no longer needed: reuse A for G_B Cwp
+    }
+    __syncthreads();
+    for (int i = tid; i < mb * mb; i += NT) {
+        const int p = i % mb, j = i / mb;
+        double s = 0.0;
+        for (int l = 0; l < ns; ++l) s += Tm[l * MAXB + p] * A[l * MAXB + j];
+        h1[p + MAXB * j] = s;
+    }
+    __syncthreads();
+    for (int j = tid; j < mb; j += NT) {
+        const double d = h1[j + MAXB * j];
+        dsc[j] = d > 1e-24 ? 1.0 / sqrt(d) : 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < mb * mb; i += NT) {
+        const int p = i % mb, j = i / mb;
+        Z[p * MAXS + j] = dsc[p] * h1[p + MAXB * j] * dsc[j];
+    }
+    __syncthreads();
+    jacobi_wg(Z, A, mb, 1e-15, 40, red, cs, sn, pp, qq);
+    if (tid == 0) {
+        int rr = 0;
+        for (int i = 0; i < mb; ++i) {
+            const double t = Z[i * MAXS + i];
+            if (t > a.drop) {
+                keep[rr] = i;
+                th[rr] = t;
+                ++rr;
+            }
+        }
+        rank_s = rr;
+    }
+    __syncthreads();
+    const int rp = rank_s;
+    for (int i = tid; i < ns * mb; i += NT) {  // Cp = Cwp D Zp_keep theta^-1/2
+        const int row = i % ns, j = i / ns;
+        double s = 0.0;
+        if (j < rp) {
+            const int zc = keep[j];
+            for (int l = 0; l < mb; ++l) s += Tm[row * MAXB + l] * dsc[l] * A[l * MAXS + zc];
+            s /= sqrt(th[j]);
+        }
+        ctrl->Cp[row + ns * j] = s;
+    }
 }
 
 // --------------------------------------------------------------------------
 // Block update from the Ritz coefficients (in place, row by row):
-//   X <- S C,  P <- S C_wp,  HX <- HS C,  HP <- HS C_wp,  W <- HX - X Lam,
-// with C_wp = C with its first nx rows zeroed; per-block partial sums of
-// |W_j|^2.  ns == nx (the start) leaves P untouched.
+//   X <- S C,  HX <- HS C,  P <- S Cp,  HP <- HS Cp,  W <- HX - X Lam,
+// and per-block partial sums of |W_j|^2.  At the start (ns == mb) P is left
+// alone.
 // --------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __restrict__ S, T* __restrict__ HS,
                                                double* __restrict__ part, const EigCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     const int ns = sol_ns(a, ctrl, ns_fixed);
-    const int mb = a.mb, nx = mb;
+    const int mb = a.mb;
     __shared__ double C[MAXS * MAXB];
+    __shared__ double Cp[MAXS * MAXB];
     __shared__ double lam[MAXB];
     __shared__ double red[MAXB * (NT / 64)];
-    for (int i = threadIdx.x; i < ns * mb; i += NT) C[i] = ctrl->C[i];
+    for (int i = threadIdx.x; i < ns * mb; i += NT) {
+        C[i] = ctrl->C[i];
+        Cp[i] = ctrl->Cp[i];
+    }
     for (int i = threadIdx.x; i < mb; i += NT) lam[i] = ctrl->lam[i];
     __syncthreads();
     double rs[MAXB];
 #pragma unroll
     for (int j = 0; j < MAXB; ++j) rs[j] = 0.0;
-    const bool has_p = ns > nx;
+    const bool has_p = ns > mb;
     for (int r = blockIdx.x * NT + threadIdx.x; r < a.n2; r += gridDim.x * NT) {
         T sv[MAXS];
 #pragma unroll
@@ -377,9 +640,8 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
 #pragma unroll
                 for (int i = 0; i < MAXS; ++i) {
                     if (i < ns) {
-                        const double t = C[i + ns * j] * (double)sv[i];
-                        x += t;
-                        if (i >= nx) p += t;
+                        x += C[i + ns * j] * (double)sv[i];
+                        p += Cp[i + ns * j] * (double)sv[i];
                     }
                 }
                 xn[j] = x;
@@ -397,9 +659,8 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
 #pragma unroll
                 for (int i = 0; i < MAXS; ++i) {
                     if (i < ns) {
-                        const double t = C[i + ns * j] * (double)sv[i];
-                        hx += t;
-                        if (i >= nx) hp += t;
+                        hx += C[i + ns * j] * (double)sv[i];
+                        hp += Cp[i + ns * j] * (double)sv[i];
                     }
                 }
                 HS[(size_t)j * a.n2 + r] = (T)hx;
@@ -446,7 +707,7 @@ __global__ void k_eig_control(EigArgs a, const double* __restrict__ part, int nb
     if (bad) {
         ctrl->status = MOTO_NAN;
         ctrl->done = 1;
-    } else if (ctrl->rank < a.mb) {
+    } else if (ctrl->rank < a.k) {
         ctrl->status = MOTO_BREAKDOWN;
         ctrl->done = 1;
     } else if (conv) {
@@ -527,7 +788,6 @@ __global__ __launch_bounds__(NT) void k_eig_out1(EigArgs a, const T* __restrict_
     }
 }
 
-// Scale factor per column: sign(v[argmax]) / |v|; also evals and residuals.
 __global__ void k_eig_out2(EigArgs a, const double* __restrict__ part, int nblk, const double* __restrict__ V,
                            int N, double* __restrict__ scale, const EigCtrl* __restrict__ ctrl,
                            double* __restrict__ evals, double* __restrict__ resid) {
@@ -544,7 +804,7 @@ __global__ void k_eig_out2(EigArgs a, const double* __restrict__ part, int nblk,
     }
     const long long idx = (long long)mi;
     const double sgn = (idx >= 0 && idx < 3LL * N && V[(size_t)j * 3 * N + idx] < 0.0) ? -1.0 : 1.0;
-    scale[j] = sgn / sqrt(n);
+    scale[j] = n > 0.0 ? sgn / sqrt(n) : 0.0;
     if (evals) evals[j] = ctrl->lam[j];
     if (resid) resid[j] = ctrl->resid[j];
 }
@@ -559,12 +819,12 @@ __global__ void k_eig_out3(int k, int N, double* __restrict__ V, const double* _
 // Launchers
 // --------------------------------------------------------------------------
 int gram_blocks(int n2) {
-    int nch = (n2 + RCH - 1) / RCH;
-    return nch < 240 ? nch : 240;
+    const int nch = (n2 + RCH - 1) / RCH;
+    return nch < 128 ? nch : 128;
 }
 
 int update_blocks(int n2) {
-    int nb = (n2 + NT - 1) / NT;
+    const int nb = (n2 + NT - 1) / NT;
     return nb < 1024 ? nb : 1024;
 }
 
@@ -581,6 +841,25 @@ hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m,
     return hipGetLastError();
 }
 
+hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* part, int nblk, double* G,
+                       EigCtrl* ctrl, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_orth_gram<double>, dim3(nblk), dim3(NT), 0, st, a, target, (const double*)S, part,
+                           ctrl);
+    else
+        hipLaunchKernelGGL(k_orth_gram<float>, dim3(nblk), dim3(NT), 0, st, a, target, (const float*)S, part,
+                           ctrl);
+    const int E = OENT;
+    hipLaunchKernelGGL(k_reduce_rows, dim3((E + NT - 1) / NT), dim3(NT), 0, st, part, nblk, E, G, ctrl);
+    hipLaunchKernelGGL(k_orth_small, dim3(1), dim3(NT), 0, st, a, target, G, ctrl);
+    const int nb = update_blocks(a.n2);
+    if (f64)
+        hipLaunchKernelGGL(k_orth_apply<double>, dim3(nb), dim3(NT), 0, st, a, target, (double*)S, ctrl);
+    else
+        hipLaunchKernelGGL(k_orth_apply<float>, dim3(nb), dim3(NT), 0, st, a, target, (float*)S, ctrl);
+    return hipGetLastError();
+}
+
 hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const void* HS, double* part, int nblk,
                        double* G, const EigCtrl* ctrl, hipStream_t st) {
     if (f64)
@@ -589,7 +868,7 @@ hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const 
     else
         hipLaunchKernelGGL(k_gram<float>, dim3(nblk), dim3(NT), 0, st, a, ns, (const float*)S, (const float*)HS,
                            part, ctrl);
-    hipLaunchKernelGGL(k_gram_final, dim3(1), dim3(NT), 0, st, a, ns, part, nblk, G, ctrl);
+    hipLaunchKernelGGL(k_reduce_rows, dim3((GENT + NT - 1) / NT), dim3(NT), 0, st, part, nblk, GENT, G, ctrl);
     return hipGetLastError();
 }
 
@@ -598,8 +877,8 @@ hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, h
     return hipGetLastError();
 }
 
-hipError_t launch_update(bool f64, const EigArgs& a, int ns, int /*nx*/, void* S, void* HS, double* part,
-                         int nblk, EigCtrl* ctrl, hipStream_t st) {
+hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, double* part, int nblk,
+                         EigCtrl* ctrl, hipStream_t st) {
     if (f64)
         hipLaunchKernelGGL(k_update<double>, dim3(nblk), dim3(NT), 0, st, a, ns, (double*)S, (double*)HS, part,
                            ctrl);
@@ -609,16 +888,15 @@ hipError_t launch_update(bool f64, const EigArgs& a, int ns, int /*nx*/, void* S
     return hipGetLastError();
 }
 
-hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, int /*ns_w*/, EigCtrl* ctrl,
-                              int first, hipStream_t st) {
+hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, EigCtrl* ctrl, int first,
+                              hipStream_t st) {
     hipLaunchKernelGGL(k_eig_control, dim3(1), dim3(64), 0, st, a, part, nblk, ctrl, first);
     return hipGetLastError();
 }
 
 hipError_t launch_eig_output(bool f64, const EigArgs& a, const void* S, const double* m, int N, double* V,
-                             double* part, int nblk_unused, const EigCtrl* ctrl, double* evals, double* resid,
-                             void* Xsave, hipStream_t st) {
-    (void)nblk_unused;
+                             double* part, const EigCtrl* ctrl, double* evals, double* resid, void* Xsave,
+                             hipStream_t st) {
     const int nb = (N + NT - 1) / NT;
     if (f64)
         hipLaunchKernelGGL(k_eig_out1<double>, dim3(nb), dim3(NT), 0, st, a, (const double*)S, m, N, V, part,

@@ -140,18 +140,26 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
             for (int b = 0; b < P.nblk; ++b) s += P.pdot[(size_t)b * MAXR + threadIdx.x];
         fr[threadIdx.x] = s;
     }
-    // entry owned by this thread (upper triangle of the nv x nv Gram)
-    int ei = 0, ej = 0;
-    if ((int)threadIdx.x < ne) {
-        int p = threadIdx.x, i = 0;
-        while (p >= nv - i) {
-            p -= nv - i;
-            ++i;
+    // entries owned by this thread (upper triangle of the nv x nv Gram)
+    constexpr int EQ = (SNE + NT - 1) / NT;
+    int ei[EQ], ej[EQ];
+#pragma unroll
+    for (int q = 0; q < EQ; ++q) {
+        ei[q] = ej[q] = 0;
+        const int e = threadIdx.x + q * NT;
+        if (e < ne) {
+            int p = e, i = 0;
+            while (p >= nv - i) {
+                p -= nv - i;
+                ++i;
+            }
+            ei[q] = i;
+            ej[q] = i + p;
         }
-        ei = i;
-        ej = i + p;
     }
-    double acc = 0.0, fn2 = 0.0;
+    double acc[EQ], fn2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < EQ; ++q) acc[q] = 0.0;
     __syncthreads();
     const size_t n3 = 3 * (size_t)a.N;
     const int nchunks = (a.N + SCH - 1) / SCH;
@@ -221,11 +229,14 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
             }
         }
         __syncthreads();
-        if ((int)threadIdx.x < ne) {
-            double sacc = 0.0;
-            for (int cc = 0; cc < 3; ++cc)
-                for (int tt = 0; tt < SCH; ++tt) sacc += stage[ei][cc][tt] * stage[ej][cc][tt];
-            acc += sacc;
+#pragma unroll
+        for (int q = 0; q < EQ; ++q) {
+            if ((int)threadIdx.x + q * NT < ne) {
+                double sacc = 0.0;
+                for (int cc = 0; cc < 3; ++cc)
+                    for (int tt = 0; tt < SCH; ++tt) sacc += stage[ei[q]][cc][tt] * stage[ej[q]][cc][tt];
+                acc[q] += sacc;
+            }
         }
         __syncthreads();
     }
@@ -235,7 +246,9 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
     __syncthreads();
     double* pg = P.pgram + (size_t)blockIdx.x * SPART;
-    if ((int)threadIdx.x < ne) pg[threadIdx.x] = acc;
+#pragma unroll
+    for (int q = 0; q < EQ; ++q)
+        if ((int)threadIdx.x + q * NT < ne) pg[threadIdx.x + q * NT] = acc[q];
     if (threadIdx.x == 0) pg[SNE] = red[0] + red[1] + red[2] + red[3];
 }
 

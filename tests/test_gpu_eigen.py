@@ -144,3 +144,19 @@ def test_min_modes_warm_start_and_iteration_cap():
     assert np.allclose(_np(r2.evals), _np(r1.evals), atol=1e-9)
     r3 = M.moto_min_modes(plan, m, 2, M.MOTO_F64, opts=M.eig_opts(M.MOTO_F64, max_iter=1))
     assert r3.status == M.NOT_CONVERGED and r3.iters == 1
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_min_modes_fp32_random_start_at_index1_saddle(seed):
+    """FP32 blocks from a random start at a point with a negative eigenvalue
+    (the 16x16 collapse saddle of the oracle): the basis stays orthonormal
+    and the pair (lambda_1 < 0 < lambda_2) is recovered."""
+    M = _M()
+    p = S.ham_nn(16)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m0 = S.add_tilt_noise(S.skyrmion(16, 16, 1.0), 0.05, np.random.default_rng(0))
+    ro = O.saddle_search(h, m0, tau_F=1e-6)
+    r = M.moto_min_modes(plan, _dev(ro.m), 2, M.MOTO_F32, opts=M.eig_opts(M.MOTO_F32, tol=1e-6, seed=seed))
+    assert r.status == M.CONVERGED, (r.status, r.iters, _np(r.evals))
+    assert np.allclose(_np(r.evals), ro.evals, atol=1e-5 * h.h_est())
