@@ -147,6 +147,23 @@ moto_status moto_tangent_hvp(moto_plan p, moto_dtype dt, moto_layout layout, int
                              const void *m, const void *c, const uint8_t *mask, int32_t n_vec,
                              const void *V, void *W, moto_stream stream);
 
+/* Autotuner of the frame-layout HVP (tile shape / staging variant): times
+ * every variant `reps` times on the caller's buffers (W is overwritten),
+ * remembers the fastest in the plan for this (dt, batch, n_vec) -- later
+ * moto_tangent_hvp and moto_min_modes calls with that key use it -- and
+ * returns its index in *chosen.  times_ms (host, may be NULL) receives
+ * moto_tangent_hvp_variants() entries, -1 for variants not applicable to dt.
+ * Synchronises with the stream. */
+int32_t moto_tangent_hvp_variants(void);
+const char *moto_tangent_hvp_variant_name(int32_t variant);
+/* Pin a variant for (dt, batch, n_vec) without timing (MOTO_EINVAL if the
+ * variant does not exist for dt). */
+moto_status moto_plan_set_hvp_variant(moto_plan p, moto_dtype dt, int32_t batch, int32_t n_vec, int32_t variant);
+moto_status moto_tangent_hvp_autotune(moto_plan p, moto_dtype dt, int32_t batch, const void *m, const void *c,
+                                      const uint8_t *mask, int32_t n_vec, const void *V, void *W, int32_t reps,
+                                      int32_t *chosen /* host */, float *times_ms /* host */,
+                                      moto_stream stream);
+
 /* Euclidean Hessian (constant) applied to ambient vectors: W_j = A V_j,
  * [batch][n_vec][3][N] (the double-backward of the energy). */
 moto_status moto_hessian_apply(moto_plan p, moto_dtype dt, int32_t batch, int32_t n_vec,
@@ -158,6 +175,13 @@ moto_status moto_hessian_apply(moto_plan p, moto_dtype dt, int32_t batch, int32_
 moto_status moto_param_mixed(moto_plan p, moto_dtype dt, int32_t batch, const void *m,
                              const void *U, double *out, void *ws, size_t ws_bytes,
                              moto_stream stream);
+
+/* Adjoint of the parameter partials, for the double backward:
+ * out[b] = sum_q w[b][q] d g(m_b) / d theta_q  (g is linear in theta), i.e.
+ * J_s: -2 sum_{delta in s} m_{i+delta};  D_s: 2 sum_{delta in s} (z x dhat) x m_{i+delta};
+ * K: -2 m_iz z;  B: -1.  w FP64 [batch][n_params]; out [batch][3][N] dtype dt. */
+moto_status moto_param_grad_apply(moto_plan p, moto_dtype dt, int32_t batch, const void *m, const double *w,
+                                  void *out, moto_stream stream);
 
 /* ---------------------------------------------------------------------
  * Inner layer: k smallest eigenpairs of the masked tangent Hessian at m by
@@ -295,6 +319,25 @@ moto_status moto_saddle_search(moto_plan p, moto_dtype hvp, double *m, const uin
                                const moto_search_opts *opts /* host */,
                                moto_search_result *res /* host */, double *evals_out,
                                double *V_out, void *ws, size_t ws_bytes, moto_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Batching form: n independent saddle searches on periodic square lattices
+ * of uneven sides L[b] (5 <= L <= 4096) in ONE persistent launch, one
+ * workgroup per search (largest lattices first), FP32 HVP with FP64 state.
+ * Same method as moto_saddle_search (k <= 2 climb modes, k_reflect = 1,
+ * L-BFGS rule, certification with k = 2); every search runs to its own
+ * stopping rule, so uneven convergence costs no host round trips.
+ *   h      host: Hamiltonian (Lx, Ly ignored)
+ *   L      host [n] lattice sides
+ *   m_all  device FP64: the n starts back to back, [3][L_b^2] each; final points out
+ *   res    device [n] results (status, iterations, HVP columns, E, ||F_mmf||, lambda_1, lambda_2)
+ * The call uploads the small descriptor arrays (synchronising once before
+ * the launch) and returns after queueing the launch.
+ * Workspace: moto_saddle_search_batched_workspace(n, L, opts) bytes. */
+size_t moto_saddle_search_batched_workspace(int32_t n, const int32_t *L /* host */, const moto_search_opts *o);
+moto_status moto_saddle_search_batched(const moto_hamiltonian *h, int32_t n, const int32_t *L /* host */,
+                                       double *m_all, const moto_search_opts *opts /* host */,
+                                       moto_search_result *res, void *ws, size_t ws_bytes, moto_stream stream);
 
 /* Defaults for the option structs. */
 void moto_default_eig_opts(moto_dtype hvp, moto_eig_opts *o);

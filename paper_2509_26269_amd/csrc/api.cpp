@@ -8,6 +8,8 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <numeric>
+#include <vector>
 
 #include "kernels.hpp"
 #include "moto.h"
@@ -21,6 +23,11 @@ struct moto_plan_s {
     double hest;
     int ns;
     int64_t* pinned;  // host read-back buffer (hipHostMalloc)
+    // autotuned frame-layout HVP variants, keyed by (dtype, batch, n_vec)
+    struct Tune {
+        int dt, batch, nvec, variant;
+    } tune[32];
+    int n_tune;
 };
 
 namespace {
@@ -85,6 +92,12 @@ int resolve_guard(int k, int guard) {
 
 bool hvp_ok(moto_dtype d) { return d == MOTO_F32 || d == MOTO_F64; }
 
+int tuned_variant(const moto_plan p, moto_dtype dt, int batch, int nvec) {
+    for (int i = 0; i < p->n_tune; ++i)
+        if (p->tune[i].dt == (int)dt && p->tune[i].batch == batch && p->tune[i].nvec == nvec) return p->tune[i].variant;
+    return -1;
+}
+
 // Read back n bytes of device memory through the plan's pinned buffer.
 moto_status readback(moto_plan p, const void* dev, size_t n, void* host, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(p->pinned, dev, n, hipMemcpyDeviceToHost, st));
@@ -139,6 +152,7 @@ moto_status moto_plan_create(const moto_hamiltonian* h, moto_plan* out) {
     p->hest = 4.0 * (sj + sd) + 4.0 * std::fabs(h->K) +
               std::sqrt(h->B[0] * h->B[0] + h->B[1] * h->B[1] + h->B[2] * h->B[2]);
     p->pinned = nullptr;
+    p->n_tune = 0;
     if (hipHostMalloc((void**)&p->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
         delete p;
         return MOTO_EHIP;
@@ -183,7 +197,64 @@ moto_status moto_tangent_hvp(moto_plan p, moto_dtype dt, moto_layout layout, int
     if (V == W) return MOTO_EINVAL;
     if (n_vec == 0) return MOTO_OK;
     HIP_TRY(launch_tangent_hvp(p->g, p->k, dt == MOTO_F64, layout == MOTO_FRAME, batch, m, c, mask, n_vec, V, W,
-                               nullptr, (hipStream_t)stream));
+                               nullptr, (hipStream_t)stream, tuned_variant(p, dt, batch, n_vec)));
+    return MOTO_OK;
+}
+
+int32_t moto_tangent_hvp_variants(void) { return HVP_NVARIANTS; }
+
+moto_status moto_plan_set_hvp_variant(moto_plan p, moto_dtype dt, int32_t batch, int32_t n_vec, int32_t variant) {
+    if (!p || !hvp_ok(dt) || batch < 1 || n_vec < 1 || !hvp_variant_ok(variant, dt == MOTO_F64)) return MOTO_EINVAL;
+    int slot = -1;
+    for (int i = 0; i < p->n_tune; ++i)
+        if (p->tune[i].dt == (int)dt && p->tune[i].batch == batch && p->tune[i].nvec == n_vec) slot = i;
+    if (slot < 0) slot = p->n_tune < 32 ? p->n_tune++ : 31;
+    p->tune[slot] = {(int)dt, batch, n_vec, variant};
+    return MOTO_OK;
+}
+
+const char* moto_tangent_hvp_variant_name(int32_t v) { return hvp_variant_name(v); }
+
+moto_status moto_tangent_hvp_autotune(moto_plan p, moto_dtype dt, int32_t batch, const void* m, const void* c,
+                                      const uint8_t* mask, int32_t n_vec, const void* V, void* W, int32_t reps,
+                                      int32_t* chosen, float* times_ms, moto_stream stream) {
+    if (!p || !m || !c || !V || !W || batch < 1 || n_vec < 1 || !hvp_ok(dt) || V == W) return MOTO_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = dt == MOTO_F64;
+    if (reps < 1) reps = 3;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int best = -1;
+    float best_t = 0.0f;
+    for (int v = 0; v < HVP_NVARIANTS; ++v) {
+        if (times_ms) times_ms[v] = -1.0f;
+        if (!hvp_variant_ok(v, f64)) continue;
+        HIP_TRY(launch_hvp_frame(v, p->g, p->k, f64, batch, m, c, mask, n_vec, V, W, nullptr, st));  // warm-up
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r)
+            HIP_TRY(launch_hvp_frame(v, p->g, p->k, f64, batch, m, c, mask, n_vec, V, W, nullptr, st));
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms /= reps;
+        if (times_ms) times_ms[v] = ms;
+        if (best < 0 || ms < best_t) {
+            best = v;
+            best_t = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int slot = -1;
+    for (int i = 0; i < p->n_tune; ++i)
+        if (p->tune[i].dt == (int)dt && p->tune[i].batch == batch && p->tune[i].nvec == n_vec) slot = i;
+    if (slot < 0) {
+        slot = p->n_tune < 32 ? p->n_tune++ : 31;
+    }
+    p->tune[slot] = {(int)dt, batch, n_vec, best};
+    if (chosen) *chosen = best;
     return MOTO_OK;
 }
 
@@ -202,6 +273,13 @@ moto_status moto_param_mixed(moto_plan p, moto_dtype dt, int32_t batch, const vo
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(launch_param_mixed(p->g, dt == MOTO_F64, batch, m, U, (double*)ws, st));
     HIP_TRY(launch_reduce_partials((double*)ws, batch, p->g.tiles, p->ns, nullptr, out, st));
+    return MOTO_OK;
+}
+
+moto_status moto_param_grad_apply(moto_plan p, moto_dtype dt, int32_t batch, const void* m, const double* w,
+                                  void* out, moto_stream stream) {
+    if (!p || !m || !w || !out || batch < 1 || !hvp_ok(dt)) return MOTO_EINVAL;
+    HIP_TRY(launch_param_grad_apply(p->g, p->ns, dt == MOTO_F64, batch, m, w, out, (hipStream_t)stream));
     return MOTO_OK;
 }
 
@@ -270,12 +348,13 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
     void* Wslot = (char*)S + es * (size_t)L.mb * L.n2;
     void* HWslot = (char*)HS + es * (size_t)L.mb * L.n2;
     const int warm = o->warm;
+    const int hv_var = tuned_variant(p, hvp, 1, L.mb);
     double* G = (double*)(ws + L.G);
     HIP_TRY(launch_eig_init(f64, a, S, m, warm == 1 ? V : nullptr, warm == 1 ? k : 0, ws + L.Xsave, warm == 2,
                             mask, N, o->seed, ctrl, st));
     // start: orthonormal X; HX = H X; Rayleigh-Ritz on span(X); W = HX - X Lam
     for (int pass = 0; pass < 2; ++pass) HIP_TRY(launch_orth(f64, a, 0, S, part, L.nblk_g, G, ctrl, st));
-    HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, S, HS, &ctrl->done, st));
+    HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, S, HS, &ctrl->done, st, hv_var));
     HIP_TRY(launch_gram(f64, a, L.mb, S, HS, part, L.nblk_g, G, ctrl, st));
     HIP_TRY(launch_rr(a, L.mb, G, ctrl, st));
     HIP_TRY(launch_update(f64, a, L.mb, S, HS, part, L.nblk_u, ctrl, st));
@@ -290,7 +369,7 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
         for (int it = 0; it < every; ++it) {
             for (int pass = 0; pass < 2; ++pass) HIP_TRY(launch_orth(f64, a, 1, S, part, L.nblk_g, G, ctrl, st));
             HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, Wslot, HWslot, &ctrl->done,
-                                       st));
+                                       st, hv_var));
             HIP_TRY(launch_gram(f64, a, -1, S, HS, part, L.nblk_g, G, ctrl, st));
             HIP_TRY(launch_rr(a, -1, G, ctrl, st));
             HIP_TRY(launch_update(f64, a, -1, S, HS, part, L.nblk_u, ctrl, st));
@@ -625,4 +704,125 @@ moto_status moto_saddle_search(moto_plan p, moto_dtype hvp, double* m, const uin
     return MOTO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched searches (one persistent launch)
+// ---------------------------------------------------------------------------
+static moto_status check_ham(const moto_hamiltonian* h, bool need_size) {
+    if (!h) return MOTO_EINVAL;
+    if (need_size && (h->Lx < 1 || h->Ly < 1)) return MOTO_EINVAL;
+    if (h->n_shells < 1 || h->n_shells > MOTO_MAX_SHELLS || h->reserved != 0) return MOTO_EINVAL;
+    for (int s = 0; s < MOTO_MAX_SHELLS; ++s) {
+        if (!std::isfinite(h->J[s]) || !std::isfinite(h->D[s])) return MOTO_EINVAL;
+        if (s >= 3 && s < h->n_shells && h->J[s] != 0.0) return MOTO_EUNSUPPORTED;
+        if (s >= 1 && h->D[s] != 0.0) return MOTO_EUNSUPPORTED;
+    }
+    if (h->n_shells > 3) return MOTO_EUNSUPPORTED;
+    return MOTO_OK;
+}
+
+struct BatchHostLayout {
+    size_t Ls, order, moff, woff, res0, total;
+    std::vector<long long> m_off, ws_off;
+};
+
+static bool batch_layout_host(int32_t n, const int32_t* L, int mem, BatchHostLayout* o) {
+    size_t p = 0;
+    o->Ls = p;
+    p += al(sizeof(int) * (size_t)n);
+    o->order = p;
+    p += al(sizeof(int) * (size_t)n);
+    o->moff = p;
+    p += al(sizeof(long long) * (size_t)n);
+    o->woff = p;
+    p += al(sizeof(long long) * (size_t)n);
+    o->res0 = p;
+    o->m_off.resize(n);
+    o->ws_off.resize(n);
+    long long mo = 0;
+    for (int i = 0; i < n; ++i) {
+        if (L[i] < 5 || L[i] > 4096) return false;
+        o->m_off[i] = mo;
+        mo += 3LL * L[i] * L[i];
+        o->ws_off[i] = (long long)(p - o->res0);
+        p += al(batch_search_bytes(L[i] * L[i], mem));
+    }
+    o->total = p;
+    return true;
+}
+
+size_t moto_saddle_search_batched_workspace(int32_t n, const int32_t* L, const moto_search_opts* o) {
+    if (n < 1 || !L) return 0;
+    moto_search_opts d;
+    if (o)
+        d = *o;
+    else
+        moto_default_search_opts(MOTO_F32, &d);
+    if (d.step.mem < 1 || d.step.mem > 16) return 0;
+    BatchHostLayout bl;
+    if (!batch_layout_host(n, L, d.step.mem, &bl)) return 0;
+    return bl.total;
+}
+
+moto_status moto_saddle_search_batched(const moto_hamiltonian* h, int32_t n, const int32_t* L, double* m_all,
+                                       const moto_search_opts* opts, moto_search_result* res, void* ws,
+                                       size_t ws_bytes, moto_stream stream) {
+    moto_status cs = check_ham(h, false);
+    if (cs != MOTO_OK) return cs;
+    if (n < 1 || !L || !m_all || !res) return MOTO_EINVAL;
+    moto_search_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_search_opts(MOTO_F32, &o);
+    if (o.k < 1 || o.k > 2 || o.k_cert > 2 || o.k_reflect != 1 || o.max_outer < 0 || o.step.rule != 0 ||
+        o.step.mem < 1 || o.step.mem > 16 || !(o.step.theta_max > 0.0) || o.eig.max_iter < 0)
+        return MOTO_EINVAL;
+    BatchHostLayout bl;
+    if (!batch_layout_host(n, L, o.step.mem, &bl)) return MOTO_EINVAL;
+    if (!ws || ws_bytes < bl.total) return MOTO_EWORKSPACE;
+    // largest lattices first
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return L[a] > L[b]; });
+    char* w = (char*)ws;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(w + bl.Ls, L, sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + bl.order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + bl.moff, bl.m_off.data(), sizeof(long long) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + bl.woff, bl.ws_off.data(), sizeof(long long) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));  // the host descriptor arrays are local
+    double sj = 0.0, sd = 0.0;
+    for (int s = 0; s < h->n_shells; ++s) {
+        sj += 6.0 * std::fabs(h->J[s]);
+        sd += 6.0 * std::fabs(h->D[s]);
+    }
+    const double hest = 4.0 * (sj + sd) + 4.0 * std::fabs(h->K) +
+                        std::sqrt(h->B[0] * h->B[0] + h->B[1] * h->B[1] + h->B[2] * h->B[2]);
+    BatchArgs a;
+    for (int s = 0; s < 3; ++s) a.k.cJ[s] = s < h->n_shells ? -2.0 * h->J[s] : 0.0;
+    a.k.cD = 2.0 * h->D[0];
+    a.k.cK = -2.0 * h->K;
+    for (int c = 0; c < 3; ++c) a.k.B[c] = h->B[c];
+    a.hest = hest;
+    a.tau_F = o.tau_F;
+    a.tau_lam = o.tau_lam > 0.0 ? o.tau_lam : 1e-4 * hest;
+    a.theta_max = o.step.theta_max;
+    a.alpha0 = o.step.alpha0 > 0.0 ? o.step.alpha0 : 1.0 / hest;
+    a.sy_min = o.step.sy_min;
+    a.eig_tol_abs = o.eig.tol * hest;
+    a.drop = 1e-9;
+    a.kk = o.k;
+    a.k_cert = 2;
+    a.mem = o.step.mem;
+    a.max_outer = o.max_outer;
+    a.eig_max_iter = o.eig.max_iter;
+    a.n = n;
+    a.seed = o.eig.seed;
+    HIP_TRY(launch_batched_search(a, m_all, (const int*)(w + bl.Ls), (const int*)(w + bl.order),
+                                  (const long long*)(w + bl.moff), (const long long*)(w + bl.woff), w + bl.res0, res, n,
+                                  st));
+    return MOTO_OK;
+}
+
 }  // extern "C"
+

@@ -29,7 +29,7 @@ struct Geo {
     int tiles_x, tiles_y, tiles;  // tiles per lattice
 };
 
-inline Geo make_geo(int Lx, int Ly) {
+__host__ __device__ inline Geo make_geo(int Lx, int Ly) {
     Geo g;
     g.Lx = Lx;
     g.Ly = Ly;

@@ -1,0 +1,333 @@
+// hvp.hip -- frame-layout tangent Hessian-vector product (Methods, HVP
+// operator mode): W_j = M H(m) M V_j with (H v)_i = P_i (A v)_i - c_i v_i and
+// tangent vectors stored as two coordinates in the per-site frame (e1, e2).
+// This is the memory-bound kernel of the inner layer: 12 bytes of spins plus
+// 16 bytes per vector and site (FP32).
+//
+// Several variants compute the same values and differ only in tiling:
+//   tiled<TX,TY>:  one output site per thread on a TX x TY tile; the
+//                  (TX+4) x (TY+4) neighbourhood of every vector is staged in
+//                  LDS one vector at a time (frames staged once per tile);
+//   band<NVP>:     tiles up to 128 sites wide (a full row band for lattices up
+//                  to 128 wide, so the periodic x-halo stays in the same cache
+//                  lines); NVP vectors staged per pass with one frame build per
+//                  site; each thread owns one column and 4 rows and sweeps the
+//                  input rows once (register sliding window).
+// All but the first order the blocks so that consecutive tiles of a lattice
+// run on the same XCD: workgroups are dealt round-robin to the 8 XCDs, each
+// with its own L2, and halo rows re-read by the next tile then hit that L2
+// instead of HBM.  The autotuner in the host API times the variants on the
+// caller's shape and keeps the fastest.
+#include "kernels.hpp"
+
+namespace moto {
+
+__device__ __forceinline__ int xcd_order(bool remap) {
+    const int G = gridDim.x;
+    return (remap && G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+}
+
+// (A u) at flat LDS index ci of three planes with row stride SX; offsets of
+// the first three shells and the NN interfacial DMI as in apply_A_tile.
+template <class T, int SX>
+__device__ __forceinline__ void apply_A_flat(const T* __restrict__ p0, const T* __restrict__ p1,
+                                             const T* __restrict__ p2, int ci, const Coef<T>& k, T out[3]) {
+    const T h = T(0.5);
+    const T r3 = T(0.86602540378443864676);
+    const T* pc[3] = {p0, p1, p2};
+#define U(c, dx, dy) pc[c][ci + (dy) * SX + (dx)]
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T s1 = U(c, 1, 0) + U(c, 0, 1) + U(c, -1, 1) + U(c, -1, 0) + U(c, 0, -1) + U(c, 1, -1);
+        const T s2 = U(c, 1, 1) + U(c, -1, 2) + U(c, -2, 1) + U(c, -1, -1) + U(c, 1, -2) + U(c, 2, -1);
+        const T s3 = U(c, 2, 0) + U(c, 0, 2) + U(c, -2, 2) + U(c, -2, 0) + U(c, 0, -2) + U(c, 2, -2);
+        out[c] = k.cJ[0] * s1 + k.cJ[1] * s2 + k.cJ[2] * s3;
+    }
+    const T d1x = U(0, 1, 0) - U(0, -1, 0), d1z = U(2, 1, 0) - U(2, -1, 0);
+    const T d2x = U(0, 0, 1) - U(0, 0, -1), d2y = U(1, 0, 1) - U(1, 0, -1), d2z = U(2, 0, 1) - U(2, 0, -1);
+    const T d3x = U(0, -1, 1) - U(0, 1, -1), d3y = U(1, -1, 1) - U(1, 1, -1), d3z = U(2, -1, 1) - U(2, 1, -1);
+    out[0] += k.cD * (d1z + h * d2z - h * d3z);
+    out[1] += k.cD * (r3 * (d2z + d3z));
+    out[2] -= k.cD * (d1x + h * d2x + r3 * d2y - h * d3x + r3 * d3y);
+    out[2] += k.cK * U(2, 0, 0);
+#undef U
+}
+
+// --------------------------------------------------------------------------
+// tiled<TX, TY>
+// --------------------------------------------------------------------------
+template <class T, int TXT, int TYT, bool REMAP>
+__global__ __launch_bounds__(NT) void k_hvp_tiled(Geo g, Coef<T> k, const T* __restrict__ m,
+                                                  const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec,
+                                                  const T* __restrict__ V, T* __restrict__ W,
+                                                  const int* __restrict__ done, int tiles_x, int tiles_y) {
+    static_assert(TXT * TYT == NT, "one site per thread");
+    if (done != nullptr && *done) return;
+    constexpr int SX = TXT + 2 * HALO, SY = TYT + 2 * HALO, SS = SX * SY;
+    __shared__ T u[3][SS];
+    __shared__ T fr[6][SS];
+    __shared__ uint8_t act[SS];
+    const int bid = xcd_order(REMAP);
+    const int tiles = tiles_x * tiles_y;
+    const int b = bid / tiles, t = bid - b * tiles;
+    const int tx0 = (t % tiles_x) * TXT, ty0 = (t / tiles_x) * TYT;
+    const size_t off1 = (size_t)b * g.N;
+    const T* mb = m + 3 * off1;
+    const uint8_t* mk = mask ? mask + off1 : nullptr;
+    const size_t vstride = (size_t)2 * g.N;
+    const T* Vb = V + (size_t)b * nvec * vstride;
+    T* Wb = W + (size_t)b * nvec * vstride;
+    int sidx[(SS + NT - 1) / NT];
+#pragma unroll
+    for (int q = 0; q < (SS + NT - 1) / NT; ++q) {
+        const int i = threadIdx.x + q * NT;
+        sidx[q] = 0;
+        if (i < SS) {
+            const int ly = i / SX, lx = i - ly * SX;
+            const int xs = wrapi(tx0 + lx - HALO, g.Lx), ys = wrapi(ty0 + ly - HALO, g.Ly);
+            const int s = xs + g.Lx * ys;
+            sidx[q] = s;
+            T e1[3], e2[3];
+            onb(mb[s], mb[g.N + s], mb[2 * g.N + s], e1, e2);
+            fr[0][i] = e1[0];
+            fr[1][i] = e1[1];
+            fr[2][i] = e1[2];
+            fr[3][i] = e2[0];
+            fr[4][i] = e2[1];
+            fr[5][i] = e2[2];
+            act[i] = mk ? (mk[s] != 0) : 1;
+        }
+    }
+    const int lx = threadIdx.x % TXT, ly = threadIdx.x / TXT;
+    const int x = tx0 + lx, y = ty0 + ly;
+    const bool valid = x < g.Lx && y < g.Ly;
+    const int ci = (ly + HALO) * SX + lx + HALO;
+    const int sc = valid ? x + g.Lx * y : 0;
+    const T cc = c[off1 + sc];
+    for (int j = 0; j < nvec; ++j) {
+        const T* vj = Vb + j * vstride;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < (SS + NT - 1) / NT; ++q) {
+            const int i = threadIdx.x + q * NT;
+            if (i < SS) {
+                const int s = sidx[q];
+                const bool on = act[i];
+                const T a = on ? vj[s] : T(0);
+                const T bb = on ? vj[g.N + s] : T(0);
+                u[0][i] = a * fr[0][i] + bb * fr[3][i];
+                u[1][i] = a * fr[1][i] + bb * fr[4][i];
+                u[2][i] = a * fr[2][i] + bb * fr[5][i];
+            }
+        }
+        __syncthreads();
+        if (valid) {
+            T Au[3];
+            apply_A_flat<T, SX>(u[0], u[1], u[2], ci, k, Au);
+            const T e10 = fr[0][ci], e11 = fr[1][ci], e12 = fr[2][ci];
+            const T e20 = fr[3][ci], e21 = fr[4][ci], e22 = fr[5][ci];
+            const T u0 = u[0][ci], u1 = u[1][ci], u2 = u[2][ci];
+            const T av = e10 * u0 + e11 * u1 + e12 * u2;
+            const T bv = e20 * u0 + e21 * u1 + e22 * u2;
+            const T wa = e10 * Au[0] + e11 * Au[1] + e12 * Au[2] - cc * av;
+            const T wb = e20 * Au[0] + e21 * Au[1] + e22 * Au[2] - cc * bv;
+            const bool on = act[ci];
+            T* wj = Wb + j * vstride;
+            wj[sc] = on ? wa : T(0);
+            wj[g.N + sc] = on ? wb : T(0);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// band<NVP>
+// --------------------------------------------------------------------------
+constexpr int BD_TX = 128;                // max tile width
+constexpr int BD_TY = 8;                  // tile height
+constexpr int BD_NG = NT / BD_TX;         // row groups per tile (2)
+constexpr int BD_R = BD_TY / BD_NG;       // rows per thread (4)
+constexpr int BD_SX = BD_TX + 2 * HALO;   // staged width (132)
+constexpr int BD_SY = BD_TY + 2 * HALO;   // staged height (12)
+
+// shell of a lattice offset (dx, dy) of the three-shell stencil, -1 if none
+__device__ constexpr int bd_shell(int dx, int dy) {
+    return (dx * dx + dx * dy + dy * dy) == 1 ? 0
+           : (dx * dx + dx * dy + dy * dy) == 3 ? 1
+           : (dx * dx + dx * dy + dy * dy) == 4 ? 2
+                                                 : -1;
+}
+
+template <class T, int NVP>
+__global__ __launch_bounds__(NT) void k_hvp_band(Geo g, Coef<T> k, const T* __restrict__ m,
+                                                 const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec,
+                                                 const T* __restrict__ V, T* __restrict__ W,
+                                                 const int* __restrict__ done, int tiles_x, int tiles_y) {
+    if (done != nullptr && *done) return;
+    __shared__ T su[NVP][3][BD_SY][BD_SX];
+    const int bid = xcd_order(true);
+    const int tiles = tiles_x * tiles_y;
+    const int b = bid / tiles;
+    const int t = bid - b * tiles;
+    const int tx0 = (t % tiles_x) * BD_TX, ty0 = (t / tiles_x) * BD_TY;
+    const int txw = min(BD_TX, g.Lx - tx0);
+    const int sxw = txw + 2 * HALO;
+    const size_t off3 = (size_t)b * 3 * g.N, off1 = (size_t)b * g.N;
+    const T* mb = m + off3;
+    const uint8_t* mk = mask ? mask + off1 : nullptr;
+    const size_t vstride = (size_t)2 * g.N;
+    const T* Vb = V + (size_t)b * nvec * vstride;
+    T* Wb = W + (size_t)b * nvec * vstride;
+    const int lx = threadIdx.x % BD_TX, rg = threadIdx.x / BD_TX;
+    const int x = tx0 + lx;
+    const bool colok = lx < txw;
+    T e1[BD_R][3], e2[BD_R][3], cc[BD_R];
+    bool act[BD_R], rok[BD_R];
+    int sc[BD_R];
+#pragma unroll
+    for (int o = 0; o < BD_R; ++o) {
+        const int y = ty0 + rg * BD_R + o;
+        rok[o] = colok && y < g.Ly;
+        sc[o] = rok[o] ? x + g.Lx * y : 0;
+        onb(mb[sc[o]], mb[g.N + sc[o]], mb[2 * g.N + sc[o]], e1[o], e2[o]);
+        cc[o] = c[off1 + sc[o]];
+        act[o] = mk == nullptr || mk[sc[o]] != 0;
+    }
+    const T h = T(0.5), r3 = T(0.86602540378443864676);
+    for (int j0 = 0; j0 < nvec; j0 += NVP) {
+        const int nv = min(NVP, nvec - j0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < BD_SY * sxw; i += NT) {
+            const int ly = i / sxw, lxs = i - ly * sxw;
+            const int xs = wrapi(tx0 + lxs - HALO, g.Lx), ys = wrapi(ty0 + ly - HALO, g.Ly);
+            const int s = xs + g.Lx * ys;
+            T f1[3], f2[3];
+            onb(mb[s], mb[g.N + s], mb[2 * g.N + s], f1, f2);
+            const bool on = mk == nullptr || mk[s] != 0;
+#pragma unroll
+            for (int j = 0; j < NVP; ++j) {
+                if (j < nv) {
+                    const T a = on ? Vb[(j0 + j) * vstride + s] : T(0);
+                    const T bb = on ? Vb[(j0 + j) * vstride + g.N + s] : T(0);
+                    su[j][0][ly][lxs] = a * f1[0] + bb * f2[0];
+                    su[j][1][ly][lxs] = a * f1[1] + bb * f2[1];
+                    su[j][2][ly][lxs] = a * f1[2] + bb * f2[2];
+                }
+            }
+        }
+        __syncthreads();
+        if (!colok) continue;
+        for (int j = 0; j < nv; ++j) {
+            T acc[BD_R][3];
+#pragma unroll
+            for (int o = 0; o < BD_R; ++o) acc[o][0] = acc[o][1] = acc[o][2] = T(0);
+            T uc[BD_R][3];
+#pragma unroll
+            for (int q = 0; q < BD_R + 2 * HALO; ++q) {
+                const int ly = rg * BD_R + q;
+                T uu[5][3];
+#pragma unroll
+                for (int dx = -2; dx <= 2; ++dx)
+#pragma unroll
+                    for (int cpt = 0; cpt < 3; ++cpt) uu[dx + 2][cpt] = su[j][cpt][ly][lx + HALO + dx];
+#pragma unroll
+                for (int o = 0; o < BD_R; ++o) {
+                    const int dy = q - (o + HALO);
+                    if (dy < -2 || dy > 2) continue;
+                    if (dy == 0) {
+                        uc[o][0] = uu[2][0];
+                        uc[o][1] = uu[2][1];
+                        uc[o][2] = uu[2][2];
+                        acc[o][2] += k.cK * uu[2][2];
+                    }
+#pragma unroll
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        const int sh = bd_shell(dx, dy);
+                        if (sh < 0) continue;
+                        const T cj = k.cJ[sh];
+                        acc[o][0] += cj * uu[dx + 2][0];
+                        acc[o][1] += cj * uu[dx + 2][1];
+                        acc[o][2] += cj * uu[dx + 2][2];
+                        if (sh == 0) {  // interfacial DMI: cD [dhat u_z - z (dhat . u)]
+                            const T dhx = T(dx) + h * T(dy), dhy = r3 * T(dy);
+                            acc[o][0] += k.cD * dhx * uu[dx + 2][2];
+                            acc[o][1] += k.cD * dhy * uu[dx + 2][2];
+                            acc[o][2] -= k.cD * (dhx * uu[dx + 2][0] + dhy * uu[dx + 2][1]);
+                        }
+                    }
+                }
+            }
+            T* wj = Wb + (j0 + j) * vstride;
+#pragma unroll
+            for (int o = 0; o < BD_R; ++o) {
+                if (!rok[o]) continue;
+                const T av = e1[o][0] * uc[o][0] + e1[o][1] * uc[o][1] + e1[o][2] * uc[o][2];
+                const T bv = e2[o][0] * uc[o][0] + e2[o][1] * uc[o][1] + e2[o][2] * uc[o][2];
+                const T wa = e1[o][0] * acc[o][0] + e1[o][1] * acc[o][1] + e1[o][2] * acc[o][2] - cc[o] * av;
+                const T wb = e2[o][0] * acc[o][0] + e2[o][1] * acc[o][1] + e2[o][2] * acc[o][2] - cc[o] * bv;
+                wj[sc[o]] = act[o] ? wa : T(0);
+                wj[g.N + sc[o]] = act[o] ? wb : T(0);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// variant table
+// --------------------------------------------------------------------------
+static const char* kNames[HVP_NVARIANTS] = {"tiled32x8", "tiled32x8+xcd", "tiled64x4+xcd", "tiled128x2+xcd",
+                                            "band128x8/4vec+xcd", "band128x8/2vec+xcd", "band128x8/1vec+xcd"};
+
+const char* hvp_variant_name(int v) { return (v >= 0 && v < HVP_NVARIANTS) ? kNames[v] : "?"; }
+
+bool hvp_variant_ok(int v, bool f64) { return v >= 0 && v < HVP_NVARIANTS && !(f64 && v == 4); }
+
+int hvp_default_variant(const Geo& g, bool f64) {
+    (void)g;
+    (void)f64;
+    return 2;
+}
+
+template <class T, int TXT, int TYT, bool REMAP>
+static void go_tiled(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
+                     int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+    const int tx = (g.Lx + TXT - 1) / TXT, ty = (g.Ly + TYT - 1) / TYT;
+    hipLaunchKernelGGL((k_hvp_tiled<T, TXT, TYT, REMAP>), dim3(batch * tx * ty), dim3(NT), 0, st, g, coef_cast<T>(kd),
+                       (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, tx, ty);
+}
+
+template <class T, int NVP>
+static void go_band(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
+                    int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+    const int tx = (g.Lx + BD_TX - 1) / BD_TX, ty = (g.Ly + BD_TY - 1) / BD_TY;
+    hipLaunchKernelGGL((k_hvp_band<T, NVP>), dim3(batch * tx * ty), dim3(NT), 0, st, g, coef_cast<T>(kd),
+                       (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, tx, ty);
+}
+
+template <class T>
+static void go(int v, const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
+               int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+    switch (v) {
+        case 0: go_tiled<T, 32, 8, false>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 1: go_tiled<T, 32, 8, true>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 3: go_tiled<T, 128, 2, true>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 4:
+            if constexpr (sizeof(T) == 4) go_band<T, 4>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+            break;
+        case 5: go_band<T, 2>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 6: go_band<T, 1>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        default: go_tiled<T, 64, 4, true>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+    }
+}
+
+hipError_t launch_hvp_frame(int variant, const Geo& g, const CoefD& kd, bool f64, int batch, const void* m,
+                            const void* c, const uint8_t* mask, int nvec, const void* V, void* W, const int* done,
+                            hipStream_t st) {
+    const int v = hvp_variant_ok(variant, f64) ? variant : hvp_default_variant(g, f64);
+    if (f64)
+        go<double>(v, g, kd, batch, m, c, mask, nvec, V, W, done, st);
+    else
+        go<float>(v, g, kd, batch, m, c, mask, nvec, V, W, done, st);
+    return hipGetLastError();
+}
+
+}  // namespace moto

@@ -20,17 +20,39 @@ struct CoefD {
     double B[3];
 };
 
+template <class T>
+inline Coef<T> coef_cast(const CoefD& d) {
+    Coef<T> k;
+    for (int s = 0; s < 3; ++s) k.cJ[s] = (T)d.cJ[s];
+    k.cD = (T)d.cD;
+    k.cK = (T)d.cK;
+    for (int a = 0; a < 3; ++a) k.B[a] = (T)d.B[a];
+    return k;
+}
+
 // ---- stencil.hip ----
 hipError_t launch_energy_grad(const Geo& g, const CoefD& k, bool f64, int batch, const void* m,
                               const uint8_t* mask, void* grad, void* c, void* F, double* part,
                               hipStream_t st);
 hipError_t launch_param_mixed(const Geo& g, bool f64, int batch, const void* m, const void* U, double* part,
                               hipStream_t st);
+hipError_t launch_param_grad_apply(const Geo& g, int ns, bool f64, int batch, const void* m, const double* w,
+                                  void* out, hipStream_t st);
 hipError_t launch_reduce_partials(const double* part, int batch, int tiles, int ns, double* E, double* dth,
                                   hipStream_t st);
+// variant: frame-layout kernel variant (-1 = default choice), see hvp.hip
 hipError_t launch_tangent_hvp(const Geo& g, const CoefD& k, bool f64, bool frame, int batch, const void* m,
                               const void* c, const uint8_t* mask, int nvec, const void* V, void* W,
-                              const int* done, hipStream_t st);
+                              const int* done, hipStream_t st, int variant = -1);
+
+// ---- hvp.hip: frame-layout tangent HVP variants (tile shapes / staging) ----
+constexpr int HVP_NVARIANTS = 7;
+bool hvp_variant_ok(int variant, bool f64);
+int hvp_default_variant(const Geo& g, bool f64);
+const char* hvp_variant_name(int variant);
+hipError_t launch_hvp_frame(int variant, const Geo& g, const CoefD& k, bool f64, int batch, const void* m,
+                            const void* c, const uint8_t* mask, int nvec, const void* V, void* W, const int* done,
+                            hipStream_t st);
 hipError_t launch_hessian_apply(const Geo& g, const CoefD& k, bool f64, int batch, int nvec, const void* V,
                                 void* W, hipStream_t st);
 hipError_t launch_topo_charge(const Geo& g, int batch, const double* m, double* part, hipStream_t st);
@@ -102,5 +124,17 @@ hipError_t launch_seed_rotate(int N, double* m, const double* v1, double scale_s
                               hipStream_t st);
 hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t st);
 hipError_t launch_mask_zero(double* v, const uint8_t* mask, int N, int ncomp, hipStream_t st);
+
+// ---- batched.hip ----
+struct BatchArgs {
+    CoefD k;
+    double hest, tau_F, tau_lam, theta_max, alpha0, sy_min, eig_tol_abs, drop;
+    int kk, k_cert, mem, max_outer, eig_max_iter, n;
+    unsigned long long seed;
+};
+size_t batch_search_bytes(int N, int mem);
+hipError_t launch_batched_search(const BatchArgs& a, double* m_all, const int* Ls, const int* order,
+                                 const long long* m_off, const long long* ws_off, char* ws, moto_search_result* res,
+                                 int grid, hipStream_t st);
 
 }  // namespace moto

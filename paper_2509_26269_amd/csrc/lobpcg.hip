@@ -19,6 +19,7 @@
 // X, P, HX, HP, W = HX - X Lam -> convergence control.  Every kernel returns
 // at once when the control block says the solve is done, so chunks of
 // iterations can be queued without host round trips.
+#include "dense_wg.hpp"
 #include "kernels.hpp"
 
 namespace moto {
@@ -154,65 +155,11 @@ __global__ __launch_bounds__(NT) void k_reduce_rows(const double* __restrict__ p
     G[e] = s;
 }
 
-__device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweeps, double* red, double* cs,
-                          double* sn, int* pp, int* qq);
-
 __global__ __launch_bounds__(NT) void k_orth_small(EigArgs a, int target, const double* __restrict__ G,
                                                    EigCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
-    __shared__ OrthCols oc;
-    __shared__ double A[MAXS * MAXS];
-    __shared__ double Z[MAXS * MAXS];
-    __shared__ double dsc[MAXB], th[MAXB], red[8], cs[MAXS / 2 + 1], sn[MAXS / 2 + 1];
-    __shared__ int pp[MAXS / 2 + 1], qq[MAXS / 2 + 1], keep[MAXB];
-    __shared__ int nkeep;
-    const int tid = threadIdx.x;
-    if (tid == 0) orth_cols(a, target, ctrl, oc);
-    __syncthreads();
-    const int mb = a.mb, nq = oc.nq, nrow = nq + mb;
-    // B = Q^T Y -> ctrl->Bw ([2mb][mb], rows in projection order)
-    for (int i = tid; i < nq * mb; i += NT) {
-        const int r = i % nq, j = i / nq;
-        ctrl->Bw[r + 2 * MAXB * j] = G[j * nrow + r];
-    }
-    // M = Y^T Y - B^T B
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int r = i % mb, c = i / mb;
-        double v = G[c * nrow + nq + r];
-        for (int l = 0; l < nq; ++l) v -= G[r * nrow + l] * G[c * nrow + l];
-        A[r * MAXS + c] = v;
-    }
-    __syncthreads();
-    for (int j = tid; j < mb; j += NT) {
-        const double full = G[j * nrow + nq + j];
-        const double proj = A[j * MAXS + j];
-        // negligible after projection (relative to the column itself): drop
-        dsc[j] = (proj > a.drop * full && proj > 0.0) ? 1.0 / sqrt(proj) : 0.0;
-    }
-    __syncthreads();
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int r = i % mb, c = i / mb;
-        A[r * MAXS + c] *= dsc[r] * dsc[c];
-    }
-    __syncthreads();
-    jacobi_wg(A, Z, mb, 1e-15, 40, red, cs, sn, pp, qq);
-    if (tid == 0) {
-        int r = 0;
-        for (int i = 0; i < mb; ++i) {
-            const double t = A[i * MAXS + i];
-            if (t > a.drop) {
-                keep[r] = i;
-                th[r] = t;
-                ++r;
-            }
-        }
-        nkeep = r;
-    }
-    __syncthreads();
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int row = i % mb, c = i / mb;
-        ctrl->Tw[row + mb * c] = c < nkeep ? dsc[row] * Z[row * MAXS + keep[c]] / sqrt(th[c]) : 0.0;
-    }
+    const int nq = target == 1 ? a.mb + ctrl->np : 0;
+    orth_small_body<MAXS>(a.mb, nq, a.drop, G, ctrl->Bw, ctrl->Tw);
 }
 
 template <class T>
@@ -320,285 +267,11 @@ __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* _
     }
 }
 
-// --------------------------------------------------------------------------
-// One-workgroup parallel cyclic Jacobi on an n x n symmetric matrix in LDS
-// (leading dimension MAXS); round-robin ordering, so the n/2 rotations of a
-// round act on disjoint index pairs (Golub & Van Loan, parallel Jacobi).
-// On return diag(A) holds the eigenvalues, Z the eigenvectors (columns).
-// --------------------------------------------------------------------------
-__device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweeps, double* red, double* cs,
-                          double* sn, int* pp, int* qq) {
-    const int tid = threadIdx.x;
-    for (int i = tid; i < n * MAXS; i += NT) {
-        const int r = i / MAXS, c = i % MAXS;
-        Z[i] = (r == c) ? 1.0 : 0.0;
-    }
-    const int ne = n + (n & 1);
-    const int half = ne / 2;
-    __syncthreads();
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        double off = 0.0, fro = 0.0;
-        for (int i = tid; i < n * n; i += NT) {
-            const int r = i / n, c = i % n;
-            const double v = A[r * MAXS + c];
-            fro += v * v;
-            if (r != c) off += v * v;
-        }
-        off = wave_sum(off);
-        fro = wave_sum(fro);
-        if ((tid & 63) == 0) {
-            red[tid >> 6] = off;
-            red[4 + (tid >> 6)] = fro;
-        }
-        __syncthreads();
-        const double offt = red[0] + red[1] + red[2] + red[3];
-        const double frot = red[4] + red[5] + red[6] + red[7];
-        __syncthreads();
-        if (!(offt > tol * tol * frot)) break;
-        for (int round = 0; round < ne - 1; ++round) {
-            if (tid < half) {
-                const int pa = tid, pb = ne - 1 - tid;
-                const int ia = pa == 0 ? 0 : 1 + (pa - 1 + round) % (ne - 1);
-                const int ib = pb == 0 ? 0 : 1 + (pb - 1 + round) % (ne - 1);
-                const int p = ia < ib ? ia : ib, q = ia < ib ? ib : ia;
-                double c = 1.0, s = 0.0;
-                if (q < n) {
-                    const double apq = A[p * MAXS + q];
-                    if (apq != 0.0) {
-                        const double tau = (A[q * MAXS + q] - A[p * MAXS + p]) / (2.0 * apq);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                    }
-                }
-                cs[tid] = c;
-                sn[tid] = s;
-                pp[tid] = p;
-                qq[tid] = q < n ? q : -1;
-            }
-            __syncthreads();
-            for (int i = tid; i < half * n; i += NT) {  // rows: A <- J^T A
-                const int kp = i / n, col = i % n;
-                const int q = qq[kp];
-                if (q < 0) continue;
-                const int p = pp[kp];
-                const double c = cs[kp], s = sn[kp];
-                const double ap = A[p * MAXS + col], aq = A[q * MAXS + col];
-                A[p * MAXS + col] = c * ap - s * aq;
-                A[q * MAXS + col] = s * ap + c * aq;
-            }
-            __syncthreads();
-            for (int i = tid; i < half * n; i += NT) {  // columns: A <- A J, Z <- Z J
-                const int kp = i / n, row = i % n;
-                const int q = qq[kp];
-                if (q < 0) continue;
-                const int p = pp[kp];
-                const double c = cs[kp], s = sn[kp];
-                const double ap = A[row * MAXS + p], aq = A[row * MAXS + q];
-                A[row * MAXS + p] = c * ap - s * aq;
-                A[row * MAXS + q] = s * ap + c * aq;
-                const double zp = Z[row * MAXS + p], zq = Z[row * MAXS + q];
-                Z[row * MAXS + p] = c * zp - s * zq;
-                Z[row * MAXS + q] = s * zp + c * zq;
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// --------------------------------------------------------------------------
-// Rayleigh-Ritz on span(S), basis size ns:
-//   G_B -> D G_B D = Z diag(theta) Z^T, keep theta > drop * max(theta),
-//   T = D Z_keep theta^-1/2  (T^T G_B T = I);
-//   T^T G_A T = Y diag(lam) Y^T;   C = T Y[:, lowest mb]   (X_new = S C);
-//   C_wp = C with its X rows zeroed, made G_B-orthogonal to C (twice) and
-//   G_B-orthonormalised with rank dropping -> Cp  (P_new = S Cp).
-// G layout: G[e] for the upper triangles of S^T HS then S^T S (row-major).
-// --------------------------------------------------------------------------
+// Rayleigh-Ritz step (one workgroup, FP64): see rr_body.
 __global__ __launch_bounds__(NT) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ Gtri,
                                            EigCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
-    const int ns = sol_ns(a, ctrl, ns_fixed);
-    const int mb = a.mb;
-    __shared__ double A[MAXS * MAXS];
-    __shared__ double Z[MAXS * MAXS];
-    __shared__ double Tm[MAXS * MAXS];
-    __shared__ double dsc[MAXS], th[MAXS], ev[MAXS], red[8], cs[MAXS / 2 + 1], sn[MAXS / 2 + 1];
-    __shared__ double h1[MAXB * MAXB];
-    __shared__ int pp[MAXS / 2 + 1], qq[MAXS / 2 + 1], keep[MAXS], order[MAXS];
-    __shared__ int rank_s;
-    const int tid = threadIdx.x;
-    const int Eh = ns * (ns + 1) / 2;
-    auto GA = [&](int i, int j) {
-        const int r = i < j ? i : j, c = i < j ? j : i;
-        return Gtri[r * ns - r * (r - 1) / 2 + (c - r)];
-    };
-    auto GB = [&](int i, int j) {
-        const int r = i < j ? i : j, c = i < j ? j : i;
-        return Gtri[Eh + r * ns - r * (r - 1) / 2 + (c - r)];
-    };
-    double gbmax = 0.0;
-    for (int i = 0; i < ns; ++i) gbmax = fmax(gbmax, GB(i, i));
-    for (int i = tid; i < ns; i += NT) {
-        const double gii = GB(i, i);
-        dsc[i] = gii > 1e-24 * gbmax ? 1.0 / sqrt(gii) : 0.0;
-    }
-    __syncthreads();
-    for (int i = tid; i < ns * ns; i += NT) {
-        const int r = i / ns, c = i % ns;
-        A[r * MAXS + c] = dsc[r] * GB(r, c) * dsc[c];
-    }
-    __syncthreads();
-    jacobi_wg(A, Z, ns, 1e-15, 40, red, cs, sn, pp, qq);
-    if (tid == 0) {
-        double tmax = 0.0;
-        for (int i = 0; i < ns; ++i) tmax = fmax(tmax, A[i * MAXS + i]);
-        int r = 0;
-        for (int i = 0; i < ns; ++i) {
-            const double t = A[i * MAXS + i];
-            if (t > a.drop * tmax) {
-                keep[r] = i;
-                th[r] = t;
-                ++r;
-            }
-        }
-        rank_s = r;
-    }
-    __syncthreads();
-    const int r = rank_s;
-    for (int i = tid; i < ns * r; i += NT) {  // T (ns x r)
-        const int row = i / r, c = i % r;
-        Tm[row * MAXS + c] = dsc[row] * Z[row * MAXS + keep[c]] / sqrt(th[c]);
-    }
-    __syncthreads();
-    for (int i = tid; i < ns * r; i += NT) {  // Z <- G_A T
-        const int row = i / r, c = i % r;
-        double s = 0.0;
-        for (int l = 0; l < ns; ++l) s += GA(row, l) * Tm[l * MAXS + c];
-        Z[row * MAXS + c] = s;
-    }
-    __syncthreads();
-    for (int i = tid; i < r * r; i += NT) {  // A <- T^T Z
-        const int row = i / r, c = i % r;
-        double s = 0.0;
-        for (int l = 0; l < ns; ++l) s += Tm[l * MAXS + row] * Z[l * MAXS + c];
-        A[row * MAXS + c] = s;
-    }
-    __syncthreads();
-    for (int i = tid; i < r * r; i += NT) {
-        const int row = i / r, c = i % r;
-        if (row < c) {
-            const double v = 0.5 * (A[row * MAXS + c] + A[c * MAXS + row]);
-            A[row * MAXS + c] = v;
-            A[c * MAXS + row] = v;
-        }
-    }
-    __syncthreads();
-    jacobi_wg(A, Z, r, 1e-15, 40, red, cs, sn, pp, qq);
-    for (int i = tid; i < r; i += NT) ev[i] = A[i * MAXS + i];
-    __syncthreads();
-    for (int i = tid; i < r; i += NT) {
-        const double li = ev[i];
-        int rk = 0;
-        for (int j = 0; j < r; ++j) rk += (ev[j] < li) || (ev[j] == li && j < i);
-        order[rk] = i;
-    }
-    __syncthreads();
-    const int mcol = r < mb ? r : mb;
-    // C = T Y[:, order[0..mb)] -> A region (ld MAXB) and ctrl->C
-    for (int i = tid; i < ns * mb; i += NT) {
-        const int row = i % ns, j = i / ns;
-        double s = 0.0;
-        if (j < mcol) {
-            const int yc = order[j];
-            for (int l = 0; l < r; ++l) s += Tm[row * MAXS + l] * Z[l * MAXS + yc];
-        }
-        A[row * MAXB + j] = s;
-        ctrl->C[row + ns * j] = s;
-    }
-    for (int j = tid; j < mb; j += NT) ctrl->lam[j] = j < mcol ? ev[order[j]] : 0.0;
-    if (tid == 0) ctrl->rank = r;
-    __syncthreads();
-    // ---- P complement: Cwp (Tm region, ld MAXB) ----
-    const int nx = mb;
-    for (int i = tid; i < ns * mb; i += NT) {
-        const int row = i % ns, j = i / ns;
-        Tm[row * MAXB + j] = row < nx ? 0.0 : A[row * MAXB + j];
-    }
-    __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int i = tid; i < ns * mb; i += NT) {  // Z <- G_B Cwp
-            const int row = i % ns, j = i / ns;
-            double s = 0.0;
-            for (int l = 0; l < ns; ++l) s += GB(row, l) * Tm[l * MAXB + j];
-            Z[row * MAXB + j] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < mb * mb; i += NT) {  // h1 <- C^T G_B Cwp
-            const int p = i % mb, j = i / mb;
-            double s = 0.0;
-            for (int l = 0; l < ns; ++l) s += A[l * MAXB + p] * Z[l * MAXB + j];
-            h1[p + MAXB * j] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < ns * mb; i += NT) {  // Cwp <- Cwp - C h1
-            const int row = i % ns, j = i / ns;
-            double s = Tm[row * MAXB + j];
-            for (int p = 0; p < mb; ++p) s -= A[row * MAXB + p] * h1[p + MAXB * j];
-            Tm[row * MAXB + j] = s;
-        }
-        __syncthreads();
-    }
-    // Mp = Cwp^T G_B Cwp  (mb x mb) -> Z region (ld MAXS) after the product
-    for (int i = tid; i < ns * mb; i += NT) {
-        const int row = i % ns, j = i / ns;
-        double s = 0.0;
-        for (int l = 0; l < ns; ++l) s += GB(row, l) * Tm[l * MAXB + j];
-        A[row * MAXB + j] = s;  // C no longer needed: reuse A for G_B Cwp
-    }
-    __syncthreads();
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int p = i % mb, j = i / mb;
-        double s = 0.0;
-        for (int l = 0; l < ns; ++l) s += Tm[l * MAXB + p] * A[l * MAXB + j];
-        h1[p + MAXB * j] = s;
-    }
-    __syncthreads();
-    for (int j = tid; j < mb; j += NT) {
-        const double d = h1[j + MAXB * j];
-        dsc[j] = d > 1e-24 ? 1.0 / sqrt(d) : 0.0;
-    }
-    __syncthreads();
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int p = i % mb, j = i / mb;
-        Z[p * MAXS + j] = dsc[p] * h1[p + MAXB * j] * dsc[j];
-    }
-    __syncthreads();
-    jacobi_wg(Z, A, mb, 1e-15, 40, red, cs, sn, pp, qq);
-    if (tid == 0) {
-        int rr = 0;
-        for (int i = 0; i < mb; ++i) {
-            const double t = Z[i * MAXS + i];
-            if (t > a.drop) {
-                keep[rr] = i;
-                th[rr] = t;
-                ++rr;
-            }
-        }
-        rank_s = rr;
-    }
-    __syncthreads();
-    const int rp = rank_s;
-    for (int i = tid; i < ns * mb; i += NT) {  // Cp = Cwp D Zp_keep theta^-1/2
-        const int row = i % ns, j = i / ns;
-        double s = 0.0;
-        if (j < rp) {
-            const int zc = keep[j];
-            for (int l = 0; l < mb; ++l) s += Tm[row * MAXB + l] * dsc[l] * A[l * MAXS + zc];
-            s /= sqrt(th[j]);
-        }
-        ctrl->Cp[row + ns * j] = s;
-    }
+    rr_body<MAXS>(a.mb, sol_ns(a, ctrl, ns_fixed), a.drop, Gtri, ctrl);
 }
 
 // --------------------------------------------------------------------------

@@ -5,6 +5,7 @@
 // wrap at the halo) and evaluates the three-shell stencil of the spin
 // Hamiltonian (Methods, Eq. param-hamiltonian) at one site per thread.
 #include "kernels.hpp"
+#include "tile_ops.hpp"
 
 namespace moto {
 
@@ -38,58 +39,12 @@ __global__ __launch_bounds__(NT) void k_energy_grad(Geo g, Coef<T> k, const T* _
     __shared__ TileLDS<T> t;
     __shared__ double red[NPART * (NT / 64)];
     const TileIdx ti = tile_of(g);
-    const size_t off3 = (size_t)ti.b * 3 * g.N;
-    const T* mb = m + off3;
-    for (int i = threadIdx.x; i < TILE_SITES; i += NT) {
-        const int lx = i % LXH, ly = i / LXH;
-        const int x = wrapi(ti.tx0 + lx - HALO, g.Lx), y = wrapi(ti.ty0 + ly - HALO, g.Ly);
-        const int s = x + g.Lx * y;
-        t.u[0][ly][lx] = mb[s];
-        t.u[1][ly][lx] = mb[g.N + s];
-        t.u[2][ly][lx] = mb[2 * g.N + s];
-    }
-    __syncthreads();
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int x = ti.tx0 + lx, y = ti.ty0 + ly;
+    const size_t off3 = (size_t)ti.b * 3 * g.N, off1 = (size_t)ti.b * g.N;
     double v[NPART];
 #pragma unroll
     for (int q = 0; q < NPART; ++q) v[q] = 0.0;
-    if (x < g.Lx && y < g.Ly) {
-        const int cx = lx + HALO, cy = ly + HALO;
-        const int s = x + g.Lx * y;
-        T a[3];
-        apply_A_tile(t, cx, cy, k, a);
-        const T mi[3] = {t.u[0][cy][cx], t.u[1][cy][cx], t.u[2][cy][cx]};
-        const T gi[3] = {a[0] - k.B[0], a[1] - k.B[1], a[2] - k.B[2]};
-        const T ci = mi[0] * gi[0] + mi[1] * gi[1] + mi[2] * gi[2];
-        if (grad) {
-            T* gb = grad + off3;
-            gb[s] = gi[0];
-            gb[g.N + s] = gi[1];
-            gb[2 * g.N + s] = gi[2];
-        }
-        if (cout) cout[(size_t)ti.b * g.N + s] = ci;
-        if (F) {
-            const bool act = mask == nullptr || mask[(size_t)ti.b * g.N + s] != 0;
-            T* fb = F + off3;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) fb[c * g.N + s] = act ? -(gi[c] - ci * mi[c]) : T(0);
-        }
-        const double mam = (double)mi[0] * a[0] + (double)mi[1] * a[1] + (double)mi[2] * a[2];
-        const double bm = (double)k.B[0] * mi[0] + (double)k.B[1] * mi[1] + (double)k.B[2] * mi[2];
-        v[0] = 0.5 * mam - bm;
-        T S[3][3], Q[3][3];
-        shell_sums(t, cx, cy, S, Q);
-#pragma unroll
-        for (int sh = 0; sh < 3; ++sh) {
-            v[1 + sh] = -((double)mi[0] * S[sh][0] + (double)mi[1] * S[sh][1] + (double)mi[2] * S[sh][2]);
-            v[4 + sh] = (double)mi[0] * Q[sh][0] + (double)mi[1] * Q[sh][1] + (double)mi[2] * Q[sh][2];
-        }
-        v[7] = -(double)mi[2] * mi[2];
-        v[8] = -(double)mi[0];
-        v[9] = -(double)mi[1];
-        v[10] = -(double)mi[2];
-    }
+    energy_tile(t, g, k, m + off3, mask ? mask + off1 : nullptr, grad ? grad + off3 : nullptr,
+                cout ? cout + off1 : nullptr, F ? F + off3 : nullptr, ti.tx0, ti.ty0, v);
     block_sum<NPART>(v, red);
     if (threadIdx.x == 0) {
 #pragma unroll
@@ -145,6 +100,47 @@ __global__ __launch_bounds__(NT) void k_param_mixed(Geo g, const T* __restrict__
     }
 }
 
+// Parameter-weighted gradient sum  out_i = sum_q w_q dg_i/dtheta_q  (the
+// adjoint of the parameter partials; g is linear in theta):
+//   J_s: -2 S_s,  D_s: 2 Q_s,  K: -2 m_z z,  B_a: -e_a.
+// w = [batch][2 ns + 4] (FP64), theta order (J_0.., D_0.., K, Bx, By, Bz).
+template <class T>
+__global__ __launch_bounds__(NT) void k_param_grad_apply(Geo g, int ns, const T* __restrict__ m,
+                                                         const double* __restrict__ w, T* __restrict__ out) {
+    __shared__ TileLDS<T> t;
+    const TileIdx ti = tile_of(g);
+    const size_t off3 = (size_t)ti.b * 3 * g.N;
+    const T* mb = m + off3;
+    for (int i = threadIdx.x; i < TILE_SITES; i += NT) {
+        const int lx = i % LXH, ly = i / LXH;
+        const int x = wrapi(ti.tx0 + lx - HALO, g.Lx), y = wrapi(ti.ty0 + ly - HALO, g.Ly);
+        const int s = x + g.Lx * y;
+        t.u[0][ly][lx] = mb[s];
+        t.u[1][ly][lx] = mb[g.N + s];
+        t.u[2][ly][lx] = mb[2 * g.N + s];
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = ti.tx0 + lx, y = ti.ty0 + ly;
+    if (x >= g.Lx || y >= g.Ly) return;
+    const int cx = lx + HALO, cy = ly + HALO;
+    const int s = x + g.Lx * y;
+    const double* wb = w + (size_t)ti.b * (2 * ns + 4);
+    T S[3][3], Q[3][3];
+    shell_sums(t, cx, cy, S, Q);
+    double o[3];
+    for (int c = 0; c < 3; ++c) {
+        double v = -wb[2 * ns + 1 + c];
+        for (int sh = 0; sh < ns; ++sh) v += -2.0 * wb[sh] * S[sh][c] + 2.0 * wb[ns + sh] * Q[sh][c];
+        o[c] = v;
+    }
+    o[2] += -2.0 * wb[2 * ns] * (double)t.u[2][cy][cx];
+    T* ob = out + off3;
+    ob[s] = (T)o[0];
+    ob[g.N + s] = (T)o[1];
+    ob[2 * g.N + s] = (T)o[2];
+}
+
 // Fixed-order reduction of the per-block partials of each lattice; maps the
 // slots to E[b] and dtheta[b][.] = (J_0..J_{ns-1}, D_0..D_{ns-1}, K, Bx, By, Bz).
 __global__ __launch_bounds__(NT) void k_reduce_partials(const double* __restrict__ part, int tiles, int ns,
@@ -194,88 +190,11 @@ __global__ __launch_bounds__(NT) void k_tangent_hvp(Geo g, Coef<T> k, const T* _
                                                     const int* __restrict__ done) {
     if (done != nullptr && *done) return;
     constexpr int DV = FRAME ? 2 : 3;
-    __shared__ TileLDS<T> t;
-    __shared__ T fr[FRAME ? 6 : 3][LYH][LXH];
-    __shared__ uint8_t act[LYH][LXH];
+    __shared__ HvpLDS<T, FRAME> sh;
     const TileIdx ti = tile_of(g);
-    const size_t off3 = (size_t)ti.b * 3 * g.N;
-    const T* mb = m + off3;
-    const uint8_t* mk = mask ? mask + (size_t)ti.b * g.N : nullptr;
-    for (int i = threadIdx.x; i < TILE_SITES; i += NT) {
-        const int lx = i % LXH, ly = i / LXH;
-        const int x = wrapi(ti.tx0 + lx - HALO, g.Lx), y = wrapi(ti.ty0 + ly - HALO, g.Ly);
-        const int s = x + g.Lx * y;
-        const T mx = mb[s], my = mb[g.N + s], mz = mb[2 * g.N + s];
-        if constexpr (FRAME) {
-            T e1[3], e2[3];
-            onb(mx, my, mz, e1, e2);
-            fr[0][ly][lx] = e1[0];
-            fr[1][ly][lx] = e1[1];
-            fr[2][ly][lx] = e1[2];
-            fr[3][ly][lx] = e2[0];
-            fr[4][ly][lx] = e2[1];
-            fr[5][ly][lx] = e2[2];
-        } else {
-            fr[0][ly][lx] = mx;
-            fr[1][ly][lx] = my;
-            fr[2][ly][lx] = mz;
-        }
-        act[ly][lx] = mk ? (mk[s] != 0) : 1;
-    }
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int x = ti.tx0 + lx, y = ti.ty0 + ly;
-    const bool valid = x < g.Lx && y < g.Ly;
-    const int cx = lx + HALO, cy = ly + HALO;
-    const int sc = x + g.Lx * y;
-    const T ci = valid ? c[(size_t)ti.b * g.N + sc] : T(0);
-    const size_t vstride = (size_t)DV * g.N;
-    const T* Vb = V + (size_t)ti.b * nvec * vstride;
-    T* Wb = W + (size_t)ti.b * nvec * vstride;
-    for (int j = 0; j < nvec; ++j) {
-        __syncthreads();
-        const T* vj = Vb + j * vstride;
-        for (int i = threadIdx.x; i < TILE_SITES; i += NT) {
-            const int lx2 = i % LXH, ly2 = i / LXH;
-            const int x2 = wrapi(ti.tx0 + lx2 - HALO, g.Lx), y2 = wrapi(ti.ty0 + ly2 - HALO, g.Ly);
-            const int s = x2 + g.Lx * y2;
-            const bool on = act[ly2][lx2];
-            if constexpr (FRAME) {
-                const T a = on ? vj[s] : T(0);
-                const T b = on ? vj[g.N + s] : T(0);
-                t.u[0][ly2][lx2] = a * fr[0][ly2][lx2] + b * fr[3][ly2][lx2];
-                t.u[1][ly2][lx2] = a * fr[1][ly2][lx2] + b * fr[4][ly2][lx2];
-                t.u[2][ly2][lx2] = a * fr[2][ly2][lx2] + b * fr[5][ly2][lx2];
-            } else {
-                t.u[0][ly2][lx2] = on ? vj[s] : T(0);
-                t.u[1][ly2][lx2] = on ? vj[g.N + s] : T(0);
-                t.u[2][ly2][lx2] = on ? vj[2 * g.N + s] : T(0);
-            }
-        }
-        __syncthreads();
-        if (valid) {
-            T a[3];
-            apply_A_tile(t, cx, cy, k, a);
-            T* wj = Wb + j * vstride;
-            const bool on = act[cy][cx];
-            const T u0 = t.u[0][cy][cx], u1 = t.u[1][cy][cx], u2 = t.u[2][cy][cx];
-            if constexpr (FRAME) {
-                const T e10 = fr[0][cy][cx], e11 = fr[1][cy][cx], e12 = fr[2][cy][cx];
-                const T e20 = fr[3][cy][cx], e21 = fr[4][cy][cx], e22 = fr[5][cy][cx];
-                const T av = e10 * u0 + e11 * u1 + e12 * u2;
-                const T bv = e20 * u0 + e21 * u1 + e22 * u2;
-                const T wa = e10 * a[0] + e11 * a[1] + e12 * a[2] - ci * av;
-                const T wb = e20 * a[0] + e21 * a[1] + e22 * a[2] - ci * bv;
-                wj[sc] = on ? wa : T(0);
-                wj[g.N + sc] = on ? wb : T(0);
-            } else {
-                const T m0 = fr[0][cy][cx], m1 = fr[1][cy][cx], m2 = fr[2][cy][cx];
-                const T ma = m0 * a[0] + m1 * a[1] + m2 * a[2];
-                wj[sc] = on ? a[0] - ma * m0 - ci * u0 : T(0);
-                wj[g.N + sc] = on ? a[1] - ma * m1 - ci * u1 : T(0);
-                wj[2 * g.N + sc] = on ? a[2] - ma * m2 - ci * u2 : T(0);
-            }
-        }
-    }
+    const size_t vb = (size_t)ti.b * nvec * DV * g.N;
+    tangent_hvp_tile<T, FRAME>(sh, g, k, m + (size_t)ti.b * 3 * g.N, c + (size_t)ti.b * g.N,
+                               mask ? mask + (size_t)ti.b * g.N : nullptr, nvec, V + vb, W + vb, ti.tx0, ti.ty0);
 }
 
 // Euclidean Hessian apply W_j = A V_j (ambient, unmasked).
@@ -354,15 +273,6 @@ __global__ __launch_bounds__(NT) void k_topo_charge(Geo g, const double* __restr
 // --------------------------------------------------------------------------
 // Launchers
 // --------------------------------------------------------------------------
-template <class T>
-static Coef<T> coef_cast(const CoefD& d) {
-    Coef<T> k;
-    for (int s = 0; s < 3; ++s) k.cJ[s] = (T)d.cJ[s];
-    k.cD = (T)d.cD;
-    k.cK = (T)d.cK;
-    for (int a = 0; a < 3; ++a) k.B[a] = (T)d.B[a];
-    return k;
-}
 
 hipError_t launch_energy_grad(const Geo& g, const CoefD& kd, bool f64, int batch, const void* m,
                               const uint8_t* mask, void* grad, void* c, void* F, double* part,
@@ -389,6 +299,18 @@ hipError_t launch_param_mixed(const Geo& g, bool f64, int batch, const void* m, 
     return hipGetLastError();
 }
 
+hipError_t launch_param_grad_apply(const Geo& g, int ns, bool f64, int batch, const void* m, const double* w,
+                                  void* out, hipStream_t st) {
+    dim3 grid(batch * g.tiles);
+    if (f64)
+        hipLaunchKernelGGL(k_param_grad_apply<double>, grid, dim3(NT), 0, st, g, ns, (const double*)m, w,
+                           (double*)out);
+    else
+        hipLaunchKernelGGL(k_param_grad_apply<float>, grid, dim3(NT), 0, st, g, ns, (const float*)m, w,
+                           (float*)out);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_partials(const double* part, int batch, int tiles, int ns, double* E, double* dth,
                                   hipStream_t st) {
     hipLaunchKernelGGL(k_reduce_partials, dim3(batch), dim3(NT), 0, st, part, tiles, ns, E, dth);
@@ -397,23 +319,15 @@ hipError_t launch_reduce_partials(const double* part, int batch, int tiles, int 
 
 hipError_t launch_tangent_hvp(const Geo& g, const CoefD& kd, bool f64, bool frame, int batch, const void* m,
                               const void* c, const uint8_t* mask, int nvec, const void* V, void* W,
-                              const int* done, hipStream_t st) {
+                              const int* done, hipStream_t st, int variant) {
+    if (frame) return launch_hvp_frame(variant, g, kd, f64, batch, m, c, mask, nvec, V, W, done, st);
     dim3 grid(batch * g.tiles);
-    if (f64) {
-        if (frame)
-            hipLaunchKernelGGL((k_tangent_hvp<double, true>), grid, dim3(NT), 0, st, g, coef_cast<double>(kd),
-                               (const double*)m, (const double*)c, mask, nvec, (const double*)V, (double*)W, done);
-        else
-            hipLaunchKernelGGL((k_tangent_hvp<double, false>), grid, dim3(NT), 0, st, g, coef_cast<double>(kd),
-                               (const double*)m, (const double*)c, mask, nvec, (const double*)V, (double*)W, done);
-    } else {
-        if (frame)
-            hipLaunchKernelGGL((k_tangent_hvp<float, true>), grid, dim3(NT), 0, st, g, coef_cast<float>(kd),
-                               (const float*)m, (const float*)c, mask, nvec, (const float*)V, (float*)W, done);
-        else
-            hipLaunchKernelGGL((k_tangent_hvp<float, false>), grid, dim3(NT), 0, st, g, coef_cast<float>(kd),
-                               (const float*)m, (const float*)c, mask, nvec, (const float*)V, (float*)W, done);
-    }
+    if (f64)
+        hipLaunchKernelGGL((k_tangent_hvp<double, false>), grid, dim3(NT), 0, st, g, coef_cast<double>(kd),
+                           (const double*)m, (const double*)c, mask, nvec, (const double*)V, (double*)W, done);
+    else
+        hipLaunchKernelGGL((k_tangent_hvp<float, false>), grid, dim3(NT), 0, st, g, coef_cast<float>(kd),
+                           (const float*)m, (const float*)c, mask, nvec, (const float*)V, (float*)W, done);
     return hipGetLastError();
 }
 

@@ -73,10 +73,6 @@ class SearchResult(ctypes.Structure):
                 ("lambda2", ctypes.c_double)]
 
 
-class BatchDesc(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("L", ctypes.POINTER(ctypes.c_int32))]
-
-
 _lib = None
 _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
@@ -101,7 +97,13 @@ def lib():
         "moto_energy_grad": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
         "moto_tangent_hvp": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
         "moto_hessian_apply": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
+        "moto_tangent_hvp_variants": (_i32, []),
+        "moto_plan_set_hvp_variant": (_i32, [_vp, _i32, _i32, _i32, _i32]),
+        "moto_tangent_hvp_variant_name": (ctypes.c_char_p, [_i32]),
+        "moto_tangent_hvp_autotune": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i32,
+                                             ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float), _vp]),
         "moto_param_mixed": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "moto_param_grad_apply": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
         "moto_min_modes_workspace": (_sz, [_vp, _i32, _i32, _i32]),
         "moto_min_modes": (_i32, [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(EigOpts), _vp, _vp, _vp,
                                   ctypes.POINTER(Info), _vp, _sz, _vp]),
@@ -119,13 +121,13 @@ def lib():
         "moto_default_search_opts": (None, [_i32, ctypes.POINTER(SearchOpts)]),
         "moto_topological_charge": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     }
-    optional = {
-        "moto_saddle_search_batched_workspace": (_sz, [_vp, _i32, ctypes.POINTER(BatchDesc),
+    sig.update({
+        "moto_saddle_search_batched_workspace": (_sz, [_i32, ctypes.POINTER(ctypes.c_int32),
                                                        ctypes.POINTER(SearchOpts)]),
-        "moto_saddle_search_batched": (_i32, [ctypes.POINTER(_Ham), _i32, ctypes.POINTER(BatchDesc), _vp,
-                                              ctypes.POINTER(SearchOpts), ctypes.POINTER(SearchResult), _vp, _sz,
-                                              _vp]),
-    }
+        "moto_saddle_search_batched": (_i32, [ctypes.POINTER(_Ham), _i32, ctypes.POINTER(ctypes.c_int32), _vp,
+                                              ctypes.POINTER(SearchOpts), _vp, _vp, _sz, _vp]),
+    })
+    optional = {}
     for name, (res, args) in list(sig.items()) + list(optional.items()):
         if not hasattr(L, name):
             if name in sig:
@@ -247,6 +249,25 @@ def moto_tangent_hvp(plan: Plan, m: torch.Tensor, c: torch.Tensor, V: torch.Tens
     _check(lib().moto_tangent_hvp(plan.handle, _dt(m), layout, batch, _ptr(m), _ptr(c), _ptr(mask), n_vec,
                                   _ptr(V), _ptr(W), _stream(stream)), "moto_tangent_hvp")
     return W
+
+
+def moto_plan_set_hvp_variant(plan: Plan, dtype: int, batch: int, n_vec: int, variant: int):
+    _check(lib().moto_plan_set_hvp_variant(plan.handle, dtype, batch, n_vec, variant), "moto_plan_set_hvp_variant")
+
+
+def moto_tangent_hvp_autotune(plan: Plan, m: torch.Tensor, c: torch.Tensor, V: torch.Tensor, W: torch.Tensor,
+                              batch: int = 1, mask: Optional[torch.Tensor] = None, reps: int = 3, stream=None):
+    """Time every frame-layout HVP variant on these buffers; the plan keeps
+    the fastest for (dtype, batch, n_vec).  Returns (chosen, {name: ms})."""
+    n_vec = V.numel() // (batch * 2 * plan.N)
+    nv = int(lib().moto_tangent_hvp_variants())
+    times = (ctypes.c_float * nv)()
+    chosen = _i32()
+    _check(lib().moto_tangent_hvp_autotune(plan.handle, _dt(m), batch, _ptr(m), _ptr(c), _ptr(mask), n_vec, _ptr(V),
+                                           _ptr(W), reps, ctypes.byref(chosen), times, _stream(stream)),
+           "moto_tangent_hvp_autotune")
+    names = [lib().moto_tangent_hvp_variant_name(i).decode() for i in range(nv)]
+    return chosen.value, {names[i]: float(times[i]) for i in range(nv) if times[i] >= 0}
 
 
 def moto_hessian_apply(plan: Plan, V: torch.Tensor, batch: int = 1, W: Optional[torch.Tensor] = None,
@@ -399,3 +420,34 @@ def moto_saddle_search(plan: Plan, m: torch.Tensor, hvp: int = MOTO_F64, mask: O
     _check(lib().moto_saddle_search(plan.handle, hvp, _ptr(m), _ptr(mask), ctypes.byref(o), ctypes.byref(res),
                                     _ptr(ev), _ptr(V), _ptr(ws), nb, _stream(stream)), "moto_saddle_search")
     return res, ev, V
+
+
+def moto_saddle_search_batched(params, Ls: Sequence[int], m_all: torch.Tensor, opts: Optional[SearchOpts] = None,
+                               stream=None):
+    """Saddle searches on square lattices of sides Ls in one persistent launch
+    (FP32 HVP, FP64 state).  m_all holds the starts back to back
+    ([3][L_b^2] each, FP64) and is updated in place.  Returns a list of
+    SearchResult (one per lattice, input order)."""
+    o = opts if opts is not None else search_opts(MOTO_F32)
+    n = len(Ls)
+    Larr = (ctypes.c_int32 * n)(*[int(v) for v in Ls])
+    nb = int(lib().moto_saddle_search_batched_workspace(n, Larr, ctypes.byref(o)))
+    if nb == 0:
+        raise MotoError("moto_saddle_search_batched_workspace: invalid sizes or options")
+    ws = _ws(nb, m_all.device)
+    res = torch.empty(n * ctypes.sizeof(SearchResult), dtype=torch.uint8, device=m_all.device)
+    h = _Ham()
+    h.Lx, h.Ly = 1, 1
+    h.n_shells = max(len(params.J), len(params.D), 1)
+    h.reserved = 0
+    for s in range(MAX_SHELLS):
+        h.J[s] = float(params.J[s]) if s < len(params.J) else 0.0
+        h.D[s] = float(params.D[s]) if s < len(params.D) else 0.0
+    h.K = float(params.K)
+    for a in range(3):
+        h.B[a] = float(params.B[a])
+    _check(lib().moto_saddle_search_batched(ctypes.byref(h), n, Larr, _ptr(m_all), ctypes.byref(o), _ptr(res),
+                                            _ptr(ws), nb, _stream(stream)), "moto_saddle_search_batched")
+    raw = bytes(res.cpu().numpy())
+    sz = ctypes.sizeof(SearchResult)
+    return [SearchResult.from_buffer_copy(raw[i * sz:(i + 1) * sz]) for i in range(n)]

@@ -1,0 +1,89 @@
+"""Batching form: each member of a ragged batch of saddle searches run in one
+persistent launch reaches the same outcome as the same search run alone
+through moto_saddle_search (and, for the 16x16 collapse start, as the FP64
+oracle).  FP32 HVP with FP64 state: same status; for saddles |dE| <= 1e-6 |E|
+and max per-site angle <= 1e-2 rad."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_26269_amd import synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _M():
+    from paper_2509_26269_amd import moto as M
+
+    return M
+
+
+def _pack(ms):
+    return torch.as_tensor(np.concatenate([m.reshape(-1) for m in ms]), dtype=torch.float64, device="cuda")
+
+
+def _unpack(t, Ls):
+    out, o = [], 0
+    a = t.cpu().numpy()
+    for L in Ls:
+        n = 3 * L * L
+        out.append(a[o:o + n].reshape(3, L * L))
+        o += n
+    return out
+
+
+def test_batched_nn_members_match_single_and_oracle():
+    M = _M()
+    p = S.ham_nn(16)
+    h = O.Ham(**p.asdict())
+    starts = [S.add_tilt_noise(S.skyrmion(16, 16, R), 0.05, np.random.default_rng(sd))
+              for R, sd in [(1.0, 0), (1.2, 1), (1.0, 2)]]
+    Ls = [16, 16, 16]
+    opts = M.search_opts(M.MOTO_F32, tau_F=1e-6, k=1, max_outer=2000, eig={"tol": 1e-6, "max_iter": 200})
+    mall = _pack(starts)
+    res = M.moto_saddle_search_batched(p, Ls, mall, opts)
+    finals = _unpack(mall, Ls)
+    plan = M.Plan.from_params(p)
+    for i, m0 in enumerate(starts):
+        md = torch.as_tensor(m0, device="cuda")
+        rs, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, opts=opts)
+        assert res[i].status == rs.status, (i, M.STATUS_NAMES[res[i].status], M.STATUS_NAMES[rs.status])
+        if rs.status == M.SADDLE:
+            assert abs(res[i].E - rs.E) <= 1e-6 * abs(rs.E)
+            assert O.max_site_angle(finals[i], md.cpu().numpy()) <= 1e-2
+    # member 0 is the oracle's collapse saddle
+    ro = O.saddle_search(h, starts[0], tau_F=1e-6)
+    assert res[0].status == M.SADDLE and ro.status == O.SADDLE
+    assert abs(res[0].E - ro.E) <= 1e-6 * abs(ro.E)
+    assert O.max_site_angle(finals[0], ro.m) <= 1e-2
+    assert abs(res[0].lambda1 - ro.evals[0]) <= 1e-4 * h.h_est()
+
+
+def test_batched_ragged_three_shell():
+    M = _M()
+    Ls = [40, 24, 33, 28, 37]
+    p = S.ham_3shell(Ls[0])
+    kinds = ["skyrmion", "antiskyrmion", "skyrmion", "antiskyrmion", "skyrmion"]
+    starts = [S.three_shell_start(L, seed=10 + i, kind=kinds[i], R=1.2) for i, L in enumerate(Ls)]
+    opts = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, max_outer=1500, eig={"tol": 1e-5, "max_iter": 200})
+    mall = _pack(starts)
+    res = M.moto_saddle_search_batched(p, Ls, mall, opts)
+    finals = _unpack(mall, Ls)
+    for i, (L, m0) in enumerate(zip(Ls, starts)):
+        plan = M.Plan.from_params(p.with_size(L, L))
+        md = torch.as_tensor(m0, device="cuda")
+        rs, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, opts=opts)
+        assert res[i].status == rs.status, (i, L, M.STATUS_NAMES[res[i].status], M.STATUS_NAMES[rs.status])
+        if rs.status == M.SADDLE:
+            assert abs(res[i].E - rs.E) <= 1e-6 * abs(rs.E)
+            assert O.max_site_angle(finals[i], md.cpu().numpy()) <= 1e-2
+        assert np.all(np.isfinite(finals[i]))
+        assert np.allclose(np.linalg.norm(finals[i], axis=0), 1.0, atol=1e-12)
+
+
+def test_batched_rejects_bad_sizes():
+    M = _M()
+    p = S.ham_3shell(8)
+    with pytest.raises(M.MotoError):
+        M.moto_saddle_search_batched(p, [4], torch.zeros(48, dtype=torch.float64, device="cuda"))

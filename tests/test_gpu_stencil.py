@@ -192,3 +192,39 @@ def test_bad_arguments_rejected():
     with pytest.raises(M.MotoError):
         M.moto_tangent_hvp(plan, m, torch.zeros(64, dtype=torch.float64, device="cuda"),
                            torch.zeros(1, 2, 64, dtype=torch.float64, device="cuda"), layout=7)
+
+
+@pytest.mark.parametrize("Lx,Ly", [(128, 16), (37, 23), (5, 7), (200, 9)])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_every_frame_hvp_variant_matches_oracle(Lx, Ly, dt):
+    """The autotuner may pick any frame-layout variant: each one, pinned in
+    turn, reproduces the oracle (batched, masked, ragged tails)."""
+    M = _M()
+    p = _params(Lx, Ly)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    rng = np.random.default_rng(3 * Lx + Ly)
+    B, nvec = 2, 5
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    ms = np.stack([S.random_texture(h.N, rng) for _ in range(B)])
+    cs = np.stack([O.energy_grad(h, ms[b])[2] for b in range(B)])
+    masks = np.stack([(rng.random(h.N) > 0.2).astype(np.uint8) for _ in range(B)])
+    a = rng.standard_normal((B, nvec, 2, h.N))
+    md, cd, ad, mk = _dev(ms, tdt), _dev(cs, tdt), _dev(a, tdt), _dev(masks, torch.uint8)
+    refs = []
+    for b in range(B):
+        mb = _np(md[b])
+        v = O.from_frame(mb, _np(ad[b]))
+        refs.append(O.to_frame(mb, O.tangent_hvp(h, mb, _np(cd[b]), v, mask=masks[b])))
+    tol = 1e-12 if dt == "f64" else 1e-4
+    ran = 0
+    for var in range(M.lib().moto_tangent_hvp_variants()):
+        dtc = M.MOTO_F64 if dt == "f64" else M.MOTO_F32
+        if M.lib().moto_plan_set_hvp_variant(plan.handle, dtc, B, nvec, var) != 0:
+            continue
+        W = _np(M.moto_tangent_hvp(plan, md, cd, ad, M.MOTO_FRAME, mask=mk, batch=B))
+        for b in range(B):
+            for j in range(nvec):
+                assert _rel(W[b, j], refs[b][j]) <= tol, (var, b, j)
+        ran += 1
+    assert ran >= 6
