@@ -97,7 +97,8 @@ def main():
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--nvec", type=int, default=4)
     ap.add_argument("--L", type=int, default=128)
-    ap.add_argument("--searches", type=int, default=8, help="one-at-a-time GPU searches timed")
+    ap.add_argument("--searches", type=int, default=2, help="one-at-a-time GPU searches timed")
+    ap.add_argument("--batched", type=int, default=64, help="searches in the batched (one-launch) leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-search", action="store_true")
     ap.add_argument("--hvp-only", action="store_true", help="only the HVP leg (for profilers)")
@@ -201,29 +202,80 @@ def main():
         extra["min_modes_128_k4_status"] = M.STATUS_NAMES[r.status]
         extra["min_modes_workspace_bytes"] = ws.nbytes
         extra["dense_hessian_bytes_avoided"] = (2 * N) ** 2 * 8
+        # block width: guard vectors beyond k trade per-iteration work for iterations
+        sweep = {}
+        for guard in (2, 4, 8):
+            wsg = M.EigWorkspace(plan, M.MOTO_F32, 4, guard)
+            og = M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=400, guard=guard)
+            M.moto_min_modes(plan, m1, 4, M.MOTO_F32, opts=og, ws=wsg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rg = M.moto_min_modes(plan, m1, 4, M.MOTO_F32, opts=og, ws=wsg)
+            torch.cuda.synchronize()
+            sweep[f"guard{guard}"] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "iters": rg.iters,
+                                      "status": M.STATUS_NAMES[rg.status]}
+        extra["min_modes_128_k4_guard_sweep"] = sweep
+        # differentiation form on 64x64 (energy, backward, double backward), FP32 spins
+        from paper_2509_26269_amd import autograd as AG
 
-    if not args.hvp_only and not args.no_search and args.searches > 0:
-        print(f"[bench] {args.searches} saddle searches on {L}x{L} one at a time", file=sys.stderr, flush=True)
-        so = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, k_cert=2, max_outer=3000,
+        p64 = S.ham_3shell(64)
+        m64 = torch.as_tensor(S.random_texture(4096, np.random.default_rng(64)), dtype=torch.float32,
+                              device="cuda").requires_grad_(True)
+        th = AG.theta_of(p64).requires_grad_(True)
+        u = torch.randn(3, 4096, device="cuda", generator=torch.Generator(device="cuda").manual_seed(65))
+        ad = {}
+        for name in ("forward", "backward", "double_backward"):
+            ts = []
+            for rep in range(6):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                E = AG.energy(m64, th, 64, 64)
+                if name != "forward":
+                    g, = torch.autograd.grad(E, m64, create_graph=(name == "double_backward"))
+                    if name == "double_backward":
+                        torch.autograd.grad((g * u).sum(), (m64, th))
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            ad[name + "_ms"] = round(1e3 * float(np.median(ts[1:])), 3)
+        extra["autograd_64x64_f32"] = ad
+
+    if not args.hvp_only and not args.no_search:
+        so = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, k_cert=2, max_outer=2000,
                            eig={"tol": 1e-5, "max_iter": 200})
-        kinds = ["skyrmion", "antiskyrmion", "biskyrmion"]
-        rng = np.random.default_rng(128)
-        stats = {}
-        t0 = time.perf_counter()
-        n_iter = 0
-        for i in range(args.searches):
-            m0 = S.three_shell_start(L, seed=int(rng.integers(1 << 30)), kind=kinds[i % 3],
-                                     R=float(rng.uniform(1.0, 3.0)))
-            md = torch.as_tensor(m0, device="cuda")
-            res, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, opts=so)
-            stats[M.STATUS_NAMES[res.status]] = stats.get(M.STATUS_NAMES[res.status], 0) + 1
-            n_iter += res.iters
-            print(f"[bench]   search {i}: {M.STATUS_NAMES[res.status]} iters={res.iters}", file=sys.stderr,
+        spec = S.fixed_size_spec(max(args.batched, args.searches), L, seed=128)
+        if args.batched > 0:
+            print(f"[bench] {args.batched} saddle searches on {L}x{L} in one persistent launch", file=sys.stderr,
                   flush=True)
-        el = time.perf_counter() - t0
-        extra["searches_per_s_one_at_a_time"] = round(args.searches / el, 4)
-        extra["search_status"] = stats
-        extra["search_mean_outer_iters"] = round(n_iter / args.searches, 1)
+            starts = [S.batch_member(spec, i) for i in range(args.batched)]
+            mall = torch.as_tensor(np.concatenate([x.reshape(-1) for x in starts]), device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = M.moto_saddle_search_batched(p, [L] * args.batched, mall, so)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            hist = {}
+            for r in res:
+                hist[M.STATUS_NAMES[r.status]] = hist.get(M.STATUS_NAMES[r.status], 0) + 1
+            extra["searches_per_s_batched"] = round(args.batched / el, 4)
+            extra["batched_search_status"] = hist
+            extra["batched_wall_s"] = round(el, 3)
+            extra["batched_mean_outer_iters"] = round(float(np.mean([r.iters for r in res])), 1)
+        if args.searches > 0:
+            print(f"[bench] {args.searches} saddle searches on {L}x{L} one at a time", file=sys.stderr, flush=True)
+            stats = {}
+            t0 = time.perf_counter()
+            n_iter = 0
+            for i in range(args.searches):
+                md = torch.as_tensor(S.batch_member(spec, i), device="cuda")
+                res1, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, opts=so)
+                stats[M.STATUS_NAMES[res1.status]] = stats.get(M.STATUS_NAMES[res1.status], 0) + 1
+                n_iter += res1.iters
+                print(f"[bench]   search {i}: {M.STATUS_NAMES[res1.status]} iters={res1.iters}", file=sys.stderr,
+                      flush=True)
+            el = time.perf_counter() - t0
+            extra["searches_per_s_one_at_a_time"] = round(args.searches / el, 4)
+            extra["one_at_a_time_search_status"] = stats
+            extra["one_at_a_time_mean_outer_iters"] = round(n_iter / args.searches, 1)
 
     if not args.hvp_only and not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

@@ -209,6 +209,8 @@ typedef struct {
     int32_t warm;        /* 0 random start, 1 V holds k start vectors, 2 reuse block */
     int32_t check_every; /* iterations between host convergence checks (default 8) */
     uint64_t seed;       /* start-block seed (SplitMix64 counter generator) */
+    int32_t use_graph;   /* 1: replay the iteration chunk as a captured HIP graph (default) */
+    int32_t reserved;
 } moto_eig_opts;
 
 typedef struct {

@@ -28,6 +28,19 @@ struct moto_plan_s {
         int dt, batch, nvec, variant;
     } tune[32];
     int n_tune;
+    // instantiated HIP graphs of the eigen-solver's iteration chunk, keyed by
+    // everything baked into the captured kernel arguments
+    struct GraphEntry {
+        hipGraphExec_t exec;
+        const void* ws;
+        const void* mask;
+        long long key[8];
+        int valid;
+    } graphs[4];
+    int next_graph;
+    // private stream the graphs are captured on (capture is not possible on
+    // the legacy default stream a caller may pass); replays use the caller's
+    hipStream_t cap_stream;
 };
 
 namespace {
@@ -153,6 +166,9 @@ moto_status moto_plan_create(const moto_hamiltonian* h, moto_plan* out) {
               std::sqrt(h->B[0] * h->B[0] + h->B[1] * h->B[1] + h->B[2] * h->B[2]);
     p->pinned = nullptr;
     p->n_tune = 0;
+    p->next_graph = 0;
+    p->cap_stream = nullptr;
+    for (auto& ge : p->graphs) ge.valid = 0;
     if (hipHostMalloc((void**)&p->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
         delete p;
         return MOTO_EHIP;
@@ -163,6 +179,9 @@ moto_status moto_plan_create(const moto_hamiltonian* h, moto_plan* out) {
 
 moto_status moto_plan_destroy(moto_plan p) {
     if (!p) return MOTO_EINVAL;
+    for (auto& ge : p->graphs)
+        if (ge.valid) (void)hipGraphExecDestroy(ge.exec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     if (p->pinned) (void)hipHostFree(p->pinned);
     delete p;
     return MOTO_OK;
@@ -204,7 +223,7 @@ moto_status moto_tangent_hvp(moto_plan p, moto_dtype dt, moto_layout layout, int
 int32_t moto_tangent_hvp_variants(void) { return HVP_NVARIANTS; }
 
 moto_status moto_plan_set_hvp_variant(moto_plan p, moto_dtype dt, int32_t batch, int32_t n_vec, int32_t variant) {
-    if (!p || !hvp_ok(dt) || batch < 1 || n_vec < 1 || !hvp_variant_ok(variant, dt == MOTO_F64)) return MOTO_EINVAL;
+    if (!p || !hvp_ok(dt) || batch < 1 || n_vec < 1 || !hvp_variant_ok(variant, p->g, dt == MOTO_F64)) return MOTO_EINVAL;
     int slot = -1;
     for (int i = 0; i < p->n_tune; ++i)
         if (p->tune[i].dt == (int)dt && p->tune[i].batch == batch && p->tune[i].nvec == n_vec) slot = i;
@@ -229,7 +248,7 @@ moto_status moto_tangent_hvp_autotune(moto_plan p, moto_dtype dt, int32_t batch,
     float best_t = 0.0f;
     for (int v = 0; v < HVP_NVARIANTS; ++v) {
         if (times_ms) times_ms[v] = -1.0f;
-        if (!hvp_variant_ok(v, f64)) continue;
+        if (!hvp_variant_ok(v, p->g, f64)) continue;
         HIP_TRY(launch_hvp_frame(v, p->g, p->k, f64, batch, m, c, mask, n_vec, V, W, nullptr, st));  // warm-up
         HIP_TRY(hipEventRecord(e0, st));
         for (int r = 0; r < reps; ++r)
@@ -302,12 +321,53 @@ void moto_default_eig_opts(moto_dtype hvp, moto_eig_opts* o) {
     o->warm = 0;
     o->check_every = 8;
     o->seed = 0x2509262690ull;
+    o->use_graph = 1;
 }
 
 size_t moto_min_modes_workspace(moto_plan p, moto_dtype hvp, int32_t k, int32_t guard) {
     if (!p || k < 1 || !hvp_ok(hvp)) return 0;
     return eig_layout(p, hvp, k, resolve_guard(k, guard)).total;
 }
+
+// Capture one chunk of launches into an instantiated graph stored in the
+// plan's cache (round robin over four slots).  Returns nullptr, with the
+// runtime's sticky error cleared, when capture or instantiation fails.
+extern "C++" {
+template <class F>
+static hipGraphExec_t capture_chunk(moto_plan p, F& launches, const long long* key, const void* ws,
+                                    const void* mask) {
+    if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        p->cap_stream = nullptr;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    const hipError_t ce = launches(p->cap_stream);
+    const hipError_t ee = hipStreamEndCapture(p->cap_stream, &graph);
+    hipGraphExec_t exec = nullptr;
+    if (ce == hipSuccess && ee == hipSuccess && graph &&
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        exec = nullptr;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!exec) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    auto& slot = p->graphs[p->next_graph];
+    p->next_graph = (p->next_graph + 1) % 4;
+    if (slot.valid) (void)hipGraphExecDestroy(slot.exec);
+    slot.exec = exec;
+    slot.ws = ws;
+    slot.mask = mask;
+    std::memcpy(slot.key, key, sizeof(slot.key));
+    slot.valid = 1;
+    return exec;
+}
+}  // extern "C++"
 
 static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, const uint8_t* mask, int k,
                                   const moto_eig_opts* o, double* evals, double* V, double* resid, moto_info* info,
@@ -361,20 +421,52 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
     HIP_TRY(launch_eig_control(a, part, L.nblk_u, ctrl, 1, st));
     const int every = o->check_every > 0 ? o->check_every : 8;
     const int max_chunks = o->max_iter / every + 2;
+    auto chunk_launches = [&](hipStream_t s) -> hipError_t {
+        for (int it = 0; it < every; ++it) {
+            for (int pass = 0; pass < 2; ++pass) {
+                hipError_t e = launch_orth(f64, a, 1, S, part, L.nblk_g, G, ctrl, s);
+                if (e != hipSuccess) return e;
+            }
+            hipError_t e = launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, Wslot, HWslot,
+                                              &ctrl->done, s, hv_var);
+            if (e == hipSuccess) e = launch_gram(f64, a, -1, S, HS, part, L.nblk_g, G, ctrl, s);
+            if (e == hipSuccess) e = launch_rr(a, -1, G, ctrl, s);
+            if (e == hipSuccess) e = launch_update(f64, a, -1, S, HS, part, L.nblk_u, ctrl, s);
+            if (e == hipSuccess) e = launch_eig_control(a, part, L.nblk_u, ctrl, 0, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    // one iteration chunk as a HIP graph, captured once per key on the plan's
+    // private stream and replayed on the caller's; any capture failure falls
+    // back to plain launches
+    hipGraphExec_t gexec = nullptr;
+    if (o->use_graph) {
+        long long key[8];
+        double tolbits = a.tol_abs;
+        std::memcpy(&key[0], &tolbits, sizeof(double));
+        key[1] = (long long)hvp;
+        key[2] = L.mb;
+        key[3] = k;
+        key[4] = every;
+        key[5] = o->max_iter;
+        key[6] = hv_var;
+        key[7] = N;
+        for (auto& ge : p->graphs)
+            if (ge.valid && ge.ws == (const void*)ws && ge.mask == (const void*)mask &&
+                std::memcmp(ge.key, key, sizeof(key)) == 0)
+                gexec = ge.exec;
+        if (!gexec) gexec = capture_chunk(p, chunk_launches, key, ws, mask);
+    }
     int hdr[4];
     for (int chunk = 0; chunk < max_chunks; ++chunk) {
         moto_status rs = readback(p, ctrl, sizeof(hdr), hdr, st);
         if (rs != MOTO_OK) return rs;
         if (hdr[0]) break;
-        for (int it = 0; it < every; ++it) {
-            for (int pass = 0; pass < 2; ++pass) HIP_TRY(launch_orth(f64, a, 1, S, part, L.nblk_g, G, ctrl, st));
-            HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, Wslot, HWslot, &ctrl->done,
-                                       st, hv_var));
-            HIP_TRY(launch_gram(f64, a, -1, S, HS, part, L.nblk_g, G, ctrl, st));
-            HIP_TRY(launch_rr(a, -1, G, ctrl, st));
-            HIP_TRY(launch_update(f64, a, -1, S, HS, part, L.nblk_u, ctrl, st));
-            HIP_TRY(launch_eig_control(a, part, L.nblk_u, ctrl, 0, st));
-        }
+        if (gexec)
+            HIP_TRY(hipGraphLaunch(gexec, st));
+        else
+            HIP_TRY(chunk_launches(st));
     }
     HIP_TRY(launch_eig_output(f64, a, S, m, N, V, part, ctrl, evals, resid, ws + L.Xsave, st));
     EigCtrl hc;

@@ -12,12 +12,18 @@
 //                  to 128 wide, so the periodic x-halo stays in the same cache
 //                  lines); NVP vectors staged per pass with one frame build per
 //                  site; each thread owns one column and 4 rows and sweeps the
-//                  input rows once (register sliding window).
+//                  input rows once (register sliding window);
+//   march<NVP>:    one workgroup per full-width strip of rows, marching down
+//                  the strip one input row at a time with the accumulators of
+//                  five output rows in registers (each input element is read
+//                  and converted once; see the kernel).
 // All but the first order the blocks so that consecutive tiles of a lattice
 // run on the same XCD: workgroups are dealt round-robin to the 8 XCDs, each
 // with its own L2, and halo rows re-read by the next tile then hit that L2
 // instead of HBM.  The autotuner in the host API times the variants on the
 // caller's shape and keeps the fastest.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace moto {
@@ -271,21 +277,259 @@ __global__ __launch_bounds__(NT) void k_hvp_band(Geo g, Coef<T> k, const T* __re
     }
 }
 
+
+// --------------------------------------------------------------------------
+// march<NVP, XW>
+// --------------------------------------------------------------------------
+// One workgroup of XW threads owns a strip of rows [y0, y1) of one lattice
+// (full width, Lx <= XW, thread x = column x) and a group of NVP vectors, and
+// marches down the strip one input row R at a time, R = y0-2 .. y1+1:
+//   * the thread of column x turns its raw row data (spin, c, mask, frame
+//     coordinates) into ambient vectors u = a e1 + b e2 and publishes them in
+//     a double-buffered LDS row (with the periodic x-halo duplicated);
+//   * every offset (dx, dy) of the stencil sends row R's value at x + dx into
+//     the accumulator of output row R - dy at column x.  The accumulators of
+//     the five rows R-2 .. R+2 live in registers (a ring rotated at compile
+//     time by unrolling the march five times), so only the four x-neighbours
+//     are read from LDS and each input element is converted exactly once;
+//   * row R - 2 is then complete and is projected onto its frame and stored.
+// The centre term -c u and the anisotropy enter the accumulator of row R
+// when R is converted; the frames of the last three rows are kept in a
+// per-thread LDS ring.  Strip halos cost 4 extra input rows per strip.
+template <int DX, int DY>
+__device__ constexpr int m_shell() {
+    return (DX * DX + DX * DY + DY * DY) == 1 ? 0 : (DX * DX + DX * DY + DY * DY) == 3 ? 1 : 2;
+}
+
+// acc (+)= M(dx, dy) u for one stencil offset: exchange of the offset's shell
+// plus, on the first shell, the interfacial DMI term cD [dhat u_z - z (dhat . u)]
+// with dhat = (dx + dy/2, sqrt(3)/2 dy) (lattice coordinates -> Cartesian).
+template <int DX, int DY, bool ASSIGN, class T>
+__device__ __forceinline__ void m_offset(T (&a)[3], const T (&u)[3], const T (&cJ)[3], T cD, T cDh, T cDr) {
+    constexpr int sh = m_shell<DX, DY>();
+    const T cj = cJ[sh];
+    if (ASSIGN) {
+        a[0] = cj * u[0];
+        a[1] = cj * u[1];
+        a[2] = cj * u[2];
+    } else {
+        a[0] += cj * u[0];
+        a[1] += cj * u[1];
+        a[2] += cj * u[2];
+    }
+    if constexpr (sh == 0) {
+        constexpr int px = 2 * DX + DY;  // 2 dhat_x in units of 1/2
+        const T dx = px == 2 ? cD : px == -2 ? -cD : px == 1 ? cDh : -cDh;
+        a[0] += dx * u[2];
+        a[2] -= dx * u[0];
+        if constexpr (DY != 0) {
+            const T dy = DY > 0 ? cDr : -cDr;
+            a[1] += dy * u[2];
+            a[2] -= dy * u[1];
+        }
+    }
+}
+
+template <class T, int NVP, int XW>
+__global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __restrict__ m,
+                                                  const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec,
+                                                  const T* __restrict__ V, T* __restrict__ W,
+                                                  const int* __restrict__ done, int nstrip, int ngroups) {
+    if (done != nullptr && *done) return;
+    constexpr int RS = XW + 4;  // halo 2 | XW columns | halo 2
+    __shared__ T rb[2][3 * NVP][RS];
+    __shared__ T cen[3][7][XW];
+    const int lid = xcd_order(true);
+    const int grp = lid % ngroups;
+    const int rest = lid / ngroups;
+    const int strip = rest % nstrip;
+    const int b = rest / nstrip;
+    const int SH = (g.Ly + nstrip - 1) / nstrip;
+    const int y0 = strip * SH;
+    const int y1 = min(g.Ly, y0 + SH);
+    if (y0 >= y1) return;
+    const int j0 = grp * NVP;
+    const int nv = min(NVP, nvec - j0);
+    const int x = threadIdx.x;
+    const bool lane = x < g.Lx;
+    // second LDS slot of this column in the periodic x-halo (needs Lx >= 4)
+    const int sec = !lane ? -1 : x >= g.Lx - 2 ? x - g.Lx + 2 : x < 2 ? x + g.Lx + 2 : -1;
+    const size_t N = g.N;
+    const T* mb = m + (size_t)b * 3 * N;
+    const T* cb = c + (size_t)b * N;
+    const uint8_t* mk = mask ? mask + (size_t)b * N : nullptr;
+    const T* Vb = V + ((size_t)b * nvec + j0) * 2 * N;
+    T* Wb = W + ((size_t)b * nvec + j0) * 2 * N;
+    const T cJ[3] = {k.cJ[0], k.cJ[1], k.cJ[2]};
+    const T cD = k.cD, cDh = T(0.5) * k.cD, cDr = T(0.86602540378443864676) * k.cD, cK = k.cK;
+
+    // raw data of the next input row (prefetched one step ahead)
+    T rm0 = 0, rm1 = 0, rm2 = 1, rc = 0, ra[NVP], rv[NVP];
+    bool ract = false;
+    int yin = wrapi(y0 - 2, g.Ly);
+    auto load_raw = [&](int yy) {
+        if (lane) {
+            const int s = x + g.Lx * yy;
+            rm0 = mb[s];
+            rm1 = mb[N + s];
+            rm2 = mb[2 * N + s];
+            rc = cb[s];
+            ract = mk == nullptr || mk[s] != 0;
+#pragma unroll
+            for (int j = 0; j < NVP; ++j) {
+                ra[j] = j < nv ? Vb[j * 2 * N + s] : T(0);
+                rv[j] = j < nv ? Vb[j * 2 * N + N + s] : T(0);
+            }
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < NVP; ++j) ra[j] = rv[j] = T(0);
+    load_raw(yin);
+
+    T acc[5][NVP][3];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int j = 0; j < NVP; ++j) acc[q][j][0] = acc[q][j][1] = acc[q][j][2] = T(0);
+
+    const int nsteps = y1 - y0 + 4;
+    int cw = 0;  // centre-ring slot of the row being converted
+
+    auto step = [&](auto qc, int R, int it) {
+        constexpr int q = decltype(qc)::value;
+        // ring slot of the accumulator of row R + d
+#define SL(d) ((q + (d) + 10) % 5)
+        const int buf = it & 1;
+        // 1. convert row R
+        T e1[3], e2[3];
+        onb(rm0, rm1, rm2, e1, e2);
+        const bool act = lane && ract;
+        const T nc = -rc;
+        T u[NVP][3];
+#pragma unroll
+        for (int j = 0; j < NVP; ++j) {
+            const T a = act ? ra[j] : T(0), bb = act ? rv[j] : T(0);
+            u[j][0] = a * e1[0] + bb * e2[0];
+            u[j][1] = a * e1[1] + bb * e2[1];
+            u[j][2] = a * e1[2] + bb * e2[2];
+            if (lane) {
+                rb[buf][3 * j + 0][x + 2] = u[j][0];
+                rb[buf][3 * j + 1][x + 2] = u[j][1];
+                rb[buf][3 * j + 2][x + 2] = u[j][2];
+            }
+            if (sec >= 0) {
+                rb[buf][3 * j + 0][sec] = u[j][0];
+                rb[buf][3 * j + 1][sec] = u[j][1];
+                rb[buf][3 * j + 2][sec] = u[j][2];
+            }
+        }
+        if (R >= y0 && R < y1) {
+            cen[cw][0][x] = e1[0];
+            cen[cw][1][x] = e1[1];
+            cen[cw][2][x] = e1[2];
+            cen[cw][3][x] = e2[0];
+            cen[cw][4][x] = e2[1];
+            cen[cw][5][x] = e2[2];
+            cen[cw][6][x] = act ? T(1) : T(0);
+        }
+        // own-column offsets (dx = 0) and the centre term
+#pragma unroll
+        for (int j = 0; j < NVP; ++j) {
+            m_offset<0, -2, true>(acc[SL(2)][j], u[j], cJ, cD, cDh, cDr);
+            m_offset<0, -1, false>(acc[SL(1)][j], u[j], cJ, cD, cDh, cDr);
+            m_offset<0, 1, false>(acc[SL(-1)][j], u[j], cJ, cD, cDh, cDr);
+            m_offset<0, 2, false>(acc[SL(-2)][j], u[j], cJ, cD, cDh, cDr);
+            acc[SL(0)][j][0] += nc * u[j][0];
+            acc[SL(0)][j][1] += nc * u[j][1];
+            acc[SL(0)][j][2] += nc * u[j][2] + cK * u[j][2];
+        }
+        // 2. prefetch row R + 1
+        if (it + 1 < nsteps) {
+            yin = yin + 1 == g.Ly ? 0 : yin + 1;
+            load_raw(yin);
+        }
+        __syncthreads();
+        // 3. x-neighbours of row R from LDS
+#pragma unroll
+        for (int j = 0; j < NVP; ++j) {
+            T um2[3], um1[3], up1[3], up2[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                um2[cc] = rb[buf][3 * j + cc][x];
+                um1[cc] = rb[buf][3 * j + cc][x + 1];
+                up1[cc] = rb[buf][3 * j + cc][x + 3];
+                up2[cc] = rb[buf][3 * j + cc][x + 4];
+            }
+            // output row R - dy receives offset (dx, dy)
+            m_offset<1, -2, false>(acc[SL(2)][j], up1, cJ, cD, cDh, cDr);
+            m_offset<2, -2, false>(acc[SL(2)][j], up2, cJ, cD, cDh, cDr);
+            m_offset<1, -1, false>(acc[SL(1)][j], up1, cJ, cD, cDh, cDr);
+            m_offset<2, -1, false>(acc[SL(1)][j], up2, cJ, cD, cDh, cDr);
+            m_offset<-1, -1, false>(acc[SL(1)][j], um1, cJ, cD, cDh, cDr);
+            m_offset<1, 0, false>(acc[SL(0)][j], up1, cJ, cD, cDh, cDr);
+            m_offset<-1, 0, false>(acc[SL(0)][j], um1, cJ, cD, cDh, cDr);
+            m_offset<2, 0, false>(acc[SL(0)][j], up2, cJ, cD, cDh, cDr);
+            m_offset<-2, 0, false>(acc[SL(0)][j], um2, cJ, cD, cDh, cDr);
+            m_offset<1, 1, false>(acc[SL(-1)][j], up1, cJ, cD, cDh, cDr);
+            m_offset<-1, 1, false>(acc[SL(-1)][j], um1, cJ, cD, cDh, cDr);
+            m_offset<-2, 1, false>(acc[SL(-1)][j], um2, cJ, cD, cDh, cDr);
+            m_offset<-1, 2, false>(acc[SL(-2)][j], um1, cJ, cD, cDh, cDr);
+            m_offset<-2, 2, false>(acc[SL(-2)][j], um2, cJ, cD, cDh, cDr);
+        }
+        // 4. row R - 2 is complete
+        const int yo = R - 2;
+        const int cr = cw == 2 ? 0 : cw + 1;  // slot of row R - 2
+        if (lane && yo >= y0 && yo < y1) {
+            const T f10 = cen[cr][0][x], f11 = cen[cr][1][x], f12 = cen[cr][2][x];
+            const T f20 = cen[cr][3][x], f21 = cen[cr][4][x], f22 = cen[cr][5][x];
+            const bool on = cen[cr][6][x] != T(0);
+            const int so = x + g.Lx * yo;
+#pragma unroll
+            for (int j = 0; j < NVP; ++j) {
+                const T wa = f10 * acc[SL(-2)][j][0] + f11 * acc[SL(-2)][j][1] + f12 * acc[SL(-2)][j][2];
+                const T wb = f20 * acc[SL(-2)][j][0] + f21 * acc[SL(-2)][j][1] + f22 * acc[SL(-2)][j][2];
+                if (j < nv) {
+                    Wb[j * 2 * N + so] = on ? wa : T(0);
+                    Wb[j * 2 * N + N + so] = on ? wb : T(0);
+                }
+            }
+        }
+        cw = cw == 2 ? 0 : cw + 1;
+#undef SL
+    };
+
+    for (int it = 0; it < nsteps; it += 5) {
+        const int R = y0 - 2 + it;
+        step(std::integral_constant<int, 0>{}, R, it);
+        if (it + 1 < nsteps) step(std::integral_constant<int, 1>{}, R + 1, it + 1);
+        if (it + 2 < nsteps) step(std::integral_constant<int, 2>{}, R + 2, it + 2);
+        if (it + 3 < nsteps) step(std::integral_constant<int, 3>{}, R + 3, it + 3);
+        if (it + 4 < nsteps) step(std::integral_constant<int, 4>{}, R + 4, it + 4);
+    }
+}
+
 // --------------------------------------------------------------------------
 // variant table
 // --------------------------------------------------------------------------
-static const char* kNames[HVP_NVARIANTS] = {"tiled32x8", "tiled32x8+xcd", "tiled64x4+xcd", "tiled128x2+xcd",
-                                            "band128x8/4vec+xcd", "band128x8/2vec+xcd", "band128x8/1vec+xcd"};
+static const char* kNames[HVP_NVARIANTS] = {"tiled32x8",          "tiled32x8+xcd",      "tiled64x4+xcd",
+                                            "tiled128x2+xcd",     "band128x8/4vec+xcd", "band128x8/2vec+xcd",
+                                            "band128x8/1vec+xcd", "march/4vec",         "march/2vec",
+                                            "march/1vec"};
 
 const char* hvp_variant_name(int v) { return (v >= 0 && v < HVP_NVARIANTS) ? kNames[v] : "?"; }
 
-bool hvp_variant_ok(int v, bool f64) { return v >= 0 && v < HVP_NVARIANTS && !(f64 && v == 4); }
+// the row march needs the whole row in one workgroup and a two-column halo
+// that does not overlap itself
+static bool march_fits(const Geo& g) { return g.Lx >= 4 && g.Lx <= 256; }
 
-int hvp_default_variant(const Geo& g, bool f64) {
-    (void)g;
-    (void)f64;
-    return 2;
+bool hvp_variant_ok(int v, const Geo& g, bool f64) {
+    if (v < 0 || v >= HVP_NVARIANTS) return false;
+    if (f64 && (v == 4 || v == 7)) return false;
+    if (v >= 7 && !march_fits(g)) return false;
+    return true;
 }
+
+int hvp_default_variant(const Geo& g, bool f64) { return march_fits(g) ? (f64 ? 8 : 7) : 2; }
 
 template <class T, int TXT, int TYT, bool REMAP>
 static void go_tiled(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
@@ -303,6 +547,35 @@ static void go_band(const Geo& g, const CoefD& kd, int batch, const void* m, con
                        (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, tx, ty);
 }
 
+// strips per lattice: enough workgroups to fill the chip, strips of at
+// least 8 rows (the 4 halo rows of a strip are re-read)
+static int march_strips(const Geo& g, int batch, int ngroups) {
+    const long long have = (long long)batch * ngroups;
+    const int want = (int)((2048 + have - 1) / have);
+    return max(1, min(want, max(1, g.Ly / 8)));
+}
+
+template <class T, int NVP, int XW>
+static void go_march_xw(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c,
+                        const uint8_t* mask, int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+    const int ngroups = (nvec + NVP - 1) / NVP;
+    const int nstrip = march_strips(g, batch, ngroups);
+    hipLaunchKernelGGL((k_hvp_march<T, NVP, XW>), dim3(batch * nstrip * ngroups), dim3(XW), 0, st, g,
+                       coef_cast<T>(kd), (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, nstrip,
+                       ngroups);
+}
+
+template <class T, int NVP>
+static void go_march(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
+                     int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+    if (g.Lx <= 64)
+        go_march_xw<T, NVP, 64>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+    else if (g.Lx <= 128)
+        go_march_xw<T, NVP, 128>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+    else
+        go_march_xw<T, NVP, 256>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+}
+
 template <class T>
 static void go(int v, const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
                int nvec, const void* V, void* W, const int* done, hipStream_t st) {
@@ -315,6 +588,11 @@ static void go(int v, const Geo& g, const CoefD& kd, int batch, const void* m, c
             break;
         case 5: go_band<T, 2>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
         case 6: go_band<T, 1>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 7:
+            if constexpr (sizeof(T) == 4) go_march<T, 4>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+            break;
+        case 8: go_march<T, 2>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 9: go_march<T, 1>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
         default: go_tiled<T, 64, 4, true>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
     }
 }
@@ -322,7 +600,7 @@ static void go(int v, const Geo& g, const CoefD& kd, int batch, const void* m, c
 hipError_t launch_hvp_frame(int variant, const Geo& g, const CoefD& kd, bool f64, int batch, const void* m,
                             const void* c, const uint8_t* mask, int nvec, const void* V, void* W, const int* done,
                             hipStream_t st) {
-    const int v = hvp_variant_ok(variant, f64) ? variant : hvp_default_variant(g, f64);
+    const int v = hvp_variant_ok(variant, g, f64) ? variant : hvp_default_variant(g, f64);
     if (f64)
         go<double>(v, g, kd, batch, m, c, mask, nvec, V, W, done, st);
     else

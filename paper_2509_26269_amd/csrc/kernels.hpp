@@ -46,8 +46,8 @@ hipError_t launch_tangent_hvp(const Geo& g, const CoefD& k, bool f64, bool frame
                               const int* done, hipStream_t st, int variant = -1);
 
 // ---- hvp.hip: frame-layout tangent HVP variants (tile shapes / staging) ----
-constexpr int HVP_NVARIANTS = 7;
-bool hvp_variant_ok(int variant, bool f64);
+constexpr int HVP_NVARIANTS = 10;
+bool hvp_variant_ok(int variant, const Geo& g, bool f64);
 int hvp_default_variant(const Geo& g, bool f64);
 const char* hvp_variant_name(int variant);
 hipError_t launch_hvp_frame(int variant, const Geo& g, const CoefD& k, bool f64, int batch, const void* m,

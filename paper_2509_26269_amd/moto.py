@@ -39,7 +39,8 @@ class _Ham(ctypes.Structure):
 
 class EigOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("guard", ctypes.c_int32),
-                ("warm", ctypes.c_int32), ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("warm", ctypes.c_int32), ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

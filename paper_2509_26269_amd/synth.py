@@ -247,6 +247,13 @@ def ragged_batch_spec(n: int = 256, seed: int = 26269, Lmin: int = 32, Lmax: int
     return BatchSpec(L, kinds, R, st, ang, seeds)
 
 
+def fixed_size_spec(n: int, L: int, seed: int = 128) -> BatchSpec:
+    """Same start rules as ragged_batch_spec on n lattices of one size L."""
+    spec = ragged_batch_spec(n, seed, L, L)
+    spec.L = [L] * n
+    return spec
+
+
 def batch_member(spec: BatchSpec, i: int, sigma: float = 0.05) -> np.ndarray:
     L = spec.L[i]
     kind = spec.kinds[i]

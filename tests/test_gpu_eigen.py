@@ -160,3 +160,23 @@ def test_min_modes_fp32_random_start_at_index1_saddle(seed):
     r = M.moto_min_modes(plan, _dev(ro.m), 2, M.MOTO_F32, opts=M.eig_opts(M.MOTO_F32, tol=1e-6, seed=seed))
     assert r.status == M.CONVERGED, (r.status, r.iters, _np(r.evals))
     assert np.allclose(_np(r.evals), ro.evals, atol=1e-5 * h.h_est())
+
+
+def test_graph_replays_match_eager_bitwise():
+    """The captured iteration chunk, replayed across calls with eager work
+    and synchronisation in between, gives bit-identical results to eager
+    launches (all reductions are fixed-order)."""
+    M = _M()
+    L = 32
+    p = S.ham_3shell(L)
+    plan = M.Plan.from_params(p)
+    m = _dev(S.three_shell_start(L, seed=4, kind="skyrmion"))
+    ws = M.EigWorkspace(plan, M.MOTO_F32, 2)
+    ref = M.moto_min_modes(plan, m, 2, M.MOTO_F32, opts=M.eig_opts(M.MOTO_F32, use_graph=0, check_every=4), ws=ws)
+    for rep in range(3):
+        _ = M.moto_energy_grad(plan, m)  # eager work between replays
+        torch.cuda.synchronize()
+        r = M.moto_min_modes(plan, m, 2, M.MOTO_F32, opts=M.eig_opts(M.MOTO_F32, use_graph=1, check_every=4),
+                             ws=ws)
+        assert r.iters == ref.iters and r.status == ref.status
+        assert torch.equal(r.evals, ref.evals) and torch.equal(r.V, ref.V)
