@@ -7,7 +7,9 @@ Headline (the 128x128 three-shell workload, FP32 HVP):
     kernel streams from HBM); one step = one batched HVP launch;
   * the roofline of that kernel (algorithmic bytes 12 + 16 n_vec per site);
   * wall time of the k = 4 eigen-solve (residual 1e-5) on one 128x128 state;
-  * saddle searches/s on 128x128 lattices (k = 2, FP32 HVP, tau_F = 1e-5);
+  * saddle searches/s (k = 2, FP32 HVP, tau_F = 1e-5, capped outer
+    iterations): 64 searches on 128x128 in one persistent launch, 256 on
+    uneven 32..96 lattices in one launch, and searches one at a time;
   * the FP64 CPU oracle timed on a bounded sample of the same HVP workload.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
@@ -98,7 +100,9 @@ def main():
     ap.add_argument("--nvec", type=int, default=4)
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--searches", type=int, default=2, help="one-at-a-time GPU searches timed")
-    ap.add_argument("--batched", type=int, default=64, help="searches in the batched (one-launch) leg")
+    ap.add_argument("--batched", type=int, default=64, help="searches on 128x128 in the batched (one-launch) leg")
+    ap.add_argument("--ragged", type=int, default=256, help="searches on uneven 32..96 lattices, one launch")
+    ap.add_argument("--max-outer", type=int, default=300, help="outer-iteration cap of every search leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-search", action="store_true")
     ap.add_argument("--hvp-only", action="store_true", help="only the HVP leg (for profilers)")
@@ -240,42 +244,61 @@ def main():
         extra["autograd_64x64_f32"] = ad
 
     if not args.hvp_only and not args.no_search:
-        so = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, k_cert=2, max_outer=2000,
+        so = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, k_cert=2, max_outer=args.max_outer,
                            eig={"tol": 1e-5, "max_iter": 200})
-        spec = S.fixed_size_spec(max(args.batched, args.searches), L, seed=128)
-        if args.batched > 0:
-            print(f"[bench] {args.batched} saddle searches on {L}x{L} in one persistent launch", file=sys.stderr,
-                  flush=True)
-            starts = [S.batch_member(spec, i) for i in range(args.batched)]
+        extra["search_opts"] = {"tau_F": 1e-5, "k": 2, "k_cert": 2, "max_outer": args.max_outer,
+                                "eig_tol_rel": 1e-5, "eig_max_iter": 200, "hvp": "f32", "rule": "lbfgs(8)"}
+
+        def batched_leg(name, Ls, starts, hp):
             mall = torch.as_tensor(np.concatenate([x.reshape(-1) for x in starts]), device="cuda")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            res = M.moto_saddle_search_batched(p, [L] * args.batched, mall, so)
+            res = M.moto_saddle_search_batched(hp, list(Ls), mall, so)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             hist = {}
             for r in res:
                 hist[M.STATUS_NAMES[r.status]] = hist.get(M.STATUS_NAMES[r.status], 0) + 1
-            extra["searches_per_s_batched"] = round(args.batched / el, 4)
-            extra["batched_search_status"] = hist
-            extra["batched_wall_s"] = round(el, 3)
-            extra["batched_mean_outer_iters"] = round(float(np.mean([r.iters for r in res])), 1)
+            its = int(sum(r.iters for r in res))
+            extra[name] = {"searches": len(Ls), "wall_s": round(el, 3),
+                           "searches_per_s": round(len(Ls) / el, 4),
+                           "outer_iters_per_s": round(its / el, 1),
+                           "mean_outer_iters": round(its / len(Ls), 1),
+                           "hvp_columns_per_outer": round(sum(r.n_hvp for r in res) / max(its, 1), 1),
+                           "status": hist}
+
+        spec = S.fixed_size_spec(max(args.batched, args.searches), L, seed=128)
+        if args.batched > 0:
+            print(f"[bench] {args.batched} saddle searches on {L}x{L} in one persistent launch", file=sys.stderr,
+                  flush=True)
+            batched_leg("batched_128", [L] * args.batched, [S.batch_member(spec, i) for i in range(args.batched)], p)
+        if args.ragged > 0:
+            rs = S.ragged_batch_spec(256, seed=26269)
+            n = min(args.ragged, 256)
+            print(f"[bench] {n} saddle searches on uneven 32..96 lattices in one persistent launch",
+                  file=sys.stderr, flush=True)
+            batched_leg("batched_ragged_32_96", rs.L[:n], [S.batch_member(rs, i) for i in range(n)], p)
         if args.searches > 0:
             print(f"[bench] {args.searches} saddle searches on {L}x{L} one at a time", file=sys.stderr, flush=True)
             stats = {}
             t0 = time.perf_counter()
             n_iter = 0
+            n_hvp = 0
             for i in range(args.searches):
                 md = torch.as_tensor(S.batch_member(spec, i), device="cuda")
                 res1, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, opts=so)
                 stats[M.STATUS_NAMES[res1.status]] = stats.get(M.STATUS_NAMES[res1.status], 0) + 1
                 n_iter += res1.iters
+                n_hvp += res1.n_hvp
                 print(f"[bench]   search {i}: {M.STATUS_NAMES[res1.status]} iters={res1.iters}", file=sys.stderr,
                       flush=True)
             el = time.perf_counter() - t0
-            extra["searches_per_s_one_at_a_time"] = round(args.searches / el, 4)
-            extra["one_at_a_time_search_status"] = stats
-            extra["one_at_a_time_mean_outer_iters"] = round(n_iter / args.searches, 1)
+            extra["one_at_a_time_128"] = {"searches": args.searches, "wall_s": round(el, 3),
+                                          "searches_per_s": round(args.searches / el, 4),
+                                          "outer_iters_per_s": round(n_iter / el, 1),
+                                          "mean_outer_iters": round(n_iter / args.searches, 1),
+                                          "hvp_columns_per_outer": round(n_hvp / max(n_iter, 1), 1),
+                                          "status": stats}
 
     if not args.hvp_only and not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

@@ -10,7 +10,9 @@
 //   the reflected force and the L-BFGS rotation step (two-loop recursion with
 //   block reductions), the index-1 certification.
 // Searches are independent, so there is no inter-workgroup communication and
-// no host round trip until the whole batch is done.
+// no host round trip until the whole batch is done.  Register arrays of the
+// reductions are indexed with compile-time indices only (a runtime index
+// would move the whole array to scratch memory).
 #include "dense_wg.hpp"
 #include "kernels.hpp"
 #include "tile_ops.hpp"
@@ -181,9 +183,14 @@ __device__ void b_orth(const BArgs& a, const BSearch& s, BShared& sh, int target
                 if (i < nrow) acc[j * 3 * BMB + i] += (double)col[i] * (double)col[nq + j];
     }
     wg_sum<NE>(acc, sh.red);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+        // static indices only: a runtime index would move acc to scratch
+#pragma unroll
         for (int j = 0; j < BMB; ++j)
-            for (int i = 0; i < nrow; ++i) s.Gsm[j * nrow + i] = acc[j * 3 * BMB + i];
+#pragma unroll
+            for (int i = 0; i < 3 * BMB; ++i)
+                if (i < nrow) s.Gsm[j * nrow + i] = acc[j * 3 * BMB + i];
+    }
     __syncthreads();
     orth_small_body<BLD>(BMB, nq, a.drop, s.Gsm, s.ctrl->Bw, s.ctrl->Tw);
     for (int i = threadIdx.x; i < 2 * MAXB * BMB; i += NT) {
@@ -216,42 +223,53 @@ __device__ void b_orth(const BArgs& a, const BSearch& s, BShared& sh, int target
     __syncthreads();
 }
 
+// Rows [I0, I1) of the upper triangle of X^T Y (Y = HS for pass 0, S for
+// pass 1) into Gsm, FP64 accumulation.  Row blocks keep the accumulators
+// within registers.
+template <int I0, int I1>
+__device__ void b_gram_rows(const BSearch& s, BShared& sh, int ns, int pass) {
+    constexpr int NE = (I1 - I0) * (2 * BNS - I0 - I1 + 1) / 2;
+    const int Eh = ns * (ns + 1) / 2;
+    double acc[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) acc[q] = 0.0;
+    for (int r = threadIdx.x; r < s.n2; r += NT) {
+        float x[BNS], y[BNS];
+#pragma unroll
+        for (int c = 0; c < BNS; ++c) {
+            x[c] = 0.0f;
+            y[c] = 0.0f;
+            if (c < ns) {
+                if (c >= I0 && c < I1) x[c] = s.S[(size_t)c * s.n2 + r];
+                y[c] = pass == 0 ? s.HS[(size_t)c * s.n2 + r] : s.S[(size_t)c * s.n2 + r];
+            }
+        }
+        int e = 0;
+#pragma unroll
+        for (int i = I0; i < I1; ++i)
+#pragma unroll
+            for (int j = i; j < BNS; ++j) acc[e++] += (double)x[i] * (double)y[j];
+    }
+    wg_sum<NE>(acc, sh.red);
+    if (threadIdx.x == 0) {
+        int e = 0;
+#pragma unroll
+        for (int i = I0; i < I1; ++i)
+#pragma unroll
+            for (int j = i; j < BNS; ++j) {
+                if (i < ns && j < ns) s.Gsm[pass * Eh + i * ns - i * (i - 1) / 2 + (j - i)] = acc[e];
+                ++e;
+            }
+    }
+    __syncthreads();
+}
+
 // Rayleigh-Ritz Grams (upper triangles of S^T HS then S^T S) into Gsm
 __device__ void b_gram(const BArgs& a, const BSearch& s, BShared& sh, int ns) {
-    constexpr int NE = BNS * (BNS + 1) / 2;  // 78
-    const int Eh = ns * (ns + 1) / 2;
+    (void)a;
     for (int pass = 0; pass < 2; ++pass) {
-        double acc[NE];
-#pragma unroll
-        for (int q = 0; q < NE; ++q) acc[q] = 0.0;
-        for (int r = threadIdx.x; r < s.n2; r += NT) {
-            float x[BNS], y[BNS];
-#pragma unroll
-            for (int c = 0; c < BNS; ++c) {
-                if (c < ns) {
-                    x[c] = s.S[(size_t)c * s.n2 + r];
-                    y[c] = pass == 0 ? s.HS[(size_t)c * s.n2 + r] : x[c];
-                }
-            }
-            int e = 0;
-#pragma unroll
-            for (int i = 0; i < BNS; ++i)
-#pragma unroll
-                for (int j = i; j < BNS; ++j) {
-                    if (i < ns && j < ns) acc[e] += (double)x[i] * (double)y[j];
-                    ++e;
-                }
-        }
-        wg_sum<NE>(acc, sh.red);
-        if (threadIdx.x == 0) {
-            int e = 0;
-            for (int i = 0; i < BNS; ++i)
-                for (int j = i; j < BNS; ++j) {
-                    if (i < ns && j < ns) s.Gsm[pass * Eh + i * ns - i * (i - 1) / 2 + (j - i)] = acc[e];
-                    ++e;
-                }
-        }
-        __syncthreads();
+        b_gram_rows<0, 4>(s, sh, ns, pass);
+        if (ns > 4) b_gram_rows<4, BNS>(s, sh, ns, pass);
     }
 }
 

@@ -330,7 +330,38 @@ __device__ __forceinline__ void m_offset(T (&a)[3], const T (&u)[3], const T (&c
     }
 }
 
-template <class T, int NVP, int XW>
+// Frame of a unit spin for the march kernel: the Duff et al. basis, with the
+// FP32 reciprocal taken by the hardware (|s + n_z| is in [1, 2], so the
+// one-ulp rcp is well conditioned); FP64 keeps the exact division.
+template <class T>
+__device__ __forceinline__ void onb_march(T nx, T ny, T nz, T e1[3], T e2[3]) {
+    const T sgn = copysign(T(1), nz);
+    T a;
+    if constexpr (sizeof(T) == 4)
+        a = -__builtin_amdgcn_rcpf(sgn + nz);
+    else
+        a = T(-1) / (sgn + nz);
+    const T b = nx * ny * a;
+    e1[0] = T(1) + sgn * nx * nx * a;
+    e1[1] = sgn * b;
+    e1[2] = -sgn * nx;
+    e2[0] = b;
+    e2[1] = sgn + ny * ny * a;
+    e2[2] = -ny;
+}
+
+// element at a 32-bit byte offset from a uniform base (selects the
+// scalar-base + 32-bit vector-offset addressing form)
+template <class T>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, unsigned byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void st_off(T* __restrict__ base, unsigned byte_off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+template <class T, int NVP, int XW, bool MASKED>
 __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __restrict__ m,
                                                   const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec,
                                                   const T* __restrict__ V, T* __restrict__ W,
@@ -338,7 +369,7 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
     if (done != nullptr && *done) return;
     constexpr int RS = XW + 4;  // halo 2 | XW columns | halo 2
     __shared__ T rb[2][3 * NVP][RS];
-    __shared__ T cen[3][7][XW];
+    __shared__ T cen[3][MASKED ? 7 : 6][XW];
     const int lid = xcd_order(true);
     const int grp = lid % ngroups;
     const int rest = lid / ngroups;
@@ -354,36 +385,44 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
     const bool lane = x < g.Lx;
     // second LDS slot of this column in the periodic x-halo (needs Lx >= 4)
     const int sec = !lane ? -1 : x >= g.Lx - 2 ? x - g.Lx + 2 : x < 2 ? x + g.Lx + 2 : -1;
+    // uniform plane pointers; per-lane offsets are 32-bit site indices
     const size_t N = g.N;
-    const T* mb = m + (size_t)b * 3 * N;
-    const T* cb = c + (size_t)b * N;
-    const uint8_t* mk = mask ? mask + (size_t)b * N : nullptr;
-    const T* Vb = V + ((size_t)b * nvec + j0) * 2 * N;
-    T* Wb = W + ((size_t)b * nvec + j0) * 2 * N;
+    const T* __restrict__ mx = m + (size_t)b * 3 * N;
+    const T* __restrict__ my = mx + N;
+    const T* __restrict__ mz = my + N;
+    const T* __restrict__ cb = c + (size_t)b * N;
+    const uint8_t* __restrict__ mk = MASKED ? mask + (size_t)b * N : nullptr;
+    const T* __restrict__ Vb = V + ((size_t)b * nvec + j0) * 2 * N;
+    T* __restrict__ Wb = W + ((size_t)b * nvec + j0) * 2 * N;
     const T cJ[3] = {k.cJ[0], k.cJ[1], k.cJ[2]};
     const T cD = k.cD, cDh = T(0.5) * k.cD, cDr = T(0.86602540378443864676) * k.cD, cK = k.cK;
 
-    // raw data of the next input row (prefetched one step ahead)
+    // raw data of the next input row (prefetched one step ahead); lanes past
+    // the row keep a zero vector, so they contribute nothing
     T rm0 = 0, rm1 = 0, rm2 = 1, rc = 0, ra[NVP], rv[NVP];
-    bool ract = false;
+    bool ract = true;
+#pragma unroll
+    for (int j = 0; j < NVP; ++j) ra[j] = rv[j] = T(0);
     int yin = wrapi(y0 - 2, g.Ly);
     auto load_raw = [&](int yy) {
         if (lane) {
-            const int s = x + g.Lx * yy;
-            rm0 = mb[s];
-            rm1 = mb[N + s];
-            rm2 = mb[2 * N + s];
-            rc = cb[s];
-            ract = mk == nullptr || mk[s] != 0;
+            const unsigned s = (unsigned)(x + g.Lx * yy);
+            const unsigned o = s * (unsigned)sizeof(T);
+            rm0 = ld_off(mx, o);
+            rm1 = ld_off(my, o);
+            rm2 = ld_off(mz, o);
+            rc = ld_off(cb, o);
+            if constexpr (MASKED) ract = ld_off(mk, s) != 0;
 #pragma unroll
             for (int j = 0; j < NVP; ++j) {
-                ra[j] = j < nv ? Vb[j * 2 * N + s] : T(0);
-                rv[j] = j < nv ? Vb[j * 2 * N + N + s] : T(0);
+                // slots past the group's end re-read vector 0; their
+                // accumulators are never stored
+                const size_t pj = j < nv ? (size_t)(2 * j) * N : 0;
+                ra[j] = ld_off(Vb + pj, o);
+                rv[j] = ld_off(Vb + pj + N, o);
             }
         }
     };
-#pragma unroll
-    for (int j = 0; j < NVP; ++j) ra[j] = rv[j] = T(0);
     load_raw(yin);
 
     T acc[5][NVP][3];
@@ -402,13 +441,16 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
         const int buf = it & 1;
         // 1. convert row R
         T e1[3], e2[3];
-        onb(rm0, rm1, rm2, e1, e2);
-        const bool act = lane && ract;
+        onb_march(rm0, rm1, rm2, e1, e2);
         const T nc = -rc;
         T u[NVP][3];
 #pragma unroll
         for (int j = 0; j < NVP; ++j) {
-            const T a = act ? ra[j] : T(0), bb = act ? rv[j] : T(0);
+            T a = ra[j], bb = rv[j];
+            if constexpr (MASKED) {
+                a = ract ? a : T(0);
+                bb = ract ? bb : T(0);
+            }
             u[j][0] = a * e1[0] + bb * e2[0];
             u[j][1] = a * e1[1] + bb * e2[1];
             u[j][2] = a * e1[2] + bb * e2[2];
@@ -430,7 +472,7 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
             cen[cw][3][x] = e2[0];
             cen[cw][4][x] = e2[1];
             cen[cw][5][x] = e2[2];
-            cen[cw][6][x] = act ? T(1) : T(0);
+            if constexpr (MASKED) cen[cw][MASKED ? 6 : 0][x] = ract ? T(1) : T(0);
         }
         // own-column offsets (dx = 0) and the centre term
 #pragma unroll
@@ -482,15 +524,17 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
         if (lane && yo >= y0 && yo < y1) {
             const T f10 = cen[cr][0][x], f11 = cen[cr][1][x], f12 = cen[cr][2][x];
             const T f20 = cen[cr][3][x], f21 = cen[cr][4][x], f22 = cen[cr][5][x];
-            const bool on = cen[cr][6][x] != T(0);
-            const int so = x + g.Lx * yo;
+            bool on = true;
+            if constexpr (MASKED) on = cen[cr][MASKED ? 6 : 0][x] != T(0);
+            const unsigned so = (unsigned)(x + g.Lx * yo) * (unsigned)sizeof(T);
 #pragma unroll
             for (int j = 0; j < NVP; ++j) {
                 const T wa = f10 * acc[SL(-2)][j][0] + f11 * acc[SL(-2)][j][1] + f12 * acc[SL(-2)][j][2];
                 const T wb = f20 * acc[SL(-2)][j][0] + f21 * acc[SL(-2)][j][1] + f22 * acc[SL(-2)][j][2];
+                T* __restrict__ wj = Wb + (size_t)(2 * j) * N;
                 if (j < nv) {
-                    Wb[j * 2 * N + so] = on ? wa : T(0);
-                    Wb[j * 2 * N + N + so] = on ? wb : T(0);
+                    st_off(wj, so, on ? wa : T(0));
+                    st_off(wj + N, so, on ? wb : T(0));
                 }
             }
         }
@@ -547,11 +591,12 @@ static void go_band(const Geo& g, const CoefD& kd, int batch, const void* m, con
                        (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, tx, ty);
 }
 
-// strips per lattice: enough workgroups to fill the chip, strips of at
-// least 8 rows (the 4 halo rows of a strip are re-read)
+// strips per lattice: about 1024 workgroups in all (one resident round at
+// the march kernels' occupancy), strips of at least 8 rows (the 4 halo rows
+// of a strip are read twice)
 static int march_strips(const Geo& g, int batch, int ngroups) {
     const long long have = (long long)batch * ngroups;
-    const int want = (int)((2048 + have - 1) / have);
+    const int want = (int)((1024 + have - 1) / have);
     return max(1, min(want, max(1, g.Ly / 8)));
 }
 
@@ -560,9 +605,14 @@ static void go_march_xw(const Geo& g, const CoefD& kd, int batch, const void* m,
                         const uint8_t* mask, int nvec, const void* V, void* W, const int* done, hipStream_t st) {
     const int ngroups = (nvec + NVP - 1) / NVP;
     const int nstrip = march_strips(g, batch, ngroups);
-    hipLaunchKernelGGL((k_hvp_march<T, NVP, XW>), dim3(batch * nstrip * ngroups), dim3(XW), 0, st, g,
-                       coef_cast<T>(kd), (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, nstrip,
-                       ngroups);
+    if (mask)
+        hipLaunchKernelGGL((k_hvp_march<T, NVP, XW, true>), dim3(batch * nstrip * ngroups), dim3(XW), 0, st, g,
+                           coef_cast<T>(kd), (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done,
+                           nstrip, ngroups);
+    else
+        hipLaunchKernelGGL((k_hvp_march<T, NVP, XW, false>), dim3(batch * nstrip * ngroups), dim3(XW), 0, st, g,
+                           coef_cast<T>(kd), (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done,
+                           nstrip, ngroups);
 }
 
 template <class T, int NVP>

@@ -19,6 +19,8 @@
 // X, P, HX, HP, W = HX - X Lam -> convergence control.  Every kernel returns
 // at once when the control block says the solve is done, so chunks of
 // iterations can be queued without host round trips.
+#include <type_traits>
+
 #include "dense_wg.hpp"
 #include "kernels.hpp"
 
@@ -162,7 +164,9 @@ __global__ __launch_bounds__(NT) void k_orth_small(EigArgs a, int target, const 
     orth_small_body<MAXS>(a.mb, nq, a.drop, G, ctrl->Bw, ctrl->Tw);
 }
 
-template <class T>
+// MB: compile-time bound on the block width (mb <= MB), so that the per-row
+// register arrays are sized for the actual block and never spill.
+template <class T, int MB>
 __global__ __launch_bounds__(NT) void k_orth_apply(EigArgs a, int target, T* __restrict__ S,
                                                    const EigCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
@@ -175,26 +179,26 @@ __global__ __launch_bounds__(NT) void k_orth_apply(EigArgs a, int target, T* __r
     __syncthreads();
     const int mb = a.mb, nq = oc.nq;
     for (int r = blockIdx.x * NT + threadIdx.x; r < a.n2; r += gridDim.x * NT) {
-        double q[MAXS], u[MAXB];
+        double q[2 * MB], u[MB];
 #pragma unroll
-        for (int i = 0; i < MAXS; ++i)
+        for (int i = 0; i < 2 * MB; ++i)
             if (i < nq) q[i] = (double)S[(size_t)oc.qcol[i] * a.n2 + r];
 #pragma unroll
-        for (int j = 0; j < MAXB; ++j) {
+        for (int j = 0; j < MB; ++j) {
             if (j < mb) {
                 double v = (double)S[(size_t)(oc.t0 + j) * a.n2 + r];
 #pragma unroll
-                for (int i = 0; i < MAXS; ++i)
+                for (int i = 0; i < 2 * MB; ++i)
                     if (i < nq) v -= B[i + 2 * MAXB * j] * q[i];
                 u[j] = v;
             }
         }
 #pragma unroll
-        for (int j = 0; j < MAXB; ++j) {
+        for (int j = 0; j < MB; ++j) {
             if (j < mb) {
                 double v = 0.0;
 #pragma unroll
-                for (int l = 0; l < MAXB; ++l)
+                for (int l = 0; l < MB; ++l)
                     if (l < mb) v += u[l] * Tw[l + mb * j];
                 S[(size_t)(oc.t0 + j) * a.n2 + r] = (T)v;
             }
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(NT) void k_rr(EigArgs a, int ns_fixed, const double
 // and per-block partial sums of |W_j|^2.  At the start (ns == mb) P is left
 // alone.
 // --------------------------------------------------------------------------
-template <class T>
+template <class T, int MB>
 __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __restrict__ S, T* __restrict__ HS,
                                                double* __restrict__ part, const EigCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
@@ -296,22 +300,22 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
     }
     for (int i = threadIdx.x; i < mb; i += NT) lam[i] = ctrl->lam[i];
     __syncthreads();
-    double rs[MAXB];
+    double rs[MB];
 #pragma unroll
-    for (int j = 0; j < MAXB; ++j) rs[j] = 0.0;
+    for (int j = 0; j < MB; ++j) rs[j] = 0.0;
     const bool has_p = ns > mb;
     for (int r = blockIdx.x * NT + threadIdx.x; r < a.n2; r += gridDim.x * NT) {
-        T sv[MAXS];
+        T sv[3 * MB];
 #pragma unroll
-        for (int i = 0; i < MAXS; ++i)
+        for (int i = 0; i < 3 * MB; ++i)
             if (i < ns) sv[i] = S[(size_t)i * a.n2 + r];
-        double xn[MAXB];
+        double xn[MB];
 #pragma unroll
-        for (int j = 0; j < MAXB; ++j) {
+        for (int j = 0; j < MB; ++j) {
             if (j < mb) {
                 double x = 0.0, p = 0.0;
 #pragma unroll
-                for (int i = 0; i < MAXS; ++i) {
+                for (int i = 0; i < 3 * MB; ++i) {
                     if (i < ns) {
                         x += C[i + ns * j] * (double)sv[i];
                         p += Cp[i + ns * j] * (double)sv[i];
@@ -323,14 +327,14 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
             }
         }
 #pragma unroll
-        for (int i = 0; i < MAXS; ++i)
+        for (int i = 0; i < 3 * MB; ++i)
             if (i < ns) sv[i] = HS[(size_t)i * a.n2 + r];
 #pragma unroll
-        for (int j = 0; j < MAXB; ++j) {
+        for (int j = 0; j < MB; ++j) {
             if (j < mb) {
                 double hx = 0.0, hp = 0.0;
 #pragma unroll
-                for (int i = 0; i < MAXS; ++i) {
+                for (int i = 0; i < 3 * MB; ++i) {
                     if (i < ns) {
                         hx += C[i + ns * j] * (double)sv[i];
                         hp += Cp[i + ns * j] * (double)sv[i];
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < MAXB; ++j) {
+    for (int j = 0; j < MB; ++j) {
         if (j < mb) {
             const double s = wave_sum(rs[j]);
             if (lane == 0) red[j * (NT / 64) + wv] = s;
@@ -501,6 +505,17 @@ int update_blocks(int n2) {
     return nb < 1024 ? nb : 1024;
 }
 
+// dispatch on the block-width bucket (4, 8 or 16 columns)
+template <class F>
+static void go_mb(int mb, F&& f) {
+    if (mb <= 4)
+        f(std::integral_constant<int, 4>{});
+    else if (mb <= 8)
+        f(std::integral_constant<int, 8>{});
+    else
+        f(std::integral_constant<int, MAXB>{});
+}
+
 hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m, const double* Vwarm, int nwarm,
                            const void* Xsave, int use_save, const uint8_t* mask, int N, uint64_t seed,
                            EigCtrl* ctrl, hipStream_t st) {
@@ -527,9 +542,15 @@ hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* 
     hipLaunchKernelGGL(k_orth_small, dim3(1), dim3(NT), 0, st, a, target, G, ctrl);
     const int nb = update_blocks(a.n2);
     if (f64)
-        hipLaunchKernelGGL(k_orth_apply<double>, dim3(nb), dim3(NT), 0, st, a, target, (double*)S, ctrl);
+        go_mb(a.mb, [&](auto mbc) {
+            hipLaunchKernelGGL((k_orth_apply<double, decltype(mbc)::value>), dim3(nb), dim3(NT), 0, st, a, target,
+                               (double*)S, ctrl);
+        });
     else
-        hipLaunchKernelGGL(k_orth_apply<float>, dim3(nb), dim3(NT), 0, st, a, target, (float*)S, ctrl);
+        go_mb(a.mb, [&](auto mbc) {
+            hipLaunchKernelGGL((k_orth_apply<float, decltype(mbc)::value>), dim3(nb), dim3(NT), 0, st, a, target,
+                               (float*)S, ctrl);
+        });
     return hipGetLastError();
 }
 
@@ -553,11 +574,15 @@ hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, h
 hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, double* part, int nblk,
                          EigCtrl* ctrl, hipStream_t st) {
     if (f64)
-        hipLaunchKernelGGL(k_update<double>, dim3(nblk), dim3(NT), 0, st, a, ns, (double*)S, (double*)HS, part,
-                           ctrl);
+        go_mb(a.mb, [&](auto mbc) {
+            hipLaunchKernelGGL((k_update<double, decltype(mbc)::value>), dim3(nblk), dim3(NT), 0, st, a, ns,
+                               (double*)S, (double*)HS, part, ctrl);
+        });
     else
-        hipLaunchKernelGGL(k_update<float>, dim3(nblk), dim3(NT), 0, st, a, ns, (float*)S, (float*)HS, part,
-                           ctrl);
+        go_mb(a.mb, [&](auto mbc) {
+            hipLaunchKernelGGL((k_update<float, decltype(mbc)::value>), dim3(nblk), dim3(NT), 0, st, a, ns,
+                               (float*)S, (float*)HS, part, ctrl);
+        });
     return hipGetLastError();
 }
 
