@@ -46,6 +46,46 @@ def hvp_inputs(M, S, torch, plan, L, B, nvec, n_distinct=32, seed=2025):
     return m, c.contiguous(), V, W, base
 
 
+def counter_traffic(variant, B, L, nvec):
+    """HBM bytes per launch of `variant` from the committed rocprofv3 counter
+    summary, or None when the workload differs or the kernel source changed
+    since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "hvp_frame_1024x128x128_counters.md")
+    if (B, L, nvec) != (1024, 128, 4) or not os.path.exists(path):
+        return None
+    src = os.path.join(ROOT, "paper_2509_26269_amd", "csrc", "hvp.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    rec, tb = None, {}
+    for line in open(path):
+        t = line.strip()
+        if t.startswith("source_sha256 hvp.hip = "):
+            rec = t.split("= ", 1)[1]
+        elif t.startswith("traffic_bytes "):
+            k, v = t[len("traffic_bytes "):].rsplit(" = ", 1)
+            tb[k] = int(v)
+    return tb.get(variant) if rec == h else None
+
+
+def copy_peak_gbs(torch, mib=1024, reps=5):
+    """Device-to-device copy of `mib` MiB (read + write bytes / time)."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def time_hvp(M, torch, plan, m, c, V, W, B, steps, warmup):
     for _ in range(warmup):
         M.moto_tangent_hvp(plan, m, c, V, M.MOTO_FRAME, W=W, batch=B)
@@ -106,6 +146,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-search", action="store_true")
     ap.add_argument("--hvp-only", action="store_true", help="only the HVP leg (for profilers)")
+    ap.add_argument("--eigen-only", action="store_true",
+                    help="only the eigen-solve leg and the search legs asked for (for profilers)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (byte-counter calibration)")
     args = ap.parse_args()
@@ -134,53 +176,63 @@ def main():
     p = S.ham_3shell(L)
     plan = M.Plan.from_params(p)
     N = L * L
+    if args.eigen_only:
+        B = 32
     print(f"[bench] inputs: {B} x {L}x{L}, n_vec={nvec}", file=sys.stderr, flush=True)
     m, c, V, W, base = hvp_inputs(M, S, torch, plan, L, B, nvec)
     torch.cuda.synchronize()
-    print("[bench] autotuning the frame-layout HVP", file=sys.stderr, flush=True)
-    chosen, vtimes = M.moto_tangent_hvp_autotune(plan, m, c, V, W, batch=B, reps=3)
-    vname = M.lib().moto_tangent_hvp_variant_name(chosen).decode()
-    print(f"[bench] variants (ms): {vtimes} -> {vname}", file=sys.stderr, flush=True)
-    print("[bench] timing batched tangent HVP", file=sys.stderr, flush=True)
-    total_ms, per, wall = time_hvp(M, torch, plan, m, c, V, W, B, args.steps, args.warmup)
-    ms_per_step = total_ms / args.steps
-    avg_launch_ms = float(np.mean(per))
-    site_vecs = B * N * nvec
-    gsites = site_vecs / (ms_per_step * 1e-3) / 1e9
-    alg_bytes = (12 + 16 * nvec) * N * B
-    achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
-    out = {
-        "metric": METRIC,
-        "value": round(gsites, 3),
-        "unit": "Gsite/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"tangent HVP, frame layout, batch of {B} periodic {L}x{L} triangular lattices "
-                        f"x {nvec} vectors, 3 exchange shells + NN DMI + K + B (J2,J3 seeded), "
-                        "seeded skyrmion/antiskyrmion states",
-            "lattice": f"{L}x{L}", "batch": B, "n_vec": nvec, "hvp": "f32",
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "kernel": f"frame-layout tangent HVP, variant {vname}",
-            "autotune_ms": {k2: round(v2, 4) for k2, v2 in vtimes.items()},
-            "alg_bytes_per_launch": alg_bytes,
-            "avg_launch_ms": round(avg_launch_ms, 5),
-        },
-    }
+    out = {"metric": METRIC, "value": None, "unit": "Gsite/s", "n_gpus": 1, "note": "eigen-only profiling run"}
+    if not args.eigen_only:
+        print("[bench] autotuning the frame-layout HVP", file=sys.stderr, flush=True)
+        chosen, vtimes = M.moto_tangent_hvp_autotune(plan, m, c, V, W, batch=B, reps=3)
+        vname = M.lib().moto_tangent_hvp_variant_name(chosen).decode()
+        print(f"[bench] variants (ms): {vtimes} -> {vname}", file=sys.stderr, flush=True)
+        print("[bench] timing batched tangent HVP", file=sys.stderr, flush=True)
+        total_ms, per, wall = time_hvp(M, torch, plan, m, c, V, W, B, args.steps, args.warmup)
+        ms_per_step = total_ms / args.steps
+        avg_launch_ms = float(np.mean(per))
+        site_vecs = B * N * nvec
+        gsites = site_vecs / (ms_per_step * 1e-3) / 1e9
+        alg_bytes = (12 + 16 * nvec) * N * B
+        achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
+        traffic = counter_traffic(vname, B, L, nvec)
+        copy_gbs = copy_peak_gbs(torch)
+        out = {
+            "metric": METRIC,
+            "value": round(gsites, 3),
+            "unit": "Gsite/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": round(ms_per_step, 5),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32",
+            "data": "synthetic",
+            "config": {
+                "workload": f"tangent HVP, frame layout, batch of {B} periodic {L}x{L} triangular lattices "
+                            f"x {nvec} vectors, 3 exchange shells + NN DMI + K + B (J2,J3 seeded), "
+                            "seeded skyrmion/antiskyrmion states",
+                "lattice": f"{L}x{L}", "batch": B, "n_vec": nvec, "hvp": "f32",
+            },
+            "roofline": {
+                "bound": "hbm",
+                "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS,
+                "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_over_alg": round(traffic / alg_bytes, 4) if traffic else None,
+                "measured_copy_GBps": round(copy_gbs, 1),
+                "frac_of_copy": round(achieved / copy_gbs, 4),
+                "kernel": f"frame-layout tangent HVP, variant {vname}",
+                "autotune_ms": {k2: round(v2, 4) for k2, v2 in vtimes.items()},
+                "alg_bytes_per_launch": alg_bytes,
+                "avg_launch_ms": round(avg_launch_ms, 5),
+            },
+        }
     del W, V, m, c
     torch.cuda.empty_cache()
 
@@ -208,7 +260,7 @@ def main():
         extra["dense_hessian_bytes_avoided"] = (2 * N) ** 2 * 8
         # block width: guard vectors beyond k trade per-iteration work for iterations
         sweep = {}
-        for guard in (2, 4, 8):
+        for guard in (() if args.eigen_only else (2, 4, 8)):
             wsg = M.EigWorkspace(plan, M.MOTO_F32, 4, guard)
             og = M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=400, guard=guard)
             M.moto_min_modes(plan, m1, 4, M.MOTO_F32, opts=og, ws=wsg)
@@ -219,6 +271,7 @@ def main():
             sweep[f"guard{guard}"] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "iters": rg.iters,
                                       "status": M.STATUS_NAMES[rg.status]}
         extra["min_modes_128_k4_guard_sweep"] = sweep
+    if not args.hvp_only and not args.eigen_only:
         # differentiation form on 64x64 (energy, backward, double backward), FP32 spins
         from paper_2509_26269_amd import autograd as AG
 
@@ -300,7 +353,7 @@ def main():
                                           "hvp_columns_per_outer": round(n_hvp / max(n_iter, 1), 1),
                                           "status": stats}
 
-    if not args.hvp_only and not args.no_cpu:
+    if not args.hvp_only and not args.eigen_only and not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         import oracle as O
 

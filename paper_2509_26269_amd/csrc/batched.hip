@@ -192,7 +192,8 @@ __device__ void b_orth(const BArgs& a, const BSearch& s, BShared& sh, int target
                 if (i < nrow) s.Gsm[j * nrow + i] = acc[j * 3 * BMB + i];
     }
     __syncthreads();
-    orth_small_body<BLD>(BMB, nq, a.drop, s.Gsm, s.ctrl->Bw, s.ctrl->Tw);
+    if (threadIdx.x < WL) orth_small_body<BLD + 1>(BMB, nq, a.drop, s.Gsm, s.ctrl->Bw, s.ctrl->Tw);
+    __syncthreads();
     for (int i = threadIdx.x; i < 2 * MAXB * BMB; i += NT) {
         const int r = i % (2 * MAXB), j = i / (2 * MAXB);
         if (r < 2 * BMB) sh.Bw[r + 2 * BMB * j] = s.ctrl->Bw[i];
@@ -394,7 +395,8 @@ __device__ void b_eig(const BArgs& a, const BSearch& s, BShared& sh, int kk, boo
     b_orth(a, s, sh, 0);
     b_hvp(a, s, sh, s.S, s.HS);
     b_gram(a, s, sh, BMB);
-    rr_body<BLD>(BMB, BMB, a.drop, s.Gsm, s.ctrl);
+    if (threadIdx.x < WL) rr_body<BLD + 1>(BMB, BMB, a.drop, s.Gsm, s.ctrl);
+    __syncthreads();
     b_update(a, s, sh, BMB, kk, true);
     for (int it = 0; it <= a.eig_max_iter + 1; ++it) {
         if (s.ctrl->done) break;
@@ -403,7 +405,8 @@ __device__ void b_eig(const BArgs& a, const BSearch& s, BShared& sh, int kk, boo
         b_hvp(a, s, sh, s.S + (size_t)BMB * s.n2, s.HS + (size_t)BMB * s.n2);
         const int ns = 2 * BMB + s.ctrl->np;
         b_gram(a, s, sh, ns);
-        rr_body<BLD>(BMB, ns, a.drop, s.Gsm, s.ctrl);
+        if (threadIdx.x < WL) rr_body<BLD + 1>(BMB, ns, a.drop, s.Gsm, s.ctrl);
+        __syncthreads();
         b_update(a, s, sh, ns, kk, false);
     }
     // output: ambient block (saved) and the first kk unit vectors

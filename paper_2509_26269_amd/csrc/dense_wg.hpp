@@ -1,7 +1,7 @@
 // dense_wg.hpp -- small dense FP64 steps of the inner layer, each executed by
-// one 256-thread workgroup: parallel cyclic Jacobi, the orthonormalising
-// transform of a projected block, and the Rayleigh-Ritz step with the
-// orthogonal complement for P.  LD is the largest basis size handled (the
+// one wavefront: parallel cyclic Jacobi, the orthonormalising transform of a
+// projected block, and the Rayleigh-Ritz step with the orthogonal complement
+// for P.  LD is the largest basis size handled (the
 // leading dimension of the LDS matrices); LD / 3 is the largest block width.
 #pragma once
 
@@ -10,90 +10,167 @@
 namespace moto {
 
 // --------------------------------------------------------------------------
+// All bodies below run on ONE wavefront (the 64 lanes of the calling wave,
+// lane = threadIdx.x & 63): the matrices are at most 48 x 48, and a single
+// wave needs no workgroup barriers between the many short steps, only
+// wave-level ordering of its LDS traffic.  Callers with larger workgroups
+// let one wave call them and synchronise the workgroup afterwards.
+// --------------------------------------------------------------------------
+constexpr int WL = 64;  // lanes
+
+// Order the LDS accesses of the wave: everything written before is visible
+// to every lane after (LDS operations of one wave execute in order; the
+// fences keep the compiler from moving accesses across).
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wlane() { return threadIdx.x & (WL - 1); }
+
+// --------------------------------------------------------------------------
 // Parallel cyclic Jacobi on an n x n symmetric matrix in LDS (leading
 // dimension LD), round-robin ordering: the n/2 rotations of a round act on
-// disjoint index pairs (Golub & Van Loan, parallel Jacobi).  On return diag(A)
-// holds the eigenvalues and the columns of Z the eigenvectors.
+// disjoint index pairs (Golub & Van Loan, parallel Jacobi).  A round applies
+// A <- R A R^T blockwise: every 2 x 2 block (pair k1, pair k2) is updated
+// from itself alone, so the lanes update disjoint blocks in place.  On
+// return diag(A) holds the eigenvalues and the columns of Z the eigenvectors.
 // --------------------------------------------------------------------------
+// Visit (a, b), a < na, b < nb, in lane-strided order of a * nb + b, with
+// one integer division per call instead of one per element.
+template <class F>
+__device__ __forceinline__ void for2(int na, int nb, F&& f) {
+    if (na <= 0 || nb <= 0) return;
+    const int lane = wlane();
+    int a = lane / nb, b = lane % nb;
+    const int qa = WL / nb, qb = WL % nb;
+    for (int i = lane; i < na * nb; i += WL) {
+        f(a, b);
+        a += qa;
+        b += qb;
+        if (b >= nb) {
+            b -= nb;
+            ++a;
+        }
+    }
+}
+
+// Pair k of round `round` in the round-robin schedule on ne (even) indices:
+// positions k and ne-1-k, position 0 fixed, the others rotating.  q = -1
+// marks the padding index of an odd n.
+__device__ __forceinline__ void rr_pair(int k, int round, int ne, int n, int& p, int& q) {
+    const int m = ne - 1;
+    int ia = 0;
+    if (k != 0) {
+        ia = k - 1 + round;
+        ia = 1 + (ia >= m ? ia - m : ia);
+    }
+    int ib = ne - 2 - k + round;
+    ib = 1 + (ib >= m ? ib - m : ib);
+    p = ia < ib ? ia : ib;
+    q = ia < ib ? ib : ia;
+    if (q >= n) q = -1;
+}
+
 template <int LD>
 __device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweeps) {
-    __shared__ double red[8];
-    __shared__ double cs[LD / 2 + 1], sn[LD / 2 + 1];
-    __shared__ int pp[LD / 2 + 1], qq[LD / 2 + 1];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < n * LD; i += NT) {
-        const int r = i / LD, c = i % LD;
-        Z[i] = (r == c) ? 1.0 : 0.0;
-    }
+    constexpr int HP = LD / 2 + 1;
+    __shared__ double cs[HP], sn[HP];
+    const int lane = wlane();
+    if (n <= 0) return;
+    if (lane < n)
+        for (int r = 0; r < n; ++r) Z[r * LD + lane] = (r == lane) ? 1.0 : 0.0;
     const int ne = n + (n & 1);
     const int half = ne / 2;
-    __syncthreads();
+    // lane-strided traversal of the half x half blocks and half x n Z items
+    const int b_qa = WL / half, b_qb = WL % half, b_a0 = lane / half, b_b0 = lane % half;
+    const int z_qa = WL / n, z_qb = WL % n, z_a0 = lane / n, z_b0 = lane % n;
+    wsync();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         double off = 0.0, fro = 0.0;
-        for (int i = tid; i < n * n; i += NT) {
-            const int r = i / n, c = i % n;
-            const double v = A[r * LD + c];
-            fro += v * v;
-            if (r != c) off += v * v;
-        }
+        if (lane < n)
+            for (int r = 0; r < n; ++r) {
+                const double v = A[r * LD + lane];
+                fro += v * v;
+                if (r != lane) off += v * v;
+            }
         off = wave_sum(off);
         fro = wave_sum(fro);
-        if ((tid & 63) == 0) {
-            red[tid >> 6] = off;
-            red[4 + (tid >> 6)] = fro;
-        }
-        __syncthreads();
-        const double offt = red[0] + red[1] + red[2] + red[3];
-        const double frot = red[4] + red[5] + red[6] + red[7];
-        __syncthreads();
-        if (!(offt > tol * tol * frot)) break;
+        if (!(off > tol * tol * fro)) break;
         for (int round = 0; round < ne - 1; ++round) {
-            if (tid < half) {
-                const int pa = tid, pb = ne - 1 - tid;
-                const int ia = pa == 0 ? 0 : 1 + (pa - 1 + round) % (ne - 1);
-                const int ib = pb == 0 ? 0 : 1 + (pb - 1 + round) % (ne - 1);
-                const int p = ia < ib ? ia : ib, q = ia < ib ? ib : ia;
+            if (lane < half) {
+                int p, q;
+                rr_pair(lane, round, ne, n, p, q);
                 double c = 1.0, s = 0.0;
-                if (q < n) {
+                if (q >= 0) {
                     const double apq = A[p * LD + q];
                     if (apq != 0.0) {
-                        const double tau = (A[q * LD + q] - A[p * LD + p]) / (2.0 * apq);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
+                        // root of t^2 + 2 tau t - 1 = 0 of smaller modulus,
+                        // tau = (a_qq - a_pp) / (2 a_pq), without forming tau
+                        const double d = A[q * LD + q] - A[p * LD + p];
+                        const double t = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
+                        c = rsqrt(1.0 + t * t);
                         s = t * c;
                     }
                 }
-                cs[tid] = c;
-                sn[tid] = s;
-                pp[tid] = p;
-                qq[tid] = q < n ? q : -1;
+                cs[lane] = c;
+                sn[lane] = s;
             }
-            __syncthreads();
-            for (int i = tid; i < half * n; i += NT) {  // rows: A <- J^T A
-                const int kp = i / n, col = i % n;
-                const int q = qq[kp];
-                if (q < 0) continue;
-                const int p = pp[kp];
-                const double c = cs[kp], s = sn[kp];
-                const double ap = A[p * LD + col], aq = A[q * LD + col];
-                A[p * LD + col] = c * ap - s * aq;
-                A[q * LD + col] = s * ap + c * aq;
+            wsync();
+            // A <- R A R^T on blocks (k1 <= k2); rows then columns, with
+            // R = [[c, -s], [s, c]] on each pair (p, q)
+            int k1 = b_a0, k2 = b_b0;
+            for (int b = lane; b < half * half; b += WL) {
+                if (k1 <= k2) {
+                    int p1, q1, p2, q2;
+                    rr_pair(k1, round, ne, n, p1, q1);
+                    rr_pair(k2, round, ne, n, p2, q2);
+                    const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
+                    const double m00 = A[p1 * LD + p2];
+                    const double m01 = q2 >= 0 ? A[p1 * LD + q2] : 0.0;
+                    const double m10 = q1 >= 0 ? A[q1 * LD + p2] : 0.0;
+                    const double m11 = (q1 >= 0 && q2 >= 0) ? A[q1 * LD + q2] : 0.0;
+                    const double n00 = c1 * m00 - s1 * m10, n01 = c1 * m01 - s1 * m11;
+                    const double n10 = s1 * m00 + c1 * m10, n11 = s1 * m01 + c1 * m11;
+                    const double b00 = c2 * n00 - s2 * n01, b01 = s2 * n00 + c2 * n01;
+                    const double b10 = c2 * n10 - s2 * n11, b11 = s2 * n10 + c2 * n11;
+                    A[p1 * LD + p2] = b00;
+                    if (q2 >= 0) A[p1 * LD + q2] = b01;
+                    if (q1 >= 0) A[q1 * LD + p2] = b10;
+                    if (q1 >= 0 && q2 >= 0) A[q1 * LD + q2] = b11;
+                    if (k1 != k2) {  // the transposed block
+                        A[p2 * LD + p1] = b00;
+                        if (q2 >= 0) A[q2 * LD + p1] = b01;
+                        if (q1 >= 0) A[p2 * LD + q1] = b10;
+                        if (q1 >= 0 && q2 >= 0) A[q2 * LD + q1] = b11;
+                    }
+                }
+                k1 += b_qa;
+                k2 += b_qb;
+                if (k2 >= half) {
+                    k2 -= half;
+                    ++k1;
+                }
             }
-            __syncthreads();
-            for (int i = tid; i < half * n; i += NT) {  // columns: A <- A J, Z <- Z J
-                const int kp = i / n, row = i % n;
-                const int q = qq[kp];
-                if (q < 0) continue;
-                const int p = pp[kp];
-                const double c = cs[kp], s = sn[kp];
-                const double ap = A[row * LD + p], aq = A[row * LD + q];
-                A[row * LD + p] = c * ap - s * aq;
-                A[row * LD + q] = s * ap + c * aq;
-                const double zp = Z[row * LD + p], zq = Z[row * LD + q];
-                Z[row * LD + p] = c * zp - s * zq;
-                Z[row * LD + q] = s * zp + c * zq;
+            int kp = z_a0, row = z_b0;
+            for (int i = lane; i < half * n; i += WL) {  // Z <- Z R^T
+                int p, q;
+                rr_pair(kp, round, ne, n, p, q);
+                if (q >= 0) {
+                    const double c = cs[kp], s = sn[kp];
+                    const double zp = Z[row * LD + p], zq = Z[row * LD + q];
+                    Z[row * LD + p] = c * zp - s * zq;
+                    Z[row * LD + q] = s * zp + c * zq;
+                }
+                kp += z_qa;
+                row += z_qb;
+                if (row >= n) {
+                    row -= n;
+                    ++kp;
+                }
             }
-            __syncthreads();
+            wsync();
         }
     }
 }
@@ -109,36 +186,38 @@ __device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweep
 // --------------------------------------------------------------------------
 template <int LD>
 __device__ void orth_small_body(int mb, int nq, double drop, const double* G, double* Bw, double* Tw) {
+    // G is read many times below: it is first copied to LDS
     constexpr int MBL = LD / 3;
     __shared__ double A[MBL * LD];
     __shared__ double Z[MBL * LD];
     __shared__ double dsc[MBL], th[MBL];
     __shared__ int keep[MBL];
     __shared__ int nkeep;
-    const int tid = threadIdx.x;
+    __shared__ double Gl[LD * MBL];
+    const int tid = wlane();
     const int nrow = nq + mb;
-    for (int i = tid; i < nq * mb; i += NT) {
-        const int r = i % nq, j = i / nq;
+    for (int i = tid; i < nrow * mb; i += WL) Gl[i] = G[i];
+    wsync();
+    G = Gl;
+    for2(mb, nq, [&](int j, int r) {
         Bw[r + 2 * MAXB * j] = G[j * nrow + r];
-    }
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int r = i % mb, c = i / mb;
+    });
+    for2(mb, mb, [&](int c, int r) {
         double v = G[c * nrow + nq + r];
         for (int l = 0; l < nq; ++l) v -= G[r * nrow + l] * G[c * nrow + l];
         A[r * LD + c] = v;
-    }
-    __syncthreads();
-    for (int j = tid; j < mb; j += NT) {
+    });
+    wsync();
+    for (int j = tid; j < mb; j += WL) {
         const double full = G[j * nrow + nq + j];
         const double proj = A[j * LD + j];
         dsc[j] = (proj > drop * full && proj > 0.0) ? 1.0 / sqrt(proj) : 0.0;
     }
-    __syncthreads();
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int r = i % mb, c = i / mb;
+    wsync();
+    for2(mb, mb, [&](int c, int r) {
         A[r * LD + c] *= dsc[r] * dsc[c];
-    }
-    __syncthreads();
+    });
+    wsync();
     jacobi_wg<LD>(A, Z, mb, 1e-15, 40);
     if (tid == 0) {
         int r = 0;
@@ -152,18 +231,18 @@ __device__ void orth_small_body(int mb, int nq, double drop, const double* G, do
         }
         nkeep = r;
     }
-    __syncthreads();
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int row = i % mb, c = i / mb;
+    wsync();
+    for2(mb, mb, [&](int c, int row) {
         Tw[row + mb * c] = c < nkeep ? dsc[row] * Z[row * LD + keep[c]] / sqrt(th[c]) : 0.0;
-    }
-    __syncthreads();
+    });
+    wsync();
 }
 
 // --------------------------------------------------------------------------
 // Rayleigh-Ritz on span(S), basis size ns (X = first mb columns):
 //   G_B -> D G_B D = Z diag(theta) Z^T, keep theta > drop * max(theta),
-//   T = D Z_keep theta^-1/2  (T^T G_B T = I);
+//   T = D Z_keep theta^-1/2  (T^T G_B T = I; when D G_B D is the identity up
+//   to rounding, T = D (I + E)^(-1/2) by its series instead);
 //   T^T G_A T = Y diag(lam) Y^T;   C = T Y[:, lowest mb]   (X_new = S C);
 //   C_wp = C with its X rows zeroed, made G_B-orthogonal to C (twice) and
 //   G_B-orthonormalised with rank dropping -> Cp  (P_new = S Cp).
@@ -180,87 +259,120 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
     __shared__ double h1[MBL * MBL];
     __shared__ int keep[LD], order[LD];
     __shared__ int rank_s;
-    const int tid = threadIdx.x;
+    __shared__ double GAf[LD * LD], GBf[LD * LD];
+    const int tid = wlane();
     const int Eh = ns * (ns + 1) / 2;
-    auto GA = [&](int i, int j) {
+    // both Grams as full symmetric matrices in LDS: the dense steps below
+    // read them many times, and a global read costs far more than an LDS one
+    for2(ns, ns, [&](int i, int j) {
         const int r = i < j ? i : j, c = i < j ? j : i;
-        return Gtri[r * ns - r * (r - 1) / 2 + (c - r)];
-    };
-    auto GB = [&](int i, int j) {
-        const int r = i < j ? i : j, c = i < j ? j : i;
-        return Gtri[Eh + r * ns - r * (r - 1) / 2 + (c - r)];
-    };
+        const int e = r * ns - r * (r - 1) / 2 + (c - r);
+        GAf[i * LD + j] = Gtri[e];
+        GBf[i * LD + j] = Gtri[Eh + e];
+    });
+    wsync();
+    auto GA = [&](int i, int j) { return GAf[i * LD + j]; };
+    auto GB = [&](int i, int j) { return GBf[i * LD + j]; };
     double gbmax = 0.0;
     for (int i = 0; i < ns; ++i) gbmax = fmax(gbmax, GB(i, i));
-    for (int i = tid; i < ns; i += NT) {
+    for (int i = tid; i < ns; i += WL) {
         const double gii = GB(i, i);
         dsc[i] = gii > 1e-24 * gbmax ? 1.0 / sqrt(gii) : 0.0;
     }
-    __syncthreads();
-    for (int i = tid; i < ns * ns; i += NT) {
-        const int r = i / ns, c = i % ns;
+    wsync();
+    for2(ns, ns, [&](int r, int c) {
         A[r * LD + c] = dsc[r] * GB(r, c) * dsc[c];
-    }
-    __syncthreads();
-    jacobi_wg<LD>(A, Z, ns, 1e-15, 40);
-    if (tid == 0) {
-        double tmax = 0.0;
-        for (int i = 0; i < ns; ++i) tmax = fmax(tmax, A[i * LD + i]);
-        int r = 0;
-        for (int i = 0; i < ns; ++i) {
-            const double t = A[i * LD + i];
-            if (t > drop * tmax) {
-                keep[r] = i;
-                th[r] = t;
-                ++r;
-            }
+    });
+    wsync();
+    // The basis is orthonormal by construction, so D G_B D = I + E with E
+    // at the level of FP32 rounding: then T = D (I + E)^(-1/2) = D (I - E/2 +
+    // 3/8 E^2) to FP64 accuracy, with the zero columns (dropped earlier) left
+    // out.  Otherwise the general path: an eigen-decomposition with rank
+    // dropping.
+    double emax = 0.0;
+    for2(ns, ns, [&](int r, int c) {
+        if (r != c) emax = fmax(emax, fabs(A[r * LD + c]));
+    });
+    emax = wave_max(emax);
+    const bool near_id = emax < 1e-5;
+    if (near_id) {
+        auto E = [&](int i, int j) { return i == j ? (dsc[i] > 0.0 ? A[i * LD + i] - 1.0 : 0.0) : A[i * LD + j]; };
+        for2(ns, ns, [&](int i, int j) {  // Z <- E^2
+            double v = 0.0;
+            for (int l = 0; l < ns; ++l) v += E(i, l) * E(l, j);
+            Z[i * LD + j] = v;
+        });
+        if (tid == 0) {
+            int r = 0;
+            for (int i = 0; i < ns; ++i)
+                if (dsc[i] > 0.0) keep[r++] = i;
+            rank_s = r;
         }
-        rank_s = r;
+        wsync();
+        const int r = rank_s;
+        for2(ns, r, [&](int row, int c) {  // T (ns x r)
+            const int k = keep[c];
+            const double t0 = (row == k ? 1.0 : 0.0) - 0.5 * E(row, k) + 0.375 * Z[row * LD + k];
+            Tm[row * LD + c] = dsc[row] * t0;
+        });
+        wsync();
+    } else {
+        jacobi_wg<LD>(A, Z, ns, 1e-15, 40);
+        if (tid == 0) {
+            double tmax = 0.0;
+            for (int i = 0; i < ns; ++i) tmax = fmax(tmax, A[i * LD + i]);
+            int r = 0;
+            for (int i = 0; i < ns; ++i) {
+                const double t = A[i * LD + i];
+                if (t > drop * tmax) {
+                    keep[r] = i;
+                    th[r] = t;
+                    ++r;
+                }
+            }
+            rank_s = r;
+        }
+        wsync();
+        const int r = rank_s;
+        for2(ns, r, [&](int row, int c) {  // T (ns x r)
+            Tm[row * LD + c] = dsc[row] * Z[row * LD + keep[c]] / sqrt(th[c]);
+        });
+        wsync();
     }
-    __syncthreads();
     const int r = rank_s;
-    for (int i = tid; i < ns * r; i += NT) {  // T (ns x r)
-        const int row = i / r, c = i % r;
-        Tm[row * LD + c] = dsc[row] * Z[row * LD + keep[c]] / sqrt(th[c]);
-    }
-    __syncthreads();
-    for (int i = tid; i < ns * r; i += NT) {  // Z <- G_A T
-        const int row = i / r, c = i % r;
+    for2(ns, r, [&](int row, int c) {  // Z <- G_A T
         double s = 0.0;
         for (int l = 0; l < ns; ++l) s += GA(row, l) * Tm[l * LD + c];
         Z[row * LD + c] = s;
-    }
-    __syncthreads();
-    for (int i = tid; i < r * r; i += NT) {  // A <- T^T Z
-        const int row = i / r, c = i % r;
+    });
+    wsync();
+    for2(r, r, [&](int row, int c) {  // A <- T^T Z
         double s = 0.0;
         for (int l = 0; l < ns; ++l) s += Tm[l * LD + row] * Z[l * LD + c];
         A[row * LD + c] = s;
-    }
-    __syncthreads();
-    for (int i = tid; i < r * r; i += NT) {
-        const int row = i / r, c = i % r;
+    });
+    wsync();
+    for2(r, r, [&](int row, int c) {
         if (row < c) {
             const double v = 0.5 * (A[row * LD + c] + A[c * LD + row]);
             A[row * LD + c] = v;
             A[c * LD + row] = v;
         }
-    }
-    __syncthreads();
+    });
+    wsync();
     jacobi_wg<LD>(A, Z, r, 1e-15, 40);
-    for (int i = tid; i < r; i += NT) ev[i] = A[i * LD + i];
-    __syncthreads();
-    for (int i = tid; i < r; i += NT) {
+    for (int i = tid; i < r; i += WL) ev[i] = A[i * LD + i];
+    wsync();
+    for (int i = tid; i < r; i += WL) {
         const double li = ev[i];
         int rk = 0;
         for (int j = 0; j < r; ++j) rk += (ev[j] < li) || (ev[j] == li && j < i);
         order[rk] = i;
     }
-    __syncthreads();
+    wsync();
     const int mcol = r < mb ? r : mb;
     // C = T Y[:, order[0..mb)] -> A region (ld MBL) and out->C
-    for (int i = tid; i < ns * mb; i += NT) {
-        const int row = i % ns, j = i / ns;
+    for2(mb, ns, [&](int j, int row) {
         double s = 0.0;
         if (j < mcol) {
             const int yc = order[j];
@@ -268,64 +380,57 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
         }
         A[row * MBL + j] = s;
         out->C[row + ns * j] = s;
-    }
-    for (int j = tid; j < mb; j += NT) out->lam[j] = j < mcol ? ev[order[j]] : 0.0;
+    });
+    for (int j = tid; j < mb; j += WL) out->lam[j] = j < mcol ? ev[order[j]] : 0.0;
     if (tid == 0) out->rank = r;
-    __syncthreads();
+    wsync();
     // ---- P complement: Cwp in the Tm region (ld MBL) ----
-    for (int i = tid; i < ns * mb; i += NT) {
-        const int row = i % ns, j = i / ns;
+    for2(mb, ns, [&](int j, int row) {
         Tm[row * MBL + j] = row < mb ? 0.0 : A[row * MBL + j];
-    }
-    __syncthreads();
+    });
+    wsync();
     for (int pass = 0; pass < 2; ++pass) {
-        for (int i = tid; i < ns * mb; i += NT) {  // Z <- G_B Cwp
-            const int row = i % ns, j = i / ns;
+        for2(mb, ns, [&](int j, int row) {  // Z <- G_B Cwp
             double s = 0.0;
             for (int l = 0; l < ns; ++l) s += GB(row, l) * Tm[l * MBL + j];
             Z[row * MBL + j] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < mb * mb; i += NT) {  // h1 <- C^T G_B Cwp
-            const int p = i % mb, j = i / mb;
+        });
+        wsync();
+        for2(mb, mb, [&](int j, int p) {  // h1 <- C^T G_B Cwp
             double s = 0.0;
             for (int l = 0; l < ns; ++l) s += A[l * MBL + p] * Z[l * MBL + j];
             h1[p + MBL * j] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < ns * mb; i += NT) {  // Cwp <- Cwp - C h1
-            const int row = i % ns, j = i / ns;
+        });
+        wsync();
+        for2(mb, ns, [&](int j, int row) {  // Cwp <- Cwp - C h1
             double s = Tm[row * MBL + j];
             for (int p = 0; p < mb; ++p) s -= A[row * MBL + p] * h1[p + MBL * j];
             Tm[row * MBL + j] = s;
-        }
-        __syncthreads();
+        });
+        wsync();
     }
     // Mp = Cwp^T G_B Cwp
-    for (int i = tid; i < ns * mb; i += NT) {
-        const int row = i % ns, j = i / ns;
+    for2(mb, ns, [&](int j, int row) {
         double s = 0.0;
         for (int l = 0; l < ns; ++l) s += GB(row, l) * Tm[l * MBL + j];
         A[row * MBL + j] = s;
-    }
-    __syncthreads();
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int p = i % mb, j = i / mb;
+    });
+    wsync();
+    for2(mb, mb, [&](int j, int p) {
         double s = 0.0;
         for (int l = 0; l < ns; ++l) s += Tm[l * MBL + p] * A[l * MBL + j];
         h1[p + MBL * j] = s;
-    }
-    __syncthreads();
-    for (int j = tid; j < mb; j += NT) {
+    });
+    wsync();
+    for (int j = tid; j < mb; j += WL) {
         const double d = h1[j + MBL * j];
         dsc[j] = d > 1e-24 ? 1.0 / sqrt(d) : 0.0;
     }
-    __syncthreads();
-    for (int i = tid; i < mb * mb; i += NT) {
-        const int p = i % mb, j = i / mb;
+    wsync();
+    for2(mb, mb, [&](int j, int p) {
         Z[p * LD + j] = dsc[p] * h1[p + MBL * j] * dsc[j];
-    }
-    __syncthreads();
+    });
+    wsync();
     jacobi_wg<LD>(Z, A, mb, 1e-15, 40);
     if (tid == 0) {
         int rr = 0;
@@ -339,10 +444,9 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
         }
         rank_s = rr;
     }
-    __syncthreads();
+    wsync();
     const int rp = rank_s;
-    for (int i = tid; i < ns * mb; i += NT) {  // Cp = Cwp D Zp_keep theta^-1/2
-        const int row = i % ns, j = i / ns;
+    for2(mb, ns, [&](int j, int row) {  // Cp = Cwp D Zp_keep theta^-1/2
         double s = 0.0;
         if (j < rp) {
             const int zc = keep[j];
@@ -350,8 +454,8 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
             s /= sqrt(th[j]);
         }
         out->Cp[row + ns * j] = s;
-    }
-    __syncthreads();
+    });
+    wsync();
 }
 
 }  // namespace moto

@@ -32,6 +32,7 @@ constexpr int GQ = (GENT + NT - 1) / NT;             // entries per thread
 constexpr int OENT = MAXS * MAXB;                    // orthonormalisation Gram entries
 constexpr int OQ = (OENT + NT - 1) / NT;
 constexpr int PSTRIDE = GENT;                        // doubles per block partial row
+constexpr int RED_BLOCKS = 64;                       // workgroups of the partial-row reduction
 
 __device__ __forceinline__ int sol_ns(const EigArgs& a, const EigCtrl* ctrl, int ns_fixed) {
     return ns_fixed >= 0 ? ns_fixed : 2 * a.mb + ctrl->np;
@@ -146,22 +147,38 @@ __global__ __launch_bounds__(NT) void k_orth_gram(EigArgs a, int target, const T
     }
 }
 
-// Multi-block fixed-order reduction of per-block partial rows: G[e] = sum_b part[b][e].
-__global__ __launch_bounds__(NT) void k_reduce_rows(const double* __restrict__ part, int nblk, int E,
-                                                    double* __restrict__ G, const EigCtrl* __restrict__ ctrl) {
+// Multi-block fixed-order reduction of per-block partial rows:
+// G[e] = sum_b part[b][e] over the entries in use (kind 0: orthonormalisation
+// Gram of `arg` = target, kind 1: Rayleigh-Ritz Grams of `arg` = ns_fixed).
+// One wavefront per entry: lane l sums blocks l, l + 64, ..., then a fixed
+// butterfly across the lanes.
+__global__ __launch_bounds__(NT) void k_reduce_rows(EigArgs a, const double* __restrict__ part, int nblk, int kind,
+                                                    int arg, double* __restrict__ G,
+                                                    const EigCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
-    const int e = blockIdx.x * NT + threadIdx.x;
-    if (e >= E) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * PSTRIDE + e];
-    G[e] = s;
+    int E;
+    if (kind == 0) {
+        const int nq = arg == 1 ? a.mb + ctrl->np : 0;
+        E = (nq + a.mb) * a.mb;
+    } else {
+        const int ns = sol_ns(a, ctrl, arg);
+        E = ns * (ns + 1);
+    }
+    const int lane = threadIdx.x & 63;
+    const int nw = gridDim.x * (NT / 64);
+    for (int e = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); e < E; e += nw) {
+        double s = 0.0;
+        for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * PSTRIDE + e];
+        s = wave_sum(s);
+        if (lane == 0) G[e] = s;
+    }
 }
 
-__global__ __launch_bounds__(NT) void k_orth_small(EigArgs a, int target, const double* __restrict__ G,
+__global__ __launch_bounds__(WL) void k_orth_small(EigArgs a, int target, const double* __restrict__ G,
                                                    EigCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     const int nq = target == 1 ? a.mb + ctrl->np : 0;
-    orth_small_body<MAXS>(a.mb, nq, a.drop, G, ctrl->Bw, ctrl->Tw);
+    orth_small_body<MAXS + 1>(a.mb, nq, a.drop, G, ctrl->Bw, ctrl->Tw);
 }
 
 // MB: compile-time bound on the block width (mb <= MB), so that the per-row
@@ -271,11 +288,11 @@ __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* _
     }
 }
 
-// Rayleigh-Ritz step (one workgroup, FP64): see rr_body.
-__global__ __launch_bounds__(NT) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ Gtri,
+// Rayleigh-Ritz step (one wavefront, FP64): see rr_body.
+__global__ __launch_bounds__(WL) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ Gtri,
                                            EigCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
-    rr_body<MAXS>(a.mb, sol_ns(a, ctrl, ns_fixed), a.drop, Gtri, ctrl);
+    rr_body<MAXS + 1>(a.mb, sol_ns(a, ctrl, ns_fixed), a.drop, Gtri, ctrl);
 }
 
 // --------------------------------------------------------------------------
@@ -363,15 +380,24 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
     }
 }
 
-// Convergence control (one thread): residual norms, NaN, rank and cap checks.
-__global__ void k_eig_control(EigArgs a, const double* __restrict__ part, int nblk, EigCtrl* __restrict__ ctrl,
-                              int first) {
-    if (threadIdx.x != 0 || ctrl->done) return;
+// Convergence control: residual norms (one wavefront per column, fixed-order
+// sums), then one thread checks NaN, rank, convergence and the cap.
+__global__ __launch_bounds__(NT) void k_eig_control(EigArgs a, const double* __restrict__ part, int nblk,
+                                                    EigCtrl* __restrict__ ctrl, int first) {
+    if (ctrl->done) return;
+    __shared__ double rsq[MAXB];
+    const int lane = threadIdx.x & 63;
+    for (int j = threadIdx.x >> 6; j < a.mb; j += NT / 64) {
+        double s = 0.0;
+        for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * MAXB + j];
+        s = wave_sum(s);
+        if (lane == 0) rsq[j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     bool conv = true, bad = false;
     for (int j = 0; j < a.mb; ++j) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * MAXB + j];
-        const double rj = sqrt(s);
+        const double rj = sqrt(rsq[j]);
         ctrl->resid[j] = rj;
         if (!isfinite(rj) || !isfinite(ctrl->lam[j])) bad = true;
         if (j < a.k && !(rj <= a.tol_abs)) conv = false;
@@ -537,9 +563,8 @@ hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* 
     else
         hipLaunchKernelGGL(k_orth_gram<float>, dim3(nblk), dim3(NT), 0, st, a, target, (const float*)S, part,
                            ctrl);
-    const int E = OENT;
-    hipLaunchKernelGGL(k_reduce_rows, dim3((E + NT - 1) / NT), dim3(NT), 0, st, part, nblk, E, G, ctrl);
-    hipLaunchKernelGGL(k_orth_small, dim3(1), dim3(NT), 0, st, a, target, G, ctrl);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS), dim3(NT), 0, st, a, part, nblk, 0, target, G, ctrl);
+    hipLaunchKernelGGL(k_orth_small, dim3(1), dim3(WL), 0, st, a, target, G, ctrl);
     const int nb = update_blocks(a.n2);
     if (f64)
         go_mb(a.mb, [&](auto mbc) {
@@ -562,12 +587,12 @@ hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const 
     else
         hipLaunchKernelGGL(k_gram<float>, dim3(nblk), dim3(NT), 0, st, a, ns, (const float*)S, (const float*)HS,
                            part, ctrl);
-    hipLaunchKernelGGL(k_reduce_rows, dim3((GENT + NT - 1) / NT), dim3(NT), 0, st, part, nblk, GENT, G, ctrl);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS), dim3(NT), 0, st, a, part, nblk, 1, ns, G, ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, hipStream_t st) {
-    hipLaunchKernelGGL(k_rr, dim3(1), dim3(NT), 0, st, a, ns, G, ctrl);
+    hipLaunchKernelGGL(k_rr, dim3(1), dim3(WL), 0, st, a, ns, G, ctrl);
     return hipGetLastError();
 }
 
@@ -588,7 +613,7 @@ hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, 
 
 hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, EigCtrl* ctrl, int first,
                               hipStream_t st) {
-    hipLaunchKernelGGL(k_eig_control, dim3(1), dim3(64), 0, st, a, part, nblk, ctrl, first);
+    hipLaunchKernelGGL(k_eig_control, dim3(1), dim3(NT), 0, st, a, part, nblk, ctrl, first);
     return hipGetLastError();
 }
 

@@ -252,31 +252,38 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
     if (threadIdx.x == 0) pg[SNE] = red[0] + red[1] + red[2] + red[3];
 }
 
-// (3) one thread: reduce the Gram, stop test, two-loop recursion in
-// coefficient space, reset test; writes the direction coefficients.
-__global__ void k_step_ctrl(StepArgs a, StepPtrs P) {
-    if (threadIdx.x != 0) return;
+// (3) reduce the Gram (one wavefront per entry, fixed-order sums), then one
+// thread: stop test, two-loop recursion in coefficient space, reset test;
+// writes the direction coefficients.
+__global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P) {
     StepHdr* h = P.hdr;
     if (h->stopped) return;
+    __shared__ double gs[SNE + 1];
     const Ring rg = ring_next(h, a.mem, a.rule);
     const int c = rg.c_new;
     const int nv = 2 * c + 1;
     const int ne = nv * (nv + 1) / 2;
+    const int lane = threadIdx.x & 63;
+    for (int e = threadIdx.x >> 6; e <= ne; e += NT / 64) {
+        const int ee = e < ne ? e : SNE;  // the last slot is |F_mmf|^2
+        double s = 0.0;
+        for (int b = lane; b < P.nblk; b += 64) s += P.pgram[(size_t)b * SPART + ee];
+        s = wave_sum(s);
+        if (lane == 0) gs[ee] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     double Gm[SNV][SNV];
     for (int e = 0; e < ne; ++e) {
-        double s = 0.0;
-        for (int b = 0; b < P.nblk; ++b) s += P.pgram[(size_t)b * SPART + e];
         int p = e, i = 0;
         while (p >= nv - i) {
             p -= nv - i;
             ++i;
         }
-        Gm[i][i + p] = s;
-        Gm[i + p][i] = s;
+        Gm[i][i + p] = gs[e];
+        Gm[i + p][i] = gs[e];
     }
-    double f2 = 0.0;
-    for (int b = 0; b < P.nblk; ++b) f2 += P.pgram[(size_t)b * SPART + SNE];
-    const double fn = sqrt(f2);
+    const double fn = sqrt(gs[SNE]);
     h->fnorm = fn;
     h->count = c;
     h->head = rg.h_new;
@@ -421,7 +428,7 @@ hipError_t launch_step(const StepArgs& a, double* m, const double* F, const doub
     const int nb = P.nblk;
     if (a.k_reflect > 0) hipLaunchKernelGGL(k_step_dots, dim3(nb), dim3(NT), 0, st, a, F, V, P);
     hipLaunchKernelGGL(k_step_gram, dim3(nb), dim3(NT), 0, st, a, m, F, V, P);
-    hipLaunchKernelGGL(k_step_ctrl, dim3(1), dim3(64), 0, st, a, P);
+    hipLaunchKernelGGL(k_step_ctrl, dim3(1), dim3(NT), 0, st, a, P);
     hipLaunchKernelGGL(k_step_dir, dim3(nb), dim3(NT), 0, st, a, m, P);
     hipLaunchKernelGGL(k_step_rot, dim3(nb), dim3(NT), 0, st, a, m, P, nb);
     hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64), 0, st, P, out);
