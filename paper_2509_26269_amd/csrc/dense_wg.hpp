@@ -218,18 +218,45 @@ __device__ void orth_small_body(int mb, int nq, double drop, const double* G, do
         A[r * LD + c] *= dsc[r] * dsc[c];
     });
     wsync();
-    jacobi_wg<LD>(A, Z, mb, 1e-15, 40);
-    if (tid == 0) {
-        int r = 0;
-        for (int i = 0; i < mb; ++i) {
-            const double t = A[i * LD + i];
-            if (t > drop) {
-                keep[r] = i;
-                th[r] = t;
-                ++r;
-            }
+    // a block that is already orthonormal (the second pass) has D M D = I + E
+    // at rounding level: (I + E)^(-1/2) = I - E/2 + 3/8 E^2 replaces the
+    // eigen-decomposition (Z holds that transform, th = 1)
+    double emax = 0.0;
+    for2(mb, mb, [&](int c, int r) {
+        if (r != c) emax = fmax(emax, fabs(A[r * LD + c]));
+    });
+    emax = wave_max(emax);
+    if (emax < 1e-5) {
+        auto E = [&](int i, int j) { return i == j ? (dsc[i] > 0.0 ? A[i * LD + i] - 1.0 : 0.0) : A[i * LD + j]; };
+        for2(mb, mb, [&](int i, int j) {
+            double v = 0.0;
+            for (int l = 0; l < mb; ++l) v += E(i, l) * E(l, j);
+            Z[i * LD + j] = (i == j ? 1.0 : 0.0) - 0.5 * E(i, j) + 0.375 * v;
+        });
+        if (tid == 0) {
+            int r = 0;
+            for (int i = 0; i < mb; ++i)
+                if (dsc[i] > 0.0) {
+                    keep[r] = i;
+                    th[r] = 1.0;
+                    ++r;
+                }
+            nkeep = r;
         }
-        nkeep = r;
+    } else {
+        jacobi_wg<LD>(A, Z, mb, 1e-15, 40);
+        if (tid == 0) {
+            int r = 0;
+            for (int i = 0; i < mb; ++i) {
+                const double t = A[i * LD + i];
+                if (t > drop) {
+                    keep[r] = i;
+                    th[r] = t;
+                    ++r;
+                }
+            }
+            nkeep = r;
+        }
     }
     wsync();
     for2(mb, mb, [&](int c, int row) {
@@ -360,7 +387,7 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
         }
     });
     wsync();
-    jacobi_wg<LD>(A, Z, r, 1e-15, 40);
+    jacobi_wg<LD>(A, Z, r, 1e-13, 40);
     for (int i = tid; i < r; i += WL) ev[i] = A[i * LD + i];
     wsync();
     for (int i = tid; i < r; i += WL) {
@@ -431,7 +458,7 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
         Z[p * LD + j] = dsc[p] * h1[p + MBL * j] * dsc[j];
     });
     wsync();
-    jacobi_wg<LD>(Z, A, mb, 1e-15, 40);
+    jacobi_wg<LD>(Z, A, mb, 1e-13, 40);
     if (tid == 0) {
         int rr = 0;
         for (int i = 0; i < mb; ++i) {

@@ -360,6 +360,16 @@ template <class T>
 __device__ __forceinline__ void st_off(T* __restrict__ base, unsigned byte_off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
+// non-temporal forms for the data a launch touches once (vectors in,
+// products out)
+template <class T>
+__device__ __forceinline__ T ld_off_nt(const T* __restrict__ base, unsigned byte_off) {
+    return __builtin_nontemporal_load(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off));
+}
+template <class T>
+__device__ __forceinline__ void st_off_nt(T* __restrict__ base, unsigned byte_off, T v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
+}
 
 template <class T, int NVP, int XW, bool MASKED>
 __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __restrict__ m,
@@ -418,8 +428,8 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
                 // slots past the group's end re-read vector 0; their
                 // accumulators are never stored
                 const size_t pj = j < nv ? (size_t)(2 * j) * N : 0;
-                ra[j] = ld_off(Vb + pj, o);
-                rv[j] = ld_off(Vb + pj + N, o);
+                ra[j] = ld_off_nt(Vb + pj, o);
+                rv[j] = ld_off_nt(Vb + pj + N, o);
             }
         }
     };
@@ -533,8 +543,270 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
                 const T wb = f20 * acc[SL(-2)][j][0] + f21 * acc[SL(-2)][j][1] + f22 * acc[SL(-2)][j][2];
                 T* __restrict__ wj = Wb + (size_t)(2 * j) * N;
                 if (j < nv) {
-                    st_off(wj, so, on ? wa : T(0));
-                    st_off(wj + N, so, on ? wb : T(0));
+                    st_off_nt(wj, so, on ? wa : T(0));
+                    st_off_nt(wj + N, so, on ? wb : T(0));
+                }
+            }
+        }
+        cw = cw == 2 ? 0 : cw + 1;
+#undef SL
+    };
+
+    for (int it = 0; it < nsteps; it += 5) {
+        const int R = y0 - 2 + it;
+        step(std::integral_constant<int, 0>{}, R, it);
+        if (it + 1 < nsteps) step(std::integral_constant<int, 1>{}, R + 1, it + 1);
+        if (it + 2 < nsteps) step(std::integral_constant<int, 2>{}, R + 2, it + 2);
+        if (it + 3 < nsteps) step(std::integral_constant<int, 3>{}, R + 3, it + 3);
+        if (it + 4 < nsteps) step(std::integral_constant<int, 4>{}, R + 4, it + 4);
+    }
+}
+
+// --------------------------------------------------------------------------
+// march2<NVP, NT2>: the row march with two adjacent columns per thread
+// --------------------------------------------------------------------------
+// Same algorithm as k_hvp_march, for even Lx: thread t owns columns 2t and
+// 2t + 1, so every global access is an aligned 8-byte pair (half the memory
+// instructions, twice the bytes per request), the LDS row is written and
+// read in pairs, and the two own columns are each other's dx = +-1
+// neighbours straight from registers.  NT2 threads cover up to 2 NT2
+// columns.
+template <class T>
+__device__ __forceinline__ void ld2(const T* __restrict__ base, unsigned byte_off, T& a, T& b) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    const V2 v = *reinterpret_cast<const V2*>(reinterpret_cast<const char*>(base) + byte_off);
+    a = v.x;
+    b = v.y;
+}
+template <class T>
+__device__ __forceinline__ void st2(T* __restrict__ base, unsigned byte_off, T a, T b) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    V2 v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<V2*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+// streaming forms for data touched once per launch (the vectors in, the
+// products out): non-temporal, so they do not displace the reused rows
+template <class T>
+__device__ __forceinline__ void ld2_nt(const T* __restrict__ base, unsigned byte_off, T& a, T& b) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(reinterpret_cast<const char*>(base) + byte_off));
+    a = v.x;
+    b = v.y;
+}
+template <class T>
+__device__ __forceinline__ void st2_nt(T* __restrict__ base, unsigned byte_off, T a, T b) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    V2 v;
+    v.x = a;
+    v.y = b;
+    __builtin_nontemporal_store(v, reinterpret_cast<V2*>(reinterpret_cast<char*>(base) + byte_off));
+}
+
+template <class T, int NVP, int NT2, bool MASKED>
+__global__ __launch_bounds__(NT2) void k_hvp_march2(Geo g, Coef<T> k, const T* __restrict__ m,
+                                                   const T* __restrict__ c, const uint8_t* __restrict__ mask,
+                                                   int nvec, const T* __restrict__ V, T* __restrict__ W,
+                                                   const int* __restrict__ done, int nstrip, int ngroups) {
+    if (done != nullptr && *done) return;
+    constexpr int XW = 2 * NT2;
+    constexpr int RS = XW + 4;  // halo 2 | XW columns | halo 2
+    __shared__ __align__(16) T rb[2][3 * NVP][RS];
+    __shared__ T cen[3][MASKED ? 7 : 6][XW];
+    const int lid = xcd_order(true);
+    const int grp = lid % ngroups;
+    const int rest = lid / ngroups;
+    const int strip = rest % nstrip;
+    const int b = rest / nstrip;
+    const int SH = (g.Ly + nstrip - 1) / nstrip;
+    const int y0 = strip * SH;
+    const int y1 = min(g.Ly, y0 + SH);
+    if (y0 >= y1) return;
+    const int j0 = grp * NVP;
+    const int nv = min(NVP, nvec - j0);
+    const int x = 2 * threadIdx.x;  // first of the two columns
+    const bool lane = x < g.Lx;      // Lx is even: both columns or neither
+    // halo: the last pair also fills slots 0,1; the first pair slots Lx+2, Lx+3
+    const int sec = !lane ? -1 : x == g.Lx - 2 ? 0 : x == 0 ? g.Lx + 2 : -1;
+    const size_t N = g.N;
+    const T* __restrict__ mx = m + (size_t)b * 3 * N;
+    const T* __restrict__ my = mx + N;
+    const T* __restrict__ mz = my + N;
+    const T* __restrict__ cb = c + (size_t)b * N;
+    const uint8_t* __restrict__ mk = MASKED ? mask + (size_t)b * N : nullptr;
+    const T* __restrict__ Vb = V + ((size_t)b * nvec + j0) * 2 * N;
+    T* __restrict__ Wb = W + ((size_t)b * nvec + j0) * 2 * N;
+    const T cJ[3] = {k.cJ[0], k.cJ[1], k.cJ[2]};
+    const T cD = k.cD, cDh = T(0.5) * k.cD, cDr = T(0.86602540378443864676) * k.cD, cK = k.cK;
+
+    // raw data of the next input row, two columns (index 0: x, 1: x + 1)
+    T rm0[2] = {0, 0}, rm1[2] = {0, 0}, rm2[2] = {1, 1}, rc[2] = {0, 0}, ra[NVP][2], rv[NVP][2];
+    bool ract[2] = {true, true};
+#pragma unroll
+    for (int j = 0; j < NVP; ++j) ra[j][0] = ra[j][1] = rv[j][0] = rv[j][1] = T(0);
+    int yin = wrapi(y0 - 2, g.Ly);
+    auto load_raw = [&](int yy) {
+        if (lane) {
+            const unsigned s = (unsigned)(x + g.Lx * yy);
+            const unsigned o = s * (unsigned)sizeof(T);
+            ld2(mx, o, rm0[0], rm0[1]);
+            ld2(my, o, rm1[0], rm1[1]);
+            ld2(mz, o, rm2[0], rm2[1]);
+            ld2(cb, o, rc[0], rc[1]);
+            if constexpr (MASKED) {
+                const unsigned short mm = *reinterpret_cast<const unsigned short*>(mk + s);
+                ract[0] = (mm & 0xff) != 0;
+                ract[1] = (mm >> 8) != 0;
+            }
+#pragma unroll
+            for (int j = 0; j < NVP; ++j) {
+                // slots past the group's end re-read vector 0; never stored
+                const size_t pj = j < nv ? (size_t)(2 * j) * N : 0;
+                ld2_nt(Vb + pj, o, ra[j][0], ra[j][1]);
+                ld2_nt(Vb + pj + N, o, rv[j][0], rv[j][1]);
+            }
+        }
+    };
+    load_raw(yin);
+
+    T acc[5][NVP][2][3];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int j = 0; j < NVP; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[q][j][h][0] = acc[q][j][h][1] = acc[q][j][h][2] = T(0);
+
+    const int nsteps = y1 - y0 + 4;
+    int cw = 0;
+
+    auto step = [&](auto qc, int R, int it) {
+        constexpr int q = decltype(qc)::value;
+#define SL(d) ((q + (d) + 10) % 5)
+        const int buf = it & 1;
+        T e1[2][3], e2[2][3];
+        onb_march(rm0[0], rm1[0], rm2[0], e1[0], e2[0]);
+        onb_march(rm0[1], rm1[1], rm2[1], e1[1], e2[1]);
+        T u[NVP][2][3];
+#pragma unroll
+        for (int j = 0; j < NVP; ++j) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                T a = ra[j][h], bb = rv[j][h];
+                if constexpr (MASKED) {
+                    a = ract[h] ? a : T(0);
+                    bb = ract[h] ? bb : T(0);
+                }
+                u[j][h][0] = a * e1[h][0] + bb * e2[h][0];
+                u[j][h][1] = a * e1[h][1] + bb * e2[h][1];
+                u[j][h][2] = a * e1[h][2] + bb * e2[h][2];
+            }
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                if (lane) st2(&rb[buf][3 * j + cc][0], (unsigned)((x + 2) * sizeof(T)), u[j][0][cc], u[j][1][cc]);
+                if (sec >= 0) st2(&rb[buf][3 * j + cc][0], (unsigned)(sec * sizeof(T)), u[j][0][cc], u[j][1][cc]);
+            }
+        }
+        if (R >= y0 && R < y1) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                cen[cw][0][x + h] = e1[h][0];
+                cen[cw][1][x + h] = e1[h][1];
+                cen[cw][2][x + h] = e1[h][2];
+                cen[cw][3][x + h] = e2[h][0];
+                cen[cw][4][x + h] = e2[h][1];
+                cen[cw][5][x + h] = e2[h][2];
+                if constexpr (MASKED) cen[cw][MASKED ? 6 : 0][x + h] = ract[h] ? T(1) : T(0);
+            }
+        }
+        // own-column offsets, the centre term, and the partner column (dx = +-1)
+#pragma unroll
+        for (int j = 0; j < NVP; ++j) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const T nc = -rc[h];
+                m_offset<0, -2, true>(acc[SL(2)][j][h], u[j][h], cJ, cD, cDh, cDr);
+                m_offset<0, -1, false>(acc[SL(1)][j][h], u[j][h], cJ, cD, cDh, cDr);
+                m_offset<0, 1, false>(acc[SL(-1)][j][h], u[j][h], cJ, cD, cDh, cDr);
+                m_offset<0, 2, false>(acc[SL(-2)][j][h], u[j][h], cJ, cD, cDh, cDr);
+                acc[SL(0)][j][h][0] += nc * u[j][h][0];
+                acc[SL(0)][j][h][1] += nc * u[j][h][1];
+                acc[SL(0)][j][h][2] += nc * u[j][h][2] + cK * u[j][h][2];
+            }
+            // column x + 1 is the dx = +1 neighbour of column x, and x the
+            // dx = -1 neighbour of x + 1
+            m_offset<1, -2, false>(acc[SL(2)][j][0], u[j][1], cJ, cD, cDh, cDr);
+            m_offset<1, -1, false>(acc[SL(1)][j][0], u[j][1], cJ, cD, cDh, cDr);
+            m_offset<1, 0, false>(acc[SL(0)][j][0], u[j][1], cJ, cD, cDh, cDr);
+            m_offset<1, 1, false>(acc[SL(-1)][j][0], u[j][1], cJ, cD, cDh, cDr);
+            m_offset<-1, -1, false>(acc[SL(1)][j][1], u[j][0], cJ, cD, cDh, cDr);
+            m_offset<-1, 0, false>(acc[SL(0)][j][1], u[j][0], cJ, cD, cDh, cDr);
+            m_offset<-1, 1, false>(acc[SL(-1)][j][1], u[j][0], cJ, cD, cDh, cDr);
+            m_offset<-1, 2, false>(acc[SL(-2)][j][1], u[j][0], cJ, cD, cDh, cDr);
+        }
+        if (it + 1 < nsteps) {
+            yin = yin + 1 == g.Ly ? 0 : yin + 1;
+            load_raw(yin);
+        }
+        __syncthreads();
+        // columns x - 2, x - 1 (pair L) and x + 2, x + 3 (pair R) from LDS
+#pragma unroll
+        for (int j = 0; j < NVP; ++j) {
+            T L0[3], L1[3], R0[3], R1[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                ld2(&rb[buf][3 * j + cc][0], (unsigned)(x * sizeof(T)), L0[cc], L1[cc]);
+                ld2(&rb[buf][3 * j + cc][0], (unsigned)((x + 4) * sizeof(T)), R0[cc], R1[cc]);
+            }
+            // column x: dx = -2 -> L0, -1 -> L1, +2 -> R0
+            m_offset<2, -2, false>(acc[SL(2)][j][0], R0, cJ, cD, cDh, cDr);
+            m_offset<2, -1, false>(acc[SL(1)][j][0], R0, cJ, cD, cDh, cDr);
+            m_offset<-1, -1, false>(acc[SL(1)][j][0], L1, cJ, cD, cDh, cDr);
+            m_offset<-1, 0, false>(acc[SL(0)][j][0], L1, cJ, cD, cDh, cDr);
+            m_offset<2, 0, false>(acc[SL(0)][j][0], R0, cJ, cD, cDh, cDr);
+            m_offset<-2, 0, false>(acc[SL(0)][j][0], L0, cJ, cD, cDh, cDr);
+            m_offset<-1, 1, false>(acc[SL(-1)][j][0], L1, cJ, cD, cDh, cDr);
+            m_offset<-2, 1, false>(acc[SL(-1)][j][0], L0, cJ, cD, cDh, cDr);
+            m_offset<-1, 2, false>(acc[SL(-2)][j][0], L1, cJ, cD, cDh, cDr);
+            m_offset<-2, 2, false>(acc[SL(-2)][j][0], L0, cJ, cD, cDh, cDr);
+            // column x + 1: dx = -2 -> L1, +1 -> R0, +2 -> R1
+            m_offset<1, -2, false>(acc[SL(2)][j][1], R0, cJ, cD, cDh, cDr);
+            m_offset<2, -2, false>(acc[SL(2)][j][1], R1, cJ, cD, cDh, cDr);
+            m_offset<1, -1, false>(acc[SL(1)][j][1], R0, cJ, cD, cDh, cDr);
+            m_offset<2, -1, false>(acc[SL(1)][j][1], R1, cJ, cD, cDh, cDr);
+            m_offset<1, 0, false>(acc[SL(0)][j][1], R0, cJ, cD, cDh, cDr);
+            m_offset<2, 0, false>(acc[SL(0)][j][1], R1, cJ, cD, cDh, cDr);
+            m_offset<-2, 0, false>(acc[SL(0)][j][1], L1, cJ, cD, cDh, cDr);
+            m_offset<1, 1, false>(acc[SL(-1)][j][1], R0, cJ, cD, cDh, cDr);
+            m_offset<-2, 1, false>(acc[SL(-1)][j][1], L1, cJ, cD, cDh, cDr);
+            m_offset<-2, 2, false>(acc[SL(-2)][j][1], L1, cJ, cD, cDh, cDr);
+        }
+        const int yo = R - 2;
+        const int cr = cw == 2 ? 0 : cw + 1;
+        if (lane && yo >= y0 && yo < y1) {
+            const unsigned so = (unsigned)(x + g.Lx * yo) * (unsigned)sizeof(T);
+            T wa[NVP][2], wb[NVP][2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const T f10 = cen[cr][0][x + h], f11 = cen[cr][1][x + h], f12 = cen[cr][2][x + h];
+                const T f20 = cen[cr][3][x + h], f21 = cen[cr][4][x + h], f22 = cen[cr][5][x + h];
+                bool on = true;
+                if constexpr (MASKED) on = cen[cr][MASKED ? 6 : 0][x + h] != T(0);
+#pragma unroll
+                for (int j = 0; j < NVP; ++j) {
+                    const T va = f10 * acc[SL(-2)][j][h][0] + f11 * acc[SL(-2)][j][h][1] + f12 * acc[SL(-2)][j][h][2];
+                    const T vb = f20 * acc[SL(-2)][j][h][0] + f21 * acc[SL(-2)][j][h][1] + f22 * acc[SL(-2)][j][h][2];
+                    wa[j][h] = on ? va : T(0);
+                    wb[j][h] = on ? vb : T(0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NVP; ++j) {
+                T* __restrict__ wj = Wb + (size_t)(2 * j) * N;
+                if (j < nv) {
+                    st2_nt(wj, so, wa[j][0], wa[j][1]);
+                    st2_nt(wj + N, so, wb[j][0], wb[j][1]);
                 }
             }
         }
@@ -558,7 +830,7 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
 static const char* kNames[HVP_NVARIANTS] = {"tiled32x8",          "tiled32x8+xcd",      "tiled64x4+xcd",
                                             "tiled128x2+xcd",     "band128x8/4vec+xcd", "band128x8/2vec+xcd",
                                             "band128x8/1vec+xcd", "march/4vec",         "march/2vec",
-                                            "march/1vec"};
+                                            "march/1vec",         "march2/2vec",        "march2/1vec"};
 
 const char* hvp_variant_name(int v) { return (v >= 0 && v < HVP_NVARIANTS) ? kNames[v] : "?"; }
 
@@ -566,10 +838,14 @@ const char* hvp_variant_name(int v) { return (v >= 0 && v < HVP_NVARIANTS) ? kNa
 // that does not overlap itself
 static bool march_fits(const Geo& g) { return g.Lx >= 4 && g.Lx <= 256; }
 
+// the paired march also needs an even width (aligned column pairs)
+static bool march2_fits(const Geo& g) { return march_fits(g) && (g.Lx % 2) == 0; }
+
 bool hvp_variant_ok(int v, const Geo& g, bool f64) {
     if (v < 0 || v >= HVP_NVARIANTS) return false;
     if (f64 && (v == 4 || v == 7)) return false;
-    if (v >= 7 && !march_fits(g)) return false;
+    if (v >= 7 && v <= 9 && !march_fits(g)) return false;
+    if (v >= 10 && !march2_fits(g)) return false;
     return true;
 }
 
@@ -626,6 +902,27 @@ static void go_march(const Geo& g, const CoefD& kd, int batch, const void* m, co
         go_march_xw<T, NVP, 256>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
 }
 
+template <class T, int NVP>
+static void go_march2(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
+                      int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+    const int ngroups = (nvec + NVP - 1) / NVP;
+    const int nstrip = march_strips(g, batch, ngroups);
+    const dim3 grid(batch * nstrip * ngroups);
+    auto launch = [&](auto ntc) {
+        constexpr int NT2 = decltype(ntc)::value;
+        if (mask)
+            hipLaunchKernelGGL((k_hvp_march2<T, NVP, NT2, true>), grid, dim3(NT2), 0, st, g, coef_cast<T>(kd),
+                               (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, nstrip, ngroups);
+        else
+            hipLaunchKernelGGL((k_hvp_march2<T, NVP, NT2, false>), grid, dim3(NT2), 0, st, g, coef_cast<T>(kd),
+                               (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, nstrip, ngroups);
+    };
+    if (g.Lx <= 128)
+        launch(std::integral_constant<int, 64>{});
+    else
+        launch(std::integral_constant<int, 128>{});
+}
+
 template <class T>
 static void go(int v, const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
                int nvec, const void* V, void* W, const int* done, hipStream_t st) {
@@ -643,6 +940,8 @@ static void go(int v, const Geo& g, const CoefD& kd, int batch, const void* m, c
             break;
         case 8: go_march<T, 2>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
         case 9: go_march<T, 1>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 10: go_march2<T, 2>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 11: go_march2<T, 1>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
         default: go_tiled<T, 64, 4, true>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
     }
 }

@@ -46,7 +46,7 @@ hipError_t launch_tangent_hvp(const Geo& g, const CoefD& k, bool f64, bool frame
                               const int* done, hipStream_t st, int variant = -1);
 
 // ---- hvp.hip: frame-layout tangent HVP variants (tile shapes / staging) ----
-constexpr int HVP_NVARIANTS = 10;
+constexpr int HVP_NVARIANTS = 12;
 bool hvp_variant_ok(int variant, const Geo& g, bool f64);
 int hvp_default_variant(const Geo& g, bool f64);
 const char* hvp_variant_name(int variant);
