@@ -133,3 +133,61 @@ def test_sign_rule():
     v[0, 0] = 0.1
     out = O.sign_fix(v)
     assert out[1, 2] == 0.8  # first of the tied largest components made positive
+
+
+# --- thick-restart Lanczos (second inner solver) ---------------------------
+def test_lanczos_matches_jacobi_random_texture_with_restarts():
+    """A small Krylov depth forces several thick restarts."""
+    p = S.ham_3shell(8)
+    h = _ham(p)
+    m = S.random_texture(h.N, np.random.default_rng(11))
+    wd, Vd = O.min_modes_dense(h, m, 4)
+    r = O.min_modes_lanczos(h, m, 4, tol=1e-11, m_max=12, keep=6)
+    assert r.converged and r.iters >= 2
+    assert np.abs(r.evals - wd).max() < 1e-9 * h.h_est()
+    for j in range(4):
+        assert abs(float((r.V[j] * Vd[j]).sum())) > 1 - 1e-8
+
+
+def test_lanczos_residual_estimate_is_the_true_residual():
+    p = S.ham_nn(16)
+    h = _ham(p)
+    m = S.nn_start(0)
+    r = O.min_modes_lanczos(h, m, 2, tol=1e-9, m_max=20)
+    assert r.converged
+    _, _, c, _ = O.energy_grad(h, m)
+    HV = O.tangent_hvp(h, m, c, r.V)
+    for j in range(2):
+        true = np.linalg.norm(HV[j] - r.evals[j] * r.V[j])
+        assert abs(true - r.resid[j]) <= 1e-9 * h.h_est() + 1e-3 * true
+
+
+def test_lanczos_masked_matches_dense_masked():
+    L = 12
+    p = S.ham_nn(L)
+    h = _ham(p)
+    m = S.nn_start(3, L=L)
+    mask = S.random_mask_disc(L, L, 3.5)
+    wd, Vd = O.min_modes_dense(h, m, 2, mask=mask)
+    r = O.min_modes_lanczos(h, m, 2, tol=1e-11, mask=mask, m_max=16)
+    assert r.converged
+    assert np.allclose(r.evals, wd, atol=1e-9)
+    assert np.all(r.V[:, :, mask == 0] == 0)
+    assert abs(float((r.V[0] * Vd[0]).sum())) > 1 - 1e-8
+
+
+def test_lanczos_fm_closed_form_and_lobpcg_agree():
+    """24x24 three-shell ferromagnet: the 4 lowest eigenvalues (2-fold pairs)
+    equal the closed form, and the two independent solvers agree."""
+    L = 24
+    p = S.ham_3shell(L)
+    h = _ham(p)
+    ref = CF.fm_z_spectrum(L, L, p.J, p.K, p.B[2])[:4]
+    r = O.min_modes_lanczos(h, S.uniform(h.N), 4, tol=1e-9, m_max=40, keep=16, max_restarts=200)
+    assert r.converged
+    assert np.abs(r.evals - ref).max() < 1e-8 * h.h_est()
+    m = S.three_shell_start(L, seed=5)
+    a = O.min_modes_lanczos(h, m, 2, tol=1e-9, m_max=32)
+    b = O.min_modes(h, m, 2, tol=1e-9, max_iter=400)
+    assert a.converged and b.converged
+    assert np.abs(a.evals - b.evals).max() < 1e-8 * h.h_est()
