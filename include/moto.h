@@ -289,6 +289,46 @@ moto_status moto_descend(moto_plan p, moto_dtype hvp, double *m, const double *v
                          moto_stream stream);
 
 /* ---------------------------------------------------------------------
+ * Second inner solver: the k smallest eigenpairs of the (masked) tangent
+ * Hessian by thick-restart Lanczos with full reorthogonalisation (Results,
+ * "Bilayer MMF": HVP-Lanczos as the alternative Krylov solver; Discussion:
+ * Krylov depth and reorthogonalisation are the solver's hyperparameters).
+ * One HVP per step; each new Krylov vector is orthogonalised against the
+ * whole basis twice (classical Gram-Schmidt, FP64 coefficients); after
+ * m_max steps one wavefront diagonalises the projected matrix in FP64 and
+ * the solve either stops (every residual estimate |beta_m y_m,i|, i < k, at
+ * most tol * moto_hessian_norm_bound) or restarts from the `keep` lowest
+ * Ritz vectors and the residual direction.  Same arguments, outputs,
+ * stopping rule and sign rule as moto_min_modes; info->iters counts
+ * restarts.  The cycles after the first are replayed as a HIP graph.  A
+ * single-vector Krylov space holds one direction per eigenspace: of an
+ * exactly degenerate cluster it returns one copy (further copies only appear
+ * through rounding); moto_min_modes resolves multiplicities.
+ *   m_max   Krylov depth, 3 <= m_max <= 64 and m_max < 2N
+ *   keep    Ritz vectors kept at a restart, k <= keep < m_max (0: max(k + 2, m_max / 2))
+ *   warm    1: start from the sum of the k vectors in V (ambient FP64)
+ * k <= 16.  Errors: MOTO_EINVAL for out-of-range sizes or options,
+ * MOTO_EWORKSPACE if ws is NULL or short, MOTO_EHIP on a runtime error.
+ * Workspace: moto_min_modes_lanczos_workspace(p, hvp, m_max) bytes. */
+typedef struct {
+    double tol;           /* relative to the norm bound (default 1e-10 F64, 1e-5 F32) */
+    int32_t m_max;        /* default 32 */
+    int32_t keep;         /* default 0 = max(k + 2, m_max / 2) */
+    int32_t max_restarts; /* default 200 */
+    int32_t warm;         /* default 0 */
+    uint64_t seed;        /* start vector when not warm */
+    int32_t use_graph;    /* default 1 */
+    int32_t reserved;
+} moto_lanczos_opts;
+
+void moto_default_lanczos_opts(moto_dtype hvp, moto_lanczos_opts *o);
+size_t moto_min_modes_lanczos_workspace(moto_plan p, moto_dtype hvp, int32_t m_max);
+moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double *m, const uint8_t *mask, int32_t k,
+                                   const moto_lanczos_opts *opts /* host */, double *evals, double *V,
+                                   double *resid, moto_info *info /* host */, void *ws, size_t ws_bytes,
+                                   moto_stream stream);
+
+/* ---------------------------------------------------------------------
  * Driver of the five calls: one saddle search (Algorithm 1, bilayer-kernel
  * loop).  Repeat {energy_grad; min_modes(k, warm-started); reflected_step}
  * until ||F_mmf||_2 <= tau_F, then certify with a k_cert >= 2 solve:

@@ -496,6 +496,164 @@ moto_status moto_min_modes(moto_plan p, moto_dtype hvp, const double* m, const u
 }
 
 // ---------------------------------------------------------------------------
+// Thick-restart Lanczos (second inner solver)
+// ---------------------------------------------------------------------------
+void moto_default_lanczos_opts(moto_dtype hvp, moto_lanczos_opts* o) {
+    if (!o) return;
+    o->tol = hvp == MOTO_F64 ? 1e-10 : 1e-5;
+    o->m_max = 32;
+    o->keep = 0;
+    o->max_restarts = 200;
+    o->warm = 0;
+    o->seed = 0x2509262690ull;
+    o->use_graph = 1;
+    o->reserved = 0;
+}
+
+namespace {
+struct LzLayout {
+    size_t mT, cT, c64, Q, part, ctrl, total;
+    int n2, nblk;
+};
+
+LzLayout lz_layout(const moto_plan p, moto_dtype hvp, int m_max) {
+    LzLayout L;
+    const size_t N = p->g.N;
+    const size_t es = hvp == MOTO_F64 ? sizeof(double) : sizeof(float);
+    L.n2 = 2 * (int)N;
+    L.nblk = lz_blocks(L.n2);
+    const int nblk_o = (int)((N + NT - 1) / NT);
+    size_t o = 0;
+    L.mT = o;
+    o += al(es * 3 * N);
+    L.cT = o;
+    o += al(es * N);
+    L.c64 = o;
+    o += al(sizeof(double) * N);
+    L.Q = o;
+    o += al(es * (size_t)(m_max + 1) * L.n2);
+    size_t part = sizeof(double) * NPART * (size_t)p->g.tiles;
+    part = std::max(part, sizeof(double) * (size_t)L.nblk * (LZ_MAXM + 2));
+    part = std::max(part, sizeof(double) * ((size_t)nblk_o * MAXB * 3 + MAXB));
+    L.part = o;
+    o += al(part);
+    L.ctrl = o;
+    o += al(sizeof(LzCtrl));
+    L.total = o;
+    return L;
+}
+
+int lz_keep(int k, int m_max, int keep) { return keep > 0 ? keep : std::max(k + 2, m_max / 2); }
+}  // namespace
+
+size_t moto_min_modes_lanczos_workspace(moto_plan p, moto_dtype hvp, int32_t m_max) {
+    if (!p || !hvp_ok(hvp) || m_max < 3 || m_max > LZ_MAXM) return 0;
+    return lz_layout(p, hvp, m_max).total;
+}
+
+moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double* m, const uint8_t* mask, int32_t k,
+                                   const moto_lanczos_opts* opts, double* evals, double* V, double* resid,
+                                   moto_info* info, void* ws_, size_t ws_bytes, moto_stream stream) {
+    if (!p || !m || !V || !evals || k < 1 || k > MAXB || !hvp_ok(hvp)) return MOTO_EINVAL;
+    moto_lanczos_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_lanczos_opts(hvp, &o);
+    const int keep = lz_keep(k, o.m_max, o.keep);
+    if (o.m_max < 3 || o.m_max > LZ_MAXM || keep < k || keep >= o.m_max || !(o.tol >= 0.0) ||
+        o.max_restarts < 0 || o.warm < 0 || o.warm > 1)
+        return MOTO_EINVAL;
+    if (o.m_max + 1 > 2 * p->g.N) return MOTO_EINVAL;  // the Krylov basis must fit the space
+    char* ws = (char*)ws_;
+    const LzLayout L = lz_layout(p, hvp, o.m_max);
+    if (!ws) return MOTO_EWORKSPACE;
+    if (ws_bytes < L.total) return MOTO_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = hvp == MOTO_F64;
+    const int N = p->g.N;
+    double* c64 = (double*)(ws + L.c64);
+    double* part = (double*)(ws + L.part);
+    LzCtrl* ctrl = (LzCtrl*)(ws + L.ctrl);
+    void* Q = ws + L.Q;
+    const size_t es = f64 ? sizeof(double) : sizeof(float);
+    HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, nullptr, nullptr, c64, nullptr, part, st));
+    const void* mT = m;
+    const void* cT = c64;
+    if (!f64) {
+        HIP_TRY(launch_f64_to_f32(m, (float*)(ws + L.mT), 3 * (size_t)N, st));
+        HIP_TRY(launch_f64_to_f32(c64, (float*)(ws + L.cT), (size_t)N, st));
+        mT = ws + L.mT;
+        cT = ws + L.cT;
+    }
+    const int hv_var = tuned_variant(p, hvp, 1, 1);
+    HIP_TRY(launch_lz_init(f64, N, Q, m, o.warm ? V : nullptr, o.warm ? k : 0, mask, o.seed, part, L.nblk, ctrl,
+                           o.m_max, st));
+    const double tol_abs = o.tol * p->hest;
+    auto steps = [&](int j0, hipStream_t s) -> hipError_t {
+        for (int j = j0; j < o.m_max; ++j) {
+            hipError_t e = launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, 1, (char*)Q + es * j * L.n2,
+                                              (char*)Q + es * (j + 1) * L.n2, &ctrl->done, s, hv_var);
+            if (e == hipSuccess) e = launch_lz_orth(f64, L.n2, Q, j, part, L.nblk, ctrl, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    // the cycles after the first repeat the same launches (steps keep..m_max-1):
+    // captured once as a HIP graph and replayed
+    hipGraphExec_t gexec = nullptr;
+    if (o.use_graph) {
+        long long key[8];
+        std::memcpy(&key[0], &tol_abs, sizeof(double));
+        key[1] = (long long)hvp + 1000;  // distinct from the eigen-solver keys
+        key[2] = o.m_max;
+        key[3] = keep;
+        key[4] = k;
+        key[5] = -1;
+        key[6] = hv_var;
+        key[7] = N;
+        for (auto& ge : p->graphs)
+            if (ge.valid && ge.ws == (const void*)ws && ge.mask == (const void*)mask &&
+                std::memcmp(ge.key, key, sizeof(key)) == 0)
+                gexec = ge.exec;
+        if (!gexec) {
+            auto cyc = [&](hipStream_t s) { return steps(keep, s); };
+            gexec = capture_chunk(p, cyc, key, ws, mask);
+        }
+    }
+    int hdr[4];
+    for (int cycle = 0; cycle <= o.max_restarts + 1; ++cycle) {
+        if (cycle == 0)
+            HIP_TRY(steps(0, st));
+        else if (gexec)
+            HIP_TRY(hipGraphLaunch(gexec, st));
+        else
+            HIP_TRY(steps(keep, st));
+        HIP_TRY(launch_lz_rr_restart(f64, L.n2, Q, k, keep, tol_abs, o.max_restarts, o.m_max, L.nblk, ctrl, st));
+        moto_status rs = readback(p, ctrl, sizeof(hdr), hdr, st);
+        if (rs != MOTO_OK) return rs;
+        if (hdr[0]) break;
+    }
+    EigArgs a;
+    a.n2 = L.n2;
+    a.mb = k;
+    a.k = k;
+    a.max_iter = 0;
+    a.tol_abs = tol_abs;
+    a.drop = 0.0;
+    HIP_TRY(launch_eig_output(f64, a, Q, m, N, V, part, &ctrl->out, evals, resid, nullptr, st));
+    EigCtrl hc;
+    moto_status rs = readback(p, &ctrl->out, 32, &hc, st);
+    if (rs != MOTO_OK) return rs;
+    if (info) {
+        info->status = hc.status;
+        info->iters = hc.iters;
+        info->n_hvp = hc.n_hvp;
+    }
+    return MOTO_OK;
+}
+
+// ---------------------------------------------------------------------------
 void moto_default_step_opts(moto_step_opts* o) {
     if (!o) return;
     o->rule = 0;

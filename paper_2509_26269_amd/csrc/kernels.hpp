@@ -86,6 +86,33 @@ struct EigArgs {
     double drop;   // rank threshold of the orthonormalisations (relative)
 };
 
+// ---- lanczos.hip ----
+constexpr int LZ_MAXM = 64;           // max Krylov depth
+constexpr int LZ_LDT = LZ_MAXM + 1;   // leading dimension of the projected matrix
+// Control block of one thick-restart Lanczos solve, resident in device memory.
+struct LzCtrl {
+    int done;        // 1 once stopped: later step launches are no-ops
+    int status;      // MOTO_CONVERGED, MOTO_NOT_CONVERGED, MOTO_NAN
+    int restarts;    // thick restarts taken
+    int m_eff;       // Krylov depth of the current cycle (smaller after a breakdown)
+    int m_max;       // Krylov depth asked for
+    int nkeep;       // Ritz vectors formed by the last restart
+    long long n_hvp; // HVP columns applied
+    double beta;     // |w| of the last step
+    double h[LZ_MAXM + 1];           // reorthogonalisation coefficients of the current pass
+    double T[LZ_LDT * LZ_LDT];       // projected matrix Q^T H Q (and beta_m below the last column)
+    double Y[LZ_MAXM * LZ_MAXM];     // Ritz vectors of T, vector i at [i * LZ_MAXM]
+    double theta[LZ_MAXM], resid[LZ_MAXM];
+    EigCtrl out;     // eigenvalues, residuals and counters in the eigen-solve layout
+};
+int lz_blocks(int n2);
+hipError_t launch_lz_init(bool f64, int N, void* Q, const double* m, const double* Vwarm, int nwarm,
+                          const uint8_t* mask, uint64_t seed, double* part, int nblk, LzCtrl* ctrl, int m_max,
+                          hipStream_t st);
+hipError_t launch_lz_orth(bool f64, int n2, void* Q, int j, double* part, int nblk, LzCtrl* ctrl, hipStream_t st);
+hipError_t launch_lz_rr_restart(bool f64, int n2, void* Q, int k, int keep, double tol_abs, int max_restarts,
+                                int m_max, int nblk, LzCtrl* ctrl, hipStream_t st);
+
 hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m, const double* Vwarm, int nwarm,
                            const void* Xsave, int use_save, const uint8_t* mask, int N, uint64_t seed,
                            EigCtrl* ctrl, hipStream_t st);

@@ -43,6 +43,12 @@ class EigOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class LanczosOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("m_max", ctypes.c_int32), ("keep", ctypes.c_int32),
+                ("max_restarts", ctypes.c_int32), ("warm", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("n_hvp", ctypes.c_int64)]
 
@@ -108,6 +114,10 @@ def lib():
         "moto_min_modes_workspace": (_sz, [_vp, _i32, _i32, _i32]),
         "moto_min_modes": (_i32, [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(EigOpts), _vp, _vp, _vp,
                                   ctypes.POINTER(Info), _vp, _sz, _vp]),
+        "moto_default_lanczos_opts": (None, [_i32, ctypes.POINTER(LanczosOpts)]),
+        "moto_min_modes_lanczos_workspace": (_sz, [_vp, _i32, _i32]),
+        "moto_min_modes_lanczos": (_i32, [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(LanczosOpts), _vp, _vp, _vp,
+                                          ctypes.POINTER(Info), _vp, _sz, _vp]),
         "moto_step_state_bytes": (_sz, [_vp, _i32]),
         "moto_reflected_step": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(StepOpts), _vp, _vp, _vp]),
         "moto_descend_workspace": (_sz, [_vp, _i32, ctypes.POINTER(DescendOpts)]),
@@ -349,6 +359,45 @@ class MinModes:
     status: int
     iters: int
     n_hvp: int
+
+
+def lanczos_opts(dtype: int = MOTO_F64, **kw) -> LanczosOpts:
+    o = LanczosOpts()
+    lib().moto_default_lanczos_opts(dtype, ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class LanczosWorkspace:
+    """Reusable workspace of the Lanczos solver (Krylov basis of m_max + 1 vectors)."""
+
+    def __init__(self, plan: Plan, hvp: int, m_max: int = 32, device="cuda"):
+        self.nbytes = int(lib().moto_min_modes_lanczos_workspace(plan.handle, hvp, m_max))
+        if self.nbytes == 0:
+            raise MotoError("moto_min_modes_lanczos_workspace: invalid arguments")
+        self.buf = _ws(self.nbytes, device)
+
+
+def moto_min_modes_lanczos(plan: Plan, m: torch.Tensor, k: int, hvp: int = MOTO_F64,
+                           mask: Optional[torch.Tensor] = None, opts: Optional[LanczosOpts] = None,
+                           V0: Optional[torch.Tensor] = None, ws: Optional[LanczosWorkspace] = None,
+                           stream=None) -> "MinModes":
+    o = opts if opts is not None else lanczos_opts(hvp)
+    dev = m.device
+    V = torch.zeros(k, 3, plan.N, dtype=torch.float64, device=dev) if V0 is None else V0.clone().contiguous()
+    if V0 is not None and o.warm == 0:
+        o.warm = 1
+    evals = torch.empty(k, dtype=torch.float64, device=dev)
+    resid = torch.empty(k, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = LanczosWorkspace(plan, hvp, o.m_max, dev)
+    info = Info()
+    _check(lib().moto_min_modes_lanczos(plan.handle, hvp, _ptr(m), _ptr(mask), k, ctypes.byref(o), _ptr(evals),
+                                        _ptr(V), _ptr(resid), ctypes.byref(info), _ptr(ws.buf), ws.nbytes,
+                                        _stream(stream)),
+           "moto_min_modes_lanczos")
+    return MinModes(evals, V, resid, info.status, info.iters, info.n_hvp)
 
 
 class EigWorkspace:

@@ -1,0 +1,193 @@
+"""GPU parity of the second inner solver (moto_min_modes_lanczos:
+thick-restart Lanczos with full reorthogonalisation) against the FP64
+oracle (its Lanczos, LOBPCG and dense Jacobi, which agree with each other)
+and the closed-form ferromagnet spectrum.  Same bars as the LOBPCG tests:
+eigenvalues |d lambda| <= 1e-5 max(|lambda|, h_est) (FP32 adds 1e-5 h_est);
+vectors 1 - |cos| <= 1e-8 (FP64) or sin(angle) <= 1e-3 (FP32) where the gap
+is >= 1e-3 h_est."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_26269_amd import synth as S
+from tests import closed_forms as CF
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _M():
+    from paper_2509_26269_amd import moto as M
+
+    return M
+
+
+def _dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _check_pairs(ev, V, ref_ev, ref_V, hest, fp32, gap_ok):
+    for j in range(len(ref_ev)):
+        assert abs(ev[j] - ref_ev[j]) <= 1e-5 * max(abs(ref_ev[j]), hest) + (0 if not fp32 else 1e-5 * hest)
+        if gap_ok[j]:
+            cos = abs(float((V[j] * ref_V[j]).sum()))
+            if fp32:
+                assert np.sqrt(max(0.0, 1 - cos * cos)) <= 1e-3
+            else:
+                assert 1 - cos <= 1e-8
+
+
+def _gaps(w, k, hest):
+    return [min(abs(w[j] - w[i]) for i in range(len(w)) if i != j) >= 1e-3 * hest for j in range(k)]
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_lanczos_fp64_matches_oracle_nn16(k):
+    M = _M()
+    p = S.ham_nn(16)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m = S.nn_start(0)
+    r = M.moto_min_modes_lanczos(plan, _dev(m), k, M.MOTO_F64, opts=M.lanczos_opts(M.MOTO_F64, tol=1e-10))
+    assert r.status == M.CONVERGED, (r.status, r.iters)
+    ro = O.min_modes_lanczos(h, m, k + 2, tol=1e-11, m_max=32)
+    w = ro.evals
+    _check_pairs(_np(r.evals), _np(r.V), w[:k], ro.V[:k], h.h_est(), False, _gaps(w, k, h.h_est()))
+    assert np.all(_np(r.resid) <= 1e-10 * h.h_est())
+    V = _np(r.V)
+    assert np.allclose(np.linalg.norm(V.reshape(k, -1), axis=1), 1.0, atol=1e-12)
+    assert np.abs((V * m[None]).sum(1)).max() < 1e-12  # tangent
+
+
+@pytest.mark.parametrize("hvp", ["f64", "f32"])
+def test_lanczos_three_shell_64_matches_oracle(hvp):
+    M = _M()
+    L = 64
+    p = S.ham_3shell(L)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m = S.three_shell_start(L, seed=1, kind="antiskyrmion")
+    dt = M.MOTO_F64 if hvp == "f64" else M.MOTO_F32
+    tol = 1e-10 if hvp == "f64" else 1e-5
+    r = M.moto_min_modes_lanczos(plan, _dev(m), 4, dt, opts=M.lanczos_opts(dt, tol=tol, m_max=40))
+    assert r.status == M.CONVERGED, (r.status, r.iters, _np(r.resid))
+    ro = O.min_modes(h, m, 6, tol=1e-11, max_iter=600)
+    w = ro.evals
+    _check_pairs(_np(r.evals), _np(r.V), w[:4], ro.V[:4], h.h_est(), hvp == "f32", _gaps(w, 4, h.h_est()))
+
+
+def test_lanczos_many_restarts_matches_oracle():
+    """A shallow Krylov depth forces many thick restarts."""
+    M = _M()
+    p = S.ham_3shell(24)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m = S.three_shell_start(24, seed=4)
+    r = M.moto_min_modes_lanczos(plan, _dev(m), 2, M.MOTO_F64,
+                                 opts=M.lanczos_opts(M.MOTO_F64, tol=1e-10, m_max=10, keep=5, max_restarts=2000))
+    assert r.status == M.CONVERGED and r.iters >= 3, (r.status, r.iters)
+    ro = O.min_modes_lanczos(h, m, 4, tol=1e-11, m_max=32)
+    w = ro.evals
+    _check_pairs(_np(r.evals), _np(r.V), w[:2], ro.V[:2], h.h_est(), False, _gaps(w, 2, h.h_est()))
+
+
+@pytest.mark.parametrize("hvp", ["f64", "f32"])
+def test_lanczos_fm_closed_form_128(hvp):
+    """Full-size 128x128 uniform state: every returned Ritz value is a
+    closed-form spin-wave eigenvalue and the first is the minimum.  The
+    ferromagnet's eigenvalues come in exactly degenerate pairs; a single-vector
+    Krylov space holds one direction per eigenspace (a second copy appears
+    only through rounding), so the values returned need not repeat the
+    multiplicities; the block solver's test pins those."""
+    M = _M()
+    L = 128
+    p = S.ham_3shell(L)
+    plan = M.Plan.from_params(p)
+    dt = M.MOTO_F64 if hvp == "f64" else M.MOTO_F32
+    tol = 1e-9 if hvp == "f64" else 1e-5
+    r = M.moto_min_modes_lanczos(plan, _dev(S.uniform(L * L)), 4, dt,
+                                 opts=M.lanczos_opts(dt, tol=tol, m_max=48, keep=24, max_restarts=400))
+    assert r.status == M.CONVERGED, (r.status, r.iters)
+    spec = CF.fm_z_spectrum(L, L, p.J, p.K, p.B[2])
+    hest = plan.hessian_norm_bound()
+    tol_e = (1e-8 if hvp == "f64" else 1e-5) * hest
+    ev = _np(r.evals)
+    assert abs(ev[0] - spec[0]) <= tol_e
+    assert np.all(np.diff(ev) >= -tol_e)
+    for e in ev:
+        assert np.min(np.abs(spec - e)) <= tol_e
+
+
+def test_lanczos_full_size_residual_property_and_lobpcg_agreement():
+    """128x128 skyrmion start, FP32 HVP, k = 4: every returned pair is an
+    eigenpair of the oracle operator within the tolerance, and the two GPU
+    solvers agree on the eigenvalues."""
+    M = _M()
+    L = 128
+    p = S.ham_3shell(L)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m = S.three_shell_start(L, seed=0, kind="skyrmion")
+    md = _dev(m)
+    r = M.moto_min_modes_lanczos(plan, md, 4, M.MOTO_F32, opts=M.lanczos_opts(M.MOTO_F32, tol=1e-5))
+    assert r.status == M.CONVERGED
+    _, _, c, _ = O.energy_grad(h, m)
+    V = _np(r.V)
+    for j in range(4):
+        Hv = O.tangent_hvp(h, m, c, V[j])
+        assert np.linalg.norm(Hv - _np(r.evals)[j] * V[j]) <= 2e-5 * h.h_est()
+    rl = M.moto_min_modes(plan, md, 4, M.MOTO_F32, opts=M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=400))
+    assert rl.status == M.CONVERGED
+    assert np.abs(_np(r.evals) - _np(rl.evals)).max() <= 2e-5 * h.h_est()
+
+
+def test_lanczos_masked_matches_oracle():
+    M = _M()
+    L = 12
+    p = S.ham_nn(L)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m = S.nn_start(3, L=L)
+    mask = S.random_mask_disc(L, L, 3.5)
+    r = M.moto_min_modes_lanczos(plan, _dev(m), 2, M.MOTO_F64, mask=_dev(mask, torch.uint8),
+                                 opts=M.lanczos_opts(M.MOTO_F64, tol=1e-11, m_max=24))
+    assert r.status == M.CONVERGED, (r.status, r.iters)
+    ro = O.min_modes_lanczos(h, m, 2, tol=1e-11, mask=mask, m_max=24)
+    assert np.allclose(_np(r.evals), ro.evals, atol=1e-9)
+    V = _np(r.V)
+    assert np.all(V[:, :, mask == 0] == 0)
+    assert abs(float((V[0] * ro.V[0]).sum())) > 1 - 1e-8
+
+
+def test_lanczos_graph_replays_match_eager_bitwise_and_warm_start():
+    M = _M()
+    p = S.ham_3shell(32)
+    plan = M.Plan.from_params(p)
+    m = _dev(S.three_shell_start(32, seed=2))
+    ws = M.LanczosWorkspace(plan, M.MOTO_F32, 16)
+    outs = []
+    for g in (0, 1, 1):
+        o = M.lanczos_opts(M.MOTO_F32, tol=1e-6, m_max=16, use_graph=g)
+        outs.append(M.moto_min_modes_lanczos(plan, m, 2, M.MOTO_F32, opts=o, ws=ws))
+    for r in outs[1:]:
+        assert r.status == outs[0].status and r.iters == outs[0].iters
+        assert torch.equal(r.evals, outs[0].evals) and torch.equal(r.V, outs[0].V)
+    # a warm start from the converged vectors converges in fewer HVPs
+    o = M.lanczos_opts(M.MOTO_F32, tol=1e-6, m_max=16)
+    rw = M.moto_min_modes_lanczos(plan, m, 2, M.MOTO_F32, opts=o, V0=outs[0].V, ws=ws)
+    assert rw.status == M.CONVERGED and rw.n_hvp <= outs[0].n_hvp
+    assert np.abs(_np(rw.evals) - _np(outs[0].evals)).max() <= 1e-5 * plan.hessian_norm_bound()
+
+
+def test_lanczos_bad_arguments_rejected():
+    M = _M()
+    plan = M.Plan.from_params(S.ham_nn(8))
+    m = _dev(S.uniform(64))
+    for kw in ({"m_max": 65}, {"m_max": 8, "keep": 8}, {"m_max": 8, "keep": 1}):
+        with pytest.raises(M.MotoError):
+            M.moto_min_modes_lanczos(plan, m, 2, M.MOTO_F64, opts=M.lanczos_opts(M.MOTO_F64, **kw),
+                                     ws=M.LanczosWorkspace(plan, M.MOTO_F64, 16))
