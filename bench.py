@@ -271,6 +271,25 @@ def main():
             sweep[f"guard{guard}"] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "iters": rg.iters,
                                       "status": M.STATUS_NAMES[rg.status]}
         extra["min_modes_128_k4_guard_sweep"] = sweep
+        # the second inner solver on the same state: thick-restart Lanczos
+        lz = {}
+        for mm in (32, 48):
+            wsl = M.LanczosWorkspace(plan, M.MOTO_F32, mm)
+            ol = M.lanczos_opts(M.MOTO_F32, tol=1e-5, m_max=mm)
+            M.moto_min_modes_lanczos(plan, m1, 4, M.MOTO_F32, opts=ol, ws=wsl)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                rl = M.moto_min_modes_lanczos(plan, m1, 4, M.MOTO_F32, opts=ol, ws=wsl)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            lz[f"m_max{mm}"] = {"ms": round(1e3 * float(np.median(ts)), 3), "restarts": rl.iters,
+                                "n_hvp": int(rl.n_hvp), "status": M.STATUS_NAMES[rl.status],
+                                "lambda": [round(float(x), 6) for x in rl.evals.cpu()],
+                                "workspace_bytes": wsl.nbytes}
+        extra["lanczos_128_k4"] = lz
+        extra["lobpcg_128_k4_lambda"] = [round(float(x), 6) for x in r.evals.cpu()]
     if not args.hvp_only and not args.eigen_only:
         # differentiation form on 64x64 (energy, backward, double backward), FP32 spins
         from paper_2509_26269_amd import autograd as AG
