@@ -613,16 +613,23 @@ def rotate(m, d) -> np.ndarray:
     return out / np.sqrt((out * out).sum(0))
 
 
+CG_RESTART = 50   # conjugate-gradient restart period (steps)
+
+
 @dataclass
 class StepRule:
     """Outer optimiser (shared rule for climb and descent): L-BFGS two-loop on
     G (memory `mem`, projection transport of the stored pairs, pairs with
     s.y <= sy_min skipped, gamma = s.y / y.y of the newest valid pair,
     gamma0 = alpha0 when none; reset when the direction does not point along
-    -G), or a fixed step alpha0 * (-G); then the per-spin rotation cap
+    -G), or a fixed step alpha0 * (-G), or nonlinear conjugate gradients
+    ("cg", the paper's second outer optimiser): p = -G + beta p_prev on the
+    transported previous direction with the Fletcher-Reeves beta = |G|^2 /
+    |P G_prev|^2, restarted (beta = 0) every CG_RESTART steps and whenever p
+    is not a descent direction, step alpha0 p; then the per-spin rotation cap
     theta_max; no line search."""
 
-    kind: str = "lbfgs"           # "lbfgs" | "fixed"
+    kind: str = "lbfgs"           # "lbfgs" | "fixed" | "cg"
     mem: int = 8
     theta_max: float = 0.1
     alpha0: Optional[float] = None  # default 1 / h_est
@@ -637,14 +644,29 @@ class LBFGS:
         self.Y: list = []
         self.d_prev = None
         self.G_prev = None
+        self.c_prev = 1.0
+        self.n_dir = 0   # directions computed so far
 
     def reset(self):
         self.S, self.Y = [], []
 
     def direction(self, m, G) -> np.ndarray:
         r = self.rule
+        alpha_cg = None
         if r.kind == "fixed":
             d = -self.alpha0 * G
+        elif r.kind == "cg":
+            alpha_cg = self.alpha0
+            p = -G
+            if self.d_prev is not None and self.n_dir % CG_RESTART != 0:
+                s = project(m, self.d_prev)          # = c_prev * (transported p_prev)
+                gp = project(m, self.G_prev)
+                gpgp = float((gp * gp).sum())
+                beta = float((G * G).sum()) / gpgp if gpgp > 0.0 else 0.0
+                p = -G + (beta / self.c_prev) * s
+                if float((p * G).sum()) >= 0.0:
+                    p = -G
+            d = alpha_cg * p
         else:
             if self.d_prev is not None:
                 self.S = [project(m, s) for s in self.S]
@@ -681,8 +703,11 @@ class LBFGS:
         d = project(m, d)
         th = np.sqrt((d * d).sum(0))
         tmax = float(th.max()) if th.size else 0.0
-        if tmax > r.theta_max:
-            d = d * (r.theta_max / tmax)
+        cap = r.theta_max / tmax if tmax > r.theta_max else 1.0
+        d = d * cap
+        if alpha_cg is not None:
+            self.c_prev = alpha_cg * cap   # the step taken is c_prev times the direction
+        self.n_dir += 1
         self.d_prev = d
         self.G_prev = G.copy()
         return d

@@ -120,3 +120,64 @@ def test_dedupe_metric():
     d = S.random_tangent(m, 1, rng)[0]
     d = 0.01 * d / np.linalg.norm(d, axis=0).max()
     assert O.max_site_angle(m, O.rotate(m, d)) == pytest.approx(0.01, rel=1e-6)
+
+
+# --- the second outer optimiser: nonlinear conjugate gradients ------------
+def test_cg_rule_stoner_wohlfarth_closed_form():
+    """The CG rule climbs to the coherent-rotation saddle and both descents
+    reach the closed-form minima with the closed-form barrier."""
+    p = S.ham_sw(8)
+    h = _ham(p)
+    b, K = p.B[0], p.K
+    cg = O.StepRule(kind="cg")
+    m0 = S.add_tilt_noise(S.uniform(h.N, (1, 0, 0)), 0.02, np.random.default_rng(0))
+    r = O.saddle_search(h, m0, tau_F=1e-8, rule=cg)
+    assert r.status == O.SADDLE
+    assert r.evals[0] == pytest.approx(b - 2 * K, abs=1e-8)
+    assert r.evals[1] == pytest.approx(b, abs=1e-8)
+    mp, mm = CF.sw_minima(b, K)
+    for sgn in (+1, -1):
+        d = O.descend(h, r.m, r.V[0], sgn, tau_F=1e-8, rule=cg)
+        assert d.converged and d.lam1 > 0
+        assert r.E - d.E == pytest.approx(CF.sw_barrier(h.N, b, K), rel=1e-9)
+        assert min(np.abs(d.m - mp[:, None]).max(), np.abs(d.m - mm[:, None]).max()) < 1e-6
+
+
+def test_cg_rule_first_step_is_steepest_and_beta_is_fletcher_reeves():
+    """First step: alpha0 (-G).  Second step written out by hand from the
+    transported quantities: beta = |G|^2 / |P G_prev|^2, p = -G + beta
+    P p_prev, step alpha0 p; the restart period resets to steepest."""
+    p = S.ham_nn(8)
+    h = _ham(p)
+    m = S.nn_start(4, L=8)
+    rule = O.StepRule(kind="cg", theta_max=10.0)
+    a0 = 1.0 / h.h_est()
+    opt = O.LBFGS(rule, a0)
+    G1 = -O.energy_grad(h, m)[3]
+    d1 = opt.direction(m, G1)
+    assert np.allclose(d1, O.project(m, -a0 * G1), atol=1e-15)
+    m2 = O.rotate(m, d1)
+    G2 = -O.energy_grad(h, m2)[3]
+    d2 = opt.direction(m2, G2)
+    gp = O.project(m2, G1)
+    beta = float((G2 * G2).sum()) / float((gp * gp).sum())
+    p_prev = O.project(m2, -G1)                 # the first direction, transported
+    pdir = -G2 + beta * p_prev
+    if float((pdir * G2).sum()) >= 0:
+        pdir = -G2
+    assert np.allclose(d2, O.project(m2, a0 * pdir), rtol=1e-10, atol=1e-14)
+    # at the restart period the direction is steepest again
+    opt.n_dir = O.CG_RESTART
+    m3 = O.rotate(m2, d2)
+    G3 = -O.energy_grad(h, m3)[3]
+    assert np.allclose(opt.direction(m3, G3), O.project(m3, -a0 * G3), atol=1e-15)
+
+
+def test_cg_rule_reaches_an_index_one_saddle_by_exact_inertia():
+    p = S.ham_nn(16)
+    h = _ham(p)
+    m0 = S.add_tilt_noise(S.skyrmion(16, 16, 1.0), 0.05, np.random.default_rng(0))
+    r = O.saddle_search(h, m0, tau_F=1e-6, rule=O.StepRule(kind="cg"))
+    assert r.status == O.SADDLE
+    w = np.linalg.eigvalsh(O.dense_tangent_hessian(h, r.m))
+    assert int((w < -1e-6 * h.h_est()).sum()) == 1
