@@ -9,7 +9,8 @@ Headline (the 128x128 three-shell workload, FP32 HVP):
   * wall time of the k = 4 eigen-solve (residual 1e-5) on one 128x128 state;
   * saddle searches/s (k = 2, FP32 HVP, tau_F = 1e-5, capped outer
     iterations): 64 searches on 128x128 in one persistent launch, 256 on
-    uneven 32..96 lattices in one launch, and searches one at a time;
+    uneven 32..96 lattices in one launch, and searches one at a time
+    (L-BFGS, and the nonlinear-CG outer rule on the same starts);
   * the FP64 CPU oracle timed on a bounded sample of the same HVP workload.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
@@ -350,27 +351,35 @@ def main():
             print(f"[bench] {n} saddle searches on uneven 32..96 lattices in one persistent launch",
                   file=sys.stderr, flush=True)
             batched_leg("batched_ragged_32_96", rs.L[:n], [S.batch_member(rs, i) for i in range(n)], p)
-        if args.searches > 0:
-            print(f"[bench] {args.searches} saddle searches on {L}x{L} one at a time", file=sys.stderr, flush=True)
+        def one_at_a_time(name, rule):
+            sor = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, k_cert=2, max_outer=args.max_outer,
+                                eig={"tol": 1e-5, "max_iter": 200}, step={"rule": rule})
+            print(f"[bench] {args.searches} saddle searches on {L}x{L} one at a time ({name})", file=sys.stderr,
+                  flush=True)
             stats = {}
             t0 = time.perf_counter()
             n_iter = 0
             n_hvp = 0
             for i in range(args.searches):
                 md = torch.as_tensor(S.batch_member(spec, i), device="cuda")
-                res1, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, opts=so)
+                res1, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, opts=sor)
                 stats[M.STATUS_NAMES[res1.status]] = stats.get(M.STATUS_NAMES[res1.status], 0) + 1
                 n_iter += res1.iters
                 n_hvp += res1.n_hvp
                 print(f"[bench]   search {i}: {M.STATUS_NAMES[res1.status]} iters={res1.iters}", file=sys.stderr,
                       flush=True)
             el = time.perf_counter() - t0
-            extra["one_at_a_time_128"] = {"searches": args.searches, "wall_s": round(el, 3),
-                                          "searches_per_s": round(args.searches / el, 4),
-                                          "outer_iters_per_s": round(n_iter / el, 1),
-                                          "mean_outer_iters": round(n_iter / args.searches, 1),
-                                          "hvp_columns_per_outer": round(n_hvp / max(n_iter, 1), 1),
-                                          "status": stats}
+            extra[name] = {"searches": args.searches, "wall_s": round(el, 3),
+                           "searches_per_s": round(args.searches / el, 4),
+                           "outer_iters_per_s": round(n_iter / el, 1),
+                           "mean_outer_iters": round(n_iter / args.searches, 1),
+                           "hvp_columns_per_outer": round(n_hvp / max(n_iter, 1), 1),
+                           "status": stats}
+
+        if args.searches > 0:
+            one_at_a_time("one_at_a_time_128", M.RULE_LBFGS)
+            # the paper's second outer optimiser on the same starts
+            one_at_a_time("one_at_a_time_128_cg", M.RULE_CG)
 
     if not args.hvp_only and not args.eigen_only and not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

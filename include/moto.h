@@ -243,7 +243,7 @@ moto_status moto_min_modes(moto_plan p, moto_dtype hvp, const double *m, const u
  *          the caller before the first step of a run
  *   out    [2] FP64 device: out[0] = ||F_mmf||_2 at m, out[1] = 1 if stopped */
 typedef struct {
-    int32_t rule;      /* 0 = L-BFGS, 1 = fixed step */
+    int32_t rule;      /* 0 = L-BFGS, 1 = fixed step, 2 = conjugate gradients */
     int32_t mem;       /* L-BFGS memory, 1..16 (default 8) */
     double theta_max;  /* rotation cap, rad (default 0.1) */
     double alpha0;     /* initial / fixed step; <= 0 means 1 / moto_hessian_norm_bound */

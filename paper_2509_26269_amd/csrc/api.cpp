@@ -670,10 +670,10 @@ size_t moto_step_state_bytes(moto_plan p, int32_t mem) {
 }
 
 static bool fill_step_args(moto_plan p, const moto_step_opts* o, int k_reflect, StepArgs* a) {
-    if (o->rule != 0 && o->rule != 1) return false;
+    if (o->rule < 0 || o->rule > 2) return false;
     if (o->mem < 1 || o->mem > 16 || !(o->theta_max > 0.0) || k_reflect < 0 || k_reflect > 4) return false;
     a->N = p->g.N;
-    a->mem = o->mem;
+    a->mem = o->rule == 2 ? 1 : o->mem;  // CG keeps one (s, y) pair
     a->rule = o->rule;
     a->k_reflect = k_reflect;
     a->theta_max = o->theta_max;

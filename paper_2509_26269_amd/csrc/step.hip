@@ -1,5 +1,6 @@
 // step.hip -- device kernels of the outer layer: reflected force and one
-// L-BFGS / fixed rotation step of every spin (Results, "Bilayer MMF";
+// L-BFGS / fixed / nonlinear-CG rotation step of every spin (Results,
+// "Bilayer MMF": L-BFGS and CG are the paper's two outer optimisers;
 // Supplementary Note 1, Algorithm 1, bilayer loop).
 //
 // The L-BFGS two-loop recursion is run in coefficient space: every vector it
@@ -24,8 +25,11 @@ struct StepHdr {
     int cu;  // number of pairs the coefficients below refer to (G is coef[2*cu])
     int pad1, pad2;
     double fnorm;
+    double cg_c;  // CG: the step taken last time = cg_c x its direction
     double coef[SNV];
 };
+
+constexpr int CG_RESTART = 50;  // CG restart period (steps)
 
 struct StepPtrs {
     StepHdr* hdr;
@@ -91,7 +95,7 @@ __device__ __forceinline__ Ring ring_next(const StepHdr* h, int mem, int rule) {
     r.slot = -1;
     r.c_new = h->count;
     r.h_new = h->head;
-    if (h->have_prev && rule == 0) {
+    if (h->have_prev && (rule == 0 || rule == 2)) {
         if (h->count < mem) {
             r.slot = (h->head + h->count) % mem;
             r.c_new = h->count + 1;
@@ -294,8 +298,20 @@ __global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P) {
     const int iG = 2 * c;
     double coef[SNV];
     for (int q = 0; q < nv; ++q) coef[q] = 0.0;
-    bool reset = (a.rule != 0);
-    if (a.rule == 0) {
+    bool reset = (a.rule == 1);
+    if (a.rule == 2) {
+        // nonlinear CG (Fletcher-Reeves) on G with one stored pair: S_0 is
+        // the transported last step = cg_c x the transported last direction,
+        // Y_0 = G - P G_prev, so |P G_prev|^2 = G.G - 2 G.Y_0 + Y_0.Y_0
+        coef[iG] = -a.alpha0;
+        if (c >= 1 && h->iters % CG_RESTART != 0) {
+            const double GG = Gm[iG][iG], Gy = Gm[c][iG], yy = Gm[c][c];
+            const double gpgp = GG - 2.0 * Gy + yy;
+            const double beta = gpgp > 0.0 ? GG / gpgp : 0.0;
+            const double bs = beta / h->cg_c;
+            if (-GG + bs * Gm[0][iG] < 0.0) coef[0] = a.alpha0 * bs;
+        }
+    } else if (a.rule == 0) {
         double q[SNV], alph[SMEM], rho[SMEM];
         bool valid[SMEM];
         for (int i = 0; i < nv; ++i) q[i] = 0.0;
@@ -387,6 +403,7 @@ __global__ __launch_bounds__(NT) void k_step_rot(StepArgs a, double* __restrict_
     }
     __syncthreads();
     const double sc = scale_s;
+    if (a.rule == 2 && blockIdx.x == 0 && threadIdx.x == 0) P.hdr->cg_c = a.alpha0 * sc;
     for (int s = blockIdx.x * NT + threadIdx.x; s < a.N; s += gridDim.x * NT) {
         double d[3], mi[3];
         double n2 = 0.0;

@@ -317,6 +317,9 @@ def eig_opts(dtype: int = MOTO_F64, **kw) -> EigOpts:
     return o
 
 
+RULE_LBFGS, RULE_FIXED, RULE_CG = 0, 1, 2
+
+
 def step_opts(**kw) -> StepOpts:
     o = StepOpts()
     lib().moto_default_step_opts(ctypes.byref(o))

@@ -171,3 +171,81 @@ def test_literal_start_degenerate_and_masked_search():
     assert abs(res.E - ro.E) <= 1e-8 * abs(ro.E)
     assert O.max_site_angle(_np(md), ro.m) <= 1e-4
     assert np.all(_np(md)[:, mask == 0] == m0[:, mask == 0])
+
+
+# --- the CG outer optimiser -------------------------------------------------
+def test_cg_steps_match_oracle_rule_across_a_restart():
+    """55 reflected CG steps with a fixed external mode (one restart period
+    passes): the spins and ||F_mmf|| follow the oracle's CG rule."""
+    M = _M()
+    L = 12
+    p = S.ham_nn(L)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    rng = np.random.default_rng(3)
+    m = S.nn_start(5, L=L)
+    v = S.random_tangent(m, 1, rng)[0]
+    v /= np.linalg.norm(v)
+    md = _dev(m)
+    st = M.StepState(plan, mem=8)
+    opts = M.step_opts(rule=M.RULE_CG, tau_F=1e-12)
+    opt = O.LBFGS(O.StepRule(kind="cg"), 1.0 / h.h_est())
+    mo = m.copy()
+    for it in range(O.CG_RESTART + 5):
+        _, _, _, F = O.energy_grad(h, mo)
+        vt = O.project(mo, v)
+        vt /= np.linalg.norm(vt)
+        Fm = O.reflected_force(F, vt[None])
+        mo = O.rotate(mo, opt.direction(mo, -Fm))
+        E, g, c, Fd, _ = M.moto_energy_grad(plan, md)
+        Vd = O.project(_np(md), v)
+        Vd /= np.linalg.norm(Vd)
+        out = M.moto_reflected_step(plan, md, Fd, _dev(Vd[None]), 1, st, opts)
+        torch.cuda.synchronize()
+        assert abs(float(out[0]) - np.linalg.norm(Fm)) <= 1e-9 * np.linalg.norm(Fm), it
+        assert np.abs(_np(md) - mo).max() <= 1e-9, it
+
+
+def test_cg_stoner_wohlfarth_search_and_descent_closed_form():
+    M = _M()
+    p = S.ham_sw(8)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    b, K = p.B[0], p.K
+    m0 = S.add_tilt_noise(S.uniform(h.N, (1, 0, 0)), 0.02, np.random.default_rng(0))
+    md = _dev(m0)
+    so = M.search_opts(M.MOTO_F64, tau_F=1e-8)
+    so.step.rule = M.RULE_CG
+    res, ev, V = M.moto_saddle_search(plan, md, M.MOTO_F64, opts=so)
+    assert res.status == M.SADDLE, M.STATUS_NAMES[res.status]
+    assert abs(res.lambda1 - (b - 2 * K)) < 1e-8 and abs(res.lambda2 - b) < 1e-8
+    ro = O.saddle_search(h, m0, tau_F=1e-8, rule=O.StepRule(kind="cg"))
+    assert ro.status == O.SADDLE and abs(res.iters - ro.iters) <= 2
+    mp, mm = CF.sw_minima(b, K)
+    for sgn in (+1, -1):
+        mdd = md.clone()
+        do = M.descend_opts(M.MOTO_F64, tau_F=1e-8)
+        do.step.rule = M.RULE_CG
+        d = M.moto_descend(plan, mdd, V[0].contiguous(), sgn, M.MOTO_F64, do)
+        assert d.converged and d.lambda1 > 0
+        assert abs((res.E - d.E) - CF.sw_barrier(h.N, b, K)) <= 1e-9 * CF.sw_barrier(h.N, b, K)
+        mf = _np(mdd)
+        assert min(np.abs(mf - mp[:, None]).max(), np.abs(mf - mm[:, None]).max()) < 1e-6
+
+
+def test_cg_collapse_saddle_matches_oracle():
+    """16x16 NN model, radius-1 start, CG rule, FP64 HVP: GPU and oracle reach
+    the same index-1 saddle."""
+    M = _M()
+    p = S.ham_nn(16)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m0 = S.add_tilt_noise(S.skyrmion(16, 16, 1.0), 0.05, np.random.default_rng(0))
+    md = _dev(m0)
+    so = M.search_opts(M.MOTO_F64, tau_F=1e-6)
+    so.step.rule = M.RULE_CG
+    res, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F64, opts=so)
+    ro = O.saddle_search(h, m0, tau_F=1e-6, rule=O.StepRule(kind="cg"))
+    assert res.status == M.SADDLE and ro.status == O.SADDLE
+    assert abs(res.E - ro.E) <= 1e-8 * abs(ro.E)
+    assert O.max_site_angle(_np(md), ro.m) <= 1e-4
