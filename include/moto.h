@@ -226,12 +226,41 @@ moto_status moto_min_modes(moto_plan p, moto_dtype hvp, const double *m, const u
                            size_t ws_bytes, moto_stream stream);
 
 /* ---------------------------------------------------------------------
+ * Inner layer over a population (Methods, multi-objective explorer: the
+ * spectral-gap objective needs the two lowest modes of every candidate of
+ * a population; Results: population size 24): P independent block-LOBPCG
+ * solves, exactly the method of moto_min_modes, on P states of the plan's
+ * lattice, run in lock step -- every kernel launch covers the whole
+ * population and the dense per-member steps run side by side, so P solves
+ * take about the time of one.  Each member stops by its own test; the call
+ * returns once all have stopped.
+ *   P      1 <= P <= MOTO_MAX_POPULATION
+ *   m      [P][3][N] FP64 device, unit spins
+ *   mask   [P][N] device (1 = active) or NULL
+ *   evals  [P][k] FP64 device;  V [P][k][3][N] FP64 device (input warm
+ *          starts when opts.warm == 1);  resid [P][k] FP64 device or NULL
+ *   info   host [P] or NULL: outcome of every member
+ * Errors: MOTO_EINVAL for P or k out of range; MOTO_EWORKSPACE when ws_bytes
+ * is below moto_min_modes_population_workspace(p, hvp, P, k, guard). */
+#define MOTO_MAX_POPULATION 256
+size_t moto_min_modes_population_workspace(moto_plan p, moto_dtype hvp, int32_t P, int32_t k,
+                                           int32_t guard);
+moto_status moto_min_modes_population(moto_plan p, moto_dtype hvp, int32_t P, const double *m,
+                                      const uint8_t *mask, int32_t k,
+                                      const moto_eig_opts *opts /* host */, double *evals, double *V,
+                                      double *resid, moto_info *info /* host */, void *ws,
+                                      size_t ws_bytes, moto_stream stream);
+
+/* ---------------------------------------------------------------------
  * Outer layer, one step (Results, "Bilayer MMF"; Algorithm 1 bilayer loop):
  *   F_mmf = F - 2 sum_{r < k_reflect} (F.v_r) v_r;   G = -F_mmf;
  *   direction d from L-BFGS on G (memory `mem`, stored pairs transported by
  *   projection onto the current tangent spaces, pairs with s.y <= sy_min
  *   skipped, initial scaling s.y/y.y of the newest valid pair or alpha0,
- *   reset to d = -alpha0 G whenever d.G >= 0) or the fixed step d = -alpha0 G;
+ *   reset to d = -alpha0 G whenever d.G >= 0), the fixed step d = -alpha0 G,
+ *   or nonlinear conjugate gradients (the paper's second outer optimiser:
+ *   d = alpha0 p, p = -G + beta P p_prev with the Fletcher-Reeves beta =
+ *   |G|^2 / |P G_prev|^2, beta = 0 every 50 steps and whenever p.G >= 0);
  *   d scaled so that max_i |d_i| <= theta_max; each spin rotated by d_i
  *   (m_i <- cos|d_i| m_i + sin|d_i| d_i/|d_i|, renormalised).
  * If ||F_mmf||_2 <= tau_F the step is not taken and the stop flag is set.

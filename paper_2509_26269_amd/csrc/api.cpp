@@ -56,12 +56,15 @@ inline size_t al(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 size_t energy_ws(const moto_plan p, int batch) { return al(sizeof(double) * NPART * (size_t)batch * p->g.tiles); }
 
 // Eigen-solve workspace layout (offsets in bytes from the workspace base).
+// Eigen-solve workspace for a population of P solves (P = 1: one solve);
+// every region holds the P members back to back.
 struct EigLayout {
-    size_t mT, cT, c64, S, HS, Xsave, part, G, ctrl, total;
+    size_t mT, cT, c64, S, HS, Xsave, part, G, ctrl, flag, total;
     int mb, n2, nblk_g, nblk_u, nblk_o;
+    long long s_ms, part_ms, g_ms;  // per-member strides (elements, doubles, doubles)
 };
 
-EigLayout eig_layout(const moto_plan p, moto_dtype hvp, int k, int guard) {
+EigLayout eig_layout(const moto_plan p, moto_dtype hvp, int k, int guard, int P = 1) {
     EigLayout L;
     const size_t N = p->g.N;
     const size_t es = hvp == MOTO_F64 ? sizeof(double) : sizeof(float);
@@ -70,29 +73,37 @@ EigLayout eig_layout(const moto_plan p, moto_dtype hvp, int k, int guard) {
     L.nblk_g = gram_blocks(L.n2);
     L.nblk_u = update_blocks(L.n2);
     L.nblk_o = (int)((N + NT - 1) / NT);
-    size_t o = 0;
-    L.mT = o;
-    o += al(es * 3 * N);
-    L.cT = o;
-    o += al(es * N);
-    L.c64 = o;
-    o += al(sizeof(double) * N);
-    L.S = o;
-    o += al(es * 3 * (size_t)L.mb * L.n2);
-    L.HS = o;
-    o += al(es * 3 * (size_t)L.mb * L.n2);
-    L.Xsave = o;
-    o += al(es * (size_t)L.mb * 3 * N);
+    L.s_ms = 3LL * L.mb * L.n2;
     size_t part = sizeof(double) * NPART * (size_t)p->g.tiles;
     part = std::max(part, sizeof(double) * (size_t)L.nblk_g * (2 * MAXS * (MAXS + 1) / 2));
     part = std::max(part, sizeof(double) * (size_t)L.nblk_u * MAXB);
     part = std::max(part, sizeof(double) * ((size_t)L.nblk_o * MAXB * 3 + MAXB));
+    part = al(part);
+    L.part_ms = (long long)(part / sizeof(double));
+    const size_t gsz = al(sizeof(double) * 2 * MAXS * (MAXS + 1) / 2);
+    L.g_ms = (long long)(gsz / sizeof(double));
+    const size_t Pz = (size_t)P;
+    size_t o = 0;
+    L.mT = o;
+    o += al(Pz * es * 3 * N);
+    L.cT = o;
+    o += al(Pz * es * N);
+    L.c64 = o;
+    o += al(Pz * sizeof(double) * N);
+    L.S = o;
+    o += al(Pz * es * (size_t)L.s_ms);
+    L.HS = o;
+    o += al(Pz * es * (size_t)L.s_ms);
+    L.Xsave = o;
+    o += al(Pz * es * (size_t)L.mb * 3 * N);
     L.part = o;
-    o += al(part);
+    o += Pz * part;
     L.G = o;
-    o += al(sizeof(double) * 2 * MAXS * (MAXS + 1) / 2);
+    o += Pz * gsz;
     L.ctrl = o;
-    o += al(sizeof(EigCtrl));
+    o += al(Pz * sizeof(EigCtrl));
+    L.flag = o;
+    o += al(sizeof(int));
     L.total = o;
     return L;
 }
@@ -369,11 +380,15 @@ static hipGraphExec_t capture_chunk(moto_plan p, F& launches, const long long* k
 }
 }  // extern "C++"
 
-static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, const uint8_t* mask, int k,
-                                  const moto_eig_opts* o, double* evals, double* V, double* resid, moto_info* info,
-                                  char* ws, size_t ws_bytes, hipStream_t st, const double* c64_in) {
+// P independent solves on lattices of the plan's geometry (P = 1: one solve).
+// m [P][3][N], mask [P][N] or null, evals [P][k], V [P][k][3][N], resid [P][k]
+// or null, info host [P] or null.
+static moto_status min_modes_pop_impl(moto_plan p, moto_dtype hvp, int P, const double* m, const uint8_t* mask,
+                                      int k, const moto_eig_opts* o, double* evals, double* V, double* resid,
+                                      moto_info* info, char* ws, size_t ws_bytes, hipStream_t st,
+                                      const double* c64_in) {
     const int guard = resolve_guard(k, o->guard);
-    const EigLayout L = eig_layout(p, hvp, k, guard);
+    const EigLayout L = eig_layout(p, hvp, k, guard, P);
     if (L.mb > MAXB || L.mb > L.n2) return MOTO_EINVAL;
     if (ws_bytes < L.total) return MOTO_EWORKSPACE;
     const bool f64 = hvp == MOTO_F64;
@@ -381,19 +396,24 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
     double* c64 = (double*)(ws + L.c64);
     double* part = (double*)(ws + L.part);
     EigCtrl* ctrl = (EigCtrl*)(ws + L.ctrl);
+    int* all_done = (int*)(ws + L.flag);
     // c_i = m_i . g_i at m (FP64)
     if (c64_in) {
-        HIP_TRY(hipMemcpyAsync(c64, c64_in, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(c64, c64_in, sizeof(double) * N * (size_t)P, hipMemcpyDeviceToDevice, st));
     } else {
-        HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, nullptr, nullptr, c64, nullptr, part, st));
+        HIP_TRY(launch_energy_grad(p->g, p->k, true, P, m, nullptr, nullptr, c64, nullptr, part, st));
     }
-    const void* mT = m;
+    // the spins are staged in the workspace in the HVP precision (a copy in
+    // FP64), so that a captured iteration chunk refers to workspace memory
+    // only and stays valid for any caller's m
+    const void* mT = ws + L.mT;
     const void* cT = c64;
     if (!f64) {
-        HIP_TRY(launch_f64_to_f32(m, (float*)(ws + L.mT), 3 * (size_t)N, st));
-        HIP_TRY(launch_f64_to_f32(c64, (float*)(ws + L.cT), (size_t)N, st));
-        mT = ws + L.mT;
+        HIP_TRY(launch_f64_to_f32(m, (float*)(ws + L.mT), 3 * (size_t)N * P, st));
+        HIP_TRY(launch_f64_to_f32(c64, (float*)(ws + L.cT), (size_t)N * P, st));
         cT = ws + L.cT;
+    } else {
+        HIP_TRY(hipMemcpyAsync(ws + L.mT, m, sizeof(double) * 3 * (size_t)N * P, hipMemcpyDeviceToDevice, st));
     }
     EigArgs a;
     a.n2 = L.n2;
@@ -402,23 +422,37 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
     a.max_iter = o->max_iter;
     a.tol_abs = o->tol * p->hest;
     a.drop = f64 ? 1e-13 : 1e-9;
+    a.P = P;
+    a.s_ms = P > 1 ? L.s_ms : 0;
+    a.part_ms = P > 1 ? L.part_ms : 0;
+    a.g_ms = P > 1 ? L.g_ms : 0;
     void* S = ws + L.S;
     void* HS = ws + L.HS;
     const size_t es = f64 ? sizeof(double) : sizeof(float);
     void* Wslot = (char*)S + es * (size_t)L.mb * L.n2;
     void* HWslot = (char*)HS + es * (size_t)L.mb * L.n2;
+    // the HVP of the whole population is one batched launch; it stops once
+    // every member is done
+    const int* hv_done = P > 1 ? all_done : &ctrl->done;
+    const long long vbs = L.s_ms;
     const int warm = o->warm;
-    const int hv_var = tuned_variant(p, hvp, 1, L.mb);
+    const int hv_var = tuned_variant(p, hvp, P, L.mb);
     double* G = (double*)(ws + L.G);
+    auto control = [&](int first, hipStream_t s) -> hipError_t {
+        hipError_t e = launch_eig_control(a, part, L.nblk_u, ctrl, first, s);
+        if (e == hipSuccess && P > 1) e = launch_eig_all_done(a, ctrl, all_done, s);
+        return e;
+    };
     HIP_TRY(launch_eig_init(f64, a, S, m, warm == 1 ? V : nullptr, warm == 1 ? k : 0, ws + L.Xsave, warm == 2,
                             mask, N, o->seed, ctrl, st));
+    if (P > 1) HIP_TRY(launch_eig_all_done(a, ctrl, all_done, st));
     // start: orthonormal X; HX = H X; Rayleigh-Ritz on span(X); W = HX - X Lam
     for (int pass = 0; pass < 2; ++pass) HIP_TRY(launch_orth(f64, a, 0, S, part, L.nblk_g, G, ctrl, st));
-    HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, S, HS, &ctrl->done, st, hv_var));
+    HIP_TRY(launch_tangent_hvp(p->g, p->k, f64, true, P, mT, cT, mask, L.mb, S, HS, hv_done, st, hv_var, vbs));
     HIP_TRY(launch_gram(f64, a, L.mb, S, HS, part, L.nblk_g, G, ctrl, st));
     HIP_TRY(launch_rr(a, L.mb, G, ctrl, st));
     HIP_TRY(launch_update(f64, a, L.mb, S, HS, part, L.nblk_u, ctrl, st));
-    HIP_TRY(launch_eig_control(a, part, L.nblk_u, ctrl, 1, st));
+    HIP_TRY(control(1, st));
     const int every = o->check_every > 0 ? o->check_every : 8;
     const int max_chunks = o->max_iter / every + 2;
     auto chunk_launches = [&](hipStream_t s) -> hipError_t {
@@ -427,12 +461,12 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
                 hipError_t e = launch_orth(f64, a, 1, S, part, L.nblk_g, G, ctrl, s);
                 if (e != hipSuccess) return e;
             }
-            hipError_t e = launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, L.mb, Wslot, HWslot,
-                                              &ctrl->done, s, hv_var);
+            hipError_t e = launch_tangent_hvp(p->g, p->k, f64, true, P, mT, cT, mask, L.mb, Wslot, HWslot, hv_done,
+                                              s, hv_var, vbs);
             if (e == hipSuccess) e = launch_gram(f64, a, -1, S, HS, part, L.nblk_g, G, ctrl, s);
             if (e == hipSuccess) e = launch_rr(a, -1, G, ctrl, s);
             if (e == hipSuccess) e = launch_update(f64, a, -1, S, HS, part, L.nblk_u, ctrl, s);
-            if (e == hipSuccess) e = launch_eig_control(a, part, L.nblk_u, ctrl, 0, s);
+            if (e == hipSuccess) e = control(0, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -451,16 +485,17 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
         key[4] = every;
         key[5] = o->max_iter;
         key[6] = hv_var;
-        key[7] = N;
+        key[7] = N + ((long long)P << 32);
         for (auto& ge : p->graphs)
             if (ge.valid && ge.ws == (const void*)ws && ge.mask == (const void*)mask &&
                 std::memcmp(ge.key, key, sizeof(key)) == 0)
                 gexec = ge.exec;
         if (!gexec) gexec = capture_chunk(p, chunk_launches, key, ws, mask);
     }
-    int hdr[4];
+    const int* done_dev = P > 1 ? all_done : &ctrl->done;
     for (int chunk = 0; chunk < max_chunks; ++chunk) {
-        moto_status rs = readback(p, ctrl, sizeof(hdr), hdr, st);
+        int hdr[1];
+        moto_status rs = readback(p, done_dev, sizeof(hdr), hdr, st);
         if (rs != MOTO_OK) return rs;
         if (hdr[0]) break;
         if (gexec)
@@ -469,15 +504,28 @@ static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, 
             HIP_TRY(chunk_launches(st));
     }
     HIP_TRY(launch_eig_output(f64, a, S, m, N, V, part, ctrl, evals, resid, ws + L.Xsave, st));
-    EigCtrl hc;
-    moto_status rs = readback(p, ctrl, 32, &hc, st);
-    if (rs != MOTO_OK) return rs;
     if (info) {
-        info->status = hc.status;
-        info->iters = hc.iters;
-        info->n_hvp = hc.n_hvp;
+        // status, iterations and HVP columns of every member, through the
+        // pinned buffer in pieces
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int y = 0; y < P; ++y) {
+            EigCtrl hc;
+            moto_status rs = readback(p, ctrl + y, 32, &hc, st);
+            if (rs != MOTO_OK) return rs;
+            info[y].status = hc.status;
+            info[y].iters = hc.iters;
+            info[y].n_hvp = hc.n_hvp;
+        }
+    } else {
+        HIP_TRY(hipStreamSynchronize(st));
     }
     return MOTO_OK;
+}
+
+static moto_status min_modes_impl(moto_plan p, moto_dtype hvp, const double* m, const uint8_t* mask, int k,
+                                  const moto_eig_opts* o, double* evals, double* V, double* resid, moto_info* info,
+                                  char* ws, size_t ws_bytes, hipStream_t st, const double* c64_in) {
+    return min_modes_pop_impl(p, hvp, 1, m, mask, k, o, evals, V, resid, info, ws, ws_bytes, st, c64_in);
 }
 
 moto_status moto_min_modes(moto_plan p, moto_dtype hvp, const double* m, const uint8_t* mask, int32_t k,
@@ -493,6 +541,27 @@ moto_status moto_min_modes(moto_plan p, moto_dtype hvp, const double* m, const u
     if (!ws) return MOTO_EWORKSPACE;
     return min_modes_impl(p, hvp, m, mask, k, &o, evals, V, resid, info, (char*)ws, ws_bytes,
                           (hipStream_t)stream, nullptr);
+}
+
+size_t moto_min_modes_population_workspace(moto_plan p, moto_dtype hvp, int32_t P, int32_t k, int32_t guard) {
+    if (!p || k < 1 || P < 1 || P > MOTO_MAX_POPULATION || !hvp_ok(hvp)) return 0;
+    return eig_layout(p, hvp, k, resolve_guard(k, guard), P).total;
+}
+
+moto_status moto_min_modes_population(moto_plan p, moto_dtype hvp, int32_t P, const double* m,
+                                      const uint8_t* mask, int32_t k, const moto_eig_opts* opts, double* evals,
+                                      double* V, double* resid, moto_info* info, void* ws, size_t ws_bytes,
+                                      moto_stream stream) {
+    if (!p || !m || !V || !evals || k < 1 || P < 1 || P > MOTO_MAX_POPULATION || !hvp_ok(hvp)) return MOTO_EINVAL;
+    moto_eig_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_eig_opts(hvp, &o);
+    if (o.max_iter < 0 || !(o.tol >= 0.0) || o.warm < 0 || o.warm > 2) return MOTO_EINVAL;
+    if (!ws) return MOTO_EWORKSPACE;
+    return min_modes_pop_impl(p, hvp, P, m, mask, k, &o, evals, V, resid, info, (char*)ws, ws_bytes,
+                              (hipStream_t)stream, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -578,13 +647,15 @@ moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double* m,
     void* Q = ws + L.Q;
     const size_t es = f64 ? sizeof(double) : sizeof(float);
     HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, nullptr, nullptr, c64, nullptr, part, st));
-    const void* mT = m;
+    // spins staged in the workspace (see min_modes_pop_impl)
+    const void* mT = ws + L.mT;
     const void* cT = c64;
     if (!f64) {
         HIP_TRY(launch_f64_to_f32(m, (float*)(ws + L.mT), 3 * (size_t)N, st));
         HIP_TRY(launch_f64_to_f32(c64, (float*)(ws + L.cT), (size_t)N, st));
-        mT = ws + L.mT;
         cT = ws + L.cT;
+    } else {
+        HIP_TRY(hipMemcpyAsync(ws + L.mT, m, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, st));
     }
     const int hv_var = tuned_variant(p, hvp, 1, 1);
     HIP_TRY(launch_lz_init(f64, N, Q, m, o.warm ? V : nullptr, o.warm ? k : 0, mask, o.seed, part, L.nblk, ctrl,

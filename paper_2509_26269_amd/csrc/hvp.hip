@@ -64,7 +64,7 @@ __device__ __forceinline__ void apply_A_flat(const T* __restrict__ p0, const T* 
 // --------------------------------------------------------------------------
 template <class T, int TXT, int TYT, bool REMAP>
 __global__ __launch_bounds__(NT) void k_hvp_tiled(Geo g, Coef<T> k, const T* __restrict__ m,
-                                                  const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec,
+                                                  const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec, long long vbs,
                                                   const T* __restrict__ V, T* __restrict__ W,
                                                   const int* __restrict__ done, int tiles_x, int tiles_y) {
     static_assert(TXT * TYT == NT, "one site per thread");
@@ -81,8 +81,8 @@ __global__ __launch_bounds__(NT) void k_hvp_tiled(Geo g, Coef<T> k, const T* __r
     const T* mb = m + 3 * off1;
     const uint8_t* mk = mask ? mask + off1 : nullptr;
     const size_t vstride = (size_t)2 * g.N;
-    const T* Vb = V + (size_t)b * nvec * vstride;
-    T* Wb = W + (size_t)b * nvec * vstride;
+    const T* Vb = V + (size_t)b * vbs;
+    T* Wb = W + (size_t)b * vbs;
     int sidx[(SS + NT - 1) / NT];
 #pragma unroll
     for (int q = 0; q < (SS + NT - 1) / NT; ++q) {
@@ -165,7 +165,7 @@ __device__ constexpr int bd_shell(int dx, int dy) {
 
 template <class T, int NVP>
 __global__ __launch_bounds__(NT) void k_hvp_band(Geo g, Coef<T> k, const T* __restrict__ m,
-                                                 const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec,
+                                                 const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec, long long vbs,
                                                  const T* __restrict__ V, T* __restrict__ W,
                                                  const int* __restrict__ done, int tiles_x, int tiles_y) {
     if (done != nullptr && *done) return;
@@ -181,8 +181,8 @@ __global__ __launch_bounds__(NT) void k_hvp_band(Geo g, Coef<T> k, const T* __re
     const T* mb = m + off3;
     const uint8_t* mk = mask ? mask + off1 : nullptr;
     const size_t vstride = (size_t)2 * g.N;
-    const T* Vb = V + (size_t)b * nvec * vstride;
-    T* Wb = W + (size_t)b * nvec * vstride;
+    const T* Vb = V + (size_t)b * vbs;
+    T* Wb = W + (size_t)b * vbs;
     const int lx = threadIdx.x % BD_TX, rg = threadIdx.x / BD_TX;
     const int x = tx0 + lx;
     const bool colok = lx < txw;
@@ -373,7 +373,7 @@ __device__ __forceinline__ void st_off_nt(T* __restrict__ base, unsigned byte_of
 
 template <class T, int NVP, int XW, bool MASKED>
 __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __restrict__ m,
-                                                  const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec,
+                                                  const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec, long long vbs,
                                                   const T* __restrict__ V, T* __restrict__ W,
                                                   const int* __restrict__ done, int nstrip, int ngroups) {
     if (done != nullptr && *done) return;
@@ -402,8 +402,8 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
     const T* __restrict__ mz = my + N;
     const T* __restrict__ cb = c + (size_t)b * N;
     const uint8_t* __restrict__ mk = MASKED ? mask + (size_t)b * N : nullptr;
-    const T* __restrict__ Vb = V + ((size_t)b * nvec + j0) * 2 * N;
-    T* __restrict__ Wb = W + ((size_t)b * nvec + j0) * 2 * N;
+    const T* __restrict__ Vb = V + (size_t)b * vbs + (size_t)j0 * 2 * N;
+    T* __restrict__ Wb = W + (size_t)b * vbs + (size_t)j0 * 2 * N;
     const T cJ[3] = {k.cJ[0], k.cJ[1], k.cJ[2]};
     const T cD = k.cD, cDh = T(0.5) * k.cD, cDr = T(0.86602540378443864676) * k.cD, cK = k.cK;
 
@@ -607,7 +607,7 @@ __device__ __forceinline__ void st2_nt(T* __restrict__ base, unsigned byte_off, 
 template <class T, int NVP, int NT2, bool MASKED>
 __global__ __launch_bounds__(NT2) void k_hvp_march2(Geo g, Coef<T> k, const T* __restrict__ m,
                                                    const T* __restrict__ c, const uint8_t* __restrict__ mask,
-                                                   int nvec, const T* __restrict__ V, T* __restrict__ W,
+                                                   int nvec, long long vbs, const T* __restrict__ V, T* __restrict__ W,
                                                    const int* __restrict__ done, int nstrip, int ngroups) {
     if (done != nullptr && *done) return;
     constexpr int XW = 2 * NT2;
@@ -635,8 +635,8 @@ __global__ __launch_bounds__(NT2) void k_hvp_march2(Geo g, Coef<T> k, const T* _
     const T* __restrict__ mz = my + N;
     const T* __restrict__ cb = c + (size_t)b * N;
     const uint8_t* __restrict__ mk = MASKED ? mask + (size_t)b * N : nullptr;
-    const T* __restrict__ Vb = V + ((size_t)b * nvec + j0) * 2 * N;
-    T* __restrict__ Wb = W + ((size_t)b * nvec + j0) * 2 * N;
+    const T* __restrict__ Vb = V + (size_t)b * vbs + (size_t)j0 * 2 * N;
+    T* __restrict__ Wb = W + (size_t)b * vbs + (size_t)j0 * 2 * N;
     const T cJ[3] = {k.cJ[0], k.cJ[1], k.cJ[2]};
     const T cD = k.cD, cDh = T(0.5) * k.cD, cDr = T(0.86602540378443864676) * k.cD, cK = k.cK;
 
@@ -853,18 +853,18 @@ int hvp_default_variant(const Geo& g, bool f64) { return march_fits(g) ? (f64 ? 
 
 template <class T, int TXT, int TYT, bool REMAP>
 static void go_tiled(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
-                     int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+                     int nvec, long long vbs, const void* V, void* W, const int* done, hipStream_t st) {
     const int tx = (g.Lx + TXT - 1) / TXT, ty = (g.Ly + TYT - 1) / TYT;
     hipLaunchKernelGGL((k_hvp_tiled<T, TXT, TYT, REMAP>), dim3(batch * tx * ty), dim3(NT), 0, st, g, coef_cast<T>(kd),
-                       (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, tx, ty);
+                       (const T*)m, (const T*)c, mask, nvec, vbs, (const T*)V, (T*)W, done, tx, ty);
 }
 
 template <class T, int NVP>
 static void go_band(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
-                    int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+                    int nvec, long long vbs, const void* V, void* W, const int* done, hipStream_t st) {
     const int tx = (g.Lx + BD_TX - 1) / BD_TX, ty = (g.Ly + BD_TY - 1) / BD_TY;
     hipLaunchKernelGGL((k_hvp_band<T, NVP>), dim3(batch * tx * ty), dim3(NT), 0, st, g, coef_cast<T>(kd),
-                       (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, tx, ty);
+                       (const T*)m, (const T*)c, mask, nvec, vbs, (const T*)V, (T*)W, done, tx, ty);
 }
 
 // strips per lattice: about 1024 workgroups in all (one resident round at
@@ -878,33 +878,33 @@ static int march_strips(const Geo& g, int batch, int ngroups) {
 
 template <class T, int NVP, int XW>
 static void go_march_xw(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c,
-                        const uint8_t* mask, int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+                        const uint8_t* mask, int nvec, long long vbs, const void* V, void* W, const int* done, hipStream_t st) {
     const int ngroups = (nvec + NVP - 1) / NVP;
     const int nstrip = march_strips(g, batch, ngroups);
     if (mask)
         hipLaunchKernelGGL((k_hvp_march<T, NVP, XW, true>), dim3(batch * nstrip * ngroups), dim3(XW), 0, st, g,
-                           coef_cast<T>(kd), (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done,
+                           coef_cast<T>(kd), (const T*)m, (const T*)c, mask, nvec, vbs, (const T*)V, (T*)W, done,
                            nstrip, ngroups);
     else
         hipLaunchKernelGGL((k_hvp_march<T, NVP, XW, false>), dim3(batch * nstrip * ngroups), dim3(XW), 0, st, g,
-                           coef_cast<T>(kd), (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done,
+                           coef_cast<T>(kd), (const T*)m, (const T*)c, mask, nvec, vbs, (const T*)V, (T*)W, done,
                            nstrip, ngroups);
 }
 
 template <class T, int NVP>
 static void go_march(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
-                     int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+                     int nvec, long long vbs, const void* V, void* W, const int* done, hipStream_t st) {
     if (g.Lx <= 64)
-        go_march_xw<T, NVP, 64>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+        go_march_xw<T, NVP, 64>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
     else if (g.Lx <= 128)
-        go_march_xw<T, NVP, 128>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+        go_march_xw<T, NVP, 128>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
     else
-        go_march_xw<T, NVP, 256>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+        go_march_xw<T, NVP, 256>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
 }
 
 template <class T, int NVP>
 static void go_march2(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
-                      int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+                      int nvec, long long vbs, const void* V, void* W, const int* done, hipStream_t st) {
     const int ngroups = (nvec + NVP - 1) / NVP;
     const int nstrip = march_strips(g, batch, ngroups);
     const dim3 grid(batch * nstrip * ngroups);
@@ -912,10 +912,10 @@ static void go_march2(const Geo& g, const CoefD& kd, int batch, const void* m, c
         constexpr int NT2 = decltype(ntc)::value;
         if (mask)
             hipLaunchKernelGGL((k_hvp_march2<T, NVP, NT2, true>), grid, dim3(NT2), 0, st, g, coef_cast<T>(kd),
-                               (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, nstrip, ngroups);
+                               (const T*)m, (const T*)c, mask, nvec, vbs, (const T*)V, (T*)W, done, nstrip, ngroups);
         else
             hipLaunchKernelGGL((k_hvp_march2<T, NVP, NT2, false>), grid, dim3(NT2), 0, st, g, coef_cast<T>(kd),
-                               (const T*)m, (const T*)c, mask, nvec, (const T*)V, (T*)W, done, nstrip, ngroups);
+                               (const T*)m, (const T*)c, mask, nvec, vbs, (const T*)V, (T*)W, done, nstrip, ngroups);
     };
     if (g.Lx <= 128)
         launch(std::integral_constant<int, 64>{});
@@ -925,35 +925,36 @@ static void go_march2(const Geo& g, const CoefD& kd, int batch, const void* m, c
 
 template <class T>
 static void go(int v, const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
-               int nvec, const void* V, void* W, const int* done, hipStream_t st) {
+               int nvec, long long vbs, const void* V, void* W, const int* done, hipStream_t st) {
     switch (v) {
-        case 0: go_tiled<T, 32, 8, false>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
-        case 1: go_tiled<T, 32, 8, true>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
-        case 3: go_tiled<T, 128, 2, true>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 0: go_tiled<T, 32, 8, false>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
+        case 1: go_tiled<T, 32, 8, true>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
+        case 3: go_tiled<T, 128, 2, true>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
         case 4:
-            if constexpr (sizeof(T) == 4) go_band<T, 4>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+            if constexpr (sizeof(T) == 4) go_band<T, 4>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
             break;
-        case 5: go_band<T, 2>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
-        case 6: go_band<T, 1>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 5: go_band<T, 2>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
+        case 6: go_band<T, 1>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
         case 7:
-            if constexpr (sizeof(T) == 4) go_march<T, 4>(g, kd, batch, m, c, mask, nvec, V, W, done, st);
+            if constexpr (sizeof(T) == 4) go_march<T, 4>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
             break;
-        case 8: go_march<T, 2>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
-        case 9: go_march<T, 1>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
-        case 10: go_march2<T, 2>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
-        case 11: go_march2<T, 1>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
-        default: go_tiled<T, 64, 4, true>(g, kd, batch, m, c, mask, nvec, V, W, done, st); break;
+        case 8: go_march<T, 2>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
+        case 9: go_march<T, 1>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
+        case 10: go_march2<T, 2>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
+        case 11: go_march2<T, 1>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
+        default: go_tiled<T, 64, 4, true>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st); break;
     }
 }
 
 hipError_t launch_hvp_frame(int variant, const Geo& g, const CoefD& kd, bool f64, int batch, const void* m,
                             const void* c, const uint8_t* mask, int nvec, const void* V, void* W, const int* done,
-                            hipStream_t st) {
+                            hipStream_t st, long long vbs) {
     const int v = hvp_variant_ok(variant, g, f64) ? variant : hvp_default_variant(g, f64);
+    if (vbs <= 0) vbs = (long long)nvec * 2 * g.N;
     if (f64)
-        go<double>(v, g, kd, batch, m, c, mask, nvec, V, W, done, st);
+        go<double>(v, g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
     else
-        go<float>(v, g, kd, batch, m, c, mask, nvec, V, W, done, st);
+        go<float>(v, g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
     return hipGetLastError();
 }
 

@@ -40,10 +40,12 @@ hipError_t launch_param_grad_apply(const Geo& g, int ns, bool f64, int batch, co
                                   void* out, hipStream_t st);
 hipError_t launch_reduce_partials(const double* part, int batch, int tiles, int ns, double* E, double* dth,
                                   hipStream_t st);
-// variant: frame-layout kernel variant (-1 = default choice), see hvp.hip
+// variant: frame-layout kernel variant (-1 = default choice), see hvp.hip;
+// vbs: elements from one lattice's vector block to the next (0 = nvec
+// vectors back to back)
 hipError_t launch_tangent_hvp(const Geo& g, const CoefD& k, bool f64, bool frame, int batch, const void* m,
                               const void* c, const uint8_t* mask, int nvec, const void* V, void* W,
-                              const int* done, hipStream_t st, int variant = -1);
+                              const int* done, hipStream_t st, int variant = -1, long long vbs = 0);
 
 // ---- hvp.hip: frame-layout tangent HVP variants (tile shapes / staging) ----
 constexpr int HVP_NVARIANTS = 12;
@@ -52,7 +54,7 @@ int hvp_default_variant(const Geo& g, bool f64);
 const char* hvp_variant_name(int variant);
 hipError_t launch_hvp_frame(int variant, const Geo& g, const CoefD& k, bool f64, int batch, const void* m,
                             const void* c, const uint8_t* mask, int nvec, const void* V, void* W, const int* done,
-                            hipStream_t st);
+                            hipStream_t st, long long vbs = 0);
 hipError_t launch_hessian_apply(const Geo& g, const CoefD& k, bool f64, int batch, int nvec, const void* V,
                                 void* W, hipStream_t st);
 hipError_t launch_topo_charge(const Geo& g, int batch, const double* m, double* part, hipStream_t st);
@@ -84,6 +86,11 @@ struct EigArgs {
     int max_iter;
     double tol_abs;
     double drop;   // rank threshold of the orthonormalisations (relative)
+    // Population of P independent solves on lattices of one geometry: member
+    // y = blockIdx.y owns S, HS at + y s_ms elements, partial rows at
+    // + y part_ms doubles, Grams at + y g_ms doubles and control block y.
+    int P = 1;
+    long long s_ms = 0, part_ms = 0, g_ms = 0;
 };
 
 // ---- lanczos.hip ----
@@ -129,6 +136,8 @@ hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, 
 int update_blocks(int n2);
 hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, EigCtrl* ctrl, int first,
                               hipStream_t st);
+// all_done = 1 once every member's control block says done (P > 1 only).
+hipError_t launch_eig_all_done(const EigArgs& a, const EigCtrl* ctrl, int* all_done, hipStream_t st);
 hipError_t launch_eig_output(bool f64, const EigArgs& a, const void* S, const double* m, int N, double* V,
                              double* part, const EigCtrl* ctrl, double* evals, double* resid, void* Xsave,
                              hipStream_t st);

@@ -19,6 +19,11 @@
 // X, P, HX, HP, W = HX - X Lam -> convergence control.  Every kernel returns
 // at once when the control block says the solve is done, so chunks of
 // iterations can be queued without host round trips.
+//
+// Populations: every kernel takes blockIdx.y as the member of a population
+// of independent solves on lattices of one geometry (EigArgs::P, strides
+// s_ms, part_ms, g_ms); the dense per-member steps then run as P
+// workgroups side by side, so a population costs about one solve's latency.
 #include <type_traits>
 
 #include "dense_wg.hpp"
@@ -48,6 +53,13 @@ __global__ void k_eig_init(EigArgs a, T* __restrict__ S, const double* __restric
                            const double* __restrict__ Vwarm, int nwarm, const T* __restrict__ Xsave, int use_save,
                            const uint8_t* __restrict__ mask, int N, uint64_t seed, EigCtrl* ctrl) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    S += y * a.s_ms;
+    m += (size_t)y * 3 * N;
+    if (Vwarm) Vwarm += (size_t)y * nwarm * 3 * N;
+    if (Xsave) Xsave += (size_t)y * a.mb * 3 * N;
+    if (mask) mask += (size_t)y * N;
+    ctrl += y;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->done = 0;
         ctrl->status = MOTO_NOT_CONVERGED;
@@ -107,6 +119,9 @@ __device__ __forceinline__ void orth_cols(const EigArgs& a, int target, const Ei
 template <class T>
 __global__ __launch_bounds__(NT) void k_orth_gram(EigArgs a, int target, const T* __restrict__ S,
                                                   double* __restrict__ part, const EigCtrl* __restrict__ ctrl) {
+    S += blockIdx.y * a.s_ms;
+    part += blockIdx.y * a.part_ms;
+    ctrl += blockIdx.y;
     if (ctrl->done) return;
     __shared__ OrthCols oc;
     __shared__ T ts[MAXS][RCH];
@@ -155,6 +170,9 @@ __global__ __launch_bounds__(NT) void k_orth_gram(EigArgs a, int target, const T
 __global__ __launch_bounds__(NT) void k_reduce_rows(EigArgs a, const double* __restrict__ part, int nblk, int kind,
                                                     int arg, double* __restrict__ G,
                                                     const EigCtrl* __restrict__ ctrl) {
+    part += blockIdx.y * a.part_ms;
+    G += blockIdx.y * a.g_ms;
+    ctrl += blockIdx.y;
     if (ctrl->done) return;
     int E;
     if (kind == 0) {
@@ -176,6 +194,8 @@ __global__ __launch_bounds__(NT) void k_reduce_rows(EigArgs a, const double* __r
 
 __global__ __launch_bounds__(WL) void k_orth_small(EigArgs a, int target, const double* __restrict__ G,
                                                    EigCtrl* __restrict__ ctrl) {
+    G += blockIdx.y * a.g_ms;
+    ctrl += blockIdx.y;
     if (ctrl->done) return;
     const int nq = target == 1 ? a.mb + ctrl->np : 0;
     orth_small_body<MAXS + 1>(a.mb, nq, a.drop, G, ctrl->Bw, ctrl->Tw);
@@ -186,6 +206,8 @@ __global__ __launch_bounds__(WL) void k_orth_small(EigArgs a, int target, const 
 template <class T, int MB>
 __global__ __launch_bounds__(NT) void k_orth_apply(EigArgs a, int target, T* __restrict__ S,
                                                    const EigCtrl* __restrict__ ctrl) {
+    S += blockIdx.y * a.s_ms;
+    ctrl += blockIdx.y;
     if (ctrl->done) return;
     __shared__ OrthCols oc;
     __shared__ double B[2 * MAXB * MAXB];
@@ -241,6 +263,10 @@ template <class T>
 __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* __restrict__ S,
                                              const T* __restrict__ HS, double* __restrict__ part,
                                              const EigCtrl* __restrict__ ctrl) {
+    S += blockIdx.y * a.s_ms;
+    HS += blockIdx.y * a.s_ms;
+    part += blockIdx.y * a.part_ms;
+    ctrl += blockIdx.y;
     if (ctrl->done) return;
     const int ns = sol_ns(a, ctrl, ns_fixed);
     const int Eh = ns * (ns + 1) / 2, E = 2 * Eh;
@@ -291,6 +317,8 @@ __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* _
 // Rayleigh-Ritz step (one wavefront, FP64): see rr_body.
 __global__ __launch_bounds__(WL) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ Gtri,
                                            EigCtrl* __restrict__ ctrl) {
+    Gtri += blockIdx.y * a.g_ms;
+    ctrl += blockIdx.y;
     if (ctrl->done) return;
     rr_body<MAXS + 1>(a.mb, sol_ns(a, ctrl, ns_fixed), a.drop, Gtri, ctrl);
 }
@@ -304,6 +332,10 @@ __global__ __launch_bounds__(WL) void k_rr(EigArgs a, int ns_fixed, const double
 template <class T, int MB>
 __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __restrict__ S, T* __restrict__ HS,
                                                double* __restrict__ part, const EigCtrl* __restrict__ ctrl) {
+    S += blockIdx.y * a.s_ms;
+    HS += blockIdx.y * a.s_ms;
+    part += blockIdx.y * a.part_ms;
+    ctrl += blockIdx.y;
     if (ctrl->done) return;
     const int ns = sol_ns(a, ctrl, ns_fixed);
     const int mb = a.mb;
@@ -384,6 +416,8 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
 // sums), then one thread checks NaN, rank, convergence and the cap.
 __global__ __launch_bounds__(NT) void k_eig_control(EigArgs a, const double* __restrict__ part, int nblk,
                                                     EigCtrl* __restrict__ ctrl, int first) {
+    part += blockIdx.y * a.part_ms;
+    ctrl += blockIdx.y;
     if (ctrl->done) return;
     __shared__ double rsq[MAXB];
     const int lane = threadIdx.x & 63;
@@ -422,6 +456,15 @@ __global__ __launch_bounds__(NT) void k_eig_control(EigArgs a, const double* __r
     }
 }
 
+// all_done = AND of the members' done flags (one wavefront, fixed order)
+__global__ __launch_bounds__(WL) void k_eig_all_done(int P, const EigCtrl* __restrict__ ctrl,
+                                                     int* __restrict__ all_done) {
+    int d = 1;
+    for (int y = threadIdx.x; y < P; y += WL) d &= ctrl[y].done != 0;
+    d = __all(d);
+    if (threadIdx.x == 0) *all_done = d;
+}
+
 // --------------------------------------------------------------------------
 // Output: the first k block columns to ambient FP64 unit vectors with the
 // sign rule (entry of largest magnitude, first in [3][N] order, positive);
@@ -434,6 +477,12 @@ __global__ __launch_bounds__(NT) void k_eig_out1(EigArgs a, const T* __restrict_
                                                  T* __restrict__ Xsave) {
     __shared__ double rn[MAXB][NT / 64], rm[MAXB][NT / 64], ri[MAXB][NT / 64];
     const int s = blockIdx.x * NT + threadIdx.x;
+    const int y = blockIdx.y;
+    S += y * a.s_ms;
+    m += (size_t)y * 3 * N;
+    V += (size_t)y * a.k * 3 * N;
+    part += y * a.part_ms;
+    if (Xsave) Xsave += (size_t)y * a.mb * 3 * N;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     T e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
     if (s < N) onb((T)m[s], (T)m[N + s], (T)m[2 * N + s], e1, e2);
@@ -494,6 +543,13 @@ __global__ __launch_bounds__(NT) void k_eig_out1(EigArgs a, const T* __restrict_
 __global__ void k_eig_out2(EigArgs a, const double* __restrict__ part, int nblk, const double* __restrict__ V,
                            int N, double* __restrict__ scale, const EigCtrl* __restrict__ ctrl,
                            double* __restrict__ evals, double* __restrict__ resid) {
+    const int y = blockIdx.y;
+    part += y * a.part_ms;
+    V += (size_t)y * a.k * 3 * N;
+    scale += y * a.part_ms;
+    ctrl += y;
+    if (evals) evals += y * a.k;
+    if (resid) resid += y * a.k;
     const int j = threadIdx.x;
     if (j >= a.k) return;
     double n = 0.0, mx = -1.0, mi = 1e300;
@@ -512,10 +568,15 @@ __global__ void k_eig_out2(EigArgs a, const double* __restrict__ part, int nblk,
     if (resid) resid[j] = ctrl->resid[j];
 }
 
-__global__ void k_eig_out3(int k, int N, double* __restrict__ V, const double* __restrict__ scale) {
+// scale of member y, column j at scale[y * part_ms + j]
+__global__ void k_eig_out3(int k, int N, int P, long long part_ms, double* __restrict__ V,
+                           const double* __restrict__ scale) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t tot = (size_t)k * 3 * N;
-    if (i < tot) V[i] *= scale[i / (3 * (size_t)N)];
+    const size_t tot = (size_t)P * k * 3 * N;
+    if (i >= tot) return;
+    const size_t col = i / (3 * (size_t)N);
+    const size_t y = col / k, j = col - y * k;
+    V[i] *= scale[y * part_ms + j];
 }
 
 // --------------------------------------------------------------------------
@@ -545,7 +606,7 @@ static void go_mb(int mb, F&& f) {
 hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m, const double* Vwarm, int nwarm,
                            const void* Xsave, int use_save, const uint8_t* mask, int N, uint64_t seed,
                            EigCtrl* ctrl, hipStream_t st) {
-    dim3 grid((N + NT - 1) / NT);
+    dim3 grid((N + NT - 1) / NT, a.P);
     if (f64)
         hipLaunchKernelGGL(k_eig_init<double>, grid, dim3(NT), 0, st, a, (double*)S, m, Vwarm, nwarm,
                            (const double*)Xsave, use_save, mask, N, seed, ctrl);
@@ -558,22 +619,22 @@ hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m,
 hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* part, int nblk, double* G,
                        EigCtrl* ctrl, hipStream_t st) {
     if (f64)
-        hipLaunchKernelGGL(k_orth_gram<double>, dim3(nblk), dim3(NT), 0, st, a, target, (const double*)S, part,
+        hipLaunchKernelGGL(k_orth_gram<double>, dim3(nblk, a.P), dim3(NT), 0, st, a, target, (const double*)S, part,
                            ctrl);
     else
-        hipLaunchKernelGGL(k_orth_gram<float>, dim3(nblk), dim3(NT), 0, st, a, target, (const float*)S, part,
+        hipLaunchKernelGGL(k_orth_gram<float>, dim3(nblk, a.P), dim3(NT), 0, st, a, target, (const float*)S, part,
                            ctrl);
-    hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS), dim3(NT), 0, st, a, part, nblk, 0, target, G, ctrl);
-    hipLaunchKernelGGL(k_orth_small, dim3(1), dim3(WL), 0, st, a, target, G, ctrl);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS, a.P), dim3(NT), 0, st, a, part, nblk, 0, target, G, ctrl);
+    hipLaunchKernelGGL(k_orth_small, dim3(1, a.P), dim3(WL), 0, st, a, target, G, ctrl);
     const int nb = update_blocks(a.n2);
     if (f64)
         go_mb(a.mb, [&](auto mbc) {
-            hipLaunchKernelGGL((k_orth_apply<double, decltype(mbc)::value>), dim3(nb), dim3(NT), 0, st, a, target,
+            hipLaunchKernelGGL((k_orth_apply<double, decltype(mbc)::value>), dim3(nb, a.P), dim3(NT), 0, st, a, target,
                                (double*)S, ctrl);
         });
     else
         go_mb(a.mb, [&](auto mbc) {
-            hipLaunchKernelGGL((k_orth_apply<float, decltype(mbc)::value>), dim3(nb), dim3(NT), 0, st, a, target,
+            hipLaunchKernelGGL((k_orth_apply<float, decltype(mbc)::value>), dim3(nb, a.P), dim3(NT), 0, st, a, target,
                                (float*)S, ctrl);
         });
     return hipGetLastError();
@@ -582,17 +643,17 @@ hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* 
 hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const void* HS, double* part, int nblk,
                        double* G, const EigCtrl* ctrl, hipStream_t st) {
     if (f64)
-        hipLaunchKernelGGL(k_gram<double>, dim3(nblk), dim3(NT), 0, st, a, ns, (const double*)S,
+        hipLaunchKernelGGL(k_gram<double>, dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (const double*)S,
                            (const double*)HS, part, ctrl);
     else
-        hipLaunchKernelGGL(k_gram<float>, dim3(nblk), dim3(NT), 0, st, a, ns, (const float*)S, (const float*)HS,
+        hipLaunchKernelGGL(k_gram<float>, dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (const float*)S, (const float*)HS,
                            part, ctrl);
-    hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS), dim3(NT), 0, st, a, part, nblk, 1, ns, G, ctrl);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS, a.P), dim3(NT), 0, st, a, part, nblk, 1, ns, G, ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, hipStream_t st) {
-    hipLaunchKernelGGL(k_rr, dim3(1), dim3(WL), 0, st, a, ns, G, ctrl);
+    hipLaunchKernelGGL(k_rr, dim3(1, a.P), dim3(WL), 0, st, a, ns, G, ctrl);
     return hipGetLastError();
 }
 
@@ -600,12 +661,12 @@ hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, 
                          EigCtrl* ctrl, hipStream_t st) {
     if (f64)
         go_mb(a.mb, [&](auto mbc) {
-            hipLaunchKernelGGL((k_update<double, decltype(mbc)::value>), dim3(nblk), dim3(NT), 0, st, a, ns,
+            hipLaunchKernelGGL((k_update<double, decltype(mbc)::value>), dim3(nblk, a.P), dim3(NT), 0, st, a, ns,
                                (double*)S, (double*)HS, part, ctrl);
         });
     else
         go_mb(a.mb, [&](auto mbc) {
-            hipLaunchKernelGGL((k_update<float, decltype(mbc)::value>), dim3(nblk), dim3(NT), 0, st, a, ns,
+            hipLaunchKernelGGL((k_update<float, decltype(mbc)::value>), dim3(nblk, a.P), dim3(NT), 0, st, a, ns,
                                (float*)S, (float*)HS, part, ctrl);
         });
     return hipGetLastError();
@@ -613,7 +674,12 @@ hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, 
 
 hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, EigCtrl* ctrl, int first,
                               hipStream_t st) {
-    hipLaunchKernelGGL(k_eig_control, dim3(1), dim3(NT), 0, st, a, part, nblk, ctrl, first);
+    hipLaunchKernelGGL(k_eig_control, dim3(1, a.P), dim3(NT), 0, st, a, part, nblk, ctrl, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_all_done(const EigArgs& a, const EigCtrl* ctrl, int* all_done, hipStream_t st) {
+    hipLaunchKernelGGL(k_eig_all_done, dim3(1), dim3(WL), 0, st, a.P, ctrl, all_done);
     return hipGetLastError();
 }
 
@@ -622,15 +688,16 @@ hipError_t launch_eig_output(bool f64, const EigArgs& a, const void* S, const do
                              hipStream_t st) {
     const int nb = (N + NT - 1) / NT;
     if (f64)
-        hipLaunchKernelGGL(k_eig_out1<double>, dim3(nb), dim3(NT), 0, st, a, (const double*)S, m, N, V, part,
+        hipLaunchKernelGGL(k_eig_out1<double>, dim3(nb, a.P), dim3(NT), 0, st, a, (const double*)S, m, N, V, part,
                            (double*)Xsave);
     else
-        hipLaunchKernelGGL(k_eig_out1<float>, dim3(nb), dim3(NT), 0, st, a, (const float*)S, m, N, V, part,
+        hipLaunchKernelGGL(k_eig_out1<float>, dim3(nb, a.P), dim3(NT), 0, st, a, (const float*)S, m, N, V, part,
                            (float*)Xsave);
     double* scale = part + (size_t)nb * MAXB * 3;
-    hipLaunchKernelGGL(k_eig_out2, dim3(1), dim3(64), 0, st, a, part, nb, V, N, scale, ctrl, evals, resid);
-    const size_t tot = (size_t)a.k * 3 * N;
-    hipLaunchKernelGGL(k_eig_out3, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a.k, N, V, scale);
+    hipLaunchKernelGGL(k_eig_out2, dim3(1, a.P), dim3(64), 0, st, a, part, nb, V, N, scale, ctrl, evals, resid);
+    const size_t tot = (size_t)a.P * a.k * 3 * N;
+    hipLaunchKernelGGL(k_eig_out3, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a.k, N, a.P, a.part_ms,
+                       V, scale);
     return hipGetLastError();
 }
 

@@ -319,8 +319,9 @@ hipError_t launch_reduce_partials(const double* part, int batch, int tiles, int 
 
 hipError_t launch_tangent_hvp(const Geo& g, const CoefD& kd, bool f64, bool frame, int batch, const void* m,
                               const void* c, const uint8_t* mask, int nvec, const void* V, void* W,
-                              const int* done, hipStream_t st, int variant) {
-    if (frame) return launch_hvp_frame(variant, g, kd, f64, batch, m, c, mask, nvec, V, W, done, st);
+                              const int* done, hipStream_t st, int variant, long long vbs) {
+    if (frame) return launch_hvp_frame(variant, g, kd, f64, batch, m, c, mask, nvec, V, W, done, st, vbs);
+    if (vbs > 0 && vbs != (long long)nvec * 3 * g.N) return hipErrorInvalidValue;
     dim3 grid(batch * g.tiles);
     if (f64)
         hipLaunchKernelGGL((k_tangent_hvp<double, false>), grid, dim3(NT), 0, st, g, coef_cast<double>(kd),

@@ -118,6 +118,9 @@ def lib():
         "moto_min_modes_lanczos_workspace": (_sz, [_vp, _i32, _i32]),
         "moto_min_modes_lanczos": (_i32, [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(LanczosOpts), _vp, _vp, _vp,
                                           ctypes.POINTER(Info), _vp, _sz, _vp]),
+        "moto_min_modes_population_workspace": (_sz, [_vp, _i32, _i32, _i32, _i32]),
+        "moto_min_modes_population": (_i32, [_vp, _i32, _i32, _vp, _vp, _i32, ctypes.POINTER(EigOpts), _vp, _vp,
+                                             _vp, _vp, _vp, _sz, _vp]),
         "moto_step_state_bytes": (_sz, [_vp, _i32]),
         "moto_reflected_step": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(StepOpts), _vp, _vp, _vp]),
         "moto_descend_workspace": (_sz, [_vp, _i32, ctypes.POINTER(DescendOpts)]),
@@ -428,6 +431,57 @@ def moto_min_modes(plan: Plan, m: torch.Tensor, k: int, hvp: int = MOTO_F64, mas
                                 _ptr(resid), ctypes.byref(info), _ptr(ws.buf), ws.nbytes, _stream(stream)),
            "moto_min_modes")
     return MinModes(evals, V, resid, info.status, info.iters, info.n_hvp)
+
+
+MAX_POPULATION = 256
+
+
+@dataclass
+class PopulationModes:
+    evals: torch.Tensor  # [P, k]
+    V: torch.Tensor      # [P, k, 3, N]
+    resid: torch.Tensor  # [P, k]
+    status: list
+    iters: list
+    n_hvp: list
+
+
+class PopulationWorkspace:
+    def __init__(self, plan: Plan, hvp: int, P: int, k: int, guard: int = -1, device="cuda"):
+        self.nbytes = int(lib().moto_min_modes_population_workspace(plan.handle, hvp, P, k, guard))
+        if self.nbytes == 0:
+            raise MotoError("population size or k out of range")
+        self.buf = _ws(self.nbytes, device)
+
+
+def moto_min_modes_population(plan: Plan, m: torch.Tensor, k: int, hvp: int = MOTO_F64,
+                              mask: Optional[torch.Tensor] = None, opts: Optional[EigOpts] = None,
+                              V0: Optional[torch.Tensor] = None, ws: Optional[PopulationWorkspace] = None,
+                              stream=None) -> PopulationModes:
+    """k lowest modes of each of the P states m [P, 3, N] (mask [P, N] or None)."""
+    if m.dim() != 3 or m.shape[1] != 3 or m.shape[2] != plan.N:
+        raise MotoError("m must be [P, 3, N]")
+    P = int(m.shape[0])
+    if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != P * plan.N):
+        raise MotoError("mask must be uint8 [P, N]")
+    if V0 is not None and V0.numel() != P * k * 3 * plan.N:
+        raise MotoError("V0 must be [P, k, 3, N]")
+    o = opts if opts is not None else eig_opts(hvp)
+    dev = m.device
+    V = torch.zeros(P, k, 3, plan.N, dtype=torch.float64, device=dev) if V0 is None else V0.clone().contiguous()
+    if V0 is not None and o.warm == 0:
+        o.warm = 1
+    evals = torch.empty(P, k, dtype=torch.float64, device=dev)
+    resid = torch.empty(P, k, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = PopulationWorkspace(plan, hvp, P, k, o.guard, dev)
+    info = (Info * P)()
+    _check(lib().moto_min_modes_population(plan.handle, hvp, P, _ptr(m), _ptr(mask), k, ctypes.byref(o),
+                                           _ptr(evals), _ptr(V), _ptr(resid), info, _ptr(ws.buf), ws.nbytes,
+                                           _stream(stream)),
+           "moto_min_modes_population")
+    return PopulationModes(evals, V, resid, [i.status for i in info], [i.iters for i in info],
+                           [i.n_hvp for i in info])
 
 
 class StepState:

@@ -180,3 +180,31 @@ def test_graph_replays_match_eager_bitwise():
                              ws=ws)
         assert r.iters == ref.iters and r.status == ref.status
         assert torch.equal(r.evals, ref.evals) and torch.equal(r.V, ref.V)
+
+
+@pytest.mark.parametrize("solver", ["lobpcg", "lanczos"])
+@pytest.mark.parametrize("hvp", ["f64", "f32"])
+def test_captured_chunk_follows_the_callers_state(solver, hvp):
+    """One workspace, three different states passed in turn with graph
+    replay on: every result equals the plain-launch solve of its own state
+    (a captured chunk must not keep reading the first caller's spins)."""
+    M = _M()
+    p = S.ham_3shell(32)
+    plan = M.Plan.from_params(p)
+    dt = M.MOTO_F64 if hvp == "f64" else M.MOTO_F32
+    tol = 1e-10 if hvp == "f64" else 1e-5
+    states = [_dev(S.three_shell_start(32, seed=20 + y)) for y in range(3)]
+    if solver == "lobpcg":
+        ws = M.EigWorkspace(plan, dt, 2)
+        run = lambda m, g, w: M.moto_min_modes(plan, m, 2, dt, opts=M.eig_opts(dt, tol=tol, use_graph=g), ws=w)
+        fresh = lambda: M.EigWorkspace(plan, dt, 2)
+    else:
+        ws = M.LanczosWorkspace(plan, dt, 32)
+        run = lambda m, g, w: M.moto_min_modes_lanczos(plan, m, 2, dt, opts=M.lanczos_opts(dt, tol=tol, use_graph=g),
+                                                       ws=w)
+        fresh = lambda: M.LanczosWorkspace(plan, dt, 32)
+    for m in states:
+        rg = run(m, 1, ws)
+        re = run(m, 0, fresh())
+        assert rg.status == re.status == M.CONVERGED and rg.iters == re.iters
+        assert torch.equal(rg.evals, re.evals) and torch.equal(rg.V, re.V)

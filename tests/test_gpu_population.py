@@ -1,0 +1,139 @@
+"""GPU parity of the inner layer over a population (moto_min_modes_population:
+P block-LOBPCG solves in lock step) against the FP64 oracle, member by
+member.  Same bars as the single-solve tests: eigenvalues
+|d lambda| <= 1e-5 max(|lambda|, h_est) (FP32 adds 1e-5 h_est); vectors
+1 - |cos| <= 1e-8 (FP64) or sin(angle) <= 1e-3 (FP32) where the gap is
+>= 1e-3 h_est."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_26269_amd import synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _M():
+    from paper_2509_26269_amd import moto as M
+
+    return M
+
+
+def _dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _check_member(ev, V, ro, k, hest, fp32):
+    w = ro.evals
+    for j in range(k):
+        assert abs(ev[j] - w[j]) <= 1e-5 * max(abs(w[j]), hest) + (1e-5 * hest if fp32 else 0.0), (j, ev[j], w[j])
+        gap = min(abs(w[j] - w[i]) for i in range(len(w)) if i != j)
+        if gap >= 1e-3 * hest:
+            cos = abs(float((V[j] * ro.V[j]).sum()))
+            if fp32:
+                assert np.sqrt(max(0.0, 1 - cos * cos)) <= 1e-3
+            else:
+                assert 1 - cos <= 1e-8
+
+
+def test_population_fp64_matches_oracle_member_by_member():
+    """Five different states (one the exactly degenerate uniform state, which
+    converges at once, beside perturbed skyrmions that take longer)."""
+    M = _M()
+    p = S.ham_nn(16)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    ms = [S.nn_start(s) for s in range(4)] + [S.uniform(h.N)]
+    k = 2
+    r = M.moto_min_modes_population(plan, _dev(np.stack(ms)), k, M.MOTO_F64,
+                                    opts=M.eig_opts(M.MOTO_F64, tol=1e-10))
+    assert all(st == M.CONVERGED for st in r.status), r.status
+    ev, V = _np(r.evals), _np(r.V)
+    for y, m in enumerate(ms):
+        ro = O.min_modes(h, m, k + 2, tol=1e-11)
+        _check_member(ev[y], V[y], ro, k, h.h_est(), False)
+        assert np.abs((V[y] * m[None]).sum(1)).max() < 1e-12  # tangent
+    # members finish independently: the uniform state needs fewer iterations
+    assert r.iters[4] < max(r.iters[:4])
+
+
+def test_population_fp32_masked_per_member_matches_oracle():
+    M = _M()
+    L = 48
+    p = S.ham_3shell(L)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    ms, masks = [], []
+    for y in range(4):
+        ms.append(S.three_shell_start(L, seed=10 + y))
+        masks.append(S.random_mask_disc(L, L, 10.0 + 2 * y) if y % 2 else np.ones(L * L, np.uint8))
+    k = 2
+    r = M.moto_min_modes_population(plan, _dev(np.stack(ms)), k, M.MOTO_F32,
+                                    mask=_dev(np.stack(masks), torch.uint8),
+                                    opts=M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=400))
+    assert all(st == M.CONVERGED for st in r.status), (r.status, r.iters)
+    ev, V = _np(r.evals), _np(r.V)
+    for y in range(4):
+        ro = O.min_modes(h, ms[y], k + 2, tol=1e-11, max_iter=600, mask=masks[y])
+        _check_member(ev[y], V[y], ro, k, h.h_est(), True)
+        assert np.all(V[y][:, :, masks[y] == 0] == 0)
+
+
+def test_population_agrees_with_single_solves_and_graph_replay():
+    """Each member equals the single-state solve of the same state to the
+    solver tolerance; replays of the captured chunk equal plain launches
+    bit for bit."""
+    M = _M()
+    p = S.ham_3shell(32)
+    plan = M.Plan.from_params(p)
+    ms = np.stack([S.three_shell_start(32, seed=20 + y) for y in range(3)])
+    md = _dev(ms)
+    outs = []
+    for g in (0, 1, 1):
+        o = M.eig_opts(M.MOTO_F64, tol=1e-10, use_graph=g)
+        outs.append(M.moto_min_modes_population(plan, md, 2, M.MOTO_F64, opts=o))
+    for r in outs[1:]:
+        assert r.status == outs[0].status and r.iters == outs[0].iters
+        assert torch.equal(r.evals, outs[0].evals) and torch.equal(r.V, outs[0].V)
+    hest = plan.hessian_norm_bound()
+    for y in range(3):
+        rs = M.moto_min_modes(plan, md[y].contiguous(), 2, M.MOTO_F64, opts=M.eig_opts(M.MOTO_F64, tol=1e-10))
+        assert np.abs(_np(rs.evals) - _np(outs[0].evals[y])).max() <= 1e-9 * hest
+
+
+def test_population_full_size_eigenpair_property():
+    """24 perturbed 128x128 states (the explorer's population size), FP32 HVP,
+    k = 2: every returned pair is an eigenpair of the oracle operator within
+    the tolerance, and the ordering holds."""
+    M = _M()
+    L = 128
+    p = S.ham_3shell(L)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    spec = S.fixed_size_spec(24, L, seed=128)
+    ms = np.stack([S.batch_member(spec, y) for y in range(24)])
+    r = M.moto_min_modes_population(plan, _dev(ms), 2, M.MOTO_F32,
+                                    opts=M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=400))
+    ev, V = _np(r.evals), _np(r.V)
+    conv = [y for y in range(24) if r.status[y] == M.CONVERGED]
+    assert len(conv) >= 20, (r.status, r.iters)
+    for y in conv[::4]:
+        _, _, c, _ = O.energy_grad(h, ms[y])
+        assert ev[y][0] <= ev[y][1] + 1e-6 * h.h_est()
+        for j in range(2):
+            Hv = O.tangent_hvp(h, ms[y], c, V[y][j])
+            assert np.linalg.norm(Hv - ev[y][j] * V[y][j]) <= 2e-5 * h.h_est(), (y, j)
+
+
+def test_population_bad_arguments_rejected():
+    M = _M()
+    plan = M.Plan.from_params(S.ham_nn(8))
+    assert M.lib().moto_min_modes_population_workspace(plan.handle, M.MOTO_F64, 0, 2, -1) == 0
+    assert M.lib().moto_min_modes_population_workspace(plan.handle, M.MOTO_F64, M.MAX_POPULATION + 1, 2, -1) == 0
+    with pytest.raises(M.MotoError):
+        M.moto_min_modes_population(plan, _dev(S.uniform(64))[None].expand(2, 3, 64).contiguous(), 17, M.MOTO_F64)
