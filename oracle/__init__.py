@@ -849,3 +849,95 @@ def max_site_angle(m1, m2) -> float:
     cr = np.cross(m1.T, m2.T)
     dt = (m1 * m2).sum(0)
     return float(np.arctan2(np.sqrt((cr * cr).sum(1)), dt).max())
+
+
+# ---------------------------------------------------------------------------
+# Explorer objectives (Methods, "Multi-objective initial-configuration
+# explorer"; Supplementary Note 1, Algorithm 1 population loop; Results,
+# "Multi-objective explorer over generations").  NSGA-II itself is not here:
+# these are the per-candidate quantities it ranks.
+# ---------------------------------------------------------------------------
+def explorer_candidates(x0, deltas, mask=None) -> np.ndarray:
+    """Candidates x = x0 + P_Omega delta followed by the projection onto the
+    spin manifold (the Methods' candidate equation): on an active site the
+    spin is (x0_i + delta_i) / |x0_i + delta_i|; an inactive site keeps x0_i,
+    and so does an active site whose sum vanishes (no nearest unit vector).
+    deltas: (P, 3, N) ambient perturbations.  Returns (P, 3, N)."""
+    x0 = _f64(x0)
+    N = x0.shape[1]
+    D = _f64(deltas).reshape(-1, 3, N)
+    act = np.ones(N, bool) if mask is None else np.asarray(mask).astype(bool)
+    out = np.empty_like(D)
+    for p in range(D.shape[0]):
+        x = x0.copy()
+        for i in range(N):
+            if not act[i]:
+                continue
+            v = x0[:, i] + D[p][:, i]
+            n = np.sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2])
+            if n > 0.0:
+                x[:, i] = v / n
+        out[p] = x
+    return out
+
+
+def l1_distance_matrix(X, Y) -> np.ndarray:
+    """D[p, q] = sum over sites and components |X_p - Y_q| (the l1 distance
+    of the Results' diversity measures), one pair at a time."""
+    X = _f64(X)
+    Y = _f64(Y)
+    X = X.reshape(X.shape[0], -1)
+    Y = Y.reshape(Y.shape[0], X.shape[1])
+    D = np.zeros((X.shape[0], Y.shape[0]))
+    for p in range(X.shape[0]):
+        for q in range(Y.shape[0]):
+            D[p, q] = np.abs(X[p] - Y[q]).sum()
+    return D
+
+
+@dataclass
+class ExplorerResult:
+    X: np.ndarray          # (P, 3, N) candidates
+    E: np.ndarray          # energies
+    evals: np.ndarray      # (P, k) lowest eigenvalues of the (masked) tangent Hessian
+    gap: np.ndarray        # lambda_2 - lambda_1
+    Q: np.ndarray          # topological charges
+    violation: np.ndarray  # |Q - Q_target|
+    l1_sum: np.ndarray     # sum of l1 distances to the other candidates
+    l1_min: np.ndarray     # smallest l1 distance to another candidate or an archive member
+    D: np.ndarray          # (P, P + A) l1 distances to the candidates, then the archive
+    converged: np.ndarray
+
+
+def explorer_objectives(ham: Ham, x0, deltas, mask=None, archive=None, Q_target: Optional[float] = None,
+                        k: int = 2, tol: float = 1e-10, max_iter: int = 200) -> ExplorerResult:
+    """The three objectives of every candidate of a population (Methods,
+    objectives (i)-(iii); Algorithm 1 evaluates them against S u A):
+      (i)   diversity: l1 distances to the other candidates and to the
+            archive A; per candidate their sum over the population and their
+            minimum over S u A (the Results plot the total pairwise l1
+            distance and the maximin distance);
+      (ii)  feasibility: the topological-charge violation |Q(x) - Q_target|
+            (Q_target = Q(x0) when not given);
+      (iii) separability: the gap lambda_2 - lambda_1 of the two lowest
+            eigenvalues of the tangent Hessian, restricted to the masked
+            subspace when a mask is given (the subspace the climb then moves
+            in), from the LOBPCG oracle."""
+    x0 = _f64(x0).reshape(3, ham.N)
+    X = explorer_candidates(x0, deltas, mask)
+    P = X.shape[0]
+    A = np.zeros((0, 3, ham.N)) if archive is None else _f64(archive).reshape(-1, 3, ham.N)
+    qt = topological_charge(ham, x0) if Q_target is None else float(Q_target)
+    E = np.array([energy(ham, X[p]) for p in range(P)])
+    ev = np.zeros((P, k))
+    conv = np.zeros(P, bool)
+    for p in range(P):
+        r = min_modes(ham, X[p], k, tol=tol, max_iter=max_iter, mask=mask)
+        ev[p] = r.evals[:k]
+        conv[p] = r.converged
+    Q = np.array([topological_charge(ham, X[p]) for p in range(P)])
+    D = np.concatenate([l1_distance_matrix(X, X), l1_distance_matrix(X, A)], axis=1)
+    l1_sum = np.array([sum(D[p, q] for q in range(P) if q != p) for p in range(P)])
+    l1_min = np.array([min([D[p, q] for q in range(P + A.shape[0]) if q != p], default=np.inf)
+                       for p in range(P)])
+    return ExplorerResult(X, E, ev, ev[:, 1] - ev[:, 0], Q, np.abs(Q - qt), l1_sum, l1_min, D, conv)
