@@ -410,6 +410,67 @@ moto_status moto_saddle_search_batched(const moto_hamiltonian *h, int32_t n, con
                                        double *m_all, const moto_search_opts *opts /* host */,
                                        moto_search_result *res, void *ws, size_t ws_bytes, moto_stream stream);
 
+/* ---------------------------------------------------------------------
+ * Explorer objectives (Methods, "Multi-objective initial-configuration
+ * explorer"; Algorithm 1, population loop; Results, "Multi-objective explorer
+ * over generations"): for a population of P candidates on the plan's lattice,
+ *   x_p = x0 + P_Omega delta_p, each active spin then projected onto the
+ *         unit sphere (an active site whose sum vanishes keeps x0; inactive
+ *         sites keep x0),
+ * and per candidate the three objectives an evolutionary selector ranks:
+ *   diversity:      l1 distances to the other candidates and to an archive
+ *                   A of n_archive configurations (sum over the population,
+ *                   minimum over population and archive);
+ *   feasibility:    |Q(x_p) - Q_target| with the Berg-Luescher charge;
+ *   separability:   lambda_2 - lambda_1 of the tangent Hessian, restricted
+ *                   to the masked subspace when a mask is given, from the
+ *                   population eigen-solve (moto_min_modes_population).
+ * The selector itself (NSGA-II) is not part of the library.
+ *   x0      [3][N] FP64 device: the reference minimum
+ *   mask    [N] device (1 = active) or NULL (all active)
+ *   delta   [P][3][N] FP64 device: ambient perturbations
+ *   archive [n_archive][3][N] FP64 device (NULL when n_archive == 0)
+ *   x_out   [P][3][N] FP64 device: the candidates
+ *   res     [P] device: objectives and the eigen-solve outcome per candidate
+ *   evals   [P][k] FP64 device or NULL; V [P][k][3][N] FP64 device or NULL
+ *           (the lowest modes, e.g. to start the climb from);
+ *   D       [P][P + n_archive] FP64 device or NULL: the l1 distances
+ * The call synchronises with the stream (the eigen-solve's convergence
+ * checks) and returns after queueing the summary.
+ * Errors: MOTO_EINVAL for P (1..MOTO_MAX_POPULATION), k or n_archive
+ * (0..MOTO_MAX_ARCHIVE) out of range, eig.warm != 0 or missing pointers;
+ * MOTO_EWORKSPACE below moto_explorer_workspace(p, hvp, P, n_archive, opts). */
+typedef struct {
+    int32_t k;          /* modes solved per candidate, 2..16 - guard (default 2) */
+    int32_t reserved;
+    double Q_target;    /* feasibility target; NaN (default): Q(x0) */
+    moto_eig_opts eig;  /* eigen-solve options (FP32 HVP default tolerance 1e-5) */
+} moto_explorer_opts;
+
+typedef struct {
+    double E;           /* energy */
+    double lambda1, lambda2;
+    double gap;         /* lambda2 - lambda1 */
+    double Q;           /* topological charge */
+    double violation;   /* |Q - Q_target| */
+    double l1_sum;      /* sum of l1 distances to the other candidates */
+    double l1_min;      /* smallest l1 distance to another candidate or an archive member (inf if none) */
+    int32_t status;     /* eigen-solve outcome (MOTO_CONVERGED, ...) */
+    int32_t iters;
+    int64_t n_hvp;
+} moto_explorer_result;
+
+#define MOTO_MAX_ARCHIVE 4096
+void moto_default_explorer_opts(moto_dtype hvp, moto_explorer_opts *o);
+size_t moto_explorer_workspace(moto_plan p, moto_dtype hvp, int32_t P, int32_t n_archive,
+                               const moto_explorer_opts *o);
+moto_status moto_explorer_objectives(moto_plan p, moto_dtype hvp, int32_t P, const double *x0,
+                                     const uint8_t *mask, const double *delta, int32_t n_archive,
+                                     const double *archive, const moto_explorer_opts *opts /* host */,
+                                     double *x_out, moto_explorer_result *res, double *evals,
+                                     double *V, double *D, void *ws, size_t ws_bytes,
+                                     moto_stream stream);
+
 /* Defaults for the option structs. */
 void moto_default_eig_opts(moto_dtype hvp, moto_eig_opts *o);
 void moto_default_step_opts(moto_step_opts *o);

@@ -55,9 +55,9 @@ inline size_t al(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 size_t energy_ws(const moto_plan p, int batch) { return al(sizeof(double) * NPART * (size_t)batch * p->g.tiles); }
 
-// Eigen-solve workspace layout (offsets in bytes from the workspace base).
-// Eigen-solve workspace for a population of P solves (P = 1: one solve);
-// every region holds the P members back to back.
+// Eigen-solve workspace layout (offsets in bytes from the workspace base)
+// for a population of P solves (P = 1: one solve); every region holds the P
+// members back to back.
 struct EigLayout {
     size_t mT, cT, c64, S, HS, Xsave, part, G, ctrl, flag, total;
     int mb, n2, nblk_g, nblk_u, nblk_o;
@@ -1142,6 +1142,119 @@ moto_status moto_saddle_search_batched(const moto_hamiltonian* h, int32_t n, con
     HIP_TRY(launch_batched_search(a, m_all, (const int*)(w + bl.Ls), (const int*)(w + bl.order),
                                   (const long long*)(w + bl.moff), (const long long*)(w + bl.woff), w + bl.res0, res, n,
                                   st));
+    return MOTO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Explorer objectives
+// ---------------------------------------------------------------------------
+void moto_default_explorer_opts(moto_dtype hvp, moto_explorer_opts* o) {
+    if (!o) return;
+    o->k = 2;
+    o->reserved = 0;
+    o->Q_target = std::nan("");
+    moto_default_eig_opts(hvp, &o->eig);
+}
+
+namespace {
+// [eig population ws][mask copies P N][c P N][energy / charge partials]
+// [E P][Q P + 1][evals P k][V P k 3N][l1 partials][D P (P + A)]
+struct ExpLayout {
+    size_t eig, mask, c, part, E, Q, ev, V, l1, D, total;
+};
+
+ExpLayout exp_layout(moto_plan p, moto_dtype hvp, int P, int A, int k, int guard) {
+    ExpLayout L;
+    const size_t N = p->g.N, Pz = (size_t)P, Qz = (size_t)(P + A);
+    size_t o = 0;
+    L.eig = o;
+    o += eig_layout(p, hvp, k, resolve_guard(k, guard), P).total;
+    L.mask = o;
+    o += al(Pz * N);
+    L.c = o;
+    o += al(sizeof(double) * Pz * N);
+    L.part = o;
+    o += energy_ws(p, P + 1);
+    L.E = o;
+    o += al(sizeof(double) * Pz);
+    L.Q = o;
+    o += al(sizeof(double) * (Pz + 1));
+    L.ev = o;
+    o += al(sizeof(double) * Pz * k);
+    L.V = o;
+    o += al(sizeof(double) * Pz * k * 3 * N);
+    L.l1 = o;
+    o += al(sizeof(double) * (size_t)l1_chunks(3LL * (long long)N) * Pz * Qz);
+    L.D = o;
+    o += al(sizeof(double) * Pz * Qz);
+    L.total = o;
+    return L;
+}
+
+bool explorer_args_ok(moto_plan p, moto_dtype hvp, int P, int A, const moto_explorer_opts& o) {
+    if (!p || !hvp_ok(hvp) || P < 1 || P > MOTO_MAX_POPULATION || A < 0 || A > MOTO_MAX_ARCHIVE) return false;
+    if (o.k < 2 || o.k + resolve_guard(o.k, o.eig.guard) > MAXB) return false;
+    if (o.eig.max_iter < 0 || !(o.eig.tol >= 0.0) || o.eig.warm != 0) return false;
+    return true;
+}
+}  // namespace
+
+size_t moto_explorer_workspace(moto_plan p, moto_dtype hvp, int32_t P, int32_t n_archive,
+                               const moto_explorer_opts* opts) {
+    moto_explorer_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_explorer_opts(hvp, &o);
+    if (!explorer_args_ok(p, hvp, P, n_archive, o)) return 0;
+    return exp_layout(p, hvp, P, n_archive, o.k, o.eig.guard).total;
+}
+
+moto_status moto_explorer_objectives(moto_plan p, moto_dtype hvp, int32_t P, const double* x0, const uint8_t* mask,
+                                     const double* delta, int32_t n_archive, const double* archive,
+                                     const moto_explorer_opts* opts, double* x_out, moto_explorer_result* res,
+                                     double* evals, double* V, double* D, void* ws, size_t ws_bytes,
+                                     moto_stream stream) {
+    moto_explorer_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_explorer_opts(hvp, &o);
+    if (!explorer_args_ok(p, hvp, P, n_archive, o)) return MOTO_EINVAL;
+    if (!x0 || !delta || !x_out || !res || (n_archive > 0 && !archive)) return MOTO_EINVAL;
+    const ExpLayout L = exp_layout(p, hvp, P, n_archive, o.k, o.eig.guard);
+    if (!ws || ws_bytes < L.total) return MOTO_EWORKSPACE;
+    char* w = (char*)ws;
+    hipStream_t st = (hipStream_t)stream;
+    const int N = p->g.N;
+    const int k = o.k;
+    uint8_t* mrep = mask ? (uint8_t*)(w + L.mask) : nullptr;
+    double* c = (double*)(w + L.c);
+    double* part = (double*)(w + L.part);
+    double* E = (double*)(w + L.E);
+    double* Qv = (double*)(w + L.Q);
+    double* ev = evals ? evals : (double*)(w + L.ev);
+    double* Vb = V ? V : (double*)(w + L.V);
+    double* Db = D ? D : (double*)(w + L.D);
+    // candidates (and one copy of the mask per candidate for the batched HVP)
+    HIP_TRY(launch_candidates(N, P, x0, mask, delta, x_out, mrep, st));
+    // energies and c = m . g of every candidate
+    HIP_TRY(launch_energy_grad(p->g, p->k, true, P, x_out, nullptr, nullptr, c, nullptr, part, st));
+    HIP_TRY(launch_reduce_partials(part, P, p->g.tiles, p->ns, E, nullptr, st));
+    // topological charges of the candidates, then of x0
+    HIP_TRY(launch_topo_charge(p->g, P, x_out, part, st));
+    HIP_TRY(launch_reduce_partials(part, P, p->g.tiles, p->ns, Qv, nullptr, st));
+    HIP_TRY(launch_topo_charge(p->g, 1, x0, part, st));
+    HIP_TRY(launch_reduce_partials(part, 1, p->g.tiles, p->ns, Qv + P, nullptr, st));
+    // l1 distances to S u A
+    HIP_TRY(launch_l1(3LL * N, P, n_archive, x_out, archive, (double*)(w + L.l1), Db, st));
+    // the k lowest modes of every candidate, in lock step
+    moto_status rs = min_modes_pop_impl(p, hvp, P, x_out, mrep, k, &o.eig, ev, Vb, nullptr, nullptr, w + L.eig,
+                                        L.mask - L.eig, st, c);
+    if (rs != MOTO_OK) return rs;
+    const EigLayout EL = eig_layout(p, hvp, k, resolve_guard(k, o.eig.guard), P);
+    const EigCtrl* ctrl = (const EigCtrl*)(w + L.eig + EL.ctrl);
+    HIP_TRY(launch_explorer_finish(P, n_archive, k, Db, E, ev, Qv, Qv + P, o.Q_target, ctrl, res, st));
     return MOTO_OK;
 }
 

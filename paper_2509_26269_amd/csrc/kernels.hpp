@@ -120,6 +120,17 @@ hipError_t launch_lz_orth(bool f64, int n2, void* Q, int j, double* part, int nb
 hipError_t launch_lz_rr_restart(bool f64, int n2, void* Q, int k, int keep, double tol_abs, int max_restarts,
                                 int m_max, int nblk, LzCtrl* ctrl, hipStream_t st);
 
+// ---- explorer.hip ----
+int l1_chunks(long long n3);
+hipError_t launch_candidates(int N, int P, const double* x0, const uint8_t* mask, const double* delta, double* X,
+                             uint8_t* mask_rep, hipStream_t st);
+// part: l1_chunks(3N) * P * (P + A) doubles; D: P * (P + A)
+hipError_t launch_l1(long long n3, int P, int A, const double* X, const double* Arch, double* part, double* D,
+                     hipStream_t st);
+hipError_t launch_explorer_finish(int P, int A, int k, const double* D, const double* E, const double* evals,
+                                  const double* Qc, const double* Qx0, double Q_target, const EigCtrl* ctrl,
+                                  moto_explorer_result* res, hipStream_t st);
+
 hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m, const double* Vwarm, int nwarm,
                            const void* Xsave, int use_save, const uint8_t* mask, int N, uint64_t seed,
                            EigCtrl* ctrl, hipStream_t st);

@@ -12,6 +12,7 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -80,6 +81,18 @@ class SearchResult(ctypes.Structure):
                 ("lambda2", ctypes.c_double)]
 
 
+class ExplorerOpts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("reserved", ctypes.c_int32), ("Q_target", ctypes.c_double),
+                ("eig", EigOpts)]
+
+
+class ExplorerResult(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double),
+                ("gap", ctypes.c_double), ("Q", ctypes.c_double), ("violation", ctypes.c_double),
+                ("l1_sum", ctypes.c_double), ("l1_min", ctypes.c_double), ("status", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("n_hvp", ctypes.c_int64)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
@@ -135,6 +148,12 @@ def lib():
         "moto_default_search_opts": (None, [_i32, ctypes.POINTER(SearchOpts)]),
         "moto_topological_charge": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     }
+    sig.update({
+        "moto_default_explorer_opts": (None, [_i32, ctypes.POINTER(ExplorerOpts)]),
+        "moto_explorer_workspace": (_sz, [_vp, _i32, _i32, _i32, ctypes.POINTER(ExplorerOpts)]),
+        "moto_explorer_objectives": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp,
+                                            ctypes.POINTER(ExplorerOpts), _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    })
     sig.update({
         "moto_saddle_search_batched_workspace": (_sz, [_i32, ctypes.POINTER(ctypes.c_int32),
                                                        ctypes.POINTER(SearchOpts)]),
@@ -558,3 +577,59 @@ def moto_saddle_search_batched(params, Ls: Sequence[int], m_all: torch.Tensor, o
     raw = bytes(res.cpu().numpy())
     sz = ctypes.sizeof(SearchResult)
     return [SearchResult.from_buffer_copy(raw[i * sz:(i + 1) * sz]) for i in range(n)]
+
+
+# ---------------------------------------------------------------------------
+# Explorer objectives
+# ---------------------------------------------------------------------------
+def explorer_opts(dtype: int = MOTO_F32, eig: Optional[dict] = None, **kw) -> ExplorerOpts:
+    o = ExplorerOpts()
+    lib().moto_default_explorer_opts(dtype, ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    for k, v in (eig or {}).items():
+        setattr(o.eig, k, v)
+    return o
+
+
+@dataclass
+class Explorer:
+    X: torch.Tensor          # [P, 3, N] candidates
+    res: dict                # per-candidate arrays: E, lambda1, lambda2, gap, Q, violation, l1_sum, l1_min,
+                             # status, iters, n_hvp
+    evals: torch.Tensor      # [P, k]
+    V: Optional[torch.Tensor]
+    D: torch.Tensor          # [P, P + A]
+
+
+def moto_explorer_objectives(plan: Plan, x0: torch.Tensor, delta: torch.Tensor, hvp: int = MOTO_F32,
+                             mask: Optional[torch.Tensor] = None, archive: Optional[torch.Tensor] = None,
+                             opts: Optional[ExplorerOpts] = None, want_V: bool = False, stream=None) -> Explorer:
+    """Objectives of the P candidates x0 + P_Omega delta (delta [P, 3, N])."""
+    N = plan.N
+    if x0.numel() != 3 * N or delta.dim() != 3 or delta.shape[1] != 3 or delta.shape[2] != N:
+        raise MotoError("x0 must be [3, N] and delta [P, 3, N]")
+    if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != N):
+        raise MotoError("mask must be uint8 [N]")
+    P = int(delta.shape[0])
+    A = 0 if archive is None else int(archive.shape[0])
+    if archive is not None and archive.numel() != A * 3 * N:
+        raise MotoError("archive must be [A, 3, N]")
+    o = opts if opts is not None else explorer_opts(hvp)
+    nb = int(lib().moto_explorer_workspace(plan.handle, hvp, P, A, ctypes.byref(o)))
+    if nb == 0:
+        raise MotoError("explorer arguments out of range")
+    dev = delta.device
+    ws = _ws(nb, dev)
+    X = torch.empty(P, 3, N, dtype=torch.float64, device=dev)
+    res = torch.empty(P * ctypes.sizeof(ExplorerResult), dtype=torch.uint8, device=dev)
+    evals = torch.empty(P, o.k, dtype=torch.float64, device=dev)
+    V = torch.empty(P, o.k, 3, N, dtype=torch.float64, device=dev) if want_V else None
+    D = torch.empty(P, P + A, dtype=torch.float64, device=dev)
+    _check(lib().moto_explorer_objectives(plan.handle, hvp, P, _ptr(x0), _ptr(mask), _ptr(delta), A, _ptr(archive),
+                                          ctypes.byref(o), _ptr(X), _ptr(res), _ptr(evals), _ptr(V), _ptr(D),
+                                          _ptr(ws), nb, _stream(stream)),
+           "moto_explorer_objectives")
+    raw = (ExplorerResult * P).from_buffer_copy(bytes(res.cpu().numpy()))
+    out = {f: np.array([getattr(r, f) for r in raw]) for f, _ in ExplorerResult._fields_}
+    return Explorer(X, out, evals, V, D)
