@@ -7,6 +7,8 @@ Headline (the 128x128 three-shell workload, FP32 HVP):
     kernel streams from HBM); one step = one batched HVP launch;
   * the roofline of that kernel (algorithmic bytes 12 + 16 n_vec per site);
   * wall time of the k = 4 eigen-solve (residual 1e-5) on one 128x128 state;
+  * a population of 24 k = 2 eigen-solves in lock step against one at a
+    time, and the explorer objectives of 24 candidates;
   * saddle searches/s (k = 2, FP32 HVP, tau_F = 1e-5, capped outer
     iterations): 64 searches on 128x128 in one persistent launch, 256 on
     uneven 32..96 lattices in one launch, and searches one at a time
@@ -144,6 +146,8 @@ def main():
     ap.add_argument("--batched", type=int, default=64, help="searches on 128x128 in the batched (one-launch) leg")
     ap.add_argument("--ragged", type=int, default=256, help="searches on uneven 32..96 lattices, one launch")
     ap.add_argument("--max-outer", type=int, default=300, help="outer-iteration cap of every search leg")
+    ap.add_argument("--population", type=int, default=24,
+                    help="population size of the lock-step eigen-solve and explorer legs (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-search", action="store_true")
     ap.add_argument("--hvp-only", action="store_true", help="only the HVP leg (for profilers)")
@@ -291,6 +295,59 @@ def main():
                                 "workspace_bytes": wsl.nbytes}
         extra["lanczos_128_k4"] = lz
         extra["lobpcg_128_k4_lambda"] = [round(float(x), 6) for x in r.evals.cpu()]
+    if not args.hvp_only and not args.eigen_only and args.population > 0:
+        # explorer scale: the two lowest modes of a population of perturbed
+        # 128x128 states, in lock step and one at a time; then the whole
+        # objective evaluation (candidates, l1 diversity, charge, gap)
+        Pp = args.population
+        print(f"[bench] population of {Pp} 128x128 k=2 FP32 eigen-solves", file=sys.stderr, flush=True)
+        spec_p = S.fixed_size_spec(Pp, L, seed=2024)
+        mp_all = torch.as_tensor(np.stack([S.batch_member(spec_p, i) for i in range(Pp)]), device="cuda")
+        op = M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=400)
+        wsp = M.PopulationWorkspace(plan, M.MOTO_F32, Pp, 2)
+        M.moto_min_modes_population(plan, mp_all, 2, M.MOTO_F32, opts=op, ws=wsp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rp = M.moto_min_modes_population(plan, mp_all, 2, M.MOTO_F32, opts=op, ws=wsp)
+        torch.cuda.synchronize()
+        t_pop = time.perf_counter() - t0
+        ws1 = M.EigWorkspace(plan, M.MOTO_F32, 2)
+        M.moto_min_modes(plan, mp_all[0].contiguous(), 2, M.MOTO_F32, opts=op, ws=ws1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its1 = 0
+        for i in range(Pp):
+            r1 = M.moto_min_modes(plan, mp_all[i].contiguous(), 2, M.MOTO_F32, opts=op, ws=ws1)
+            its1 += r1.iters
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t0
+        st_hist = {}
+        for stt in rp.status:
+            st_hist[M.STATUS_NAMES[stt]] = st_hist.get(M.STATUS_NAMES[stt], 0) + 1
+        extra["population_eigen_128_k2"] = {
+            "P": Pp, "lock_step_ms": round(1e3 * t_pop, 2), "one_at_a_time_ms": round(1e3 * t_one, 2),
+            "speedup": round(t_one / t_pop, 2), "max_iters": int(max(rp.iters)),
+            "mean_iters": round(float(np.mean(rp.iters)), 1), "one_at_a_time_mean_iters": round(its1 / Pp, 1),
+            "status": st_hist}
+        print(f"[bench] explorer objectives, population {Pp} on 128x128, masked disc, archive 8", file=sys.stderr,
+              flush=True)
+        x0e = torch.as_tensor(S.three_shell_start(L, seed=0, kind="skyrmion"), device="cuda")
+        rng = np.random.default_rng(24)
+        mask_e = torch.as_tensor(S.random_mask_disc(L, L, 20.0), device="cuda")
+        de = torch.as_tensor(0.25 * rng.standard_normal((Pp, 3, N)), device="cuda")
+        arch = torch.as_tensor(np.stack([S.batch_member(spec_p, i) for i in range(8)]), device="cuda")
+        oe = M.explorer_opts(M.MOTO_F32, eig={"tol": 1e-5, "max_iter": 400})
+        M.moto_explorer_objectives(plan, x0e, de, M.MOTO_F32, mask=mask_e, archive=arch, opts=oe)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        re_ = M.moto_explorer_objectives(plan, x0e, de, M.MOTO_F32, mask=mask_e, archive=arch, opts=oe)
+        torch.cuda.synchronize()
+        t_exp = time.perf_counter() - t0
+        extra["explorer_128_P%d" % Pp] = {
+            "wall_ms": round(1e3 * t_exp, 2), "candidates_per_s": round(Pp / t_exp, 1),
+            "max_iters": int(re_.res["iters"].max()),
+            "converged": int((re_.res["status"] == M.CONVERGED).sum()),
+            "gap_median": float(np.median(re_.res["gap"])), "l1_min_median": float(np.median(re_.res["l1_min"]))}
     if not args.hvp_only and not args.eigen_only:
         # differentiation form on 64x64 (energy, backward, double backward), FP32 spins
         from paper_2509_26269_amd import autograd as AG
