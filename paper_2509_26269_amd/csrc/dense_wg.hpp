@@ -30,6 +30,143 @@ __device__ __forceinline__ void wsync() {
 __device__ __forceinline__ int wlane() { return threadIdx.x & (WL - 1); }
 
 // --------------------------------------------------------------------------
+// Symmetric eigen-decomposition on one wavefront, the solver of every small
+// dense step: Householder reduction to tridiagonal form with the reflections
+// accumulated (lane r owns row r of the matrix and of Z), then the implicit
+// QL iteration with Wilkinson shifts on the tridiagonal, its plane rotations
+// applied to the columns of Z (Golub & Van Loan, Sections 8.3.1 and 8.3.5).
+// The scalar recurrences of the QL sweep are computed by every lane alike,
+// so control flow stays uniform.  Same contract as jacobi_wg: on return
+// diag(A) holds the eigenvalues (in no particular order) and column j of Z
+// the eigenvector of A[j][j]; the off-diagonal part of A is left undefined.
+// About n^2 short serial steps instead of the Jacobi's ~ 6 n rounds of n^2/2
+// rotations, which is what a single wavefront is limited by.
+// --------------------------------------------------------------------------
+// value of v held by lane i (i uniform across the wave)
+__device__ __forceinline__ double rdlane(double v, int i) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), i);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), i);
+    return __hiloint2double(hi, lo);
+}
+
+template <int LD>
+__device__ void symeig_wg(double* A, double* Z, int n) {
+    __shared__ double hv[LD], hw[LD];
+    const int lane = wlane();
+    if (n <= 0) return;
+    for (int r = lane; r < n; r += WL)
+        for (int c = 0; c < n; ++c) Z[r * LD + c] = (r == c) ? 1.0 : 0.0;
+    wsync();
+    // ---- tridiagonalisation: A <- H A H, Z <- Z H, H = I - 2 v v^T ----
+    for (int k = 0; k + 2 < n; ++k) {
+        double x2 = 0.0;
+        for (int i = k + 1 + lane; i < n; i += WL) {
+            const double x = A[i * LD + k];
+            x2 += x * x;
+        }
+        x2 = wave_sum(x2);
+        if (x2 == 0.0) continue;
+        const double x0 = A[(k + 1) * LD + k];
+        const double nx = sqrt(x2);
+        const double alpha = x0 >= 0.0 ? -nx : nx;
+        // |v|^2 = |x|^2 - 2 alpha x0 + alpha^2 = 2 (|x|^2 - alpha x0) > 0
+        const double inv = 1.0 / sqrt(2.0 * (x2 - alpha * x0));
+        for (int i = k + 1 + lane; i < n; i += WL) hv[i] = (A[i * LD + k] - (i == k + 1 ? alpha : 0.0)) * inv;
+        wsync();
+        // p = A22 v, K = v^T p, w = p - K v
+        double vp = 0.0;
+        for (int i = k + 1 + lane; i < n; i += WL) {
+            double pi = 0.0;
+            for (int j = k + 1; j < n; ++j) pi += A[i * LD + j] * hv[j];
+            hw[i] = pi;
+            vp += pi * hv[i];
+        }
+        const double K = wave_sum(vp);
+        wsync();
+        for (int i = k + 1 + lane; i < n; i += WL) hw[i] -= K * hv[i];
+        wsync();
+        // A22 <- A22 - 2 (v w^T + w v^T); column k reduced to alpha e_(k+1)
+        for (int i = k + 1 + lane; i < n; i += WL) {
+            const double vi = hv[i], wi = hw[i];
+            for (int j = k + 1; j < n; ++j) A[i * LD + j] -= 2.0 * (vi * hw[j] + wi * hv[j]);
+            const double a = i == k + 1 ? alpha : 0.0;
+            A[i * LD + k] = a;
+            A[k * LD + i] = a;
+        }
+        // Z <- Z - 2 (Z v) v^T on columns k+1..n-1
+        for (int r = lane; r < n; r += WL) {
+            double t = 0.0;
+            for (int j = k + 1; j < n; ++j) t += Z[r * LD + j] * hv[j];
+            t *= 2.0;
+            for (int j = k + 1; j < n; ++j) Z[r * LD + j] -= t * hv[j];
+        }
+        wsync();
+    }
+    // ---- implicit QL on the tridiagonal (d, e): lane i holds d_i and e_i
+    // (= T[i+1][i]) in registers; the sweep's scalars are read with readlane
+    // and computed by every lane alike, so control flow stays uniform ----
+    double di = 0.0, ei = 0.0;
+    if (lane < n) {
+        di = A[lane * LD + lane];
+        ei = lane + 1 < n ? A[(lane + 1) * LD + lane] : 0.0;
+    }
+    constexpr double eps = 2.220446049250313e-16;
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0; iter < 64; ++iter) {
+            // m = first index >= l with a negligible e_m (or n - 1)
+            const double dn = __shfl_down(di, 1, WL);
+            const bool small = lane + 1 >= n || fabs(ei) <= eps * (fabs(di) + fabs(dn));
+            const unsigned long long msk = __ballot(small && lane >= l);
+            const int m = (int)__builtin_ctzll(msk);
+            if (m == l) break;
+            const double dl = rdlane(di, l), el = rdlane(ei, l);
+            double g = (rdlane(di, l + 1) - dl) / (2.0 * el);
+            double r = sqrt(g * g + 1.0);
+            g = rdlane(di, m) - dl + el / (g + (g >= 0.0 ? r : -r));
+            double sn = 1.0, cs = 1.0, p = 0.0;
+            bool deflated = false;
+            double dnext = rdlane(di, m);  // d_(i+1) before its update
+            for (int i = m - 1; i >= l; --i) {
+                const double e_i = rdlane(ei, i), d_i = rdlane(di, i);
+                const double f = sn * e_i, b = cs * e_i;
+                r = sqrt(f * f + g * g);
+                if (lane == i + 1) ei = r;
+                if (r == 0.0) {
+                    if (lane == i + 1) di = dnext - p;
+                    if (lane == m) ei = 0.0;
+                    deflated = true;
+                    break;
+                }
+                const double inv = 1.0 / r;
+                sn = f * inv;
+                cs = g * inv;
+                g = dnext - p;
+                r = (d_i - g) * sn + 2.0 * cs * b;
+                p = sn * r;
+                if (lane == i + 1) di = g + p;
+                g = cs * r - b;
+                dnext = d_i;
+                for (int row = lane; row < n; row += WL) {
+                    const double z1 = Z[row * LD + i + 1], z0 = Z[row * LD + i];
+                    Z[row * LD + i + 1] = sn * z0 + cs * z1;
+                    Z[row * LD + i] = cs * z0 - sn * z1;
+                }
+            }
+            if (deflated) continue;
+            if (lane == l) {
+                di -= p;
+                ei = g;
+            }
+            if (lane == m) ei = 0.0;
+        }
+    }
+    wsync();
+    if (lane < n) A[lane * LD + lane] = di;
+    wsync();
+}
+
+// --------------------------------------------------------------------------
 // Parallel cyclic Jacobi on an n x n symmetric matrix in LDS (leading
 // dimension LD), round-robin ordering: the n/2 rotations of a round act on
 // disjoint index pairs (Golub & Van Loan, parallel Jacobi).  A round applies
@@ -244,7 +381,7 @@ __device__ void orth_small_body(int mb, int nq, double drop, const double* G, do
             nkeep = r;
         }
     } else {
-        jacobi_wg<LD>(A, Z, mb, 1e-15, 40);
+        symeig_wg<LD>(A, Z, mb);
         if (tid == 0) {
             int r = 0;
             for (int i = 0; i < mb; ++i) {
@@ -344,7 +481,7 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
         });
         wsync();
     } else {
-        jacobi_wg<LD>(A, Z, ns, 1e-15, 40);
+        symeig_wg<LD>(A, Z, ns);
         if (tid == 0) {
             double tmax = 0.0;
             for (int i = 0; i < ns; ++i) tmax = fmax(tmax, A[i * LD + i]);
@@ -387,7 +524,7 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
         }
     });
     wsync();
-    jacobi_wg<LD>(A, Z, r, 1e-13, 40);
+    symeig_wg<LD>(A, Z, r);
     for (int i = tid; i < r; i += WL) ev[i] = A[i * LD + i];
     wsync();
     for (int i = tid; i < r; i += WL) {
@@ -458,7 +595,7 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
         Z[p * LD + j] = dsc[p] * h1[p + MBL * j] * dsc[j];
     });
     wsync();
-    jacobi_wg<LD>(Z, A, mb, 1e-13, 40);
+    symeig_wg<LD>(Z, A, mb);
     if (tid == 0) {
         int rr = 0;
         for (int i = 0; i < mb; ++i) {

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
     const double bm = full ? ctrl->T[m * LZ_LDT + m - 1] : 0.0;
     for2(m, m, [&](int r, int c) { A[r * LD + c] = 0.5 * (ctrl->T[r * LZ_LDT + c] + ctrl->T[c * LZ_LDT + r]); });
     wsync();
-    jacobi_wg<LD>(A, Z, m, 1e-14, 40);
+    symeig_wg<LD>(A, Z, m);
     for (int i = lane; i < m; i += WL) ev[i] = A[i * LD + i];
     wsync();
     for (int i = lane; i < m; i += WL) {
