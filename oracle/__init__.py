@@ -22,7 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmoto_oracle.so")
-MAX_SHELLS = 8
+MAX_SHELLS = 36
 
 
 def _load():

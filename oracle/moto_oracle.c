@@ -26,8 +26,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_MAX_SHELLS 8
-#define ORC_MAX_OFFSETS 128
+#define ORC_MAX_SHELLS 36
+#define ORC_MAX_OFFSETS 512
 #define ORC_SEARCH_R 12
 #define ORC_MAX_GEN_SHELLS 64
 

@@ -25,6 +25,33 @@ SHELL_OFFSETS = [
 ]
 
 
+def _table_s1_offsets():
+    """Offsets of all 35 shells, enumerated from the distances and bond counts
+    of the paper's Table S1 (tests/golden fixture; distances in units of the
+    lattice constant a, nearest neighbour a/sqrt2): shell s holds every
+    lattice vector whose squared length, in nearest-neighbour units, is the
+    s-th printed distance squared.  The three hand-listed shells come first."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table_s1_shells.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    out = []
+    for r, cnt in rows:
+        d2 = int(round((float(r) / 0.707107) ** 2))
+        offs = [(dx, dy) for dy in range(-12, 13) for dx in range(-12, 13) if dx * dx + dx * dy + dy * dy == d2]
+        assert len(offs) == int(cnt), (r, cnt, len(offs))
+        out.append(offs)
+    for s in range(3):
+        assert sorted(out[s]) == sorted(SHELL_OFFSETS[s])
+    return out
+
+
+SHELL_OFFSETS_35 = _table_s1_offsets()
+
+
+def shell_count(s):
+    return len(SHELL_OFFSETS_35[s])
+
+
 def cart(dx, dy):
     return dx * A1 + dy * A2
 
@@ -38,7 +65,7 @@ def kgrid(Lx, Ly):
 def shell_sum(k, s):
     """S_s(k) = sum_{delta in shell s} (1 - cos k.delta)."""
     out = np.zeros(len(k))
-    for dx, dy in SHELL_OFFSETS[s]:
+    for dx, dy in SHELL_OFFSETS_35[s]:
         d = cart(dx, dy)
         out += 1.0 - np.cos(k @ d)
     return out
@@ -65,8 +92,9 @@ def fm_z_spectrum(Lx, Ly, J, K, bz):
 
 
 def fm_z_energy(N, J, K, bz):
-    """E/N = -sum_delta J_delta - bz - K for m = +z (6 offsets per shell)."""
-    return N * (-6.0 * sum(J) - bz - K)
+    """E/N = -sum_delta J_delta - bz - K for m = +z (every offset of every
+    shell: 6, 12 or 24 per shell)."""
+    return N * (-sum(shell_count(s) * Js for s, Js in enumerate(J)) - bz - K)
 
 
 def fm_x_spectrum(Lx, Ly, J, D1, K, bx):
@@ -101,7 +129,7 @@ def cycloid_energy(Lx, Ly, n1, n2, J, D1, K, bz):
     qh = q / np.linalg.norm(q)
     e = 0.0
     for s, Js in enumerate(J):
-        for dx, dy in SHELL_OFFSETS[s]:
+        for dx, dy in SHELL_OFFSETS_35[s]:
             e += -Js * np.cos(q @ cart(dx, dy))
     for dx, dy in SHELL_OFFSETS[0]:
         d = cart(dx, dy)
