@@ -56,8 +56,16 @@
  *   pinned host memory for convergence read-back: use one plan from one host
  *   thread at a time.
  *
- * GPU SCOPE: up to 3 exchange shells and DMI on the nearest-neighbour shell
- * (D[1..] must be 0); other Hamiltonians return MOTO_EUNSUPPORTED.
+ * GPU SCOPE: up to MOTO_MAX_SHELLS exchange shells (the shells of the
+ * triangular lattice by increasing distance, 6, 12, 18 or 24 bonds each; the
+ * paper's Pd/Fe/Ir(111) parameters, Supplementary Note 4, use 35) and DMI on
+ * the nearest-neighbour shell (D[1..] must be 0); other Hamiltonians return
+ * MOTO_EUNSUPPORTED.  Up to 3 shells the lattice kernels are specialised
+ * (row march, register rings); beyond, a general-shell tile kernel stages a
+ * halo of up to 12 rows and sums the shells from LDS.  With more than 3
+ * shells, moto_hessian_apply, moto_param_mixed, moto_param_grad_apply and
+ * the batched search return MOTO_EUNSUPPORTED, and energy partials carry E
+ * only (no parameter derivatives).
  */
 #ifndef MOTO_H
 #define MOTO_H
@@ -90,7 +98,7 @@ typedef int32_t moto_status;
 typedef enum { MOTO_F32 = 0, MOTO_F64 = 1 } moto_dtype;
 typedef enum { MOTO_AMBIENT = 0, MOTO_FRAME = 1 } moto_layout;
 
-#define MOTO_MAX_SHELLS 8
+#define MOTO_MAX_SHELLS 36
 
 /* Spin Hamiltonian (Methods, Eq. param-hamiltonian), reduced units. */
 typedef struct {

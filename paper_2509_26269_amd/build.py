@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmoto.so")
-SOURCES = ["stencil.hip", "hvp.hip", "lobpcg.hip", "lanczos.hip", "step.hip", "batched.hip", "explorer.hip", "api.cpp"]
+SOURCES = ["stencil.hip", "hvp.hip", "lobpcg.hip", "lanczos.hip", "step.hip", "batched.hip", "explorer.hip", "shells.hip", "api.cpp"]
 ARCH = os.environ.get("MOTO_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -41,6 +41,8 @@ struct moto_plan_s {
     // private stream the graphs are captured on (capture is not possible on
     // the legacy default stream a caller may pass); replays use the caller's
     hipStream_t cap_stream;
+    // shell table of a Hamiltonian with more than three shells (k.gen points here)
+    GenShells gen;
 };
 
 namespace {
@@ -122,6 +124,41 @@ int tuned_variant(const moto_plan p, moto_dtype dt, int batch, int nvec) {
     return -1;
 }
 
+// Offsets of the first ns shells of the triangular lattice (every lattice
+// vector dx a1 + dy a2, |.|^2 = dx^2 + dx dy + dy^2, grouped by length in
+// increasing order).  All offsets up to |.|^2 = 3 (R + 1)^2 / 4 lie in the
+// box |dx|, |dy| <= R = GEN_RMAX, which covers MOTO_MAX_SHELLS shells.
+bool shell_table(int ns, GenShells* t) {
+    std::vector<int> lens;
+    for (int dy = -GEN_RMAX; dy <= GEN_RMAX; ++dy)
+        for (int dx = -GEN_RMAX; dx <= GEN_RMAX; ++dx) {
+            const int d2 = dx * dx + dx * dy + dy * dy;
+            if (d2 > 0) lens.push_back(d2);
+        }
+    std::sort(lens.begin(), lens.end());
+    lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
+    if (ns < 1 || ns > GEN_MAX_SHELLS || ns > (int)lens.size()) return false;
+    if (4 * lens[ns - 1] >= 3 * (GEN_RMAX + 1) * (GEN_RMAX + 1)) return false;
+    int n = 0, R = 0;
+    for (int s = 0; s < ns; ++s) {
+        t->start[s] = n;
+        for (int dy = -GEN_RMAX; dy <= GEN_RMAX; ++dy)
+            for (int dx = -GEN_RMAX; dx <= GEN_RMAX; ++dx)
+                if (dx * dx + dx * dy + dy * dy == lens[s]) {
+                    if (n >= GEN_MAX_OFF) return false;
+                    t->dx[n] = (signed char)dx;
+                    t->dy[n] = (signed char)dy;
+                    R = std::max(R, std::max(std::abs(dx), std::abs(dy)));
+                    ++n;
+                }
+    }
+    t->start[ns] = n;
+    t->ns = ns;
+    t->n_off = n;
+    t->R = R;
+    return true;
+}
+
 // Read back n bytes of device memory through the plan's pinned buffer.
 moto_status readback(moto_plan p, const void* dev, size_t n, void* host, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(p->pinned, dev, n, hipMemcpyDeviceToHost, st));
@@ -153,10 +190,8 @@ moto_status moto_plan_create(const moto_hamiltonian* h, moto_plan* out) {
     if ((int64_t)h->Lx * h->Ly > (int64_t)1 << 28) return MOTO_EINVAL;
     for (int s = 0; s < MOTO_MAX_SHELLS; ++s) {
         if (!std::isfinite(h->J[s]) || !std::isfinite(h->D[s])) return MOTO_EINVAL;
-        if (s >= 3 && s < h->n_shells && h->J[s] != 0.0) return MOTO_EUNSUPPORTED;
         if (s >= 1 && h->D[s] != 0.0) return MOTO_EUNSUPPORTED;
     }
-    if (h->n_shells > 3) return MOTO_EUNSUPPORTED;
     if (!std::isfinite(h->K) || !std::isfinite(h->B[0]) || !std::isfinite(h->B[1]) || !std::isfinite(h->B[2]))
         return MOTO_EINVAL;
     moto_plan p = new (std::nothrow) moto_plan_s;
@@ -168,10 +203,17 @@ moto_status moto_plan_create(const moto_hamiltonian* h, moto_plan* out) {
     p->k.cD = 2.0 * h->D[0];
     p->k.cK = -2.0 * h->K;
     for (int a = 0; a < 3; ++a) p->k.B[a] = h->B[a];
+    if (!shell_table(h->n_shells, &p->gen)) {
+        delete p;
+        return MOTO_EUNSUPPORTED;
+    }
+    for (int s = 0; s < h->n_shells; ++s) p->gen.cJ[s] = -2.0 * h->J[s];
+    p->k.gen = h->n_shells > 3 ? &p->gen : nullptr;
     double sj = 0.0, sd = 0.0;
     for (int s = 0; s < h->n_shells; ++s) {
-        sj += 6.0 * std::fabs(h->J[s]);
-        sd += 6.0 * std::fabs(h->D[s]);
+        const int cnt = p->gen.start[s + 1] - p->gen.start[s];
+        sj += cnt * std::fabs(h->J[s]);
+        sd += cnt * std::fabs(h->D[s]);
     }
     p->hest = 4.0 * (sj + sd) + 4.0 * std::fabs(h->K) +
               std::sqrt(h->B[0] * h->B[0] + h->B[1] * h->B[1] + h->B[2] * h->B[2]);
@@ -211,6 +253,7 @@ moto_status moto_energy_grad(moto_plan p, moto_dtype dt, int32_t batch, const vo
                              double* E, void* grad, void* c, void* F, double* dE_dtheta, void* ws,
                              size_t ws_bytes, moto_stream stream) {
     if (!p || !m || batch < 1 || !hvp_ok(dt)) return MOTO_EINVAL;
+    if (p->k.gen && dE_dtheta) return MOTO_EUNSUPPORTED;
     const bool need_red = E || dE_dtheta;
     if (!ws || ws_bytes < energy_ws(p, batch)) return MOTO_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
@@ -235,6 +278,7 @@ int32_t moto_tangent_hvp_variants(void) { return HVP_NVARIANTS; }
 
 moto_status moto_plan_set_hvp_variant(moto_plan p, moto_dtype dt, int32_t batch, int32_t n_vec, int32_t variant) {
     if (!p || !hvp_ok(dt) || batch < 1 || n_vec < 1 || !hvp_variant_ok(variant, p->g, dt == MOTO_F64)) return MOTO_EINVAL;
+    if (p->k.gen) return MOTO_EUNSUPPORTED;
     int slot = -1;
     for (int i = 0; i < p->n_tune; ++i)
         if (p->tune[i].dt == (int)dt && p->tune[i].batch == batch && p->tune[i].nvec == n_vec) slot = i;
@@ -249,6 +293,7 @@ moto_status moto_tangent_hvp_autotune(moto_plan p, moto_dtype dt, int32_t batch,
                                       const uint8_t* mask, int32_t n_vec, const void* V, void* W, int32_t reps,
                                       int32_t* chosen, float* times_ms, moto_stream stream) {
     if (!p || !m || !c || !V || !W || batch < 1 || n_vec < 1 || !hvp_ok(dt) || V == W) return MOTO_EINVAL;
+    if (p->k.gen) return MOTO_EUNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = dt == MOTO_F64;
     if (reps < 1) reps = 3;
@@ -291,6 +336,7 @@ moto_status moto_tangent_hvp_autotune(moto_plan p, moto_dtype dt, int32_t batch,
 moto_status moto_hessian_apply(moto_plan p, moto_dtype dt, int32_t batch, int32_t n_vec, const void* V, void* W,
                                moto_stream stream) {
     if (!p || !V || !W || batch < 1 || n_vec < 0 || !hvp_ok(dt) || V == W) return MOTO_EINVAL;
+    if (p->k.gen) return MOTO_EUNSUPPORTED;
     if (n_vec == 0) return MOTO_OK;
     HIP_TRY(launch_hessian_apply(p->g, p->k, dt == MOTO_F64, batch, n_vec, V, W, (hipStream_t)stream));
     return MOTO_OK;
@@ -299,6 +345,7 @@ moto_status moto_hessian_apply(moto_plan p, moto_dtype dt, int32_t batch, int32_
 moto_status moto_param_mixed(moto_plan p, moto_dtype dt, int32_t batch, const void* m, const void* U, double* out,
                              void* ws, size_t ws_bytes, moto_stream stream) {
     if (!p || !m || !U || !out || batch < 1 || !hvp_ok(dt)) return MOTO_EINVAL;
+    if (p->k.gen) return MOTO_EUNSUPPORTED;
     if (!ws || ws_bytes < energy_ws(p, batch)) return MOTO_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(launch_param_mixed(p->g, dt == MOTO_F64, batch, m, U, (double*)ws, st));
@@ -309,6 +356,7 @@ moto_status moto_param_mixed(moto_plan p, moto_dtype dt, int32_t batch, const vo
 moto_status moto_param_grad_apply(moto_plan p, moto_dtype dt, int32_t batch, const void* m, const double* w,
                                   void* out, moto_stream stream) {
     if (!p || !m || !w || !out || batch < 1 || !hvp_ok(dt)) return MOTO_EINVAL;
+    if (p->k.gen) return MOTO_EUNSUPPORTED;
     HIP_TRY(launch_param_grad_apply(p->g, p->ns, dt == MOTO_F64, batch, m, w, out, (hipStream_t)stream));
     return MOTO_OK;
 }

@@ -13,11 +13,26 @@ namespace moto {
 constexpr int NPART = 11;
 
 // Stencil coefficients in FP64 (cast to the kernel precision at launch).
+// Shell table of a Hamiltonian with more than three exchange shells: the
+// lattice offsets of every shell (sorted by distance, shell s = offsets
+// [start[s], start[s+1])), the largest |dx|, |dy| (the tile halo) and the
+// stencil coefficients cJ[s] = -2 J_s.  Passed by value as a kernel argument.
+constexpr int GEN_MAX_SHELLS = MOTO_MAX_SHELLS;
+constexpr int GEN_MAX_OFF = 448;
+constexpr int GEN_RMAX = 12;
+struct GenShells {
+    int ns, n_off, R;
+    int start[GEN_MAX_SHELLS + 1];
+    signed char dx[GEN_MAX_OFF], dy[GEN_MAX_OFF];
+    double cJ[GEN_MAX_SHELLS];
+};
+
 struct CoefD {
     double cJ[3];
     double cD;
     double cK;
     double B[3];
+    const GenShells* gen = nullptr;  // set for more than three shells
 };
 
 template <class T>
@@ -46,6 +61,13 @@ hipError_t launch_reduce_partials(const double* part, int batch, int tiles, int 
 hipError_t launch_tangent_hvp(const Geo& g, const CoefD& k, bool f64, bool frame, int batch, const void* m,
                               const void* c, const uint8_t* mask, int nvec, const void* V, void* W,
                               const int* done, hipStream_t st, int variant = -1, long long vbs = 0);
+
+// ---- shells.hip: general-shell lattice kernels (more than three shells) ----
+hipError_t launch_energy_grad_gen(const Geo& g, const CoefD& k, bool f64, int batch, const void* m,
+                                  const uint8_t* mask, void* grad, void* c, void* F, double* part, hipStream_t st);
+hipError_t launch_tangent_hvp_gen(const Geo& g, const CoefD& k, bool f64, bool frame, int batch, const void* m,
+                                  const void* c, const uint8_t* mask, int nvec, long long vbs, const void* V, void* W,
+                                  const int* done, hipStream_t st);
 
 // ---- hvp.hip: frame-layout tangent HVP variants (tile shapes / staging) ----
 constexpr int HVP_NVARIANTS = 12;

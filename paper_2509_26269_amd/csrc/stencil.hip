@@ -277,6 +277,7 @@ __global__ __launch_bounds__(NT) void k_topo_charge(Geo g, const double* __restr
 hipError_t launch_energy_grad(const Geo& g, const CoefD& kd, bool f64, int batch, const void* m,
                               const uint8_t* mask, void* grad, void* c, void* F, double* part,
                               hipStream_t st) {
+    if (kd.gen) return launch_energy_grad_gen(g, kd, f64, batch, m, mask, grad, c, F, part, st);
     dim3 grid(batch * g.tiles);
     if (f64)
         hipLaunchKernelGGL(k_energy_grad<double>, grid, dim3(NT), 0, st, g, coef_cast<double>(kd),
@@ -320,6 +321,7 @@ hipError_t launch_reduce_partials(const double* part, int batch, int tiles, int 
 hipError_t launch_tangent_hvp(const Geo& g, const CoefD& kd, bool f64, bool frame, int batch, const void* m,
                               const void* c, const uint8_t* mask, int nvec, const void* V, void* W,
                               const int* done, hipStream_t st, int variant, long long vbs) {
+    if (kd.gen) return launch_tangent_hvp_gen(g, kd, f64, frame, batch, m, c, mask, nvec, vbs, V, W, done, st);
     if (frame) return launch_hvp_frame(variant, g, kd, f64, batch, m, c, mask, nvec, V, W, done, st, vbs);
     if (vbs > 0 && vbs != (long long)nvec * 3 * g.N) return hipErrorInvalidValue;
     dim3 grid(batch * g.tiles);

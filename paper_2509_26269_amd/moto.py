@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmoto.so")
 
 MOTO_F32, MOTO_F64 = 0, 1
 MOTO_AMBIENT, MOTO_FRAME = 0, 1
-MAX_SHELLS = 8
+MAX_SHELLS = 36
 
 SADDLE = CONVERGED = 0
 NOT_CONVERGED, DEGENERATE, HIGHER_INDEX, NAN, BREAKDOWN = 1, 2, 3, 4, 5

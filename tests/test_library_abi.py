@@ -43,10 +43,10 @@ def test_host_only_entry_points_without_gpu():
     h.Lx, h.Ly, h.n_shells = 0, 4, 1
     p = ctypes.c_void_p()
     assert L.moto_plan_create(ctypes.byref(h), ctypes.byref(p)) == -1
-    h.Lx, h.n_shells = 4, 5
-    h.J[4] = 1.0
-    assert L.moto_plan_create(ctypes.byref(h), ctypes.byref(p)) == -6
+    # more shells than the table holds
+    h.Lx, h.n_shells = 4, M.MAX_SHELLS + 1
+    assert L.moto_plan_create(ctypes.byref(h), ctypes.byref(p)) == -1
+    # DMI beyond the nearest-neighbour shell is outside the GPU scope
     h.n_shells = 2
-    h.J[4] = 0.0
     h.D[1] = 0.1
     assert L.moto_plan_create(ctypes.byref(h), ctypes.byref(p)) == -6
