@@ -7,6 +7,8 @@ Headline (the 128x128 three-shell workload, FP32 HVP):
     kernel streams from HBM); one step = one batched HVP launch;
   * the roofline of that kernel (algorithmic bytes 12 + 16 n_vec per site);
   * wall time of the k = 4 eigen-solve (residual 1e-5) on one 128x128 state;
+  * the 35-shell Pd/Fe/Ir(111) exchange (360 bonds per site) HVP on 64
+    128x128 lattices, against the VALU and LDS ceilings;
   * a population of 24 k = 2 eigen-solves in lock step against one at a
     time, and the explorer objectives of 24 candidates;
   * saddle searches/s (k = 2, FP32 HVP, tau_F = 1e-5, capped outer
@@ -146,6 +148,8 @@ def main():
     ap.add_argument("--batched", type=int, default=64, help="searches on 128x128 in the batched (one-launch) leg")
     ap.add_argument("--ragged", type=int, default=256, help="searches on uneven 32..96 lattices, one launch")
     ap.add_argument("--max-outer", type=int, default=300, help="outer-iteration cap of every search leg")
+    ap.add_argument("--shells35", type=int, default=64,
+                    help="lattices in the 35-shell (Pd/Fe/Ir(111)) HVP leg (0: skip)")
     ap.add_argument("--population", type=int, default=24,
                     help="population size of the lock-step eigen-solve and explorer legs (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -295,6 +299,37 @@ def main():
                                 "workspace_bytes": wsl.nbytes}
         extra["lanczos_128_k4"] = lz
         extra["lobpcg_128_k4_lambda"] = [round(float(x), 6) for x in r.evals.cpu()]
+    if not args.hvp_only and not args.eigen_only and args.shells35 > 0:
+        # the many-shell regime: the 35-shell Pd/Fe/Ir(111) exchange of Table S1
+        # (360 bonds per site) on 128x128 lattices, FP32 frame HVP
+        B35 = args.shells35
+        print(f"[bench] 35-shell HVP, {B35} x 128x128 x {nvec} FP32 vectors", file=sys.stderr, flush=True)
+        p35 = S.ham_pdfeir(L)
+        plan35 = M.Plan.from_params(p35)
+        spec35 = S.fixed_size_spec(B35, L, seed=35)
+        m35 = torch.as_tensor(np.stack([S.batch_member(spec35, i) for i in range(B35)]), device="cuda")
+        _, _, c35, _, _ = M.moto_energy_grad(plan35, m35, want_grad=False, want_F=False)
+        m35f, c35f = m35.float().contiguous(), c35.float().contiguous()
+        g35 = torch.Generator(device="cuda").manual_seed(350)
+        V35 = torch.randn(B35, nvec, 2, N, device="cuda", generator=g35)
+        W35 = torch.empty_like(V35)
+        _, per35, _ = time_hvp(M, torch, plan35, m35f, c35f, V35, W35, B35, 10, 3)
+        t35 = float(np.mean(per35)) * 1e-3
+        sv = B35 * nvec * N
+        n_off = 360
+        # per site-vector: one add per bond and component, one multiply per
+        # shell and component, DMI (6 bonds x 4) and frame in/out (12)
+        ops = n_off * 3 + 35 * 3 + 24 + 12
+        lds_bytes = n_off * 3 * 4
+        extra["hvp_35shell_128"] = {
+            "batch": B35, "n_vec": nvec, "ms_per_launch": round(1e3 * t35, 4),
+            "Gsite_vectors_per_s": round(sv / t35 / 1e9, 3),
+            "valu_ops_per_site_vector": ops, "valu_Tops": round(sv * ops / t35 / 1e12, 2),
+            "valu_frac_of_39.3T": round(sv * ops / t35 / 39.3e12, 3),
+            "lds_bytes_per_site_vector": lds_bytes, "lds_TBps": round(sv * lds_bytes / t35 / 1e12, 2),
+            "lds_frac_of_78.6TBps": round(sv * lds_bytes / t35 / 78.6e12, 3)}
+        del m35, c35, m35f, c35f, V35, W35
+        torch.cuda.empty_cache()
     if not args.hvp_only and not args.eigen_only and args.population > 0:
         # explorer scale: the two lowest modes of a population of perturbed
         # 128x128 states, in lock step and one at a time; then the whole

@@ -126,37 +126,23 @@ int tuned_variant(const moto_plan p, moto_dtype dt, int batch, int nvec) {
 
 // Offsets of the first ns shells of the triangular lattice (every lattice
 // vector dx a1 + dy a2, |.|^2 = dx^2 + dx dy + dy^2, grouped by length in
-// increasing order).  All offsets up to |.|^2 = 3 (R + 1)^2 / 4 lie in the
-// box |dx|, |dy| <= R = GEN_RMAX, which covers MOTO_MAX_SHELLS shells.
+// increasing order), copied from the compile-time table the kernels use,
+// and the halo they need (largest |dx|, |dy|).
 bool shell_table(int ns, GenShells* t) {
-    std::vector<int> lens;
-    for (int dy = -GEN_RMAX; dy <= GEN_RMAX; ++dy)
-        for (int dx = -GEN_RMAX; dx <= GEN_RMAX; ++dx) {
-            const int d2 = dx * dx + dx * dy + dy * dy;
-            if (d2 > 0) lens.push_back(d2);
-        }
-    std::sort(lens.begin(), lens.end());
-    lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
-    if (ns < 1 || ns > GEN_MAX_SHELLS || ns > (int)lens.size()) return false;
-    if (4 * lens[ns - 1] >= 3 * (GEN_RMAX + 1) * (GEN_RMAX + 1)) return false;
-    int n = 0, R = 0;
-    for (int s = 0; s < ns; ++s) {
-        t->start[s] = n;
-        for (int dy = -GEN_RMAX; dy <= GEN_RMAX; ++dy)
-            for (int dx = -GEN_RMAX; dx <= GEN_RMAX; ++dx)
-                if (dx * dx + dx * dy + dy * dy == lens[s]) {
-                    if (n >= GEN_MAX_OFF) return false;
-                    t->dx[n] = (signed char)dx;
-                    t->dy[n] = (signed char)dy;
-                    R = std::max(R, std::max(std::abs(dx), std::abs(dy)));
-                    ++n;
-                }
+    if (ns < 1 || ns > GEN_MAX_SHELLS) return false;
+    const ShellGeom& G = kShellGeom;
+    int R = 0;
+    for (int s = 0; s <= ns; ++s) t->start[s] = G.start[s];
+    for (int o = 0; o < G.start[ns]; ++o) {
+        t->dx[o] = G.dx[o];
+        t->dy[o] = G.dy[o];
+        R = std::max(R, std::max(std::abs((int)G.dx[o]), std::abs((int)G.dy[o])));
     }
-    t->start[ns] = n;
     t->ns = ns;
-    t->n_off = n;
+    t->n_off = G.start[ns];
     t->R = R;
-    return true;
+    for (int s = 0; s < GEN_MAX_SHELLS; ++s) t->cJ[s] = 0.0;
+    return R <= GEN_RMAX;
 }
 
 // Read back n bytes of device memory through the plan's pinned buffer.

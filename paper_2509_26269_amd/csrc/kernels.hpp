@@ -27,6 +27,49 @@ struct GenShells {
     double cJ[GEN_MAX_SHELLS];
 };
 
+// The same offsets as a compile-time table (the shell geometry is fixed;
+// only the couplings vary), so that the general-shell kernels address LDS
+// with immediate offsets.  Shell s: squared length = the s-th smallest
+// value of dx^2 + dx dy + dy^2 > 0 over |dx|, |dy| <= GEN_RMAX.
+struct ShellGeom {
+    int n_off;
+    int start[GEN_MAX_SHELLS + 1];
+    signed char dx[GEN_MAX_OFF], dy[GEN_MAX_OFF];
+};
+
+constexpr ShellGeom make_shell_geom() {
+    ShellGeom t{};
+    int len[GEN_MAX_SHELLS] = {};
+    int last = 0;
+    for (int s = 0; s < GEN_MAX_SHELLS; ++s) {
+        int best = 1 << 30;
+        for (int dy = -GEN_RMAX; dy <= GEN_RMAX; ++dy)
+            for (int dx = -GEN_RMAX; dx <= GEN_RMAX; ++dx) {
+                const int d2 = dx * dx + dx * dy + dy * dy;
+                if (d2 > last && d2 < best) best = d2;
+            }
+        len[s] = best;
+        last = best;
+    }
+    int n = 0;
+    for (int s = 0; s < GEN_MAX_SHELLS; ++s) {
+        t.start[s] = n;
+        for (int dy = -GEN_RMAX; dy <= GEN_RMAX; ++dy)
+            for (int dx = -GEN_RMAX; dx <= GEN_RMAX; ++dx)
+                if (dx * dx + dx * dy + dy * dy == len[s] && n < GEN_MAX_OFF) {
+                    t.dx[n] = (signed char)dx;
+                    t.dy[n] = (signed char)dy;
+                    ++n;
+                }
+    }
+    t.start[GEN_MAX_SHELLS] = n;
+    t.n_off = n;
+    return t;
+}
+constexpr ShellGeom kShellGeom = make_shell_geom();
+static_assert(kShellGeom.n_off < GEN_MAX_OFF, "shell table capacity");
+static_assert(kShellGeom.start[35] == 360, "the 35 shells of the Pd/Fe/Ir(111) table hold 360 bonds");
+
 struct CoefD {
     double cJ[3];
     double cD;
