@@ -132,79 +132,38 @@ __global__ __launch_bounds__(NT) void k_energy_grad_gen(Geo g, GenShells gs, Coe
 
 // Tangent HVP (frame or ambient layout, as the three-shell tile kernel):
 // W_j = M H(m) M V_j with (H v)_i = P_i (A v)_i - c_i v_i, one vector at a
-// time through an HX x HY tile with the full GEN_RMAX halo.  Each thread owns
-// HN sites HS apart in x, so the address arithmetic and the offset-table
-// reads of every bond are shared by HN sites; the rest is one LDS read and
-// one add per bond and component.
-constexpr int HX = 64, HY = 16, HN = 4, HS = HX / HN;
+// time through an HX x HY tile staged with the full GEN_RMAX halo.
+//
+// The exchange sum over the disc of bonds is evaluated row by row as a 1-D
+// convolution: a thread owns HSP consecutive sites of one row and, for each
+// row offset dy, reads the HSP + 2 GEN_RMAX values of that input row once
+// (16-byte LDS reads) into registers and applies the row's 2 GEN_RMAX + 1
+// couplings (a per-block LDS table, zero off the disc and beyond the plan's
+// shells) to all HSP sites from there: about 2 LDS values per site, row and
+// component instead of one per bond, at the price of multiply-adds over the
+// full square of offsets (the disc fills 58 % of it).  DMI (nearest
+// neighbours) and anisotropy are added per site afterwards.
+constexpr int HX = 64, HY = 16, HSP = 8, HNT = (HX / HSP) * HY;
 constexpr int HLX = HX + 2 * GEN_RMAX, HLY = HY + 2 * GEN_RMAX;
-static_assert((HX / HN) * HY == NT, "one thread per HN sites");
+constexpr int HW = 2 * GEN_RMAX + 1;   // couplings per row
+constexpr int HWIN = HSP + 2 * GEN_RMAX;  // window values per row
+static_assert(HLX % 4 == 0 && HSP % 4 == 0, "16-byte aligned row windows");
 
 template <class T>
 struct HvpGenLDS {
     T u[3][HLY][HLX];
+    T wt[HW][HW];  // wt[dy + R][dx + R] = cJ of the shell of (dx, dy)
 };
 
-// (A u) at the HN sites of a thread (LDS row cy, columns cx + k HS,
-// k < HN): shell by shell over the plan's offsets; one address per offset
-// serves the HN sites (immediate offsets k HS from it).  Sites HS apart keep
-// the lanes of a wave on consecutive words (no LDS bank conflicts).
-template <class T>
-__device__ __forceinline__ void apply_A_blk(const HvpGenLDS<T>& L, const int* __restrict__ rel, const GenShells& gs,
-                                            T cD, int cy, int cx, T (&acc)[HN][3]) {
-    constexpr int PL = HLY * HLX;  // plane stride
-    const T* base = &L.u[0][0][0] + cy * HLX + cx;
-    for (int s = 0; s < gs.ns; ++s) {
-        T sm[HN][3];
-#pragma unroll
-        for (int k = 0; k < HN; ++k) sm[k][0] = sm[k][1] = sm[k][2] = T(0);
-        const int o1 = gs.start[s + 1];
-#pragma unroll 6
-        for (int o = gs.start[s]; o < o1; ++o) {
-            const T* p = base + rel[o];
-#pragma unroll
-            for (int k = 0; k < HN; ++k) {
-                sm[k][0] += p[k * HS];
-                sm[k][1] += p[PL + k * HS];
-                sm[k][2] += p[2 * PL + k * HS];
-            }
-        }
-        const T cj = (T)gs.cJ[s];
-#pragma unroll
-        for (int k = 0; k < HN; ++k) {
-            acc[k][0] += cj * sm[k][0];
-            acc[k][1] += cj * sm[k][1];
-            acc[k][2] += cj * sm[k][2];
-        }
-    }
-    if (cD != T(0)) {
-        for (int o = gs.start[0]; o < gs.start[1]; ++o) {
-            const int ddx = gs.dx[o], ddy = gs.dy[o];
-            const T* p = base + ddy * HLX + ddx;
-            const T hx = cD * (T(ddx) + T(0.5) * T(ddy));
-            const T hy = cD * (T(0.86602540378443864676) * T(ddy));
-#pragma unroll
-            for (int k = 0; k < HN; ++k) {
-                const T u0 = p[k * HS], u1 = p[PL + k * HS], u2 = p[2 * PL + k * HS];
-                acc[k][0] += hx * u2;
-                acc[k][1] += hy * u2;
-                acc[k][2] -= hx * u0 + hy * u1;
-            }
-        }
-    }
-}
-
 template <class T, bool FRAME>
-__global__ __launch_bounds__(NT) void k_tangent_hvp_gen(Geo g, GenShells gs, Coef<T> k, const T* __restrict__ m,
-                                                        const T* __restrict__ c, const uint8_t* __restrict__ mask,
-                                                        int nvec, long long vbs, const T* __restrict__ V,
-                                                        T* __restrict__ W, const int* __restrict__ done) {
+__global__ __launch_bounds__(HNT) void k_tangent_hvp_gen(Geo g, GenShells gs, Coef<T> k, const T* __restrict__ m,
+                                                         const T* __restrict__ c, const uint8_t* __restrict__ mask,
+                                                         int nvec, long long vbs, const T* __restrict__ V,
+                                                         T* __restrict__ W, const int* __restrict__ done) {
     if (done != nullptr && *done) return;
     constexpr int DV = FRAME ? 2 : 3;
-    __shared__ HvpGenLDS<T> L;
+    __shared__ __align__(16) HvpGenLDS<T> L;
     __shared__ uint8_t act[HLY][HLX];
-    __shared__ int rel[GEN_MAX_OFF];  // LDS offset of every bond, dy HLX + dx
-    for (int o = threadIdx.x; o < gs.n_off; o += NT) rel[o] = gs.dy[o] * HLX + gs.dx[o];
     const int ntx = (g.Lx + HX - 1) / HX, nty = (g.Ly + HY - 1) / HY;
     const int bid = blockIdx.x;
     const int b = bid / (ntx * nty);
@@ -215,46 +174,27 @@ __global__ __launch_bounds__(NT) void k_tangent_hvp_gen(Geo g, GenShells gs, Coe
     const uint8_t* mk = mask ? mask + (size_t)b * N : nullptr;
     const T* Vb = V + (size_t)b * vbs;
     T* Wb = W + (size_t)b * vbs;
-    for (int i = threadIdx.x; i < HLX * HLY; i += NT) {
+    // couplings of the disc, activity of the staged sites
+    for (int i = threadIdx.x; i < HW * HW; i += HNT) (&L.wt[0][0])[i] = T(0);
+    for (int i = threadIdx.x; i < HLX * HLY; i += HNT) {
         const int lx = i % HLX, ly = i / HLX;
         const int s = wrapi(tx0 + lx - GEN_RMAX, g.Lx) + g.Lx * wrapi(ty0 + ly - GEN_RMAX, g.Ly);
         act[ly][lx] = mk ? (mk[s] != 0) : 1;
     }
-    const int lxo = threadIdx.x % HS, lyo = threadIdx.x / HS;
-    const int y = ty0 + lyo;
-    const int cy = lyo + GEN_RMAX, cx = lxo + GEN_RMAX;
-    // own sites: frames (or spins) and c
-    T f[HN][6], cc[HN];
-    int so[HN];
-    bool val[HN];
-#pragma unroll
-    for (int q = 0; q < HN; ++q) {
-        const int x = tx0 + lxo + q * HS;
-        val[q] = x < g.Lx && y < g.Ly;
-        so[q] = val[q] ? x + g.Lx * y : 0;
-        const T m0 = val[q] ? mb[so[q]] : T(0), m1 = val[q] ? mb[N + so[q]] : T(0),
-                m2 = val[q] ? mb[2 * N + so[q]] : T(1);
-        cc[q] = val[q] ? c[(size_t)b * N + so[q]] : T(0);
-        if constexpr (FRAME) {
-            T e1[3], e2[3];
-            onb(m0, m1, m2, e1, e2);
-            f[q][0] = e1[0];
-            f[q][1] = e1[1];
-            f[q][2] = e1[2];
-            f[q][3] = e2[0];
-            f[q][4] = e2[1];
-            f[q][5] = e2[2];
-        } else {
-            f[q][0] = m0;
-            f[q][1] = m1;
-            f[q][2] = m2;
-            f[q][3] = f[q][4] = f[q][5] = T(0);
-        }
+    __syncthreads();
+    for (int o = threadIdx.x; o < gs.n_off; o += HNT) {
+        int sh = 0;
+        while (o >= gs.start[sh + 1]) ++sh;
+        L.wt[gs.dy[o] + GEN_RMAX][gs.dx[o] + GEN_RMAX] = (T)gs.cJ[sh];
     }
+    const int lx0 = (threadIdx.x % (HX / HSP)) * HSP, ly0 = threadIdx.x / (HX / HSP);
+    const int y = ty0 + ly0;
+    const int cy = ly0 + GEN_RMAX, cx = lx0 + GEN_RMAX;
+    const int R = gs.R;
     for (int j = 0; j < nvec; ++j) {
         const T* vj = Vb + (size_t)j * DV * N;
         __syncthreads();
-        for (int i = threadIdx.x; i < HLX * HLY; i += NT) {
+        for (int i = threadIdx.x; i < HLX * HLY; i += HNT) {
             const int lx = i % HLX, ly = i / HLX;
             const int s = wrapi(tx0 + lx - GEN_RMAX, g.Lx) + g.Lx * wrapi(ty0 + ly - GEN_RMAX, g.Ly);
             const bool on = act[ly][lx];
@@ -273,29 +213,71 @@ __global__ __launch_bounds__(NT) void k_tangent_hvp_gen(Geo g, GenShells gs, Coe
             }
         }
         __syncthreads();
-        T acc[HN][3];
+        // exchange: row-by-row convolution of each component
+        T a[HSP][3];
+        for (int cc = 0; cc < 3; ++cc) {
+            T acc[HSP];
 #pragma unroll
-        for (int q = 0; q < HN; ++q) acc[q][0] = acc[q][1] = acc[q][2] = T(0);
-        apply_A_blk<T>(L, rel, gs, k.cD, cy, cx, acc);
+            for (int q = 0; q < HSP; ++q) acc[q] = T(0);
+            for (int dy = -R; dy <= R; ++dy) {
+                const T* rp = &L.u[cc][cy + dy][lx0];
+                T win[HWIN];
+#pragma unroll
+                for (int i = 0; i < HWIN; ++i) win[i] = rp[i];
+                const T* wr = &L.wt[dy + GEN_RMAX][0];
+#pragma unroll
+                for (int d = 0; d < HW; ++d) {
+                    const T w = wr[d];
+#pragma unroll
+                    for (int q = 0; q < HSP; ++q) acc[q] += w * win[q + d];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < HSP; ++q) a[q][cc] = acc[q];
+        }
+        // nearest-neighbour DMI and anisotropy, per site
+        if (k.cD != T(0)) {
+#pragma unroll
+            for (int o = 0; o < 6; ++o) {
+                constexpr int NDX[6] = {1, 0, -1, -1, 0, 1}, NDY[6] = {0, 1, 1, 0, -1, -1};
+                const int ddx = NDX[o], ddy = NDY[o];
+                const T hx = k.cD * (T(ddx) + T(0.5) * T(ddy));
+                const T hy = k.cD * (T(0.86602540378443864676) * T(ddy));
+#pragma unroll
+                for (int q = 0; q < HSP; ++q) {
+                    const T u0 = L.u[0][cy + ddy][cx + q + ddx], u1 = L.u[1][cy + ddy][cx + q + ddx],
+                            u2 = L.u[2][cy + ddy][cx + q + ddx];
+                    a[q][0] += hx * u2;
+                    a[q][1] += hy * u2;
+                    a[q][2] -= hx * u0 + hy * u1;
+                }
+            }
+        }
         T* wj = Wb + (size_t)j * DV * N;
 #pragma unroll
-        for (int q = 0; q < HN; ++q) {
-            if (!val[q]) continue;
-            const bool on = act[cy][cx + q * HS];
-            const T u0 = L.u[0][cy][cx + q * HS], u1 = L.u[1][cy][cx + q * HS], u2 = L.u[2][cy][cx + q * HS];
-            const T a0 = acc[q][0], a1 = acc[q][1], a2 = acc[q][2] + k.cK * u2;
+        for (int q = 0; q < HSP; ++q) {
+            const int x = tx0 + lx0 + q;
+            if (x >= g.Lx || y >= g.Ly) continue;
+            const int so = x + g.Lx * y;
+            const bool on = act[cy][cx + q];
+            const T u0 = L.u[0][cy][cx + q], u1 = L.u[1][cy][cx + q], u2 = L.u[2][cy][cx + q];
+            const T ci = c[(size_t)b * N + so];
+            const T m0 = mb[so], m1 = mb[N + so], m2 = mb[2 * N + so];
+            const T a0 = a[q][0], a1 = a[q][1], a2 = a[q][2] + k.cK * u2;
             if constexpr (FRAME) {
-                const T av = f[q][0] * u0 + f[q][1] * u1 + f[q][2] * u2;
-                const T bv = f[q][3] * u0 + f[q][4] * u1 + f[q][5] * u2;
-                const T wa = f[q][0] * a0 + f[q][1] * a1 + f[q][2] * a2 - cc[q] * av;
-                const T wb = f[q][3] * a0 + f[q][4] * a1 + f[q][5] * a2 - cc[q] * bv;
-                wj[so[q]] = on ? wa : T(0);
-                wj[N + so[q]] = on ? wb : T(0);
+                T e1[3], e2[3];
+                onb(m0, m1, m2, e1, e2);
+                const T av = e1[0] * u0 + e1[1] * u1 + e1[2] * u2;
+                const T bv = e2[0] * u0 + e2[1] * u1 + e2[2] * u2;
+                const T wa = e1[0] * a0 + e1[1] * a1 + e1[2] * a2 - ci * av;
+                const T wb = e2[0] * a0 + e2[1] * a1 + e2[2] * a2 - ci * bv;
+                wj[so] = on ? wa : T(0);
+                wj[N + so] = on ? wb : T(0);
             } else {
-                const T ma = f[q][0] * a0 + f[q][1] * a1 + f[q][2] * a2;
-                wj[so[q]] = on ? a0 - ma * f[q][0] - cc[q] * u0 : T(0);
-                wj[N + so[q]] = on ? a1 - ma * f[q][1] - cc[q] * u1 : T(0);
-                wj[2 * N + so[q]] = on ? a2 - ma * f[q][2] - cc[q] * u2 : T(0);
+                const T ma = m0 * a0 + m1 * a1 + m2 * a2;
+                wj[so] = on ? a0 - ma * m0 - ci * u0 : T(0);
+                wj[N + so] = on ? a1 - ma * m1 - ci * u1 : T(0);
+                wj[2 * N + so] = on ? a2 - ma * m2 - ci * u2 : T(0);
             }
         }
     }
@@ -324,7 +306,7 @@ hipError_t launch_tangent_hvp_gen(const Geo& g, const CoefD& kd, bool f64, bool 
     auto go = [&](auto tc, auto fc) {
         using T = decltype(tc);
         constexpr bool FR = decltype(fc)::value;
-        hipLaunchKernelGGL((k_tangent_hvp_gen<T, FR>), grid, dim3(NT), 0, st, g, *kd.gen, coef_cast<T>(kd),
+        hipLaunchKernelGGL((k_tangent_hvp_gen<T, FR>), grid, dim3(HNT), 0, st, g, *kd.gen, coef_cast<T>(kd),
                            (const T*)m, (const T*)c, mask, nvec, vbs, (const T*)V, (T*)W, done);
     };
     if (f64) {
