@@ -400,6 +400,30 @@ moto_status moto_saddle_search(moto_plan p, moto_dtype hvp, double *m, const uin
                                double *V_out, void *ws, size_t ws_bytes, moto_stream stream);
 
 /* ---------------------------------------------------------------------
+ * Searches over a population: P saddle searches on states of the plan's
+ * lattice (same method, options and results as moto_saddle_search) run in
+ * lock step: every outer iteration is one batched energy/gradient launch,
+ * one population eigen-solve (moto_min_modes_population, warm-started) and
+ * one reflected step per member still climbing; a member stops by its own
+ * test and is left in place while the others go on.  This is the form for
+ * many starts of one size (an explorer's Pareto front, Results): all steps
+ * of all members share each launch, where the persistent batched kernel
+ * below gives each search one workgroup.
+ *   m      [P][3][N] FP64 device: starts in, final points out
+ *   mask   [P][N] device or NULL
+ *   res    host [P] results
+ *   evals_out [P][k_cert] FP64 device or NULL; V_out [P][k_cert][3][N] or NULL
+ * The call synchronises with the stream at every outer iteration.
+ * Errors: MOTO_EINVAL (P outside 1..MOTO_MAX_POPULATION, bad options),
+ * MOTO_EWORKSPACE below moto_saddle_search_population_workspace(p, hvp, P, opts). */
+size_t moto_saddle_search_population_workspace(moto_plan p, moto_dtype hvp, int32_t P,
+                                               const moto_search_opts *o);
+moto_status moto_saddle_search_population(moto_plan p, moto_dtype hvp, int32_t P, double *m,
+                                          const uint8_t *mask, const moto_search_opts *opts /* host */,
+                                          moto_search_result *res /* host */, double *evals_out,
+                                          double *V_out, void *ws, size_t ws_bytes, moto_stream stream);
+
+/* ---------------------------------------------------------------------
  * Batching form: n independent saddle searches on periodic square lattices
  * of uneven sides L[b] (5 <= L <= 4096) in ONE persistent launch, one
  * workgroup per search (largest lattices first), FP32 HVP with FP64 state.

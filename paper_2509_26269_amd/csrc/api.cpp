@@ -61,7 +61,7 @@ size_t energy_ws(const moto_plan p, int batch) { return al(sizeof(double) * NPAR
 // for a population of P solves (P = 1: one solve); every region holds the P
 // members back to back.
 struct EigLayout {
-    size_t mT, cT, c64, S, HS, Xsave, part, G, ctrl, flag, total;
+    size_t mT, cT, c64, S, HS, Xsave, part, G, ctrl, flag, info, total;
     int mb, n2, nblk_g, nblk_u, nblk_o;
     long long s_ms, part_ms, g_ms;  // per-member strides (elements, doubles, doubles)
 };
@@ -106,6 +106,8 @@ EigLayout eig_layout(const moto_plan p, moto_dtype hvp, int k, int guard, int P 
     o += al(Pz * sizeof(EigCtrl));
     L.flag = o;
     o += al(sizeof(int));
+    L.info = o;
+    o += al(sizeof(moto_info) * Pz);
     L.total = o;
     return L;
 }
@@ -539,17 +541,11 @@ static moto_status min_modes_pop_impl(moto_plan p, moto_dtype hvp, int P, const 
     }
     HIP_TRY(launch_eig_output(f64, a, S, m, N, V, part, ctrl, evals, resid, ws + L.Xsave, st));
     if (info) {
-        // status, iterations and HVP columns of every member, through the
-        // pinned buffer in pieces
-        HIP_TRY(hipStreamSynchronize(st));
-        for (int y = 0; y < P; ++y) {
-            EigCtrl hc;
-            moto_status rs = readback(p, ctrl + y, 32, &hc, st);
-            if (rs != MOTO_OK) return rs;
-            info[y].status = hc.status;
-            info[y].iters = hc.iters;
-            info[y].n_hvp = hc.n_hvp;
-        }
+        // status, iterations and HVP columns of every member, gathered and
+        // read back at once (P <= MOTO_MAX_POPULATION fits the pinned buffer)
+        HIP_TRY(launch_eig_gather_info(P, ctrl, (moto_info*)(ws + L.info), st));
+        moto_status rs = readback(p, ws + L.info, sizeof(moto_info) * (size_t)P, info, st);
+        if (rs != MOTO_OK) return rs;
     } else {
         HIP_TRY(hipStreamSynchronize(st));
     }
@@ -1055,6 +1051,181 @@ moto_status moto_saddle_search(moto_plan p, moto_dtype hvp, double* m, const uin
     res->lambda2 = lam[1];
     if (evals_out) HIP_TRY(hipMemcpyAsync(evals_out, ev, sizeof(double) * kc, hipMemcpyDeviceToDevice, st));
     if (V_out) HIP_TRY(hipMemcpyAsync(V_out, V, sizeof(double) * 3 * (size_t)N * kc, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MOTO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Searches over a population (lock step)
+// ---------------------------------------------------------------------------
+namespace {
+// [energy partials P][F P 3N][out P x 2][step states P][eig population ws]
+// [V P kmax 3N][evals P kmax][E P][info P]
+struct PopSearchLayout {
+    size_t epart, F, out, state, eig, V, ev, E, total;
+    size_t state_b;
+};
+
+PopSearchLayout pop_search_layout(moto_plan p, moto_dtype hvp, int P, int mem, int kmax, int guard) {
+    PopSearchLayout L;
+    const size_t N = p->g.N, Pz = (size_t)P;
+    size_t o = 0;
+    L.epart = o;
+    o += energy_ws(p, P);
+    L.F = o;
+    o += al(sizeof(double) * 3 * N * Pz);
+    L.out = o;
+    o += al(sizeof(double) * 2 * Pz);
+    L.state_b = al(step_state_bytes((int)N, mem));
+    L.state = o;
+    o += L.state_b * Pz;
+    L.eig = o;
+    o += al(eig_layout(p, hvp, kmax, resolve_guard(kmax, guard), P).total);
+    L.V = o;
+    o += al(sizeof(double) * 3 * N * (size_t)kmax * Pz);
+    L.ev = o;
+    o += al(sizeof(double) * (size_t)kmax * Pz);
+    L.E = o;
+    o += al(sizeof(double) * Pz);
+    L.total = o;
+    return L;
+}
+
+bool pop_search_opts_ok(const moto_search_opts& o) {
+    return o.k >= 1 && o.k_reflect >= 0 && o.k_reflect <= o.k && o.k_reflect <= 4 && o.max_outer >= 0 &&
+           std::max(o.k, std::max(o.k_cert, 2)) + resolve_guard(std::max(o.k, std::max(o.k_cert, 2)), o.eig.guard) <=
+               MAXB;
+}
+}  // namespace
+
+size_t moto_saddle_search_population_workspace(moto_plan p, moto_dtype hvp, int32_t P, const moto_search_opts* opts) {
+    if (!p || !hvp_ok(hvp) || P < 1 || P > MOTO_MAX_POPULATION) return 0;
+    moto_search_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_search_opts(hvp, &o);
+    if (!pop_search_opts_ok(o) || o.step.mem < 1 || o.step.mem > 16) return 0;
+    const int kmax = std::max(o.k, std::max(o.k_cert, 2));
+    return pop_search_layout(p, hvp, P, o.step.mem, kmax, o.eig.guard).total;
+}
+
+moto_status moto_saddle_search_population(moto_plan p, moto_dtype hvp, int32_t P, double* m, const uint8_t* mask,
+                                          const moto_search_opts* opts, moto_search_result* res, double* evals_out,
+                                          double* V_out, void* ws, size_t ws_bytes, moto_stream stream) {
+    if (!p || !m || !res || !hvp_ok(hvp) || P < 1 || P > MOTO_MAX_POPULATION) return MOTO_EINVAL;
+    moto_search_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_search_opts(hvp, &o);
+    if (!pop_search_opts_ok(o)) return MOTO_EINVAL;
+    const int kc = std::max(o.k_cert, 2);
+    const int kmax = std::max(o.k, kc);
+    o.step.tau_F = o.tau_F;
+    StepArgs a;
+    if (!fill_step_args(p, &o.step, o.k_reflect, &a)) return MOTO_EINVAL;
+    const PopSearchLayout L = pop_search_layout(p, hvp, P, o.step.mem, kmax, o.eig.guard);
+    if (!ws || ws_bytes < L.total) return MOTO_EWORKSPACE;
+    char* w = (char*)ws;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t N = p->g.N, N3 = 3 * N;
+    double* F = (double*)(w + L.F);
+    double* out = (double*)(w + L.out);
+    double* part = (double*)(w + L.epart);
+    double* V = (double*)(w + L.V);
+    double* ev = (double*)(w + L.ev);
+    double* E = (double*)(w + L.E);
+    char* eigw = w + L.eig;
+    const size_t eig_bytes = L.V - L.eig;
+    HIP_TRY(hipMemsetAsync(w + L.state, 0, L.state_b * (size_t)P, st));
+    HIP_TRY(hipMemsetAsync(out, 0, sizeof(double) * 2 * (size_t)P, st));
+    const double tau_lam = o.tau_lam > 0.0 ? o.tau_lam : (hvp == MOTO_F64 ? 1e-6 : 1e-4) * p->hest;
+    std::vector<int> done(P, 0), iters(P, 0), nanm(P, 0);
+    std::vector<double> ho(2 * (size_t)P, 0.0), fnorm(P, INFINITY);
+    std::vector<long long> n_hvp(P, 0);
+    std::vector<moto_info> inf(P);
+    for (int it = 0; it <= o.max_outer; ++it) {
+        HIP_TRY(launch_energy_grad(p->g, p->k, true, P, m, mask, nullptr, nullptr, F, part, st));
+        moto_eig_opts eo = o.eig;
+        eo.warm = it == 0 ? 0 : 2;
+        moto_status rs = min_modes_pop_impl(p, hvp, P, m, mask, o.k, &eo, ev, V, nullptr, inf.data(), eigw,
+                                            eig_bytes, st, nullptr);
+        if (rs != MOTO_OK) return rs;
+        int active = 0;
+        for (int y = 0; y < P; ++y) {
+            if (done[y]) continue;
+            n_hvp[y] += inf[y].n_hvp;
+            if (inf[y].status == MOTO_NAN) {
+                nanm[y] = 1;
+                done[y] = 1;
+                continue;
+            }
+            StepArgs ay = a;
+            if (it == o.max_outer) ay.tau_F = INFINITY;  // last iterate: ||F_mmf|| without moving
+            HIP_TRY(launch_step(ay, m + (size_t)y * N3, F + (size_t)y * N3, V + (size_t)y * o.k * N3,
+                                w + L.state + L.state_b * (size_t)y, out + 2 * (size_t)y, st));
+            ++active;
+        }
+        if (active == 0) break;
+        rs = readback(p, out, sizeof(double) * 2 * (size_t)P, ho.data(), st);
+        if (rs != MOTO_OK) return rs;
+        int left = 0;
+        for (int y = 0; y < P; ++y) {
+            if (done[y]) continue;
+            fnorm[y] = ho[2 * y];
+            if (ho[2 * y + 1] != 0.0 || !std::isfinite(ho[2 * y])) done[y] = 1;
+            else ++left;
+        }
+        if (left == 0) break;
+    }
+    // certification of every member at its final point
+    moto_eig_opts eo = o.eig;
+    eo.warm = 0;
+    eo.seed = o.eig.seed + 1;
+    moto_status rs = min_modes_pop_impl(p, hvp, P, m, mask, kc, &eo, ev, V, nullptr, inf.data(), eigw, eig_bytes, st,
+                                        nullptr);
+    if (rs != MOTO_OK) return rs;
+    HIP_TRY(launch_energy_grad(p->g, p->k, true, P, m, mask, nullptr, nullptr, F, part, st));
+    HIP_TRY(launch_reduce_partials(part, P, p->g.tiles, p->ns, E, nullptr, st));
+    std::vector<double> hE(P), hev((size_t)P * kc);
+    rs = readback(p, E, sizeof(double) * (size_t)P, hE.data(), st);
+    if (rs != MOTO_OK) return rs;
+    const int cap = 4096 / (int)(sizeof(double) * kc);  // members per read-back of the pinned buffer
+    for (int y0 = 0; y0 < P; y0 += cap) {
+        const int ny = std::min(P - y0, cap);
+        rs = readback(p, ev + (size_t)y0 * kc, sizeof(double) * kc * (size_t)ny, hev.data() + (size_t)y0 * kc, st);
+        if (rs != MOTO_OK) return rs;
+    }
+    for (int y = 0; y < P; ++y) {
+        int hdr[5];
+        rs = readback(p, w + L.state + L.state_b * (size_t)y, sizeof(hdr), hdr, st);
+        if (rs != MOTO_OK) return rs;
+        iters[y] = hdr[4];
+        const double l1 = hev[(size_t)y * kc], l2 = hev[(size_t)y * kc + 1];
+        const bool conv = std::isfinite(fnorm[y]) && fnorm[y] <= o.tau_F;
+        int status;
+        if (nanm[y] || !std::isfinite(fnorm[y]) || !std::isfinite(l1) || !std::isfinite(l2) ||
+            inf[y].status == MOTO_NAN)
+            status = MOTO_NAN;
+        else if (!conv)
+            status = MOTO_NOT_CONVERGED;
+        else if (l1 < -tau_lam && l2 > tau_lam)
+            status = MOTO_SADDLE;
+        else if (l2 < -tau_lam)
+            status = MOTO_HIGHER_INDEX;
+        else
+            status = MOTO_DEGENERATE;
+        res[y].status = status;
+        res[y].iters = iters[y];
+        res[y].n_hvp = n_hvp[y] + inf[y].n_hvp;
+        res[y].E = hE[y];
+        res[y].fnorm = fnorm[y];
+        res[y].lambda1 = l1;
+        res[y].lambda2 = l2;
+    }
+    if (evals_out) HIP_TRY(hipMemcpyAsync(evals_out, ev, sizeof(double) * kc * (size_t)P, hipMemcpyDeviceToDevice, st));
+    if (V_out) HIP_TRY(hipMemcpyAsync(V_out, V, sizeof(double) * N3 * kc * (size_t)P, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     return MOTO_OK;
 }

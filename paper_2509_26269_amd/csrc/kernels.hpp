@@ -212,6 +212,7 @@ hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, 
 int update_blocks(int n2);
 hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, EigCtrl* ctrl, int first,
                               hipStream_t st);
+hipError_t launch_eig_gather_info(int P, const EigCtrl* ctrl, moto_info* out, hipStream_t st);
 // all_done = 1 once every member's control block says done (P > 1 only).
 hipError_t launch_eig_all_done(const EigArgs& a, const EigCtrl* ctrl, int* all_done, hipStream_t st);
 hipError_t launch_eig_output(bool f64, const EigArgs& a, const void* S, const double* m, int N, double* V,

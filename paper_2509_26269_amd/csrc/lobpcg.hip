@@ -678,6 +678,22 @@ hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, Ei
     return hipGetLastError();
 }
 
+// outcome of every member in one array (status, iterations, HVP columns)
+__global__ void k_eig_gather_info(int P, const EigCtrl* __restrict__ ctrl, moto_info* __restrict__ out) {
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= P) return;
+    moto_info r;
+    r.status = ctrl[y].status;
+    r.iters = ctrl[y].iters;
+    r.n_hvp = ctrl[y].n_hvp;
+    out[y] = r;
+}
+
+hipError_t launch_eig_gather_info(int P, const EigCtrl* ctrl, moto_info* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_eig_gather_info, dim3((P + 63) / 64), dim3(64), 0, st, P, ctrl, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_eig_all_done(const EigArgs& a, const EigCtrl* ctrl, int* all_done, hipStream_t st) {
     hipLaunchKernelGGL(k_eig_all_done, dim3(1), dim3(WL), 0, st, a.P, ctrl, all_done);
     return hipGetLastError();

@@ -149,6 +149,9 @@ def lib():
         "moto_topological_charge": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     }
     sig.update({
+        "moto_saddle_search_population_workspace": (_sz, [_vp, _i32, _i32, ctypes.POINTER(SearchOpts)]),
+        "moto_saddle_search_population": (_i32, [_vp, _i32, _i32, _vp, _vp, ctypes.POINTER(SearchOpts), _vp, _vp,
+                                                 _vp, _vp, _sz, _vp]),
         "moto_default_explorer_opts": (None, [_i32, ctypes.POINTER(ExplorerOpts)]),
         "moto_explorer_workspace": (_sz, [_vp, _i32, _i32, _i32, ctypes.POINTER(ExplorerOpts)]),
         "moto_explorer_objectives": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp,
@@ -531,6 +534,31 @@ def moto_descend(plan: Plan, m: torch.Tensor, v1: torch.Tensor, sign: int, hvp: 
     _check(lib().moto_descend(plan.handle, hvp, _ptr(m), _ptr(v1), int(sign), ctypes.byref(o), ctypes.byref(res),
                               _ptr(ws), nb, _stream(stream)), "moto_descend")
     return res
+
+
+def moto_saddle_search_population(plan: Plan, m: torch.Tensor, hvp: int = MOTO_F64,
+                                  mask: Optional[torch.Tensor] = None, opts: Optional[SearchOpts] = None,
+                                  stream=None):
+    """P searches in lock step on m [P, 3, N] (updated in place).  Returns
+    (list of SearchResult, evals [P, k_cert], V [P, k_cert, 3, N])."""
+    if m.dim() != 3 or m.shape[1] != 3 or m.shape[2] != plan.N:
+        raise MotoError("m must be [P, 3, N]")
+    P = int(m.shape[0])
+    if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != P * plan.N):
+        raise MotoError("mask must be uint8 [P, N]")
+    o = opts if opts is not None else search_opts(hvp)
+    kc = max(o.k_cert, 2)
+    nb = int(lib().moto_saddle_search_population_workspace(plan.handle, hvp, P, ctypes.byref(o)))
+    if nb == 0:
+        raise MotoError("population size or options out of range")
+    ws = _ws(nb, m.device)
+    ev = torch.empty(P, kc, dtype=torch.float64, device=m.device)
+    V = torch.empty(P, kc, 3, plan.N, dtype=torch.float64, device=m.device)
+    res = (SearchResult * P)()
+    _check(lib().moto_saddle_search_population(plan.handle, hvp, P, _ptr(m), _ptr(mask), ctypes.byref(o), res,
+                                               _ptr(ev), _ptr(V), _ptr(ws), nb, _stream(stream)),
+           "moto_saddle_search_population")
+    return list(res), ev, V
 
 
 def moto_saddle_search(plan: Plan, m: torch.Tensor, hvp: int = MOTO_F64, mask: Optional[torch.Tensor] = None,

@@ -137,3 +137,53 @@ def test_population_bad_arguments_rejected():
     assert M.lib().moto_min_modes_population_workspace(plan.handle, M.MOTO_F64, M.MAX_POPULATION + 1, 2, -1) == 0
     with pytest.raises(M.MotoError):
         M.moto_min_modes_population(plan, _dev(S.uniform(64))[None].expand(2, 3, 64).contiguous(), 17, M.MOTO_F64)
+
+
+# --- searches in lock step ----------------------------------------------------
+def test_population_search_matches_one_at_a_time_searches():
+    """Three collapse-type starts on the 16x16 NN model (FP64 HVP) and a
+    masked member: every member ends where the one-at-a-time search from the
+    same start ends (status, iterations, energy, spins)."""
+    M = _M()
+    p = S.ham_nn(16)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    starts = [S.add_tilt_noise(S.skyrmion(16, 16, 1.0), 0.05, np.random.default_rng(s)) for s in range(3)]
+    mask = np.ones((3, h.N), np.uint8)
+    mask[2] = S.random_mask_disc(16, 16, 5.0)
+    so = M.search_opts(M.MOTO_F64, tau_F=1e-6)
+    mp = _dev(np.stack(starts))
+    res, ev, V = M.moto_saddle_search_population(plan, mp, M.MOTO_F64, mask=_dev(mask, torch.uint8), opts=so)
+    for y in range(3):
+        md = _dev(starts[y])
+        r1, ev1, _ = M.moto_saddle_search(plan, md, M.MOTO_F64, mask=_dev(mask[y], torch.uint8) if y == 2 else None,
+                                          opts=so)
+        assert res[y].status == r1.status, (y, res[y].status, r1.status)
+        assert res[y].iters == r1.iters
+        assert abs(res[y].E - r1.E) <= 1e-10 * abs(r1.E)
+        assert O.max_site_angle(_np(mp[y]), _np(md)) <= 1e-8
+        assert np.abs(_np(ev[y]) - _np(ev1)).max() <= 1e-9 * h.h_est()
+    assert res[0].status == M.SADDLE
+
+
+def test_population_search_stoner_wohlfarth_closed_form():
+    M = _M()
+    p = S.ham_sw(8)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    b, K = p.B[0], p.K
+    starts = np.stack([S.add_tilt_noise(S.uniform(h.N, (1, 0, 0)), 0.02, np.random.default_rng(s))
+                       for s in range(4)])
+    res, ev, _ = M.moto_saddle_search_population(plan, _dev(starts), M.MOTO_F64,
+                                                 opts=M.search_opts(M.MOTO_F64, tau_F=1e-8))
+    for r in res:
+        assert r.status == M.SADDLE
+        assert abs(r.lambda1 - (b - 2 * K)) < 1e-8 and abs(r.lambda2 - b) < 1e-8
+
+
+def test_population_search_bad_arguments():
+    M = _M()
+    plan = M.Plan.from_params(S.ham_nn(8))
+    with pytest.raises(M.MotoError):
+        M.moto_saddle_search_population(plan, _dev(S.uniform(64))[None].contiguous(), M.MOTO_F64,
+                                        opts=M.search_opts(M.MOTO_F64, k=20))
