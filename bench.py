@@ -12,7 +12,8 @@ Headline (the 128x128 three-shell workload, FP32 HVP):
   * a population of 24 k = 2 eigen-solves in lock step against one at a
     time, and the explorer objectives of 24 candidates;
   * saddle searches/s (k = 2, FP32 HVP, tau_F = 1e-5, capped outer
-    iterations): 64 searches on 128x128 in one persistent launch, 256 on
+    iterations): 64 searches on 128x128 in lock step over the whole chip and
+    in one persistent launch, 256 on
     uneven 32..96 lattices in one launch, and searches one at a time
     (L-BFGS, and the nonlinear-CG outer rule on the same starts);
   * the FP64 CPU oracle timed on a bounded sample of the same HVP workload.
@@ -434,6 +435,26 @@ def main():
 
         spec = S.fixed_size_spec(max(args.batched, args.searches), L, seed=128)
         if args.batched > 0:
+            # the same starts as searches in lock step over the whole chip
+            print(f"[bench] {args.batched} saddle searches on {L}x{L} in lock step (population)", file=sys.stderr,
+                  flush=True)
+            mpop = torch.as_tensor(np.stack([S.batch_member(spec, i) for i in range(args.batched)]), device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            resp, _, _ = M.moto_saddle_search_population(plan, mpop, M.MOTO_F32, opts=so)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            hist = {}
+            for r in resp:
+                hist[M.STATUS_NAMES[r.status]] = hist.get(M.STATUS_NAMES[r.status], 0) + 1
+            its = int(sum(r.iters for r in resp))
+            extra["population_128"] = {"searches": len(resp), "wall_s": round(el, 3),
+                                       "searches_per_s": round(len(resp) / el, 4),
+                                       "outer_iters_per_s": round(its / el, 1),
+                                       "mean_outer_iters": round(its / len(resp), 1),
+                                       "hvp_columns_per_outer": round(sum(r.n_hvp for r in resp) / max(its, 1), 1),
+                                       "status": hist}
+            del mpop
             print(f"[bench] {args.batched} saddle searches on {L}x{L} in one persistent launch", file=sys.stderr,
                   flush=True)
             batched_leg("batched_128", [L] * args.batched, [S.batch_member(spec, i) for i in range(args.batched)], p)
