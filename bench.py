@@ -7,6 +7,8 @@ Headline (the 128x128 three-shell workload, FP32 HVP):
     kernel streams from HBM); one step = one batched HVP launch;
   * the roofline of that kernel (algorithmic bytes 12 + 16 n_vec per site);
   * wall time of the k = 4 eigen-solve (residual 1e-5) on one 128x128 state;
+  * a k = 8 solve on a 512x512 two-skyrmion state and k = 2 solves from
+    16x16 to 1024x1024 (time and workspace against size);
   * the 35-shell Pd/Fe/Ir(111) exchange (360 bonds per site) HVP on 64
     128x128 lattices, against the VALU and LDS ceilings;
   * a population of 24 k = 2 eigen-solves in lock step against one at a
@@ -137,6 +139,51 @@ def cpu_baseline(O, S, p, base, nvec, budget_s=12.0):
     return n_done, el
 
 
+def _cpu_worker(args):
+    """One host process of the all-cores baseline: the FP64 oracle HVP on
+    its share of the distinct seeded states (the recipe of hvp_inputs)."""
+    wid, nproc, L, nvec, n_distinct, seed, budget_s = args
+    sys.path.insert(0, ROOT)
+    import oracle as O
+    from paper_2509_26269_amd import synth as S
+
+    h = O.Ham(**S.ham_3shell(L).asdict())
+    kinds = ["skyrmion", "antiskyrmion"]
+    rng = np.random.default_rng(7 + wid)
+    n_done = 0
+    t0 = time.perf_counter()
+    i = wid
+    while time.perf_counter() - t0 < budget_s:
+        m = S.three_shell_start(L, seed=seed + i % n_distinct, kind=kinds[(i % n_distinct) % 2])
+        _, _, c, _ = O.energy_grad(h, m)
+        a = rng.standard_normal((nvec, 2, h.N))
+        w = O.tangent_hvp(h, m, c, O.from_frame(m, a))
+        _ = O.to_frame(m, w)
+        n_done += nvec
+        i += nproc
+    return n_done, time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(L, nvec, budget_s=12.0, n_distinct=32, seed=2025):
+    """The same oracle sample spread over the host cores (one process each,
+    spawned so that none inherits the GPU context); cores capped at 16."""
+    import multiprocessing as mp
+
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncores = os.cpu_count() or 1
+    ncores = max(1, min(ncores, 16))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(ncores) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_cpu_worker, [(w, ncores, L, nvec, n_distinct, seed, budget_s) for w in range(ncores)])
+        wall = time.perf_counter() - t0
+    n_done = sum(r[0] for r in res)
+    el = max(r[1] for r in res)
+    return n_done, el, ncores, wall
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +196,7 @@ def main():
     ap.add_argument("--batched", type=int, default=64, help="searches on 128x128 in the batched (one-launch) leg")
     ap.add_argument("--ragged", type=int, default=256, help="searches on uneven 32..96 lattices, one launch")
     ap.add_argument("--max-outer", type=int, default=300, help="outer-iteration cap of every search leg")
+    ap.add_argument("--large", type=int, default=1, help="512x512 k=8 solve and the k=2 size sweep (0: skip)")
     ap.add_argument("--shells35", type=int, default=64,
                     help="lattices in the 35-shell (Pd/Fe/Ir(111)) HVP leg (0: skip)")
     ap.add_argument("--population", type=int, default=24,
@@ -241,7 +289,10 @@ def main():
                 "autotune_ms": {k2: round(v2, 4) for k2, v2 in vtimes.items()},
                 "alg_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": round(avg_launch_ms, 5),
+                "launch_ms_p10_p50_p90": [round(float(np.percentile(per, q)), 5) for q in (10, 50, 90)],
             },
+            "device": {"name": torch.cuda.get_device_name(0), "hip": torch.version.hip,
+                       "compute_units": torch.cuda.get_device_properties(0).multi_processor_count},
         }
     del W, V, m, c
     torch.cuda.empty_cache()
@@ -300,6 +351,49 @@ def main():
                                 "workspace_bytes": wsl.nbytes}
         extra["lanczos_128_k4"] = lz
         extra["lobpcg_128_k4_lambda"] = [round(float(x), 6) for x in r.evals.cpu()]
+    if not args.hvp_only and not args.eigen_only and args.large:
+        # 512x512 with two skyrmions (Q = 2), k = 8: the size where a dense
+        # tangent Hessian (2N)^2 FP64 = 2.2 TB is out of reach
+        print("[bench] 512x512 two-skyrmion state, k=8 FP32 eigen-solve", file=sys.stderr, flush=True)
+        L2 = 512
+        p2 = S.ham_3shell(L2)
+        plan2 = M.Plan.from_params(p2)
+        m2 = torch.as_tensor(S.two_skyrmions(L2), device="cuda")
+        o2 = M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=200)
+        ws2 = M.EigWorkspace(plan2, M.MOTO_F32, 8)
+        M.moto_min_modes(plan2, m2, 8, M.MOTO_F32, opts=o2, ws=ws2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r2 = M.moto_min_modes(plan2, m2, 8, M.MOTO_F32, opts=o2, ws=ws2)
+        torch.cuda.synchronize()
+        extra["min_modes_512_two_skyrmions_k8"] = {
+            "ms": round(1e3 * (time.perf_counter() - t0), 2), "iters": r2.iters, "n_hvp": int(r2.n_hvp),
+            "status": M.STATUS_NAMES[r2.status], "workspace_bytes": ws2.nbytes,
+            "dense_hessian_bytes": (2 * L2 * L2) ** 2 * 8,
+            "lambda": [round(float(x), 6) for x in r2.evals.cpu()]}
+        del m2, ws2
+        # time and workspace of the k = 2 solve against the lattice size
+        # (the paper's Fig. 2b-c axes), uniform and skyrmion states
+        scal = {}
+        for Ls in (16, 32, 64, 128, 256, 512, 1024):
+            ps = S.ham_3shell(Ls)
+            pls = M.Plan.from_params(ps)
+            for kind in ("fm", "skyrmion"):
+                ms_ = S.uniform(Ls * Ls) if kind == "fm" else S.three_shell_start(Ls, seed=0, kind="skyrmion")
+                md_ = torch.as_tensor(ms_, device="cuda")
+                os_ = M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=200)
+                wss = M.EigWorkspace(pls, M.MOTO_F32, 2)
+                M.moto_min_modes(pls, md_, 2, M.MOTO_F32, opts=os_, ws=wss)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rs_ = M.moto_min_modes(pls, md_, 2, M.MOTO_F32, opts=os_, ws=wss)
+                torch.cuda.synchronize()
+                scal[f"{Ls}_{kind}"] = {"ms": round(1e3 * (time.perf_counter() - t0), 2), "iters": rs_.iters,
+                                        "status": M.STATUS_NAMES[rs_.status], "workspace_MB": round(wss.nbytes / 2**20, 2)}
+                del md_, wss
+            print(f"[bench]   k=2 solves on {Ls}x{Ls} done", file=sys.stderr, flush=True)
+        extra["min_modes_k2_scaling"] = scal
+        torch.cuda.empty_cache()
     if not args.hvp_only and not args.eigen_only and args.shells35 > 0:
         # the many-shell regime: the 35-shell Pd/Fe/Ir(111) exchange of Table S1
         # (360 bonds per site) on 128x128 lattices, FP32 frame HVP
@@ -498,14 +592,19 @@ def main():
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         import oracle as O
 
-        n_done, el = cpu_baseline(O, S, p, base, nvec)
+        n1, el1 = cpu_baseline(O, S, p, base, nvec, budget_s=8.0)
+        print("[bench] CPU oracle baseline on all host cores", file=sys.stderr, flush=True)
+        na, ela, ncores, _ = cpu_baseline_all_cores(L, nvec, budget_s=10.0)
         out["cpu_baseline"] = {
-            "value": round(n_done * N / el / 1e9, 6),
+            "value": round(na * N / ela / 1e9, 6),
             "unit": "Gsite/s",
-            "cores": 1,
+            "cores": ncores,
             "kind": "oracle",
-            "sample": f"{n_done} FP64 oracle HVPs ({n_done // nvec} {L}x{L} states, cycling over {len(base)} "
-                      f"distinct seeded states, x {nvec} vectors, frame coordinates in and out) in {el:.1f} s",
+            "sample": f"{na} FP64 oracle HVPs ({na // nvec} {L}x{L} states from {len(base)} distinct seeded "
+                      f"states, x {nvec} vectors, frame coordinates in and out) in {ela:.1f} s on {ncores} "
+                      f"processes (one per core)",
+            "value_1core": round(n1 * N / el1 / 1e9, 6),
+            "sample_1core": f"{n1} HVPs in {el1:.1f} s on one core",
         }
     out["extra"] = extra
     print(json.dumps(out), flush=True)

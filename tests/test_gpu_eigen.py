@@ -208,3 +208,27 @@ def test_captured_chunk_follows_the_callers_state(solver, hvp):
         re = run(m, 0, fresh())
         assert rg.status == re.status == M.CONVERGED and rg.iters == re.iters
         assert torch.equal(rg.evals, re.evals) and torch.equal(rg.V, re.V)
+
+
+def test_min_modes_512_two_skyrmions_residual_property():
+    """512x512 with two skyrmions (Q = 2), FP32 HVP: the start has the seeded
+    charge and every returned pair is an eigenpair of the oracle's operator
+    within the tolerance, in ascending order.  k = 4: the skyrmions' internal
+    modes (0.005 .. 0.03); the next levels are the bottom of the magnon band,
+    spaced ~1e-4 apart on a lattice this large, which a 12-column block
+    resolves only slowly."""
+    M = _M()
+    L = 512
+    p = S.ham_3shell(L)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m = S.two_skyrmions(L)
+    assert abs(O.topological_charge(h, m) - 2.0) < 1e-6
+    r = M.moto_min_modes(plan, _dev(m), 4, M.MOTO_F32, opts=M.eig_opts(M.MOTO_F32, tol=1e-5, max_iter=400))
+    assert r.status == M.CONVERGED, (r.status, r.iters)
+    ev, V = _np(r.evals), _np(r.V)
+    assert np.all(np.diff(ev) >= -1e-6 * h.h_est())
+    _, _, c, _ = O.energy_grad(h, m)
+    for j in range(4):
+        Hv = O.tangent_hvp(h, m, c, V[j])
+        assert np.linalg.norm(Hv - ev[j] * V[j]) <= 2e-5 * h.h_est(), j
