@@ -194,7 +194,7 @@ moto_status moto_param_grad_apply(moto_plan p, moto_dtype dt, int32_t batch, con
 /* ---------------------------------------------------------------------
  * Inner layer: k smallest eigenpairs of the masked tangent Hessian at m by
  * block LOBPCG (Knyazev 2001) with HVPs only, Rayleigh-Ritz on [X W P] in
- * FP64 (SVQB orthonormalisation, Stathopoulos & Wu 2002, then Jacobi), block
+ * FP64 (SVQB orthonormalisation, Stathopoulos & Wu 2002, then a Householder-QL eigen-solve), block
  * width k + guard.  HVP and blocks in `hvp` precision; Gram, Rayleigh-Ritz
  * and the returned vectors in FP64.
  * Stopping rule: ||H v_j - lambda_j v_j||_2 <= tol * moto_hessian_norm_bound

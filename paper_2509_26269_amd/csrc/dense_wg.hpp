@@ -1,7 +1,7 @@
 // dense_wg.hpp -- small dense FP64 steps of the inner layer, each executed by
-// one wavefront: parallel cyclic Jacobi, the orthonormalising transform of a
-// projected block, and the Rayleigh-Ritz step with the orthogonal complement
-// for P.  LD is the largest basis size handled (the
+// one wavefront: the symmetric eigen-solve (Householder tridiagonalisation
+// and implicit QL), the orthonormalising transform of a projected block, and
+// the Rayleigh-Ritz step with the orthogonal complement for P.  LD is the largest basis size handled (the
 // leading dimension of the LDS matrices); LD / 3 is the largest block width.
 #pragma once
 
@@ -36,11 +36,11 @@ __device__ __forceinline__ int wlane() { return threadIdx.x & (WL - 1); }
 // QL iteration with Wilkinson shifts on the tridiagonal, its plane rotations
 // applied to the columns of Z (Golub & Van Loan, Sections 8.3.1 and 8.3.5).
 // The scalar recurrences of the QL sweep are computed by every lane alike,
-// so control flow stays uniform.  Same contract as jacobi_wg: on return
+// so control flow stays uniform.  On return
 // diag(A) holds the eigenvalues (in no particular order) and column j of Z
 // the eigenvector of A[j][j]; the off-diagonal part of A is left undefined.
-// About n^2 short serial steps instead of the Jacobi's ~ 6 n rounds of n^2/2
-// rotations, which is what a single wavefront is limited by.
+// About n^2 short serial steps instead of a cyclic Jacobi's ~ 6 n rounds of
+// n^2/2 rotations, which is what a single wavefront is limited by.
 // --------------------------------------------------------------------------
 // value of v held by lane i (i uniform across the wave)
 __device__ __forceinline__ double rdlane(double v, int i) {
@@ -167,13 +167,6 @@ __device__ void symeig_wg(double* A, double* Z, int n) {
 }
 
 // --------------------------------------------------------------------------
-// Parallel cyclic Jacobi on an n x n symmetric matrix in LDS (leading
-// dimension LD), round-robin ordering: the n/2 rotations of a round act on
-// disjoint index pairs (Golub & Van Loan, parallel Jacobi).  A round applies
-// A <- R A R^T blockwise: every 2 x 2 block (pair k1, pair k2) is updated
-// from itself alone, so the lanes update disjoint blocks in place.  On
-// return diag(A) holds the eigenvalues and the columns of Z the eigenvectors.
-// --------------------------------------------------------------------------
 // Visit (a, b), a < na, b < nb, in lane-strided order of a * nb + b, with
 // one integer division per call instead of one per element.
 template <class F>
@@ -189,125 +182,6 @@ __device__ __forceinline__ void for2(int na, int nb, F&& f) {
         if (b >= nb) {
             b -= nb;
             ++a;
-        }
-    }
-}
-
-// Pair k of round `round` in the round-robin schedule on ne (even) indices:
-// positions k and ne-1-k, position 0 fixed, the others rotating.  q = -1
-// marks the padding index of an odd n.
-__device__ __forceinline__ void rr_pair(int k, int round, int ne, int n, int& p, int& q) {
-    const int m = ne - 1;
-    int ia = 0;
-    if (k != 0) {
-        ia = k - 1 + round;
-        ia = 1 + (ia >= m ? ia - m : ia);
-    }
-    int ib = ne - 2 - k + round;
-    ib = 1 + (ib >= m ? ib - m : ib);
-    p = ia < ib ? ia : ib;
-    q = ia < ib ? ib : ia;
-    if (q >= n) q = -1;
-}
-
-template <int LD>
-__device__ void jacobi_wg(double* A, double* Z, int n, double tol, int max_sweeps) {
-    constexpr int HP = LD / 2 + 1;
-    __shared__ double cs[HP], sn[HP];
-    const int lane = wlane();
-    if (n <= 0) return;
-    if (lane < n)
-        for (int r = 0; r < n; ++r) Z[r * LD + lane] = (r == lane) ? 1.0 : 0.0;
-    const int ne = n + (n & 1);
-    const int half = ne / 2;
-    // lane-strided traversal of the half x half blocks and half x n Z items
-    const int b_qa = WL / half, b_qb = WL % half, b_a0 = lane / half, b_b0 = lane % half;
-    const int z_qa = WL / n, z_qb = WL % n, z_a0 = lane / n, z_b0 = lane % n;
-    wsync();
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        double off = 0.0, fro = 0.0;
-        if (lane < n)
-            for (int r = 0; r < n; ++r) {
-                const double v = A[r * LD + lane];
-                fro += v * v;
-                if (r != lane) off += v * v;
-            }
-        off = wave_sum(off);
-        fro = wave_sum(fro);
-        if (!(off > tol * tol * fro)) break;
-        for (int round = 0; round < ne - 1; ++round) {
-            if (lane < half) {
-                int p, q;
-                rr_pair(lane, round, ne, n, p, q);
-                double c = 1.0, s = 0.0;
-                if (q >= 0) {
-                    const double apq = A[p * LD + q];
-                    if (apq != 0.0) {
-                        // root of t^2 + 2 tau t - 1 = 0 of smaller modulus,
-                        // tau = (a_qq - a_pp) / (2 a_pq), without forming tau
-                        const double d = A[q * LD + q] - A[p * LD + p];
-                        const double t = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
-                        c = rsqrt(1.0 + t * t);
-                        s = t * c;
-                    }
-                }
-                cs[lane] = c;
-                sn[lane] = s;
-            }
-            wsync();
-            // A <- R A R^T on blocks (k1 <= k2); rows then columns, with
-            // R = [[c, -s], [s, c]] on each pair (p, q)
-            int k1 = b_a0, k2 = b_b0;
-            for (int b = lane; b < half * half; b += WL) {
-                if (k1 <= k2) {
-                    int p1, q1, p2, q2;
-                    rr_pair(k1, round, ne, n, p1, q1);
-                    rr_pair(k2, round, ne, n, p2, q2);
-                    const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
-                    const double m00 = A[p1 * LD + p2];
-                    const double m01 = q2 >= 0 ? A[p1 * LD + q2] : 0.0;
-                    const double m10 = q1 >= 0 ? A[q1 * LD + p2] : 0.0;
-                    const double m11 = (q1 >= 0 && q2 >= 0) ? A[q1 * LD + q2] : 0.0;
-                    const double n00 = c1 * m00 - s1 * m10, n01 = c1 * m01 - s1 * m11;
-                    const double n10 = s1 * m00 + c1 * m10, n11 = s1 * m01 + c1 * m11;
-                    const double b00 = c2 * n00 - s2 * n01, b01 = s2 * n00 + c2 * n01;
-                    const double b10 = c2 * n10 - s2 * n11, b11 = s2 * n10 + c2 * n11;
-                    A[p1 * LD + p2] = b00;
-                    if (q2 >= 0) A[p1 * LD + q2] = b01;
-                    if (q1 >= 0) A[q1 * LD + p2] = b10;
-                    if (q1 >= 0 && q2 >= 0) A[q1 * LD + q2] = b11;
-                    if (k1 != k2) {  // the transposed block
-                        A[p2 * LD + p1] = b00;
-                        if (q2 >= 0) A[q2 * LD + p1] = b01;
-                        if (q1 >= 0) A[p2 * LD + q1] = b10;
-                        if (q1 >= 0 && q2 >= 0) A[q2 * LD + q1] = b11;
-                    }
-                }
-                k1 += b_qa;
-                k2 += b_qb;
-                if (k2 >= half) {
-                    k2 -= half;
-                    ++k1;
-                }
-            }
-            int kp = z_a0, row = z_b0;
-            for (int i = lane; i < half * n; i += WL) {  // Z <- Z R^T
-                int p, q;
-                rr_pair(kp, round, ne, n, p, q);
-                if (q >= 0) {
-                    const double c = cs[kp], s = sn[kp];
-                    const double zp = Z[row * LD + p], zq = Z[row * LD + q];
-                    Z[row * LD + p] = c * zp - s * zq;
-                    Z[row * LD + q] = s * zp + c * zq;
-                }
-                kp += z_qa;
-                row += z_qb;
-                if (row >= n) {
-                    row -= n;
-                    ++kp;
-                }
-            }
-            wsync();
         }
     }
 }

@@ -9,10 +9,10 @@
 //   beta = |w|, q_{j+1} = w / beta
 // Q lives in one [m_max + 1][2N] array; w is written straight into column
 // j + 1.  At the end of a cycle one wavefront diagonalises the projected
-// matrix T (FP64 Jacobi), tests the residual estimates |beta_m y_m,i| and
-// either stops or restarts from the `keep` lowest Ritz vectors plus the
-// residual direction (Wu & Simon 2000): T becomes diag(theta) bordered by
-// beta_m y_m.  All reductions are FP64 with a fixed order.
+// matrix T (FP64, Householder tridiagonalisation and implicit QL), tests the
+// residual estimates |beta_m y_m,i| and either stops or restarts from the
+// `keep` lowest Ritz vectors plus the residual direction (Wu & Simon 2000):
+// T becomes diag(theta) bordered by beta_m y_m.  All reductions are FP64 with a fixed order.
 #include <type_traits>
 
 #include "dense_wg.hpp"

@@ -15,7 +15,7 @@
 //   * Rayleigh-Ritz still orthonormalises the Gram (SVQB, Stathopoulos & Wu
 //     2002) and drops dependent directions before the eigen-solve.
 // One iteration: orth(W) x2 -> HW = H W -> Grams S^T HS, S^T S (FP64,
-// fixed-order reduction) -> Rayleigh-Ritz (cyclic Jacobi) -> block update
+// fixed-order reduction) -> Rayleigh-Ritz (tridiagonal QL) -> block update
 // X, P, HX, HP, W = HX - X Lam -> convergence control.  Every kernel returns
 // at once when the control block says the solve is done, so chunks of
 // iterations can be queued without host round trips.
