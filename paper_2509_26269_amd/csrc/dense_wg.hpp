@@ -50,6 +50,16 @@ __device__ __forceinline__ double rdlane(double v, int i) {
     return __hiloint2double(hi, lo);
 }
 
+// 1/sqrt(t) for t > 0 to FP64 accuracy: the hardware estimate refined by two
+// Newton steps (each doubles the correct bits), a short dependent chain in
+// place of a correctly rounded square root followed by a division.
+__device__ __forceinline__ double rsqrt_nr(double t) {
+    double y = __builtin_amdgcn_rsq(t);
+    y = y * (1.5 - 0.5 * t * y * y);
+    y = y * (1.5 - 0.5 * t * y * y);
+    return y;
+}
+
 template <int LD>
 __device__ void symeig_wg(double* A, double* Z, int n) {
     __shared__ double hv[LD], hw[LD];
@@ -78,6 +88,7 @@ __device__ void symeig_wg(double* A, double* Z, int n) {
         double vp = 0.0;
         for (int i = k + 1 + lane; i < n; i += WL) {
             double pi = 0.0;
+#pragma unroll 4
             for (int j = k + 1; j < n; ++j) pi += A[i * LD + j] * hv[j];
             hw[i] = pi;
             vp += pi * hv[i];
@@ -89,6 +100,7 @@ __device__ void symeig_wg(double* A, double* Z, int n) {
         // A22 <- A22 - 2 (v w^T + w v^T); column k reduced to alpha e_(k+1)
         for (int i = k + 1 + lane; i < n; i += WL) {
             const double vi = hv[i], wi = hw[i];
+#pragma unroll 4
             for (int j = k + 1; j < n; ++j) A[i * LD + j] -= 2.0 * (vi * hw[j] + wi * hv[j]);
             const double a = i == k + 1 ? alpha : 0.0;
             A[i * LD + k] = a;
@@ -97,8 +109,10 @@ __device__ void symeig_wg(double* A, double* Z, int n) {
         // Z <- Z - 2 (Z v) v^T on columns k+1..n-1
         for (int r = lane; r < n; r += WL) {
             double t = 0.0;
+#pragma unroll 4
             for (int j = k + 1; j < n; ++j) t += Z[r * LD + j] * hv[j];
             t *= 2.0;
+#pragma unroll 4
             for (int j = k + 1; j < n; ++j) Z[r * LD + j] -= t * hv[j];
         }
         wsync();
@@ -127,32 +141,40 @@ __device__ void symeig_wg(double* A, double* Z, int n) {
             double sn = 1.0, cs = 1.0, p = 0.0;
             bool deflated = false;
             double dnext = rdlane(di, m);  // d_(i+1) before its update
+            // column i + 1 of the lane's row of Z as updated by the previous
+            // rotation of this sweep (carried in a register, stored once final)
+            double zc = lane < n ? Z[lane * LD + m] : 0.0;
+            int ilast = m;
             for (int i = m - 1; i >= l; --i) {
                 const double e_i = rdlane(ei, i), d_i = rdlane(di, i);
+                const double z0 = lane < n ? Z[lane * LD + i] : 0.0;
                 const double f = sn * e_i, b = cs * e_i;
-                r = sqrt(f * f + g * g);
-                if (lane == i + 1) ei = r;
-                if (r == 0.0) {
-                    if (lane == i + 1) di = dnext - p;
+                const double t = f * f + g * g;
+                if (t == 0.0) {
+                    if (lane == i + 1) {
+                        ei = 0.0;
+                        di = dnext - p;
+                    }
                     if (lane == m) ei = 0.0;
                     deflated = true;
                     break;
                 }
-                const double inv = 1.0 / r;
-                sn = f * inv;
-                cs = g * inv;
+                const double ri = rsqrt_nr(t);
+                r = t * ri;
+                if (lane == i + 1) ei = r;
+                sn = f * ri;
+                cs = g * ri;
                 g = dnext - p;
                 r = (d_i - g) * sn + 2.0 * cs * b;
                 p = sn * r;
                 if (lane == i + 1) di = g + p;
                 g = cs * r - b;
                 dnext = d_i;
-                for (int row = lane; row < n; row += WL) {
-                    const double z1 = Z[row * LD + i + 1], z0 = Z[row * LD + i];
-                    Z[row * LD + i + 1] = sn * z0 + cs * z1;
-                    Z[row * LD + i] = cs * z0 - sn * z1;
-                }
+                if (lane < n) Z[lane * LD + i + 1] = sn * z0 + cs * zc;
+                zc = cs * z0 - sn * zc;
+                ilast = i;
             }
+            if (lane < n) Z[lane * LD + ilast] = zc;
             if (deflated) continue;
             if (lane == l) {
                 di -= p;
