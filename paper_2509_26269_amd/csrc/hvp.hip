@@ -296,6 +296,12 @@ __global__ __launch_bounds__(NT) void k_hvp_band(Geo g, Coef<T> k, const T* __re
 // The centre term -c u and the anisotropy enter the accumulator of row R
 // when R is converted; the frames of the last three rows are kept in a
 // per-thread LDS ring.  Strip halos cost 4 extra input rows per strip.
+// The products are written with raw buffer stores and no branch: a row
+// outside the strip, a lane past the row's end or a slot past the vector
+// group gets an offset beyond the buffer's range, and the hardware drops
+// that store.  With the stores unconditional the compiler counts the ones
+// issued after a prefetch, so the wait for a prefetched row no longer
+// waits for the previous row's stores to complete.
 template <int DX, int DY>
 __device__ constexpr int m_shell() {
     return (DX * DX + DX * DY + DY * DY) == 1 ? 0 : (DX * DX + DX * DY + DY * DY) == 3 ? 1 : 2;
@@ -371,6 +377,22 @@ __device__ __forceinline__ void st_off_nt(T* __restrict__ base, unsigned byte_of
     __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
 }
 
+// raw buffer stores (stride 0: the range is num_records bytes; a store at
+// or past it is dropped)
+constexpr unsigned BUF_OOB = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, long long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+// non-temporal (AUX 2): the products are not read again by this launch
+template <class T>
+__device__ __forceinline__ void buf_st_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, T v) {
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 2);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, voff, soff, 2);
+}
+
 template <class T, int NVP, int XW, bool MASKED>
 __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __restrict__ m,
                                                   const T* __restrict__ c, const uint8_t* __restrict__ mask, int nvec, long long vbs,
@@ -403,7 +425,8 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
     const T* __restrict__ cb = c + (size_t)b * N;
     const uint8_t* __restrict__ mk = MASKED ? mask + (size_t)b * N : nullptr;
     const T* __restrict__ Vb = V + (size_t)b * vbs + (size_t)j0 * 2 * N;
-    T* __restrict__ Wb = W + (size_t)b * vbs + (size_t)j0 * 2 * N;
+    const int PB = (int)(N * sizeof(T));  // bytes of one coordinate plane
+    const __amdgpu_buffer_rsrc_t rwb = buf_rsrc(W + (size_t)b * vbs + (size_t)j0 * 2 * N, 2LL * nv * PB);
     const T cJ[3] = {k.cJ[0], k.cJ[1], k.cJ[2]};
     const T cD = k.cD, cDh = T(0.5) * k.cD, cDr = T(0.86602540378443864676) * k.cD, cK = k.cK;
 
@@ -434,6 +457,11 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
         }
     };
     load_raw(yin);
+    // every later prefetch is followed by its step's stores; dropped stores
+    // here give the loop's entry the same pattern, so the first wait of the
+    // loop also counts them instead of draining the queue
+#pragma unroll
+    for (int j = 0; j < 2 * NVP; ++j) buf_st_nt<T>(rwb, BUF_OOB, j * PB, T(0));
 
     T acc[5][NVP][3];
 #pragma unroll
@@ -531,21 +559,22 @@ __global__ __launch_bounds__(XW) void k_hvp_march(Geo g, Coef<T> k, const T* __r
         // 4. row R - 2 is complete
         const int yo = R - 2;
         const int cr = cw == 2 ? 0 : cw + 1;  // slot of row R - 2
-        if (lane && yo >= y0 && yo < y1) {
+        {
+            // before the strip's first row the slot holds stale frames:
+            // those stores are out of range and dropped
             const T f10 = cen[cr][0][x], f11 = cen[cr][1][x], f12 = cen[cr][2][x];
             const T f20 = cen[cr][3][x], f21 = cen[cr][4][x], f22 = cen[cr][5][x];
             bool on = true;
             if constexpr (MASKED) on = cen[cr][MASKED ? 6 : 0][x] != T(0);
-            const unsigned so = (unsigned)(x + g.Lx * yo) * (unsigned)sizeof(T);
+            const bool row_ok = lane && yo >= y0 && yo < y1;
+            const unsigned so = row_ok ? (unsigned)(x + g.Lx * yo) * (unsigned)sizeof(T) : BUF_OOB;
 #pragma unroll
             for (int j = 0; j < NVP; ++j) {
                 const T wa = f10 * acc[SL(-2)][j][0] + f11 * acc[SL(-2)][j][1] + f12 * acc[SL(-2)][j][2];
                 const T wb = f20 * acc[SL(-2)][j][0] + f21 * acc[SL(-2)][j][1] + f22 * acc[SL(-2)][j][2];
-                T* __restrict__ wj = Wb + (size_t)(2 * j) * N;
-                if (j < nv) {
-                    st_off_nt(wj, so, on ? wa : T(0));
-                    st_off_nt(wj + N, so, on ? wb : T(0));
-                }
+                const unsigned sj = j < nv ? so : BUF_OOB;
+                buf_st_nt<T>(rwb, sj, 2 * j * PB, on ? wa : T(0));
+                buf_st_nt<T>(rwb, sj, (2 * j + 1) * PB, on ? wb : T(0));
             }
         }
         cw = cw == 2 ? 0 : cw + 1;
@@ -586,8 +615,8 @@ __device__ __forceinline__ void st2(T* __restrict__ base, unsigned byte_off, T a
     v.y = b;
     *reinterpret_cast<V2*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
-// streaming forms for data touched once per launch (the vectors in, the
-// products out): non-temporal, so they do not displace the reused rows
+// streaming form for the vectors, read once per launch: non-temporal, so
+// they do not displace the reused rows
 template <class T>
 __device__ __forceinline__ void ld2_nt(const T* __restrict__ base, unsigned byte_off, T& a, T& b) {
     typedef T V2 __attribute__((ext_vector_type(2)));
@@ -595,13 +624,26 @@ __device__ __forceinline__ void ld2_nt(const T* __restrict__ base, unsigned byte
     a = v.x;
     b = v.y;
 }
+// an aligned pair of products as one raw buffer store (non-temporal)
 template <class T>
-__device__ __forceinline__ void st2_nt(T* __restrict__ base, unsigned byte_off, T a, T b) {
-    typedef T V2 __attribute__((ext_vector_type(2)));
-    V2 v;
-    v.x = a;
-    v.y = b;
-    __builtin_nontemporal_store(v, reinterpret_cast<V2*>(reinterpret_cast<char*>(base) + byte_off));
+__device__ __forceinline__ void buf_st2_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, T a, T b) {
+    if constexpr (sizeof(T) == 4) {
+        typedef unsigned U2 __attribute__((ext_vector_type(2)));
+        U2 v;
+        v.x = __builtin_bit_cast(unsigned, a);
+        v.y = __builtin_bit_cast(unsigned, b);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 2);
+    } else {
+        typedef unsigned U4 __attribute__((ext_vector_type(4)));
+        const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+        const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+        U4 v;
+        v.x = (unsigned)ua;
+        v.y = (unsigned)(ua >> 32);
+        v.z = (unsigned)ub;
+        v.w = (unsigned)(ub >> 32);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 2);
+    }
 }
 
 template <class T, int NVP, int NT2, bool MASKED>
@@ -636,7 +678,8 @@ __global__ __launch_bounds__(NT2) void k_hvp_march2(Geo g, Coef<T> k, const T* _
     const T* __restrict__ cb = c + (size_t)b * N;
     const uint8_t* __restrict__ mk = MASKED ? mask + (size_t)b * N : nullptr;
     const T* __restrict__ Vb = V + (size_t)b * vbs + (size_t)j0 * 2 * N;
-    T* __restrict__ Wb = W + (size_t)b * vbs + (size_t)j0 * 2 * N;
+    const int PB = (int)(N * sizeof(T));  // bytes of one coordinate plane
+    const __amdgpu_buffer_rsrc_t rwb = buf_rsrc(W + (size_t)b * vbs + (size_t)j0 * 2 * N, 2LL * nv * PB);
     const T cJ[3] = {k.cJ[0], k.cJ[1], k.cJ[2]};
     const T cD = k.cD, cDh = T(0.5) * k.cD, cDr = T(0.86602540378443864676) * k.cD, cK = k.cK;
 
@@ -669,6 +712,10 @@ __global__ __launch_bounds__(NT2) void k_hvp_march2(Geo g, Coef<T> k, const T* _
         }
     };
     load_raw(yin);
+    // dropped stores: the loop's entry sees the same prefetch-then-stores
+    // pattern as every later step (see k_hvp_march)
+#pragma unroll
+    for (int j = 0; j < 2 * NVP; ++j) buf_st2_nt<T>(rwb, BUF_OOB, j * PB, T(0), T(0));
 
     T acc[5][NVP][2][3];
 #pragma unroll
@@ -784,8 +831,11 @@ __global__ __launch_bounds__(NT2) void k_hvp_march2(Geo g, Coef<T> k, const T* _
         }
         const int yo = R - 2;
         const int cr = cw == 2 ? 0 : cw + 1;
-        if (lane && yo >= y0 && yo < y1) {
-            const unsigned so = (unsigned)(x + g.Lx * yo) * (unsigned)sizeof(T);
+        {
+            // unconditional stores; rows outside the strip (stale frames)
+            // and lanes past the row go out of range and are dropped
+            const bool row_ok = lane && yo >= y0 && yo < y1;
+            const unsigned so = row_ok ? (unsigned)(x + g.Lx * yo) * (unsigned)sizeof(T) : BUF_OOB;
             T wa[NVP][2], wb[NVP][2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -803,11 +853,9 @@ __global__ __launch_bounds__(NT2) void k_hvp_march2(Geo g, Coef<T> k, const T* _
             }
 #pragma unroll
             for (int j = 0; j < NVP; ++j) {
-                T* __restrict__ wj = Wb + (size_t)(2 * j) * N;
-                if (j < nv) {
-                    st2_nt(wj, so, wa[j][0], wa[j][1]);
-                    st2_nt(wj + N, so, wb[j][0], wb[j][1]);
-                }
+                const unsigned sj = j < nv ? so : BUF_OOB;
+                buf_st2_nt<T>(rwb, sj, 2 * j * PB, wa[j][0], wa[j][1]);
+                buf_st2_nt<T>(rwb, sj, (2 * j + 1) * PB, wb[j][0], wb[j][1]);
             }
         }
         cw = cw == 2 ? 0 : cw + 1;
@@ -836,7 +884,9 @@ const char* hvp_variant_name(int v) { return (v >= 0 && v < HVP_NVARIANTS) ? kNa
 
 // the row march needs the whole row in one workgroup and a two-column halo
 // that does not overlap itself
-static bool march_fits(const Geo& g) { return g.Lx >= 4 && g.Lx <= 256; }
+// the march's store range is 32-bit: a vector group's slice (at most 4
+// FP64 vectors x 2 coordinates) must stay below 2^31 bytes
+static bool march_fits(const Geo& g) { return g.Lx >= 4 && g.Lx <= 256 && (long long)g.N * 64 < (1LL << 31); }
 
 // the paired march also needs an even width (aligned column pairs)
 static bool march2_fits(const Geo& g) { return march_fits(g) && (g.Lx % 2) == 0; }
