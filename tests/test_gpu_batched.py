@@ -87,3 +87,39 @@ def test_batched_rejects_bad_sizes():
     p = S.ham_3shell(8)
     with pytest.raises(M.MotoError):
         M.moto_saddle_search_batched(p, [4], torch.zeros(48, dtype=torch.float64, device="cuda"))
+
+
+def test_batched_full_size_ragged_256():
+    """The benchmark's batching workload at full size: 256 searches on uneven
+    32..96 lattices (k = 2, FP32 HVP) in one persistent launch, capped at 30
+    outer steps.  Every member: finite unit spins, iterations within the cap,
+    a valid status.  Sampled members (first, last, a seeded draw): the
+    reported energy is the oracle energy of the returned state, and the
+    reported lambda_1 the oracle's lowest tangent eigenvalue there (to the
+    FP32 inner tolerance)."""
+    M = _M()
+    rs = S.ragged_batch_spec(256, seed=26269)
+    Ls = list(rs.L)
+    p = S.ham_3shell(Ls[0])
+    starts = [S.batch_member(rs, i) for i in range(256)]
+    cap = 30
+    opts = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, max_outer=cap, eig={"tol": 1e-5, "max_iter": 200})
+    mall = _pack(starts)
+    res = M.moto_saddle_search_batched(p, Ls, mall, opts)
+    finals = _unpack(mall, Ls)
+    assert len(res) == 256
+    for i, (L, mf) in enumerate(zip(Ls, finals)):
+        assert np.all(np.isfinite(mf)), i
+        assert np.allclose(np.linalg.norm(mf, axis=0), 1.0, atol=1e-12), i
+        assert 0 < res[i].iters <= cap, (i, res[i].iters)
+        assert res[i].status in (M.SADDLE, M.NOT_CONVERGED, M.DEGENERATE, M.HIGHER_INDEX), (i, res[i].status)
+        assert res[i].n_hvp > 0
+    pick = sorted({0, 255, int(np.random.default_rng(7).integers(1, 255))})
+    for i in pick:
+        L = Ls[i]
+        h = O.Ham(**p.with_size(L, L).asdict())
+        Eo = O.energy(h, finals[i])
+        assert abs(res[i].E - Eo) <= 1e-9 * abs(Eo), (i, L, res[i].E, Eo)
+        ro = O.min_modes(h, finals[i], 2, tol=1e-8, max_iter=800)
+        assert ro.converged
+        assert abs(res[i].lambda1 - ro.evals[0]) <= 1e-4 * h.h_est(), (i, L, res[i].lambda1, ro.evals[0])

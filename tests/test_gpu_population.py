@@ -187,3 +187,48 @@ def test_population_search_bad_arguments():
     with pytest.raises(M.MotoError):
         M.moto_saddle_search_population(plan, _dev(S.uniform(64))[None].contiguous(), M.MOTO_F64,
                                         opts=M.search_opts(M.MOTO_F64, k=20))
+
+
+def test_population_search_full_size_masked_128():
+    """The benchmark's masked lock-step workload at full size: 64 seeded
+    perturbed skyrmion / antiskyrmion / biskyrmion starts on 128x128, climb
+    confined to a disc of radius 8 around the core, k = 2, FP32 HVP, at most
+    300 outer steps.  Every member: finite unit spins, spins outside the
+    disc untouched, iterations within the cap.  Sampled members (the first
+    certified saddle and the first other member): the reported energy is
+    the oracle energy of the returned state and lambda_1 the oracle's lowest
+    masked tangent eigenvalue; at the saddle the oracle's masked force is
+    below tau_F and its tangent spectrum has exactly one negative
+    eigenvalue."""
+    M = _M()
+    L, P, cap, tau_F = 128, 64, 300, 1e-5
+    p = S.ham_3shell(L)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    spec = S.fixed_size_spec(P, L, seed=128)
+    starts = np.stack([S.batch_member(spec, i) for i in range(P)])
+    disc = S.random_mask_disc(L, L, 8.0)
+    mp = _dev(starts)
+    so = M.search_opts(M.MOTO_F32, tau_F=tau_F, k=2, k_cert=2, max_outer=cap, eig={"tol": 1e-5, "max_iter": 200})
+    res, ev, _ = M.moto_saddle_search_population(plan, mp, M.MOTO_F32, mask=_dev(np.stack([disc] * P), torch.uint8),
+                                                 opts=so)
+    fin = _np(mp)
+    off = disc == 0
+    for y in range(P):
+        assert np.all(np.isfinite(fin[y])), y
+        assert np.allclose(np.linalg.norm(fin[y], axis=0), 1.0, atol=1e-12), y
+        assert np.array_equal(fin[y][:, off], starts[y][:, off]), y
+        assert 0 < res[y].iters <= cap, (y, res[y].iters)
+    sad = [y for y in range(P) if res[y].status == M.SADDLE]
+    assert sad, "no certified saddle among the masked searches"
+    other = next(y for y in range(P) if res[y].status != M.SADDLE)
+    for y in (sad[0], other):
+        Eo, _, _, F = O.energy_grad(h, fin[y])
+        assert abs(res[y].E - Eo) <= 1e-9 * abs(Eo), (y, res[y].E, Eo)
+        ro = O.min_modes(h, fin[y], 2, tol=1e-10, max_iter=2000, mask=disc)
+        assert ro.converged
+        assert abs(res[y].lambda1 - ro.evals[0]) <= 1e-4 * h.h_est(), (y, res[y].lambda1, ro.evals[0])
+        if y == sad[0]:
+            fo = np.linalg.norm(F[:, disc != 0])
+            assert fo <= tau_F and abs(fo - res[y].fnorm) <= 1e-6 * tau_F, (fo, res[y].fnorm)
+            assert ro.evals[0] < -1e-3 < 1e-3 < ro.evals[1], ro.evals
