@@ -242,7 +242,7 @@ def main():
     out = {"metric": METRIC, "value": None, "unit": "Gsite/s", "n_gpus": 1, "note": "eigen-only profiling run"}
     if not args.eigen_only:
         print("[bench] autotuning the frame-layout HVP", file=sys.stderr, flush=True)
-        chosen, vtimes = M.moto_tangent_hvp_autotune(plan, m, c, V, W, batch=B, reps=3)
+        chosen, vtimes = M.moto_tangent_hvp_autotune(plan, m, c, V, W, batch=B, reps=10)
         vname = M.lib().moto_tangent_hvp_variant_name(chosen).decode()
         print(f"[bench] variants (ms): {vtimes} -> {vname}", file=sys.stderr, flush=True)
         print("[bench] timing batched tangent HVP", file=sys.stderr, flush=True)
