@@ -20,8 +20,8 @@ Headline (the 128x128 three-shell workload, FP32 HVP):
     (L-BFGS, and the nonlinear-CG outer rule on the same starts);
   * the FP64 CPU oracle timed on a bounded sample of the same HVP workload.
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
-one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the library and
+this benchmark run on one GPU.
 """
 import argparse
 import json
@@ -210,8 +210,8 @@ def main():
                     help="first run one plain device copy of this many MiB (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(the path would shard by independent lattices, see the design notes).", file=sys.stderr)
+        print("bench.py: runs on one GPU only; multi-GPU runs are not supported "
+              "(independent lattices would shard across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
 
     import torch
