@@ -72,23 +72,30 @@ __global__ __launch_bounds__(NT) void k_lz_init(int N, T* __restrict__ Q, const 
     if (threadIdx.x == 0) part[(size_t)blockIdx.x * LZP + LZ_MAXM + 1] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Partial dots of w = Q[j + 1] with Q[0..j]: wave w of a block takes the
-// columns c = w, w + 4, ...; lane l the rows start + l, start + l + 64, ...
+// Partial dots of w = Q[j + 1] with Q[0..j]: blockIdx.x picks the rows,
+// wave w of block (x, y) the column c = 4 y + w, so every column's rows are
+// read by its own wave in parallel; lane l takes the rows start + l,
+// start + l + 64, ... into two alternating partial sums (fixed order).
 template <class T>
 __global__ __launch_bounds__(NT) void k_lz_dots(int n2, const T* __restrict__ Q, int j, double* __restrict__ part,
                                                 const LzCtrl* __restrict__ ctrl) {
     if (ctrl->done || j >= ctrl->m_eff) return;
+    const int c = blockIdx.y * (NT / 64) + (threadIdx.x >> 6);
+    if (c > j) return;
     const int per = lz_rows_per_block(n2, gridDim.x);
     const int r0 = blockIdx.x * per, r1 = min(n2, r0 + per);
     const int lane = threadIdx.x & 63;
     const T* __restrict__ w = Q + (size_t)(j + 1) * n2;
-    for (int c = threadIdx.x >> 6; c <= j; c += NT / 64) {
-        const T* __restrict__ q = Q + (size_t)c * n2;
-        double s = 0.0;
-        for (int r = r0 + lane; r < r1; r += 64) s += (double)q[r] * (double)w[r];
-        s = wave_sum(s);
-        if (lane == 0) part[(size_t)blockIdx.x * LZP + c] = s;
+    const T* __restrict__ q = Q + (size_t)c * n2;
+    double s0 = 0.0, s1 = 0.0;
+    int r = r0 + lane;
+    for (; r + 64 < r1; r += 128) {
+        s0 += (double)q[r] * (double)w[r];
+        s1 += (double)q[r + 64] * (double)w[r + 64];
     }
+    if (r < r1) s0 += (double)q[r] * (double)w[r];
+    const double s = wave_sum(s0 + s1);
+    if (lane == 0) part[(size_t)blockIdx.x * LZP + c] = s;
 }
 
 // h_c = sum_b part[b][c] for c <= j (one wavefront per column).  pass 0
@@ -302,11 +309,12 @@ hipError_t launch_lz_init(bool f64, int N, void* Q, const double* m, const doubl
 // normalise it, record beta.
 hipError_t launch_lz_orth(bool f64, int n2, void* Q, int j, double* part, int nblk, LzCtrl* ctrl, hipStream_t st) {
     const int rb = (j + 1 + NT / 64 - 1) / (NT / 64);
+    const int cg = rb < 1 ? 1 : rb;  // column groups of the dot kernel (one column per wave)
     for (int pass = 0; pass < 2; ++pass) {
         if (f64)
-            hipLaunchKernelGGL(k_lz_dots<double>, dim3(nblk), dim3(NT), 0, st, n2, (const double*)Q, j, part, ctrl);
+            hipLaunchKernelGGL(k_lz_dots<double>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const double*)Q, j, part, ctrl);
         else
-            hipLaunchKernelGGL(k_lz_dots<float>, dim3(nblk), dim3(NT), 0, st, n2, (const float*)Q, j, part, ctrl);
+            hipLaunchKernelGGL(k_lz_dots<float>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const float*)Q, j, part, ctrl);
         hipLaunchKernelGGL(k_lz_reduce, dim3(rb < 1 ? 1 : rb), dim3(NT), 0, st, part, nblk, j, pass, ctrl);
         if (f64)
             hipLaunchKernelGGL(k_lz_update<double>, dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, j, pass, part,

@@ -32,12 +32,29 @@
 namespace moto {
 
 constexpr int RCH = 64;                              // rows per staged chunk
+static_assert(RCH % 4 == 0, "dot_chunk takes four rows per step");
 constexpr int GENT = 2 * MAXS * (MAXS + 1) / 2;      // Gram entries (upper triangles of 2 matrices)
 constexpr int GQ = (GENT + NT - 1) / NT;             // entries per thread
 constexpr int OENT = MAXS * MAXB;                    // orthonormalisation Gram entries
 constexpr int OQ = (OENT + NT - 1) / NT;
 constexpr int PSTRIDE = GENT;                        // doubles per block partial row
 constexpr int RED_BLOCKS = 64;                       // workgroups of the partial-row reduction
+
+// FP64 dot product of two staged chunks (RCH rows) with four interleaved
+// partial sums, so the chain of dependent adds is RCH / 4 long; the order is
+// fixed, so the result is reproducible
+template <class T>
+__device__ __forceinline__ double dot_chunk(const T* __restrict__ x, const T* __restrict__ y) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 4
+    for (int rr = 0; rr < RCH; rr += 4) {
+        s0 += (double)x[rr] * (double)y[rr];
+        s1 += (double)x[rr + 1] * (double)y[rr + 1];
+        s2 += (double)x[rr + 2] * (double)y[rr + 2];
+        s3 += (double)x[rr + 3] * (double)y[rr + 3];
+    }
+    return (s0 + s1) + (s2 + s3);
+}
 
 __device__ __forceinline__ int sol_ns(const EigArgs& a, const EigCtrl* ctrl, int ns_fixed) {
     return ns_fixed >= 0 ? ns_fixed : 2 * a.mb + ctrl->np;
@@ -149,9 +166,7 @@ __global__ __launch_bounds__(NT) void k_orth_gram(EigArgs a, int target, const T
                 const int j = e / nrow, i = e % nrow;
                 const T* x = ts[i];
                 const T* y = ts[oc.nq + j];
-                double s = 0.0;
-                for (int rr = 0; rr < RCH; ++rr) s += (double)x[rr] * (double)y[rr];
-                acc[q] += s;
+                acc[q] += dot_chunk(x, y);
             }
         }
     }
@@ -301,9 +316,7 @@ __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* _
             if (threadIdx.x + q * NT < E) {
                 const T* x = ts[ei[q]];
                 const T* y = ew[q] ? ts[ej[q]] : th[ej[q]];
-                double sacc = 0.0;
-                for (int rr = 0; rr < RCH; ++rr) sacc += (double)x[rr] * (double)y[rr];
-                acc[q] += sacc;
+                acc[q] += dot_chunk(x, y);
             }
         }
     }
@@ -584,7 +597,7 @@ __global__ void k_eig_out3(int k, int N, int P, long long part_ms, double* __res
 // --------------------------------------------------------------------------
 int gram_blocks(int n2) {
     const int nch = (n2 + RCH - 1) / RCH;
-    return nch < 128 ? nch : 128;
+    return nch < 256 ? nch : 256;
 }
 
 int update_blocks(int n2) {
