@@ -283,9 +283,11 @@ __global__ __launch_bounds__(NT) void k_lz_restart(int n2, T* __restrict__ Q, Lz
 }
 
 // --------------------------------------------------------------------------
+// one row per thread up to 1024 workgroups: the row kernels walk the basis
+// columns with one load each, so their time grows with the rows a thread has
 int lz_blocks(int n2) {
-    const int nb = (n2 + 4 * NT - 1) / (4 * NT);
-    return nb < 1 ? 1 : (nb > 512 ? 512 : nb);
+    const int nb = (n2 + NT - 1) / NT;
+    return nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
 }
 
 hipError_t launch_lz_init(bool f64, int N, void* Q, const double* m, const double* Vwarm, int nwarm,
