@@ -184,6 +184,54 @@ def cpu_baseline_all_cores(L, nvec, budget_s=12.0, n_distinct=32, seed=2025):
     return n_done, el, ncores, wall
 
 
+def _cpu_search_worker(args):
+    """One host process of the oracle search baseline: the FP64 oracle climb
+    (k = 2, tau_F = 1e-5) from one seeded 128x128 start of the lock-step
+    search leg, for a bounded number of outer steps."""
+    wid, L, n, max_outer = args
+    sys.path.insert(0, ROOT)
+    import oracle as O
+    from paper_2509_26269_amd import synth as S
+
+    h = O.Ham(**S.ham_3shell(L).asdict())
+    m0 = S.batch_member(S.fixed_size_spec(n, L, seed=128), wid)
+    t0 = time.perf_counter()
+    r = O.saddle_search(h, m0, tau_F=1e-5, k=2, eig_tol=1e-5, max_outer=max_outer)
+    return r.iters, time.perf_counter() - t0
+
+
+def cpu_search_all_cores(L, max_outer, n_starts=64):
+    """Oracle climbs from the first `cores` starts, one single-threaded
+    process per core (spawned, cores capped at 16): outer iterations per
+    second."""
+    import multiprocessing as mp
+
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncores = os.cpu_count() or 1
+    ncores = max(1, min(ncores, 16, n_starts))
+    # one BLAS / OpenMP thread per worker process: the oracle's dense steps
+    # would otherwise start a thread per core in every process
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(ncores) as pool:
+            res = pool.map(_cpu_search_worker, [(w, L, n_starts, max_outer) for w in range(ncores)])
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    its = sum(r[0] for r in res)
+    el = max(r[1] for r in res)
+    return its, el, ncores
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +399,59 @@ def main():
                                 "workspace_bytes": wsl.nbytes}
         extra["lanczos_128_k4"] = lz
         extra["lobpcg_128_k4_lambda"] = [round(float(x), 6) for x in r.evals.cpu()]
+    c0_gpu = {}
+    if not args.hvp_only and not args.eigen_only:
+        # the plain method on the 16x16 nearest-neighbour model, FP64: one
+        # search per seed to ||F|| < 1e-6 with k = 1, certified with k = 2;
+        # R = 3 starts (seeds 0-7) and the R = 1 collapse starts (seeds 0-7)
+        print("[bench] 16x16 plain-method searches (FP64)", file=sys.stderr, flush=True)
+        p0 = S.ham_nn(16)
+        plan0 = M.Plan.from_params(p0)
+        so0 = M.search_opts(M.MOTO_F64, tau_F=1e-6, k=1, k_cert=2)
+        for tag, R in (("R3", 3.0), ("R1", 1.0)):
+            rows = []
+            for sd in range(8):
+                m0h = S.add_tilt_noise(S.skyrmion(16, 16, R), 0.05, np.random.default_rng(sd))
+                md = torch.as_tensor(m0h, device="cuda")
+                E0, _, _, _, _ = M.moto_energy_grad(plan0, md, want_grad=False, want_F=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r0, _, _ = M.moto_saddle_search(plan0, md, M.MOTO_F64, opts=so0)
+                torch.cuda.synchronize()
+                rows.append((time.perf_counter() - t0, r0, float(E0)))
+            hist = {}
+            for _, r0, _ in rows:
+                hist[M.STATUS_NAMES[r0.status]] = hist.get(M.STATUS_NAMES[r0.status], 0) + 1
+            c0_gpu[tag] = rows
+            extra[f"plain_16x16_{tag}_f64"] = {
+                "searches": 8, "median_ms": round(1e3 * float(np.median([t for t, _, _ in rows])), 2),
+                "mean_outer_iters": round(float(np.mean([r0.iters for _, r0, _ in rows])), 1),
+                "mean_hvp": round(float(np.mean([r0.n_hvp for _, r0, _ in rows])), 1),
+                "status": hist,
+                "seed0": {"lambda": [rows[0][1].lambda1, rows[0][1].lambda2],
+                          "dE": rows[0][1].E - rows[0][2], "iters": rows[0][1].iters}}
+        del plan0
+    if not args.hvp_only and not args.eigen_only and args.large:
+        # tangent HVP at 512x512: one state with the 24-column block of a
+        # k = 8 solve (L2/MALL-resident), and 16 states x 4 vectors (335 MB,
+        # beyond the 256 MB MALL)
+        print("[bench] 512x512 tangent HVP bandwidth", file=sys.stderr, flush=True)
+        L2 = 512
+        plan5 = M.Plan.from_params(S.ham_3shell(L2))
+        h5 = {}
+        for tag, nb5, nv5 in (("one_state_24vec", 1, 24), ("batch16_4vec", 16, 4)):
+            m5, c5, V5, W5, _ = hvp_inputs(M, S, torch, plan5, L2, nb5, nv5, n_distinct=min(nb5, 4))
+            M.moto_tangent_hvp_autotune(plan5, m5, c5, V5, W5, batch=nb5, reps=5)
+            _, per5, _ = time_hvp(M, torch, plan5, m5, c5, V5, W5, nb5, 20, 5)
+            t5 = float(np.median(per5)) * 1e-3
+            b5 = (12 + 16 * nv5) * L2 * L2 * nb5
+            h5[tag] = {"ms": round(1e3 * t5, 4), "Gsite_vectors_per_s": round(nb5 * L2 * L2 * nv5 / t5 / 1e9, 2),
+                       "GBps_alg": round(b5 / t5 / 1e9, 1), "frac_of_8TBps": round(b5 / t5 / 8e12, 3),
+                       "footprint_MB": round((b5 + 4 * L2 * L2 * nb5) / 1e6, 1)}
+            del m5, c5, V5, W5
+        extra["hvp_512"] = h5
+        del plan5
+        torch.cuda.empty_cache()
     if not args.hvp_only and not args.eigen_only and args.large:
         # 512x512 with two skyrmions (Q = 2), k = 8: the size where a dense
         # tangent Hessian (2N)^2 FP64 = 2.2 TB is out of reach
@@ -635,6 +736,31 @@ def main():
             "value_1core": round(n1 * N / el1 / 1e9, 6),
             "sample_1core": f"{n1} HVPs in {el1:.1f} s on one core",
         }
+    if not args.hvp_only and not args.eigen_only and not args.no_cpu:
+        import oracle as O
+
+        if c0_gpu:
+            # the oracle on seed 0 of each 16x16 start family (host process)
+            h0 = O.Ham(**S.ham_nn(16).asdict())
+            for tag, R in (("R3", 3.0), ("R1", 1.0)):
+                m0h = S.add_tilt_noise(S.skyrmion(16, 16, R), 0.05, np.random.default_rng(0))
+                t0 = time.perf_counter()
+                ro = O.saddle_search(h0, m0h, tau_F=1e-6, k=1)
+                el0 = time.perf_counter() - t0
+                rg = c0_gpu[tag][0][1]
+                extra[f"plain_16x16_{tag}_f64"]["oracle_seed0"] = {
+                    "s": round(el0, 2), "status": int(ro.status), "iters": int(ro.iters),
+                    "gpu_status_matches": int(rg.status) == int(ro.status),  # same status codes
+                    "dE_gpu_vs_oracle": abs(rg.E - ro.E)}
+        if args.batched > 0:
+            # the oracle climb on the first starts of the 128x128 search legs,
+            # all host cores, 3 outer steps each (a bounded sample)
+            print("[bench] CPU oracle searches on 128x128 (all cores, 3 outer steps each)", file=sys.stderr,
+                  flush=True)
+            its, elc, ncs = cpu_search_all_cores(L, 3)
+            extra["oracle_search_128"] = {"outer_iters_per_s": round(its / elc, 3), "cores": ncs,
+                                          "sample": f"{ncs} starts x 3 outer steps (+ certification), "
+                                                    f"{its} outer steps in {elc:.1f} s"}
     out["extra"] = extra
     print(json.dumps(out), flush=True)
 

@@ -886,7 +886,7 @@ const char* hvp_variant_name(int v) { return (v >= 0 && v < HVP_NVARIANTS) ? kNa
 // that does not overlap itself
 // the march's store range is 32-bit: a vector group's slice (at most 4
 // FP64 vectors x 2 coordinates) must stay below 2^31 bytes
-static bool march_fits(const Geo& g) { return g.Lx >= 4 && g.Lx <= 256 && (long long)g.N * 64 < (1LL << 31); }
+static bool march_fits(const Geo& g) { return g.Lx >= 4 && g.Lx <= 512 && (long long)g.N * 64 < (1LL << 31); }
 
 // the paired march also needs an even width (aligned column pairs)
 static bool march2_fits(const Geo& g) { return march_fits(g) && (g.Lx % 2) == 0; }
@@ -917,12 +917,13 @@ static void go_band(const Geo& g, const CoefD& kd, int batch, const void* m, con
                        (const T*)m, (const T*)c, mask, nvec, vbs, (const T*)V, (T*)W, done, tx, ty);
 }
 
-// strips per lattice: about 1024 workgroups in all (one resident round at
-// the march kernels' occupancy), strips of at least 8 rows (the 4 halo rows
-// of a strip are read twice)
-static int march_strips(const Geo& g, int batch, int ngroups) {
+// strips per lattice: about `target` workgroups in all (one resident round
+// at the march kernels' occupancy: 1024 of up to 256 threads, 256 of the
+// 512-thread rows), strips of at least 8 rows (the 4 halo rows of a strip
+// are read twice)
+static int march_strips(const Geo& g, int batch, int ngroups, int target) {
     const long long have = (long long)batch * ngroups;
-    const int want = (int)((1024 + have - 1) / have);
+    const int want = (int)((target + have - 1) / have);
     return max(1, min(want, max(1, g.Ly / 8)));
 }
 
@@ -930,7 +931,7 @@ template <class T, int NVP, int XW>
 static void go_march_xw(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c,
                         const uint8_t* mask, int nvec, long long vbs, const void* V, void* W, const int* done, hipStream_t st) {
     const int ngroups = (nvec + NVP - 1) / NVP;
-    const int nstrip = march_strips(g, batch, ngroups);
+    const int nstrip = march_strips(g, batch, ngroups, XW > 256 ? 256 : 1024);
     if (mask)
         hipLaunchKernelGGL((k_hvp_march<T, NVP, XW, true>), dim3(batch * nstrip * ngroups), dim3(XW), 0, st, g,
                            coef_cast<T>(kd), (const T*)m, (const T*)c, mask, nvec, vbs, (const T*)V, (T*)W, done,
@@ -948,15 +949,17 @@ static void go_march(const Geo& g, const CoefD& kd, int batch, const void* m, co
         go_march_xw<T, NVP, 64>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
     else if (g.Lx <= 128)
         go_march_xw<T, NVP, 128>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
-    else
+    else if (g.Lx <= 256)
         go_march_xw<T, NVP, 256>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
+    else
+        go_march_xw<T, NVP, 512>(g, kd, batch, m, c, mask, nvec, vbs, V, W, done, st);
 }
 
 template <class T, int NVP>
 static void go_march2(const Geo& g, const CoefD& kd, int batch, const void* m, const void* c, const uint8_t* mask,
                       int nvec, long long vbs, const void* V, void* W, const int* done, hipStream_t st) {
     const int ngroups = (nvec + NVP - 1) / NVP;
-    const int nstrip = march_strips(g, batch, ngroups);
+    const int nstrip = march_strips(g, batch, ngroups, g.Lx > 256 ? 256 : 1024);
     const dim3 grid(batch * nstrip * ngroups);
     auto launch = [&](auto ntc) {
         constexpr int NT2 = decltype(ntc)::value;
@@ -969,8 +972,10 @@ static void go_march2(const Geo& g, const CoefD& kd, int batch, const void* m, c
     };
     if (g.Lx <= 128)
         launch(std::integral_constant<int, 64>{});
-    else
+    else if (g.Lx <= 256)
         launch(std::integral_constant<int, 128>{});
+    else
+        launch(std::integral_constant<int, 256>{});
 }
 
 template <class T>

@@ -194,7 +194,8 @@ def test_bad_arguments_rejected():
                            torch.zeros(1, 2, 64, dtype=torch.float64, device="cuda"), layout=7)
 
 
-@pytest.mark.parametrize("Lx,Ly", [(128, 16), (37, 23), (5, 7), (200, 9), (4, 5), (64, 1), (3, 3)])
+@pytest.mark.parametrize("Lx,Ly", [(128, 16), (37, 23), (5, 7), (200, 9), (4, 5), (64, 1), (3, 3), (320, 12),
+                                   (301, 5), (512, 6)])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_every_frame_hvp_variant_matches_oracle(Lx, Ly, dt):
     """The autotuner may pick any frame-layout variant: each one, pinned in
