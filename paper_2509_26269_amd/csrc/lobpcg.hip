@@ -595,9 +595,13 @@ __global__ void k_eig_out3(int k, int N, int P, long long part_ms, double* __res
 // --------------------------------------------------------------------------
 // Launchers
 // --------------------------------------------------------------------------
+// workgroups of the Gram kernels: up to 256, and up to 1024 for bases of
+// more than 2^18 rows, where a workgroup would otherwise walk hundreds of
+// chunks one after another (the partial rows grow with the count)
 int gram_blocks(int n2) {
     const int nch = (n2 + RCH - 1) / RCH;
-    return nch < 256 ? nch : 256;
+    const int cap = n2 > (1 << 18) ? 1024 : 256;
+    return nch < cap ? nch : cap;
 }
 
 int update_blocks(int n2) {
