@@ -596,8 +596,9 @@ __global__ void k_eig_out3(int k, int N, int P, long long part_ms, double* __res
 // Launchers
 // --------------------------------------------------------------------------
 // workgroups of the Gram kernels: up to 256, and up to 1024 for bases of
-// more than 2^18 rows, where a workgroup would otherwise walk hundreds of
-// chunks one after another (the partial rows grow with the count)
+// more than 2^18 rows, where each of 256 workgroups would walk 16 or more
+// RCH-row chunks one after another (128 on a 1024x1024 lattice); the
+// partial-row workspace is sized from this count
 int gram_blocks(int n2) {
     const int nch = (n2 + RCH - 1) / RCH;
     const int cap = n2 > (1 << 18) ? 1024 : 256;
