@@ -233,6 +233,11 @@ __global__ __launch_bounds__(NT) void k_orth_apply(EigArgs a, int target, T* __r
     __syncthreads();
     const int mb = a.mb, nq = oc.nq;
     for (int r = blockIdx.x * NT + threadIdx.x; r < a.n2; r += gridDim.x * NT) {
+        // at the widest bucket, keep the compiler from hoisting the LDS
+        // coefficients (B: 2 MB x MB, Tw: MB x MB doubles) out of the row
+        // loop into registers: that runs at the register limit and spills
+        // to scratch; re-reading them from LDS per row does not
+        if constexpr (MB > 8) asm volatile("" ::: "memory");
         double q[2 * MB], u[MB];
 #pragma unroll
         for (int i = 0; i < 2 * MB; ++i)
