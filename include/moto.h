@@ -89,7 +89,7 @@ typedef int32_t moto_status;
 /* outcome codes reported in the result structs (device-detected) */
 #define MOTO_SADDLE 0        /* certified index-1 saddle (lambda_1 < -tau < tau < lambda_2) */
 #define MOTO_CONVERGED 0     /* eigen-solve: all k residuals below tolerance */
-#define MOTO_NOT_CONVERGED 1 /* iteration cap reached */
+#define MOTO_NOT_CONVERGED 1 /* iteration cap reached (or an unconverged certifying solve) */
 #define MOTO_DEGENERATE 2    /* |lambda_1| or |lambda_2| within tau of zero */
 #define MOTO_HIGHER_INDEX 3  /* lambda_2 < -tau */
 #define MOTO_NAN 4           /* non-finite value met */
@@ -327,23 +327,33 @@ moto_status moto_descend(moto_plan p, moto_dtype hvp, double *m, const double *v
 
 /* ---------------------------------------------------------------------
  * Second inner solver: the k smallest eigenpairs of the (masked) tangent
- * Hessian by thick-restart Lanczos with full reorthogonalisation (Results,
- * "Bilayer MMF": HVP-Lanczos as the alternative Krylov solver; Discussion:
- * Krylov depth and reorthogonalisation are the solver's hyperparameters).
- * One HVP per step; each new Krylov vector is orthogonalised against the
- * whole basis twice (classical Gram-Schmidt, FP64 coefficients); after
- * m_max steps one wavefront diagonalises the projected matrix in FP64 and
- * the solve either stops (every residual estimate |beta_m y_m,i|, i < k, at
- * most tol * moto_hessian_norm_bound) or restarts from the `keep` lowest
- * Ritz vectors and the residual direction.  Same arguments, outputs,
- * stopping rule and sign rule as moto_min_modes; info->iters counts
- * restarts.  The cycles after the first are replayed as a HIP graph.  A
- * single-vector Krylov space holds one direction per eigenspace: of an
- * exactly degenerate cluster it returns one copy (further copies only appear
- * through rounding); moto_min_modes resolves multiplicities.
- *   m_max   Krylov depth, 3 <= m_max <= 64 and m_max < 2N
- *   keep    Ritz vectors kept at a restart, k <= keep < m_max (0: max(k + 2, m_max / 2))
- *   warm    1: start from the sum of the k vectors in V (ambient FP64)
+ * Hessian by thick-restart band Lanczos with full reorthogonalisation
+ * (Results, "Bilayer MMF": HVP-Lanczos as the alternative Krylov solver;
+ * Discussion: Krylov depth and reorthogonalisation are the solver's
+ * hyperparameters).  The Krylov space grows from a block of `block`
+ * orthonormal start vectors (Ruhe's band Lanczos): step j applies one HVP to
+ * basis vector j and orthogonalises the image against the whole basis twice
+ * (classical Gram-Schmidt, FP64 coefficients).  After m_max steps one
+ * wavefront diagonalises the projected matrix in FP64 and the solve either
+ * stops (every residual norm |T[m..m+b)[0..m) y_i|, i < k, at most tol *
+ * moto_hessian_norm_bound) or restarts from the `keep` lowest Ritz vectors
+ * and the residual block.  A single start vector (block = 1) may leave the
+ * second member of a close eigenvalue pair out of the space after the first
+ * has met the stopping rule, and holds one direction per exactly degenerate
+ * eigenspace; a block of b vectors brings up to b such directions in
+ * together.  A breakdown (a new Krylov vector of negligible norm) ends the
+ * cycle; the solve never reports CONVERGED with fewer than k Ritz pairs, and
+ * the restart replaces the dependent direction by a fresh random one.  Same
+ * arguments, outputs, stopping rule and sign rule as moto_min_modes;
+ * info->iters counts restarts; MOTO_BREAKDOWN if the start block has no
+ * independent direction.  The cycles after the first are replayed as a HIP
+ * graph.
+ *   m_max   Krylov depth, 3 <= m_max <= 64 and m_max + block <= 2N
+ *   keep    Ritz vectors kept at a restart, k <= keep <= m_max - block
+ *           (0: max(k + 2, m_max / 2))
+ *   block   start-block size b, 1..4 (0: 2)
+ *   warm    1: the first start vector is the sum of the k vectors in V
+ *           (ambient FP64), the others random
  * k <= 16.  Errors: MOTO_EINVAL for out-of-range sizes or options,
  * MOTO_EWORKSPACE if ws is NULL or short, MOTO_EHIP on a runtime error.
  * Workspace: moto_min_modes_lanczos_workspace(p, hvp, m_max) bytes. */
@@ -353,9 +363,9 @@ typedef struct {
     int32_t keep;         /* default 0 = max(k + 2, m_max / 2) */
     int32_t max_restarts; /* default 200 */
     int32_t warm;         /* default 0 */
-    uint64_t seed;        /* start vector when not warm */
+    uint64_t seed;        /* start block when not warm */
     int32_t use_graph;    /* default 1 */
-    int32_t reserved;
+    int32_t block;        /* start-block size, default 0 = 2 */
 } moto_lanczos_opts;
 
 void moto_default_lanczos_opts(moto_dtype hvp, moto_lanczos_opts *o);
@@ -370,7 +380,10 @@ moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double *m,
  * loop).  Repeat {energy_grad; min_modes(k, warm-started); reflected_step}
  * until ||F_mmf||_2 <= tau_F, then certify with a k_cert >= 2 solve:
  * MOTO_SADDLE if lambda_1 < -tau_lam and lambda_2 > tau_lam, else
- * MOTO_HIGHER_INDEX / MOTO_DEGENERATE; MOTO_NOT_CONVERGED after max_outer.
+ * MOTO_HIGHER_INDEX / MOTO_DEGENERATE; MOTO_NOT_CONVERGED after max_outer,
+ * and also when the certifying solve itself stops unconverged (its Ritz
+ * values only bound the eigenvalues from above, so they cannot exclude a
+ * second negative mode).
  *   m    [3][N] FP64: start in, final point out
  *   evals_out [k_cert] FP64 device (or NULL), V_out [k_cert][3][N] FP64 device (or NULL) */
 typedef struct {

@@ -493,72 +493,108 @@ def min_modes(ham: Ham, m, k: int, tol: float = 1e-10, max_iter: int = 200,
 
 
 # ---------------------------------------------------------------------------
-# Inner layer, second solver: thick-restart Lanczos with full
+# Inner layer, second solver: thick-restart band Lanczos with full
 # reorthogonalisation (the paper's HVP-Lanczos operator mode; the Krylov depth
-# and the reorthogonalisation are its named hyperparameters).  The projected
-# matrix is accumulated column by column from the reorthogonalisation
-# coefficients, so after a restart it holds the kept Ritz values and their
-# coupling to the residual direction (Wu & Simon 2000).  Parity: pinned
-# against Jacobi, the ferromagnet closed form and the LOBPCG oracle.
+# and the reorthogonalisation are its named hyperparameters).  A start block of
+# b orthonormal vectors; step j applies the operator to basis vector j and
+# orthogonalises the image against every vector so far (the band Lanczos of
+# Ruhe 1979), so the Krylov space grows from b directions at once and a split
+# pair of eigenvalues enters it as fast as a single one (a single start vector
+# can leave the second member of a close pair out of the space long after the
+# first has converged).  The projected matrix is accumulated column by column
+# from the reorthogonalisation coefficients, so after a restart it holds the
+# kept Ritz values and their couplings to the residual block (Wu & Simon
+# 2000).  Parity: pinned against Jacobi, the ferromagnet closed form and the
+# LOBPCG oracle.
 # ---------------------------------------------------------------------------
-def lanczos(op, v0, k: int, tol_abs: float, m_max: int = 32, keep: Optional[int] = None,
-            max_restarts: int = 100):
+def lanczos(op, V0, k: int, tol_abs: float, m_max: int = 32, keep: Optional[int] = None,
+            max_restarts: int = 100, fresh=None):
     """k smallest eigenpairs of the symmetric operator op (applied to one
-    vector).  Returns (theta[:keep], Y-rotated basis X[:, :keep], residual
-    norms, restarts, n_hvp, converged)."""
-    n = v0.shape[0]
+    vector), from the start block V0 (n, b) (a single vector (n,) is a block
+    of one).  fresh() returns a new random vector for a direction the Krylov
+    space can no longer supply.  Returns (theta[:keep], Ritz vectors
+    X[:, :keep], residual norms, restarts, n_hvp, converged)."""
+    V0 = np.asarray(V0, dtype=np.float64)
+    if V0.ndim == 1:
+        V0 = V0[:, None]
+    n, b = V0.shape
     if keep is None:
         keep = max(k + 2, m_max // 2)
-    assert k <= keep < m_max
-    Q = np.zeros((n, m_max + 1))
-    T = np.zeros((m_max + 1, m_max + 1))
-    Q[:, 0] = v0 / np.linalg.norm(v0)
+    assert k <= keep and keep + b <= m_max
+    if fresh is None:
+        rng = np.random.default_rng(12345)
+        fresh = lambda: rng.standard_normal(n)  # noqa: E731
+    Q = np.zeros((n, m_max + b))
+    T = np.zeros((m_max + b, m_max + b))
+
+    def put(c, v):
+        """Column c <- v orthogonalised twice against columns 0..c-1 and
+        normalised; a dependent v is replaced by fresh random directions."""
+        for _ in range(8):
+            for _ in range(2):
+                v = v - Q[:, :c] @ (Q[:, :c].T @ v)
+            nv = float(np.linalg.norm(v))
+            if nv > 1e-8:
+                Q[:, c] = v / nv
+                return
+            v = fresh()
+        raise RuntimeError("no independent direction left")
+
+    for l in range(b):
+        put(l, V0[:, l] / max(np.linalg.norm(V0[:, l]), 1e-300))
     j0 = 0
     n_hvp = 0
     restarts = 0
     while True:
         m = m_max
         for j in range(j0, m_max):
+            c = j + b
             w = op(Q[:, j])
             n_hvp += 1
-            h = Q[:, : j + 1].T @ w          # classical Gram-Schmidt, twice
-            w = w - Q[:, : j + 1] @ h
-            h2 = Q[:, : j + 1].T @ w
-            w = w - Q[:, : j + 1] @ h2
+            h = Q[:, :c].T @ w              # classical Gram-Schmidt, twice
+            w = w - Q[:, :c] @ h
+            h2 = Q[:, :c].T @ w
+            w = w - Q[:, :c] @ h2
             h = h + h2
-            T[: j + 1, j] = h                # column j of Q^T H Q
-            T[j, : j + 1] = h
-            beta = np.linalg.norm(w)
-            T[j + 1, j] = T[j, j + 1] = beta
-            if beta <= 1e-14 * max(1.0, abs(h[j])):   # invariant subspace
+            T[:c, j] = h                    # column j of Q^T H Q
+            T[j, :c] = h
+            beta = float(np.linalg.norm(w))
+            T[c, j] = T[j, c] = beta
+            if beta <= 1e-14 * max(1.0, abs(h[j])):   # the block Krylov space is invariant
                 m = j + 1
-                beta = 0.0
                 break
-            Q[:, j + 1] = w / beta
+            Q[:, c] = w / beta
         theta, Y = np.linalg.eigh(T[:m, :m])
-        rn = np.abs(T[m, m - 1] * Y[m - 1, :]) if m == m_max else np.zeros(m)
-        if np.all(rn[:k] <= tol_abs) or restarts >= max_restarts or m < m_max:
-            X = Q[:, :m] @ Y[:, :keep]
-            return theta[:keep], X, rn[:keep], restarts, n_hvp, bool(np.all(rn[:k] <= tol_abs))
-        # thick restart: the `keep` lowest Ritz vectors and the residual direction
+        # H Q_m Y - Q_m Y diag(theta) = Q[:, m:m+b] T[m:m+b, :m] Y
+        rn = np.linalg.norm(T[m:m + b, :m] @ Y, axis=0)
+        conv = m >= k and bool(np.all(rn[:k] <= tol_abs))
+        kk = min(keep, m)
+        if conv or restarts >= max_restarts:
+            X = Q[:, :m] @ Y[:, :kk]
+            return theta[:kk], X, rn[:kk], restarts, n_hvp, conv
+        # thick restart: the kk lowest Ritz vectors and the residual block
+        # (re-orthonormalised; after a breakdown its dependent last column is
+        # a fresh direction)
         restarts += 1
-        bm = T[m, m - 1]
-        Xk = Q[:, :m] @ Y[:, :keep]
-        qn = Q[:, m].copy()
+        Xk = Q[:, :m] @ Y[:, :kk]
+        Rb = Q[:, m:m + b].copy()
+        if m < m_max:
+            Rb[:, b - 1] = fresh()
         Q[:] = 0.0
-        Q[:, :keep] = Xk
-        Q[:, keep] = qn
+        Q[:, :kk] = Xk
+        for l in range(b):
+            put(kk + l, Rb[:, l])
         T[:] = 0.0
-        T[np.arange(keep), np.arange(keep)] = theta[:keep]
-        T[keep, :keep] = T[:keep, keep] = bm * Y[m - 1, :keep]
-        j0 = keep
+        T[np.arange(kk), np.arange(kk)] = theta[:kk]
+        j0 = kk
 
 
 def min_modes_lanczos(ham: Ham, m, k: int, tol: float = 1e-10, m_max: int = 32, keep: Optional[int] = None,
-                      max_restarts: int = 100, mask=None, seed: int = 0, c=None) -> EigResult:
+                      max_restarts: int = 100, mask=None, seed: int = 0, c=None, block: int = 2) -> EigResult:
     """k smallest eigenpairs of the (masked) tangent Hessian by FP64
-    thick-restart Lanczos in frame coordinates; same stopping rule and
-    output conventions as min_modes."""
+    thick-restart band Lanczos (start block of `block` random vectors) in
+    frame coordinates; same stopping rule and output conventions as
+    min_modes."""
     m = _f64(m).reshape(3, ham.N)
     N = ham.N
     if c is None:
@@ -577,10 +613,16 @@ def min_modes_lanczos(ham: Ham, m, k: int, tol: float = 1e-10, m_max: int = 32, 
         out[N:][~act] = 0.0
         return out
 
-    v0 = np.random.default_rng(seed).standard_normal(2 * N)
-    v0[:N][~act] = 0.0
-    v0[N:][~act] = 0.0
-    lam, X, rn, it, n_hvp, conv = lanczos(op, v0, k, tol * ham.h_est(), m_max, keep, max_restarts)
+    rng = np.random.default_rng(seed)
+
+    def fresh():
+        v = rng.standard_normal(2 * N)
+        v[:N][~act] = 0.0
+        v[N:][~act] = 0.0
+        return v
+
+    V0 = np.stack([fresh() for _ in range(block)], axis=1)
+    lam, X, rn, it, n_hvp, conv = lanczos(op, V0, k, tol * ham.h_est(), m_max, keep, max_restarts, fresh)
     a = X[:, :k].T.reshape(k, 2, N)
     V = np.stack([sign_fix(a[j, 0] * e1 + a[j, 1] * e2) for j in range(k)])
     V = V / np.linalg.norm(V.reshape(k, -1), axis=1)[:, None, None]
@@ -730,22 +772,43 @@ class SearchResult:
     trace: list
 
 
-def certify(evals, tau_lam: float) -> int:
-    """Index-1 signature lambda_1 < 0 < lambda_2 with tolerance tau_lam."""
+def certify(evals, tau_lam: float, converged: bool = True, n_negative: Optional[int] = None) -> int:
+    """Index-1 signature lambda_1 < 0 < lambda_2 with tolerance tau_lam
+    (Supplementary Note 1, item ii).  The two eigenvalues must come from a
+    converged solve: an unconverged Ritz value only bounds its eigenvalue
+    from above, so lambda_2 > tau_lam would not exclude a second negative
+    mode -- such a point is NOT_CONVERGED.  n_negative, when given, is the
+    exact count of tangent eigenvalues below -tau_lam (dense inertia); more
+    than one makes the point HIGHER_INDEX whatever the two Ritz values say."""
     l1, l2 = float(evals[0]), float(evals[1])
     if not (np.isfinite(l1) and np.isfinite(l2)):
         return NAN_STATUS
+    if not converged:
+        return NOT_CONVERGED
+    if n_negative is not None and n_negative >= 2:
+        return HIGHER_INDEX
     if l1 < -tau_lam and l2 > tau_lam:
-        return SADDLE
+        return SADDLE if n_negative is None or n_negative == 1 else DEGENERATE
     if l2 < -tau_lam:
         return HIGHER_INDEX
     return DEGENERATE
 
 
+DENSE_INERTIA_MAX_DOF = 2048   # tangent DOF up to which certification also counts negatives exactly
+
+
+def negative_count(ham: Ham, m, tau_lam: float, mask=None) -> int:
+    """Number of eigenvalues of the dense (masked) tangent Hessian below
+    -tau_lam: the exact inertia the certification criterion asks for."""
+    w = np.linalg.eigvalsh(dense_tangent_hessian(ham, m, mask=mask))
+    return int((w < -tau_lam).sum())
+
+
 def saddle_search(ham: Ham, m0, tau_F: float = 1e-6, k: int = 1, k_cert: int = 2,
                   eig_tol: float = 1e-10, eig_max_iter: int = 200, tau_lam: Optional[float] = None,
                   max_outer: int = 5000, rule: Optional[StepRule] = None, mask=None,
-                  k_reflect: int = 1, seed: int = 0, trace: bool = False) -> SearchResult:
+                  k_reflect: int = 1, seed: int = 0, trace: bool = False,
+                  cert_max_iter: Optional[int] = None) -> SearchResult:
     """Bilayer MMF climb (Supplementary Note 1, Algorithm 1, bilayer-kernel
     loop): min mode -> force -> reflected force -> rotation step, until
     ||F_mmf||_2 <= tau_F; then a k_cert >= 2 solve certifies
@@ -789,10 +852,13 @@ def saddle_search(ham: Ham, m0, tau_F: float = 1e-6, k: int = 1, k_cert: int = 2
         m = rotate(m, d)
     E, g, c, F = energy_grad(ham, m)
     kc = max(k_cert, 2)
-    ec = min_modes(ham, m, kc, tol=eig_tol, max_iter=eig_max_iter, mask=act, seed=seed + 1, c=c)
+    ec = min_modes(ham, m, kc, tol=eig_tol, max_iter=eig_max_iter if cert_max_iter is None else cert_max_iter,
+                   mask=act, seed=seed + 1, c=c)
     n_hvp += ec.n_hvp
     if fnorm <= tau_F:
-        status = certify(ec.evals, tau_lam)
+        n_act = ham.N if act is None else int(np.count_nonzero(act))
+        n_neg = negative_count(ham, m, tau_lam, mask=act) if 2 * n_act <= DENSE_INERTIA_MAX_DOF else None
+        status = certify(ec.evals, tau_lam, converged=ec.converged, n_negative=n_neg)
     return SearchResult(status, m, E, fnorm, it, n_hvp, ec.evals, ec.V, tr)
 
 

@@ -165,7 +165,9 @@ const char* moto_status_string(moto_status s) {
         case MOTO_EINVAL: return "invalid argument";
         case MOTO_EHIP: return "HIP runtime error";
         case MOTO_EWORKSPACE: return "workspace too small";
-        case MOTO_EUNSUPPORTED: return "Hamiltonian outside the GPU scope (<= 3 shells, NN DMI)";
+        case MOTO_EUNSUPPORTED:
+            return "outside the GPU scope (more than 36 exchange shells, DMI beyond the first shell, or a call "
+                   "limited to three shells)";
         default: return "unknown status";
     }
 }
@@ -606,7 +608,7 @@ void moto_default_lanczos_opts(moto_dtype hvp, moto_lanczos_opts* o) {
     o->warm = 0;
     o->seed = 0x2509262690ull;
     o->use_graph = 1;
-    o->reserved = 0;
+    o->block = 0;
 }
 
 namespace {
@@ -615,6 +617,8 @@ struct LzLayout {
     int n2, nblk;
 };
 
+// the basis holds m_max + LZ_MAXBLK columns whatever the block size, so that
+// the workspace size depends on the depth alone
 LzLayout lz_layout(const moto_plan p, moto_dtype hvp, int m_max) {
     LzLayout L;
     const size_t N = p->g.N;
@@ -630,9 +634,9 @@ LzLayout lz_layout(const moto_plan p, moto_dtype hvp, int m_max) {
     L.c64 = o;
     o += al(sizeof(double) * N);
     L.Q = o;
-    o += al(es * (size_t)(m_max + 1) * L.n2);
+    o += al(es * (size_t)(m_max + LZ_MAXBLK) * L.n2);
     size_t part = sizeof(double) * NPART * (size_t)p->g.tiles;
-    part = std::max(part, sizeof(double) * (size_t)L.nblk * (LZ_MAXM + 2));
+    part = std::max(part, sizeof(double) * (size_t)L.nblk * (LZ_NCOL + 1));
     part = std::max(part, sizeof(double) * ((size_t)nblk_o * MAXB * 3 + MAXB));
     L.part = o;
     o += al(part);
@@ -643,6 +647,7 @@ LzLayout lz_layout(const moto_plan p, moto_dtype hvp, int m_max) {
 }
 
 int lz_keep(int k, int m_max, int keep) { return keep > 0 ? keep : std::max(k + 2, m_max / 2); }
+int lz_block(int block) { return block > 0 ? block : 2; }
 }  // namespace
 
 size_t moto_min_modes_lanczos_workspace(moto_plan p, moto_dtype hvp, int32_t m_max) {
@@ -660,10 +665,11 @@ moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double* m,
     else
         moto_default_lanczos_opts(hvp, &o);
     const int keep = lz_keep(k, o.m_max, o.keep);
-    if (o.m_max < 3 || o.m_max > LZ_MAXM || keep < k || keep >= o.m_max || !(o.tol >= 0.0) ||
-        o.max_restarts < 0 || o.warm < 0 || o.warm > 1)
+    const int b = lz_block(o.block);
+    if (o.m_max < 3 || o.m_max > LZ_MAXM || b > LZ_MAXBLK || o.block < 0 || keep < k || keep + b > o.m_max ||
+        !(o.tol >= 0.0) || o.max_restarts < 0 || o.warm < 0 || o.warm > 1)
         return MOTO_EINVAL;
-    if (o.m_max + 1 > 2 * p->g.N) return MOTO_EINVAL;  // the Krylov basis must fit the space
+    if (o.m_max + b > 2 * p->g.N) return MOTO_EINVAL;  // the Krylov basis must fit the space
     char* ws = (char*)ws_;
     const LzLayout L = lz_layout(p, hvp, o.m_max);
     if (!ws) return MOTO_EWORKSPACE;
@@ -688,19 +694,25 @@ moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double* m,
         HIP_TRY(hipMemcpyAsync(ws + L.mT, m, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, st));
     }
     const int hv_var = tuned_variant(p, hvp, 1, 1);
-    HIP_TRY(launch_lz_init(f64, N, Q, m, o.warm ? V : nullptr, o.warm ? k : 0, mask, o.seed, part, L.nblk, ctrl,
-                           o.m_max, st));
+    HIP_TRY(launch_lz_init(f64, N, b, Q, m, o.warm ? V : nullptr, o.warm ? k : 0, mask, o.seed, ctrl, o.m_max, st));
     const double tol_abs = o.tol * p->hest;
-    auto steps = [&](int j0, hipStream_t s) -> hipError_t {
+    // one cycle from kept column j0: re-orthonormalise the b columns j0.. (the
+    // start block, or the residual block after a restart), then the steps
+    // j0 .. m_max-1, each an HVP of column j into column j + b
+    auto cycle = [&](int j0, hipStream_t s) -> hipError_t {
+        for (int l = 0; l < b; ++l) {
+            hipError_t e = launch_lz_orth(f64, L.n2, Q, j0 + l, -1, part, L.nblk, ctrl, s);
+            if (e != hipSuccess) return e;
+        }
         for (int j = j0; j < o.m_max; ++j) {
             hipError_t e = launch_tangent_hvp(p->g, p->k, f64, true, 1, mT, cT, mask, 1, (char*)Q + es * j * L.n2,
-                                              (char*)Q + es * (j + 1) * L.n2, &ctrl->done, s, hv_var);
-            if (e == hipSuccess) e = launch_lz_orth(f64, L.n2, Q, j, part, L.nblk, ctrl, s);
+                                              (char*)Q + es * (j + b) * L.n2, &ctrl->done, s, hv_var);
+            if (e == hipSuccess) e = launch_lz_orth(f64, L.n2, Q, j + b, j, part, L.nblk, ctrl, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     };
-    // the cycles after the first repeat the same launches (steps keep..m_max-1):
+    // the cycles after the first repeat the same launches (from column keep):
     // captured once as a HIP graph and replayed
     hipGraphExec_t gexec = nullptr;
     if (o.use_graph) {
@@ -710,7 +722,7 @@ moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double* m,
         key[2] = o.m_max;
         key[3] = keep;
         key[4] = k;
-        key[5] = -1;
+        key[5] = -b;
         key[6] = hv_var;
         key[7] = N;
         for (auto& ge : p->graphs)
@@ -718,19 +730,20 @@ moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double* m,
                 std::memcmp(ge.key, key, sizeof(key)) == 0)
                 gexec = ge.exec;
         if (!gexec) {
-            auto cyc = [&](hipStream_t s) { return steps(keep, s); };
+            auto cyc = [&](hipStream_t s) { return cycle(keep, s); };
             gexec = capture_chunk(p, cyc, key, ws, mask);
         }
     }
-    int hdr[4];
-    for (int cycle = 0; cycle <= o.max_restarts + 1; ++cycle) {
-        if (cycle == 0)
-            HIP_TRY(steps(0, st));
-        else if (gexec)
+    int hdr[6] = {0, 0, 0, 0, 0, keep};  // done, status, restarts, m_eff, m_max, nkeep
+    for (int c = 0; c <= o.max_restarts + 1; ++c) {
+        if (c == 0)
+            HIP_TRY(cycle(0, st));
+        else if (gexec && hdr[5] == keep)
             HIP_TRY(hipGraphLaunch(gexec, st));
         else
-            HIP_TRY(steps(keep, st));
-        HIP_TRY(launch_lz_rr_restart(f64, L.n2, Q, k, keep, tol_abs, o.max_restarts, o.m_max, L.nblk, ctrl, st));
+            HIP_TRY(cycle(hdr[5], st));  // a breakdown kept fewer Ritz vectors than `keep`
+        HIP_TRY(launch_lz_rr_restart(f64, L.n2, b, Q, k, keep, tol_abs, o.max_restarts, o.m_max, L.nblk, mask, N,
+                                     o.seed, ctrl, st));
         moto_status rs = readback(p, ctrl, sizeof(hdr), hdr, st);
         if (rs != MOTO_OK) return rs;
         if (hdr[0]) break;
@@ -1029,7 +1042,9 @@ moto_status moto_saddle_search(moto_plan p, moto_dtype hvp, double* m, const uin
     const bool conv = std::isfinite(ho[0]) && ho[0] <= o.tau_F;
     if (nan || !std::isfinite(ho[0]) || !std::isfinite(lam[0]) || !std::isfinite(lam[1]) || inf.status == MOTO_NAN)
         status = MOTO_NAN;
-    else if (!conv)
+    else if (!conv || inf.status != MOTO_CONVERGED)
+        // an unconverged certifying solve only bounds the eigenvalues from
+        // above: no SADDLE / HIGHER_INDEX verdict from it
         status = MOTO_NOT_CONVERGED;
     else if (lam[0] < -tau_lam && lam[1] > tau_lam)
         status = MOTO_SADDLE;
@@ -1208,7 +1223,7 @@ moto_status moto_saddle_search_population(moto_plan p, moto_dtype hvp, int32_t P
         if (nanm[y] || !std::isfinite(fnorm[y]) || !std::isfinite(l1) || !std::isfinite(l2) ||
             inf[y].status == MOTO_NAN)
             status = MOTO_NAN;
-        else if (!conv)
+        else if (!conv || inf[y].status != MOTO_CONVERGED)
             status = MOTO_NOT_CONVERGED;
         else if (l1 < -tau_lam && l2 > tau_lam)
             status = MOTO_SADDLE;

@@ -654,7 +654,9 @@ __global__ __launch_bounds__(NT) void k_batched_search(BArgs a, double* __restri
             const bool conv = isfinite(fnorm) && fnorm <= a.tau_F;
             if (nan || !isfinite(fnorm) || !isfinite(l1) || !isfinite(l2) || s.ctrl->status == MOTO_NAN)
                 status = MOTO_NAN;
-            else if (!conv)
+            else if (!conv || s.ctrl->status != MOTO_CONVERGED)
+                // an unconverged certifying solve only bounds the eigenvalues
+                // from above: no SADDLE / HIGHER_INDEX verdict from it
                 status = MOTO_NOT_CONVERGED;
             else if (l1 < -a.tau_lam && l2 > a.tau_lam)
                 status = MOTO_SADDLE;

@@ -159,31 +159,42 @@ struct EigArgs {
 };
 
 // ---- lanczos.hip ----
-constexpr int LZ_MAXM = 64;           // max Krylov depth
-constexpr int LZ_LDT = LZ_MAXM + 1;   // leading dimension of the projected matrix
-// Control block of one thick-restart Lanczos solve, resident in device memory.
+constexpr int LZ_MAXM = 64;                 // max Krylov depth
+constexpr int LZ_MAXBLK = 4;                // max start-block size of the band Lanczos
+constexpr int LZ_NCOL = LZ_MAXM + LZ_MAXBLK;  // basis columns (depth + residual block)
+constexpr int LZ_LDT = LZ_NCOL;             // leading dimension of the projected matrix
+// Control block of one thick-restart band-Lanczos solve, resident in device memory.
 struct LzCtrl {
     int done;        // 1 once stopped: later step launches are no-ops
-    int status;      // MOTO_CONVERGED, MOTO_NOT_CONVERGED, MOTO_NAN
+    int status;      // MOTO_CONVERGED, MOTO_NOT_CONVERGED, MOTO_NAN, MOTO_BREAKDOWN
     int restarts;    // thick restarts taken
     int m_eff;       // Krylov depth of the current cycle (smaller after a breakdown)
     int m_max;       // Krylov depth asked for
     int nkeep;       // Ritz vectors formed by the last restart
+    int blk;         // start-block size b
+    int brk;         // 1: the cycle ended on a breakdown (dependent new column)
     long long n_hvp; // HVP columns applied
-    double beta;     // |w| of the last step
-    double h[LZ_MAXM + 1];           // reorthogonalisation coefficients of the current pass
-    double T[LZ_LDT * LZ_LDT];       // projected matrix Q^T H Q (and beta_m below the last column)
+    double beta;     // |w| of the last orthogonalisation
+    double h[LZ_NCOL];               // reorthogonalisation coefficients of the current pass
+    double T[LZ_LDT * LZ_LDT];       // projected matrix Q^T H Q and the residual rows below it
     double Y[LZ_MAXM * LZ_MAXM];     // Ritz vectors of T, vector i at [i * LZ_MAXM]
     double theta[LZ_MAXM], resid[LZ_MAXM];
     EigCtrl out;     // eigenvalues, residuals and counters in the eigen-solve layout
 };
 int lz_blocks(int n2);
-hipError_t launch_lz_init(bool f64, int N, void* Q, const double* m, const double* Vwarm, int nwarm,
-                          const uint8_t* mask, uint64_t seed, double* part, int nblk, LzCtrl* ctrl, int m_max,
+// Start block: column 0 = sum of the nwarm warm vectors (or SplitMix64 entries),
+// columns 1..b-1 SplitMix64 entries; masked sites zero.  Resets the control block.
+hipError_t launch_lz_init(bool f64, int N, int b, void* Q, const double* m, const double* Vwarm, int nwarm,
+                          const uint8_t* mask, uint64_t seed, LzCtrl* ctrl, int m_max, hipStream_t st);
+// Orthogonalise column c against columns 0..c-1 twice and normalise it.  tj >= 0:
+// column c is the image of column tj (c = tj + b): the coefficients of both
+// passes fill column tj of T and |w| goes to T[c][tj]; a negligible |w| ends the
+// cycle (m_eff = tj + 1).  tj < 0: no T entries (start and residual blocks).
+hipError_t launch_lz_orth(bool f64, int n2, void* Q, int c, int tj, double* part, int nblk, LzCtrl* ctrl,
                           hipStream_t st);
-hipError_t launch_lz_orth(bool f64, int n2, void* Q, int j, double* part, int nblk, LzCtrl* ctrl, hipStream_t st);
-hipError_t launch_lz_rr_restart(bool f64, int n2, void* Q, int k, int keep, double tol_abs, int max_restarts,
-                                int m_max, int nblk, LzCtrl* ctrl, hipStream_t st);
+hipError_t launch_lz_rr_restart(bool f64, int n2, int b, void* Q, int k, int keep, double tol_abs, int max_restarts,
+                                int m_max, int nblk, const uint8_t* mask, int N, uint64_t seed, LzCtrl* ctrl,
+                                hipStream_t st);
 
 // ---- explorer.hip ----
 int l1_chunks(long long n3);

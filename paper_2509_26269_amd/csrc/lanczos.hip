@@ -1,18 +1,29 @@
-// lanczos.hip -- the second inner solver: thick-restart Lanczos with full
-// reorthogonalisation on the (masked) tangent Hessian in frame coordinates
-// (the paper's HVP-Lanczos operator mode; Krylov depth and
-// reorthogonalisation are its named hyperparameters).  One step j:
+// lanczos.hip -- the second inner solver: thick-restart band Lanczos with
+// full reorthogonalisation on the (masked) tangent Hessian in frame
+// coordinates (the paper's HVP-Lanczos operator mode; Krylov depth and
+// reorthogonalisation are its named hyperparameters).
+//
+// The Krylov space grows from a start block of b orthonormal vectors (band
+// Lanczos, Ruhe 1979).  Step j:
 //   w = H q_j                       (the HVP kernel, one vector)
-//   h = Q_{0..j}^T w, w -= Q h      (classical Gram-Schmidt, twice; the
+//   h = Q_{0..j+b-1}^T w, w -= Q h  (classical Gram-Schmidt, twice; the
 //                                    coefficients of both passes summed are
 //                                    column j of Q^T H Q)
-//   beta = |w|, q_{j+1} = w / beta
-// Q lives in one [m_max + 1][2N] array; w is written straight into column
-// j + 1.  At the end of a cycle one wavefront diagonalises the projected
-// matrix T (FP64, Householder tridiagonalisation and implicit QL), tests the
-// residual estimates |beta_m y_m,i| and either stops or restarts from the
-// `keep` lowest Ritz vectors plus the residual direction (Wu & Simon 2000):
-// T becomes diag(theta) bordered by beta_m y_m.  All reductions are FP64 with a fixed order.
+//   beta = |w|, q_{j+b} = w / beta
+// so H Q_m = Q_m T_m + Q_{m..m+b-1} T[m..m+b-1][0..m): a Ritz pair (theta, y)
+// of T_m has the residual norm |T[m..m+b-1][0..m) y|.  A single start vector
+// (b = 1) can keep the second member of a close eigenvalue pair out of the
+// space long after the first has met the stopping rule; a block of b
+// directions brings such a pair in together.
+// Q lives in one [m_max + b][2N] array; w is written straight into its
+// column.  At the end of a cycle one wavefront diagonalises T (FP64,
+// Householder tridiagonalisation and implicit QL), tests the residuals and
+// either stops or restarts from the `keep` lowest Ritz vectors plus the
+// residual block (Wu & Simon 2000), which is re-orthonormalised before the
+// next cycle; the steps of that cycle fill the couplings of T.  A breakdown
+// (a new column with negligible norm) ends the cycle early; the residual rows
+// stay exact, and the restart puts a fresh SplitMix64 direction in place of
+// the dependent column.  All reductions are FP64 with a fixed order.
 #include <type_traits>
 
 #include "dense_wg.hpp"
@@ -20,73 +31,82 @@
 
 namespace moto {
 
-constexpr int LZP = LZ_MAXM + 2;  // doubles per block partial row (columns, then |w|^2)
+constexpr int LZP = LZ_NCOL + 1;  // doubles per block partial row (columns, then |w|^2)
 
 __device__ __forceinline__ int lz_rows_per_block(int n2, int nblk) {
     const int per = (n2 + nblk - 1) / nblk;
     return (per + 63) & ~63;
 }
 
-// Start vector: the sum of the warm vectors (ambient, FP64) in frame
-// coordinates, else SplitMix64 entries; masked sites zero.  Partial |q|^2.
+// Start block: column 0 is the sum of the warm vectors (ambient, FP64) in
+// frame coordinates, or SplitMix64 entries; columns 1..b-1 SplitMix64 entries
+// of their own; masked sites zero.  Resets the control block.
 template <class T>
-__global__ __launch_bounds__(NT) void k_lz_init(int N, T* __restrict__ Q, const double* __restrict__ m,
+__global__ __launch_bounds__(NT) void k_lz_init(int N, int b, T* __restrict__ Q, const double* __restrict__ m,
                                                 const double* __restrict__ Vwarm, int nwarm,
                                                 const uint8_t* __restrict__ mask, uint64_t seed,
-                                                double* __restrict__ part, LzCtrl* __restrict__ ctrl, int m_max) {
-    __shared__ double red[NT / 64];
+                                                LzCtrl* __restrict__ ctrl, int m_max) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->done = 0;
         ctrl->status = MOTO_NOT_CONVERGED;
         ctrl->restarts = 0;
         ctrl->m_eff = m_max;
         ctrl->m_max = m_max;
+        ctrl->nkeep = 0;
+        ctrl->blk = b;
+        ctrl->brk = 0;
         ctrl->n_hvp = 0;
+        ctrl->out.status = MOTO_NOT_CONVERGED;
+        ctrl->out.iters = 0;
+        ctrl->out.n_hvp = 0;
     }
-    double s2 = 0.0;
+    // entries of T below the band are never written by a step: start from zero
+    for (int i = blockIdx.x * NT + threadIdx.x; i < LZ_LDT * LZ_LDT; i += gridDim.x * NT) ctrl->T[i] = 0.0;
+    const size_t n2 = 2 * (size_t)N;
     for (int s = blockIdx.x * NT + threadIdx.x; s < N; s += gridDim.x * NT) {
-        double a = 0.0, b = 0.0;
         const bool on = mask == nullptr || mask[s] != 0;
-        if (on) {
-            if (nwarm > 0) {
-                double e1[3], e2[3];
-                onb(m[s], m[N + s], m[2 * N + s], e1, e2);
-                for (int j = 0; j < nwarm; ++j) {
-                    const double* v = Vwarm + (size_t)j * 3 * N;
-                    a += e1[0] * v[s] + e1[1] * v[N + s] + e1[2] * v[2 * N + s];
-                    b += e2[0] * v[s] + e2[1] * v[N + s] + e2[2] * v[2 * N + s];
+        for (int l = 0; l < b; ++l) {
+            double a = 0.0, bb = 0.0;
+            if (on) {
+                if (l == 0 && nwarm > 0) {
+                    double e1[3], e2[3];
+                    onb(m[s], m[N + s], m[2 * N + s], e1, e2);
+                    for (int j = 0; j < nwarm; ++j) {
+                        const double* v = Vwarm + (size_t)j * 3 * N;
+                        a += e1[0] * v[s] + e1[1] * v[N + s] + e1[2] * v[2 * N + s];
+                        bb += e2[0] * v[s] + e2[1] * v[N + s] + e2[2] * v[2 * N + s];
+                    }
+                } else {
+                    a = splitmix_uniform(seed, (uint64_t)l * n2 + s);
+                    bb = splitmix_uniform(seed, (uint64_t)l * n2 + N + s);
                 }
-            } else {
-                a = splitmix_uniform(seed, (uint64_t)s);
-                b = splitmix_uniform(seed, (uint64_t)N + s);
             }
+            Q[(size_t)l * n2 + s] = (T)a;
+            Q[(size_t)l * n2 + N + s] = (T)bb;
         }
-        const T ta = (T)a, tb = (T)b;
-        Q[s] = ta;
-        Q[N + s] = tb;
-        s2 += (double)ta * ta + (double)tb * tb;
     }
-    s2 = wave_sum(s2);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s2;
-    __syncthreads();
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * LZP + LZ_MAXM + 1] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Partial dots of w = Q[j + 1] with Q[0..j]: blockIdx.x picks the rows,
-// wave w of block (x, y) the column c = 4 y + w, so every column's rows are
-// read by its own wave in parallel; lane l takes the rows start + l,
-// start + l + 64, ... into two alternating partial sums (fixed order).
+// the kernels of step tj (tj >= 0) do nothing once the cycle has ended
+__device__ __forceinline__ bool lz_skip(const LzCtrl* ctrl, int tj) {
+    return ctrl->done || (tj >= 0 && tj >= ctrl->m_eff);
+}
+
+// Partial dots of w = Q[c] with Q[0..c): blockIdx.x picks the rows, wave w of
+// block (x, y) the column q = 4 y + w, so every column's rows are read by its
+// own wave in parallel; lane l takes the rows start + l, start + l + 64, ...
+// into two alternating partial sums (fixed order).
 template <class T>
-__global__ __launch_bounds__(NT) void k_lz_dots(int n2, const T* __restrict__ Q, int j, double* __restrict__ part,
-                                                const LzCtrl* __restrict__ ctrl) {
-    if (ctrl->done || j >= ctrl->m_eff) return;
-    const int c = blockIdx.y * (NT / 64) + (threadIdx.x >> 6);
-    if (c > j) return;
+__global__ __launch_bounds__(NT) void k_lz_dots(int n2, const T* __restrict__ Q, int c, int tj,
+                                                double* __restrict__ part, const LzCtrl* __restrict__ ctrl) {
+    if (lz_skip(ctrl, tj)) return;
+    const int col = blockIdx.y * (NT / 64) + (threadIdx.x >> 6);
+    if (col >= c) return;
     const int per = lz_rows_per_block(n2, gridDim.x);
     const int r0 = blockIdx.x * per, r1 = min(n2, r0 + per);
     const int lane = threadIdx.x & 63;
-    const T* __restrict__ w = Q + (size_t)(j + 1) * n2;
-    const T* __restrict__ q = Q + (size_t)c * n2;
+    const T* __restrict__ w = Q + (size_t)c * n2;
+    const T* __restrict__ q = Q + (size_t)col * n2;
     double s0 = 0.0, s1 = 0.0;
     int r = r0 + lane;
     for (; r + 64 < r1; r += 128) {
@@ -95,42 +115,44 @@ __global__ __launch_bounds__(NT) void k_lz_dots(int n2, const T* __restrict__ Q,
     }
     if (r < r1) s0 += (double)q[r] * (double)w[r];
     const double s = wave_sum(s0 + s1);
-    if (lane == 0) part[(size_t)blockIdx.x * LZP + c] = s;
+    if (lane == 0) part[(size_t)blockIdx.x * LZP + col] = s;
 }
 
-// h_c = sum_b part[b][c] for c <= j (one wavefront per column).  pass 0
-// stores h and sets column j of T; pass 1 stores h and adds it to T.
-__global__ __launch_bounds__(NT) void k_lz_reduce(const double* __restrict__ part, int nblk, int j, int pass,
+// h_q = sum_b part[b][q] for q < c (one wavefront per column).  With tj >= 0,
+// pass 0 sets column tj of T to h and pass 1 adds h to it.
+__global__ __launch_bounds__(NT) void k_lz_reduce(const double* __restrict__ part, int nblk, int c, int tj, int pass,
                                                   LzCtrl* __restrict__ ctrl) {
-    if (ctrl->done || j >= ctrl->m_eff) return;
+    if (lz_skip(ctrl, tj)) return;
     const int lane = threadIdx.x & 63;
-    for (int c = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); c <= j; c += gridDim.x * (NT / 64)) {
+    for (int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); q < c; q += gridDim.x * (NT / 64)) {
         double s = 0.0;
-        for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * LZP + c];
+        for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * LZP + q];
         s = wave_sum(s);
         if (lane == 0) {
-            ctrl->h[c] = s;
-            const double t = pass == 0 ? s : ctrl->T[c * LZ_LDT + j] + s;
-            ctrl->T[c * LZ_LDT + j] = t;
-            ctrl->T[j * LZ_LDT + c] = t;
+            ctrl->h[q] = s;
+            if (tj >= 0) {
+                const double t = pass == 0 ? s : ctrl->T[q * LZ_LDT + tj] + s;
+                ctrl->T[q * LZ_LDT + tj] = t;
+                ctrl->T[tj * LZ_LDT + q] = t;
+            }
         }
     }
 }
 
-// w -= Q[0..j] h; on the last pass also the partial |w|^2.
+// w -= Q[0..c) h; on the last pass also the partial |w|^2.
 template <class T>
-__global__ __launch_bounds__(NT) void k_lz_update(int n2, T* __restrict__ Q, int j, int want_norm,
+__global__ __launch_bounds__(NT) void k_lz_update(int n2, T* __restrict__ Q, int c, int tj, int want_norm,
                                                   double* __restrict__ part, const LzCtrl* __restrict__ ctrl) {
-    if (ctrl->done || j >= ctrl->m_eff) return;
-    __shared__ double h[LZ_MAXM + 1];
+    if (lz_skip(ctrl, tj)) return;
+    __shared__ double h[LZ_NCOL];
     __shared__ double red[NT / 64];
-    for (int c = threadIdx.x; c <= j; c += NT) h[c] = ctrl->h[c];
+    for (int q = threadIdx.x; q < c; q += NT) h[q] = ctrl->h[q];
     __syncthreads();
-    T* __restrict__ w = Q + (size_t)(j + 1) * n2;
+    T* __restrict__ w = Q + (size_t)c * n2;
     double s2 = 0.0;
     for (int r = blockIdx.x * NT + threadIdx.x; r < n2; r += gridDim.x * NT) {
         double v = (double)w[r];
-        for (int c = 0; c <= j; ++c) v -= h[c] * (double)Q[(size_t)c * n2 + r];
+        for (int q = 0; q < c; ++q) v -= h[q] * (double)Q[(size_t)q * n2 + r];
         const T tv = (T)v;
         w[r] = tv;
         s2 += (double)tv * tv;
@@ -139,17 +161,19 @@ __global__ __launch_bounds__(NT) void k_lz_update(int n2, T* __restrict__ Q, int
     s2 = wave_sum(s2);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s2;
     __syncthreads();
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * LZP + LZ_MAXM + 1] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * LZP + LZ_NCOL] = red[0] + red[1] + red[2] + red[3];
 }
 
-// beta = |w| from the partials (one workgroup).  col < 0: the start vector
-// (no T entry, no HVP count).  A negligible beta ends the cycle at j + 1.
-__global__ __launch_bounds__(NT) void k_lz_beta(const double* __restrict__ part, int nblk, int j,
+// beta = |w| from the partials (one workgroup).  tj >= 0: one HVP counted,
+// T[c][tj] = beta, and a negligible beta ends the cycle after column tj.
+// tj < 0 (start or residual block): a vanishing column means no independent
+// direction is left (MOTO_BREAKDOWN).
+__global__ __launch_bounds__(NT) void k_lz_beta(const double* __restrict__ part, int nblk, int c, int tj,
                                                 LzCtrl* __restrict__ ctrl) {
-    if (ctrl->done || j >= ctrl->m_eff) return;
+    if (lz_skip(ctrl, tj)) return;
     __shared__ double red[NT / 64];
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += NT) s += part[(size_t)b * LZP + LZ_MAXM + 1];
+    for (int b = threadIdx.x; b < nblk; b += NT) s += part[(size_t)b * LZP + LZ_NCOL];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -161,36 +185,52 @@ __global__ __launch_bounds__(NT) void k_lz_beta(const double* __restrict__ part,
         ctrl->done = 1;
         return;
     }
-    if (j < 0) return;
+    if (tj < 0) {
+        if (!(beta > 1e-30)) {
+            ctrl->status = MOTO_BREAKDOWN;
+            ctrl->done = 1;
+        }
+        return;
+    }
     ctrl->n_hvp += 1;
-    ctrl->T[(j + 1) * LZ_LDT + j] = beta;
-    ctrl->T[j * LZ_LDT + j + 1] = beta;
-    if (beta <= 1e-14 * fmax(1.0, fabs(ctrl->T[j * LZ_LDT + j]))) ctrl->m_eff = j + 1;
+    ctrl->T[c * LZ_LDT + tj] = beta;
+    ctrl->T[tj * LZ_LDT + c] = beta;
+    if (beta <= 1e-14 * fmax(1.0, fabs(ctrl->T[tj * LZ_LDT + tj]))) {
+        ctrl->m_eff = tj + 1;
+        ctrl->brk = 1;
+    }
 }
 
-// q_{j+1} = w / beta (column `col` = j + 1)
+// q_c = w / beta (not after a breakdown: the restart replaces that column)
 template <class T>
-__global__ __launch_bounds__(NT) void k_lz_scale(int n2, T* __restrict__ Q, int col, const LzCtrl* __restrict__ ctrl) {
-    if (ctrl->done || (col > 0 && col - 1 >= ctrl->m_eff)) return;
+__global__ __launch_bounds__(NT) void k_lz_scale(int n2, T* __restrict__ Q, int c, int tj,
+                                                 const LzCtrl* __restrict__ ctrl) {
+    if (ctrl->done || (tj >= 0 && (tj >= ctrl->m_eff || (ctrl->brk && tj + 1 == ctrl->m_eff)))) return;
     const double beta = ctrl->beta;
     const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-    T* __restrict__ q = Q + (size_t)col * n2;
+    T* __restrict__ q = Q + (size_t)c * n2;
     for (int r = blockIdx.x * NT + threadIdx.x; r < n2; r += gridDim.x * NT) q[r] = (T)((double)q[r] * inv);
 }
 
 // Rayleigh-Ritz on T[0..m) (one wavefront): eigenpairs in ascending order,
-// residual estimates, stop test; when going on, the restarted T.
+// residual norms |T[m..m+b)[0..m) y_i|, stop test.
 __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, int max_restarts,
                                               LzCtrl* __restrict__ ctrl) {
     constexpr int LD = LZ_MAXM + 1;
     __shared__ double A[LD * LD], Z[LD * LD];
     __shared__ double ev[LZ_MAXM];
     __shared__ int order[LZ_MAXM];
-    if (ctrl->status == MOTO_NAN) return;
     const int lane = wlane();
+    if (ctrl->done) {  // stopped inside the cycle (NaN, no direction left)
+        if (lane == 0) {
+            ctrl->out.status = ctrl->status;
+            ctrl->out.iters = ctrl->restarts;
+            ctrl->out.n_hvp = ctrl->n_hvp;
+        }
+        return;
+    }
     const int m = ctrl->m_eff;
-    const bool full = m == ctrl->m_max;
-    const double bm = full ? ctrl->T[m * LZ_LDT + m - 1] : 0.0;
+    const int b = ctrl->blk;
     for2(m, m, [&](int r, int c) { A[r * LD + c] = 0.5 * (ctrl->T[r * LZ_LDT + c] + ctrl->T[c * LZ_LDT + r]); });
     wsync();
     symeig_wg<LD>(A, Z, m);
@@ -206,8 +246,15 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
     const int kk = keep < m ? keep : m;
     for2(kk, m, [&](int i, int r) { ctrl->Y[i * LZ_MAXM + r] = Z[r * LD + order[i]]; });
     for (int i = lane; i < kk; i += WL) {
-        const double th = ev[order[i]];
-        const double rn = fabs(bm * Z[(m - 1) * LD + order[i]]);
+        const int zi = order[i];
+        double r2 = 0.0;
+        for (int l = 0; l < b; ++l) {
+            double t = 0.0;
+            for (int c = 0; c < m; ++c) t += ctrl->T[(m + l) * LZ_LDT + c] * Z[c * LD + zi];
+            r2 += t * t;
+        }
+        const double th = ev[zi];
+        const double rn = sqrt(r2);
         ctrl->theta[i] = th;
         ctrl->resid[i] = rn;
         if (i < MAXB) {
@@ -217,7 +264,7 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
     }
     wsync();
     if (lane != 0) return;
-    bool conv = true, bad = false;
+    bool conv = m >= k, bad = false;
     for (int i = 0; i < k && i < kk; ++i) {
         if (!isfinite(ctrl->theta[i]) || !isfinite(ctrl->resid[i])) bad = true;
         if (!(ctrl->resid[i] <= tol_abs)) conv = false;
@@ -226,7 +273,7 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
     if (bad) {
         ctrl->status = MOTO_NAN;
         ctrl->done = 1;
-    } else if (conv || !full) {
+    } else if (conv) {
         ctrl->status = MOTO_CONVERGED;
         ctrl->done = 1;
     } else if (ctrl->restarts >= max_restarts) {
@@ -240,16 +287,21 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
     ctrl->out.n_hvp = ctrl->n_hvp;
 }
 
-// After k_lz_rr: Q[:, 0..keep) = Q[:, 0..m) Y (rows in place), and, when
-// going on, Q[:, keep] = Q[:, m] and T = diag(theta) bordered by beta_m y_m.
+// After k_lz_rr: Q[:, 0..kk) = Q[:, 0..m) Y (rows in place); when going on,
+// Q[:, kk + l] = Q[:, m + l] (l < b; after a breakdown the dependent last
+// column becomes fresh SplitMix64 entries) and T = diag(theta).  Destination
+// columns never exceed their sources, so the copies run in increasing l.
 template <class T, int MM>
-__global__ __launch_bounds__(NT) void k_lz_restart(int n2, T* __restrict__ Q, LzCtrl* __restrict__ ctrl) {
+__global__ __launch_bounds__(NT) void k_lz_restart(int n2, T* __restrict__ Q, const uint8_t* __restrict__ mask,
+                                                   int N, uint64_t seed, LzCtrl* __restrict__ ctrl) {
     __shared__ double Y[MM * MM];
-    const int m = ctrl->m_eff, kk = ctrl->nkeep;
-    if (ctrl->status == MOTO_NAN) return;
+    if (ctrl->status == MOTO_NAN || ctrl->status == MOTO_BREAKDOWN) return;
+    const int m = ctrl->m_eff, kk = ctrl->nkeep, b = ctrl->blk;
+    const bool brk = ctrl->brk != 0;
     for (int i = threadIdx.x; i < kk * m; i += NT) Y[i] = ctrl->Y[(i / m) * LZ_MAXM + (i % m)];
     __syncthreads();
     const bool go_on = ctrl->done == 0;
+    const uint64_t fseed = seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(ctrl->restarts + 1));
     for (int r = blockIdx.x * NT + threadIdx.x; r < n2; r += gridDim.x * NT) {
         T q[MM];
 #pragma unroll
@@ -262,23 +314,34 @@ __global__ __launch_bounds__(NT) void k_lz_restart(int n2, T* __restrict__ Q, Lz
                 if (c < m) s += (double)q[c] * Y[i * m + c];
             Q[(size_t)i * n2 + r] = (T)s;
         }
-        if (go_on) Q[(size_t)kk * n2 + r] = Q[(size_t)m * n2 + r];
-    }
-    if (go_on && blockIdx.x == 0) {
-        __syncthreads();
-        // the restarted projected matrix (block 0 only; the next kernels
-        // read it after this launch)
-        const double bm = ctrl->T[m * LZ_LDT + m - 1];
-        __syncthreads();  // every wave holds beta_m before the matrix is cleared
-        for (int i = threadIdx.x; i < LZ_LDT * LZ_LDT; i += NT) ctrl->T[i] = 0.0;
-        __syncthreads();
-        for (int i = threadIdx.x; i < kk; i += NT) {
-            ctrl->T[i * LZ_LDT + i] = ctrl->theta[i];
-            const double cpl = bm * Y[i * m + m - 1];
-            ctrl->T[i * LZ_LDT + kk] = cpl;
-            ctrl->T[kk * LZ_LDT + i] = cpl;
+        if (go_on) {
+            for (int l = 0; l < b; ++l) {
+                T v;
+                if (brk && l == b - 1) {
+                    const int site = r < N ? r : r - N;
+                    v = (mask == nullptr || mask[site] != 0) ? (T)splitmix_uniform(fseed, (uint64_t)r) : T(0);
+                } else {
+                    v = Q[(size_t)(m + l) * n2 + r];
+                }
+                Q[(size_t)(kk + l) * n2 + r] = v;
+            }
         }
-        if (threadIdx.x == 0) ctrl->m_eff = ctrl->m_max;
+    }
+}
+
+// The restarted projected matrix: the kept Ritz values on the diagonal; the
+// couplings to the residual block are filled by the steps of the next cycle.
+// A launch of its own, after every block of k_lz_restart has read m_eff and brk.
+__global__ __launch_bounds__(NT) void k_lz_restart_ctrl(LzCtrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int kk = ctrl->nkeep;
+    for (int i = threadIdx.x; i < LZ_LDT * LZ_LDT; i += NT) {
+        const int r = i / LZ_LDT, c = i - r * LZ_LDT;
+        ctrl->T[i] = (r == c && r < kk) ? ctrl->theta[r] : 0.0;
+    }
+    if (threadIdx.x == 0) {
+        ctrl->m_eff = ctrl->m_max;
+        ctrl->brk = 0;
     }
 }
 
@@ -290,62 +353,64 @@ int lz_blocks(int n2) {
     return nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
 }
 
-hipError_t launch_lz_init(bool f64, int N, void* Q, const double* m, const double* Vwarm, int nwarm,
-                          const uint8_t* mask, uint64_t seed, double* part, int nblk, LzCtrl* ctrl, int m_max,
-                          hipStream_t st) {
+hipError_t launch_lz_init(bool f64, int N, int b, void* Q, const double* m, const double* Vwarm, int nwarm,
+                          const uint8_t* mask, uint64_t seed, LzCtrl* ctrl, int m_max, hipStream_t st) {
+    const int nb = lz_blocks(N);
     if (f64)
-        hipLaunchKernelGGL(k_lz_init<double>, dim3(nblk), dim3(NT), 0, st, N, (double*)Q, m, Vwarm, nwarm, mask,
-                           seed, part, ctrl, m_max);
+        hipLaunchKernelGGL(k_lz_init<double>, dim3(nb), dim3(NT), 0, st, N, b, (double*)Q, m, Vwarm, nwarm, mask,
+                           seed, ctrl, m_max);
     else
-        hipLaunchKernelGGL(k_lz_init<float>, dim3(nblk), dim3(NT), 0, st, N, (float*)Q, m, Vwarm, nwarm, mask,
-                           seed, part, ctrl, m_max);
-    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(NT), 0, st, part, nblk, -1, ctrl);
-    if (f64)
-        hipLaunchKernelGGL(k_lz_scale<double>, dim3(nblk), dim3(NT), 0, st, 2 * N, (double*)Q, 0, ctrl);
-    else
-        hipLaunchKernelGGL(k_lz_scale<float>, dim3(nblk), dim3(NT), 0, st, 2 * N, (float*)Q, 0, ctrl);
+        hipLaunchKernelGGL(k_lz_init<float>, dim3(nb), dim3(NT), 0, st, N, b, (float*)Q, m, Vwarm, nwarm, mask,
+                           seed, ctrl, m_max);
     return hipGetLastError();
 }
 
-// Orthogonalise column j + 1 (already H q_j) against columns 0..j twice,
-// normalise it, record beta.
-hipError_t launch_lz_orth(bool f64, int n2, void* Q, int j, double* part, int nblk, LzCtrl* ctrl, hipStream_t st) {
-    const int rb = (j + 1 + NT / 64 - 1) / (NT / 64);
+hipError_t launch_lz_orth(bool f64, int n2, void* Q, int c, int tj, double* part, int nblk, LzCtrl* ctrl,
+                          hipStream_t st) {
+    const int rb = (c + NT / 64 - 1) / (NT / 64);
     const int cg = rb < 1 ? 1 : rb;  // column groups of the dot kernel (one column per wave)
     for (int pass = 0; pass < 2; ++pass) {
         if (f64)
-            hipLaunchKernelGGL(k_lz_dots<double>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const double*)Q, j, part, ctrl);
-        else
-            hipLaunchKernelGGL(k_lz_dots<float>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const float*)Q, j, part, ctrl);
-        hipLaunchKernelGGL(k_lz_reduce, dim3(rb < 1 ? 1 : rb), dim3(NT), 0, st, part, nblk, j, pass, ctrl);
-        if (f64)
-            hipLaunchKernelGGL(k_lz_update<double>, dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, j, pass, part,
+            hipLaunchKernelGGL(k_lz_dots<double>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const double*)Q, c, tj, part,
                                ctrl);
         else
-            hipLaunchKernelGGL(k_lz_update<float>, dim3(nblk), dim3(NT), 0, st, n2, (float*)Q, j, pass, part, ctrl);
+            hipLaunchKernelGGL(k_lz_dots<float>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const float*)Q, c, tj, part,
+                               ctrl);
+        hipLaunchKernelGGL(k_lz_reduce, dim3(cg), dim3(NT), 0, st, part, nblk, c, tj, pass, ctrl);
+        if (f64)
+            hipLaunchKernelGGL(k_lz_update<double>, dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, c, tj, pass, part,
+                               ctrl);
+        else
+            hipLaunchKernelGGL(k_lz_update<float>, dim3(nblk), dim3(NT), 0, st, n2, (float*)Q, c, tj, pass, part,
+                               ctrl);
     }
-    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(NT), 0, st, part, nblk, j, ctrl);
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(NT), 0, st, part, nblk, c, tj, ctrl);
     if (f64)
-        hipLaunchKernelGGL(k_lz_scale<double>, dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, j + 1, ctrl);
+        hipLaunchKernelGGL(k_lz_scale<double>, dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, c, tj, ctrl);
     else
-        hipLaunchKernelGGL(k_lz_scale<float>, dim3(nblk), dim3(NT), 0, st, n2, (float*)Q, j + 1, ctrl);
+        hipLaunchKernelGGL(k_lz_scale<float>, dim3(nblk), dim3(NT), 0, st, n2, (float*)Q, c, tj, ctrl);
     return hipGetLastError();
 }
 
-hipError_t launch_lz_rr_restart(bool f64, int n2, void* Q, int k, int keep, double tol_abs, int max_restarts,
-                                int m_max, int nblk, LzCtrl* ctrl, hipStream_t st) {
+hipError_t launch_lz_rr_restart(bool f64, int n2, int b, void* Q, int k, int keep, double tol_abs, int max_restarts,
+                                int m_max, int nblk, const uint8_t* mask, int N, uint64_t seed, LzCtrl* ctrl,
+                                hipStream_t st) {
+    (void)b;
     hipLaunchKernelGGL(k_lz_rr, dim3(1), dim3(WL), 0, st, k, keep, tol_abs, max_restarts, ctrl);
     auto go = [&](auto mmc) {
         constexpr int MM = decltype(mmc)::value;
         if (f64)
-            hipLaunchKernelGGL((k_lz_restart<double, MM>), dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, ctrl);
+            hipLaunchKernelGGL((k_lz_restart<double, MM>), dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, mask, N, seed,
+                               ctrl);
         else
-            hipLaunchKernelGGL((k_lz_restart<float, MM>), dim3(nblk), dim3(NT), 0, st, n2, (float*)Q, ctrl);
+            hipLaunchKernelGGL((k_lz_restart<float, MM>), dim3(nblk), dim3(NT), 0, st, n2, (float*)Q, mask, N, seed,
+                               ctrl);
     };
     if (m_max <= 32)
         go(std::integral_constant<int, 32>{});
     else
         go(std::integral_constant<int, LZ_MAXM>{});
+    hipLaunchKernelGGL(k_lz_restart_ctrl, dim3(1), dim3(NT), 0, st, ctrl);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ class EigOpts(ctypes.Structure):
 class LanczosOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("m_max", ctypes.c_int32), ("keep", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("warm", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("block", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

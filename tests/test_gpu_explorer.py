@@ -12,6 +12,7 @@ import pytest
 
 import oracle as O
 from paper_2509_26269_amd import synth as S
+from tests import parity as P
 from tests import closed_forms as CF
 
 torch = pytest.importorskip("torch")
@@ -33,7 +34,7 @@ def _np(t):
 
 
 def _eig_tol(lam, hest, fp32):
-    return 1e-5 * max(abs(lam), hest) + (1e-5 * hest if fp32 else 0.0)
+    return P.eig_bar(lam, hest, not fp32)
 
 
 def test_explorer_fp64_matches_oracle_masked_with_archive():

@@ -10,6 +10,7 @@ import pytest
 
 import oracle as O
 from paper_2509_26269_amd import synth as S
+from tests import parity as P
 from tests import closed_forms as CF
 
 torch = pytest.importorskip("torch")
@@ -32,7 +33,7 @@ def _np(t):
 
 def _check_pairs(ev, V, ref_ev, ref_V, hest, fp32, gap_ok):
     for j in range(len(ref_ev)):
-        assert abs(ev[j] - ref_ev[j]) <= 1e-5 * max(abs(ref_ev[j]), hest) + (0 if not fp32 else 1e-5 * hest)
+        assert abs(ev[j] - ref_ev[j]) <= P.eig_bar(ref_ev[j], hest, not fp32), (j, ev[j], ref_ev[j])
         if gap_ok[j]:
             cos = abs(float((V[j] * ref_V[j]).sum()))
             if fp32:

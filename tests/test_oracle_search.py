@@ -181,3 +181,166 @@ def test_cg_rule_reaches_an_index_one_saddle_by_exact_inertia():
     assert r.status == O.SADDLE
     w = np.linalg.eigvalsh(O.dense_tangent_hessian(h, r.m))
     assert int((w < -1e-6 * h.h_est()).sum()) == 1
+
+
+# --- the L-BFGS two-loop rule (Methods, outer ascent optimisers) -----------
+def _tangent_pairs(m, n, rng, scale=1.0):
+    """n random tangent pairs (s, y) at m with s.y > 0: y = B s + small noise
+    for a random symmetric positive definite B acting per site."""
+    N = m.shape[1]
+    pairs = []
+    for _ in range(n):
+        s = O.project(m, rng.standard_normal((3, N))) * scale
+        y = O.project(m, 2.0 * s + 0.3 * O.project(m, rng.standard_normal((3, N))) * scale)
+        assert float((s * y).sum()) > 0
+        pairs.append((s, y))
+    return pairs
+
+
+def _preloaded(m, pairs, alpha0=0.05):
+    """An optimiser whose history holds `pairs` at m and no pending step (so
+    a call of direction() runs the two-loop on exactly these pairs)."""
+    opt = O.LBFGS(O.StepRule(kind="lbfgs", mem=8, theta_max=1e9), alpha0)
+    opt.S = [s.copy() for s, _ in pairs]
+    opt.Y = [y.copy() for _, y in pairs]
+    return opt
+
+
+def _dense_lbfgs(pairs, gamma):
+    """The L-BFGS inverse-Hessian approximation as a dense matrix, built by
+    applying the BFGS update H <- V^T H V + rho s s^T, V = I - rho y s^T, for
+    every pair from the oldest to the newest, starting from gamma I
+    (Nocedal & Wright, Numerical Optimization, Eq. 7.19 expanded)."""
+    n = pairs[0][0].size
+    H = gamma * np.eye(n)
+    for s, y in pairs:
+        s, y = s.reshape(-1), y.reshape(-1)
+        rho = 1.0 / float(s @ y)
+        V = np.eye(n) - rho * np.outer(y, s)
+        H = V.T @ H @ V + rho * np.outer(s, s)
+    return H
+
+
+def test_lbfgs_secant_condition_on_the_newest_pair():
+    """The two-loop matrix H maps the newest y onto the newest s, whatever the
+    older pairs and the initial scaling: d(G = y_new) = -s_new."""
+    rng = np.random.default_rng(10)
+    m = S.random_texture(16, rng)
+    for n in (1, 2, 3, 5):
+        pairs = _tangent_pairs(m, n, rng)
+        opt = _preloaded(m, pairs)
+        d = opt.direction(m, pairs[-1][1].copy())
+        assert np.allclose(d, -pairs[-1][0], rtol=1e-11, atol=1e-13), n
+
+
+def test_lbfgs_two_pair_step_written_out_densely():
+    """Two stored pairs: the direction equals -H G with H the dense BFGS
+    recursion from gamma I, gamma = s.y / y.y of the NEWEST pair; a wrong
+    gamma (the oldest pair's) or a reversed pair order gives another step."""
+    rng = np.random.default_rng(11)
+    m = S.random_texture(12, rng)
+    pairs = _tangent_pairs(m, 2, rng)
+    G = O.project(m, rng.standard_normal(m.shape))
+    s1, y1 = pairs[-1]
+    gamma = float((s1 * y1).sum()) / float((y1 * y1).sum())
+    want = -(_dense_lbfgs(pairs, gamma) @ G.reshape(-1)).reshape(G.shape)
+    d = _preloaded(m, pairs).direction(m, G.copy())
+    assert np.allclose(d, want, rtol=1e-10, atol=1e-13)
+    s0, y0 = pairs[0]
+    wrong_gamma = float((s0 * y0).sum()) / float((y0 * y0).sum())
+    alt1 = -(_dense_lbfgs(pairs, wrong_gamma) @ G.reshape(-1)).reshape(G.shape)
+    alt2 = -(_dense_lbfgs(pairs[::-1], gamma) @ G.reshape(-1)).reshape(G.shape)
+    assert np.abs(alt1 - want).max() > 1e-3 * np.abs(want).max()
+    assert np.abs(alt2 - want).max() > 1e-3 * np.abs(want).max()
+
+
+def test_lbfgs_first_step_and_curvature_skip():
+    """No pairs: d = -alpha0 G.  A pair with s.y <= sy_min is left out of the
+    recursion: the direction equals the one computed without it."""
+    rng = np.random.default_rng(12)
+    m = S.random_texture(10, rng)
+    G = O.project(m, rng.standard_normal(m.shape))
+    opt = O.LBFGS(O.StepRule(kind="lbfgs", theta_max=1e9), 0.05)
+    assert np.allclose(opt.direction(m, G.copy()), -0.05 * G, atol=1e-15)
+    good = _tangent_pairs(m, 2, rng)
+    s_bad = O.project(m, rng.standard_normal(m.shape))
+    y_bad = -s_bad  # s.y < 0
+    mixed = [good[0], (s_bad, y_bad), good[1]]
+    d_mixed = _preloaded(m, mixed).direction(m, G.copy())
+    d_good = _preloaded(m, good).direction(m, G.copy())
+    assert np.allclose(d_mixed, d_good, rtol=1e-12, atol=1e-15)
+
+
+def test_lbfgs_direction_is_descent_and_reset_clears_history():
+    """With curvature-valid pairs the two-loop matrix is positive definite,
+    so d.G < 0 for every nonzero G and the reset branch is not taken; when G
+    vanishes d.G = 0 triggers the reset: history cleared, d = -alpha0 G = 0."""
+    rng = np.random.default_rng(13)
+    m = S.random_texture(10, rng)
+    for trial in range(5):
+        pairs = _tangent_pairs(m, 4, rng)
+        G = O.project(m, rng.standard_normal(m.shape))
+        opt = _preloaded(m, pairs)
+        d = opt.direction(m, G.copy())
+        assert float((d * G).sum()) < 0
+        assert len(opt.S) == 4
+        assert np.all(np.linalg.eigvalsh(_dense_lbfgs(pairs, 0.7)) > 0)
+    opt = _preloaded(m, _tangent_pairs(m, 3, rng))
+    d = opt.direction(m, np.zeros_like(m))
+    assert np.all(d == 0.0) and opt.S == [] and opt.Y == []
+
+
+def test_lbfgs_projection_transport_and_memory():
+    """After a rotation the stored pairs are projected onto the new tangent
+    spaces, the new pair is (P d_prev, G - P G_prev), and the ring keeps the
+    `mem` newest pairs."""
+    p = S.ham_nn(8)
+    h = _ham(p)
+    m = S.nn_start(2, L=8)
+    rule = O.StepRule(kind="lbfgs", mem=2, theta_max=0.05)
+    opt = O.LBFGS(rule, 1.0 / h.h_est())
+    hist_s, hist_y = [], []
+    prev = None
+    for step in range(4):
+        G = -O.energy_grad(h, m)[3]
+        if prev is not None:
+            d_prev, G_prev = prev
+            hist_s = [O.project(m, s) for s in hist_s] + [O.project(m, d_prev)]
+            hist_y = [O.project(m, y) for y in hist_y] + [G - O.project(m, G_prev)]
+            hist_s, hist_y = hist_s[-2:], hist_y[-2:]
+        d = opt.direction(m, G.copy())
+        assert len(opt.S) == len(hist_s) <= 2
+        for a, b in zip(opt.S + opt.Y, hist_s + hist_y):
+            assert np.allclose(a, b, rtol=1e-13, atol=1e-15)
+            assert np.abs((a * m).sum(0)).max() < 1e-13   # tangent at the current m
+        prev = (d.copy(), G.copy())
+        m = O.rotate(m, d)
+
+
+# --- certification needs a converged solve (Supplementary Note 1, item ii) --
+def test_certify_rejects_unconverged_and_counts_inertia():
+    tau = 1e-3
+    assert O.certify([-1.0, 0.5], tau) == O.SADDLE
+    # an unconverged solve only bounds the eigenvalues from above
+    assert O.certify([-1.0, 0.5], tau, converged=False) == O.NOT_CONVERGED
+    # the exact inertia overrides the two Ritz values
+    assert O.certify([-1.0, 0.5], tau, n_negative=2) == O.HIGHER_INDEX
+    assert O.certify([-1.0, 0.5], tau, n_negative=1) == O.SADDLE
+    assert O.certify([-1.0, -0.5], tau) == O.HIGHER_INDEX
+    assert O.certify([-1e-4, 0.5], tau) == O.DEGENERATE
+    assert O.certify([np.nan, 0.5], tau) == O.NAN_STATUS
+
+
+def test_search_with_capped_certifying_solve_is_not_a_saddle():
+    """Stoner-Wohlfarth climb to the coherent-rotation saddle whose final
+    k = 2 solve is capped at one iteration: from a random block it cannot
+    converge, so the point is not certified, although it is index 1 (the
+    uncapped search certifies it)."""
+    p = S.ham_sw(8)
+    h = _ham(p)
+    m0 = S.add_tilt_noise(S.uniform(h.N, (1, 0, 0)), 0.02, np.random.default_rng(0))
+    r = O.saddle_search(h, m0, tau_F=1e-8, cert_max_iter=1)
+    assert r.fnorm <= 1e-8
+    assert r.status == O.NOT_CONVERGED
+    assert O.negative_count(h, r.m, 1e-6 * h.h_est()) == 1
+    assert O.saddle_search(h, m0, tau_F=1e-8).status == O.SADDLE
