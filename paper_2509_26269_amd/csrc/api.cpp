@@ -483,6 +483,7 @@ static moto_status min_modes_pop_impl(moto_plan p, moto_dtype hvp, int P, const 
     };
     HIP_TRY(launch_eig_init(f64, a, S, m, warm == 1 ? V : nullptr, warm == 1 ? k : 0, ws + L.Xsave, warm == 2,
                             mask, N, o->seed, ctrl, st));
+    HIP_TRY(launch_check_finite(m, c64, N, P, ctrl, st));
     if (P > 1) HIP_TRY(launch_eig_all_done(a, ctrl, all_done, st));
     // start: orthonormal X; HX = H X; Rayleigh-Ritz on span(X); W = HX - X Lam
     for (int pass = 0; pass < 2; ++pass) HIP_TRY(launch_orth(f64, a, 0, S, part, L.nblk_g, G, ctrl, st));
@@ -695,6 +696,7 @@ moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double* m,
     }
     const int hv_var = tuned_variant(p, hvp, 1, 1);
     HIP_TRY(launch_lz_init(f64, N, b, Q, m, o.warm ? V : nullptr, o.warm ? k : 0, mask, o.seed, ctrl, o.m_max, st));
+    HIP_TRY(launch_check_finite(m, c64, N, ctrl, st));
     const double tol_abs = o.tol * p->hest;
     // one cycle from kept column j0: re-orthonormalise the b columns j0.. (the
     // start block, or the residual block after a restart), then the steps

@@ -421,7 +421,8 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
     });
     wsync();
     symeig_wg<LD>(A, Z, r);
-    for (int i = tid; i < r; i += WL) ev[i] = A[i * LD + i];
+    // NaN ranks as +inf, so that the ranks below always form a permutation
+    for (int i = tid; i < r; i += WL) ev[i] = A[i * LD + i] == A[i * LD + i] ? A[i * LD + i] : INFINITY;
     wsync();
     for (int i = tid; i < r; i += WL) {
         const double li = ev[i];

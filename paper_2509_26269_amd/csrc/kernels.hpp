@@ -175,12 +175,17 @@ struct LzCtrl {
     int brk;         // 1: the cycle ended on a breakdown (dependent new column)
     long long n_hvp; // HVP columns applied
     double beta;     // |w| of the last orthogonalisation
+    double w0sq;     // |w|^2 of a start/residual column before its projection
     double h[LZ_NCOL];               // reorthogonalisation coefficients of the current pass
     double T[LZ_LDT * LZ_LDT];       // projected matrix Q^T H Q and the residual rows below it
     double Y[LZ_MAXM * LZ_MAXM];     // Ritz vectors of T, vector i at [i * LZ_MAXM]
     double theta[LZ_MAXM], resid[LZ_MAXM];
     EigCtrl out;     // eigenvalues, residuals and counters in the eigen-solve layout
 };
+// NaN or infinite spins or Weingarten scalars: the solve ends at once with
+// MOTO_NAN (P members of the LOBPCG population, or one Lanczos solve).
+hipError_t launch_check_finite(const double* m, const double* c, int N, int P, EigCtrl* ctrl, hipStream_t st);
+hipError_t launch_check_finite(const double* m, const double* c, int N, LzCtrl* ctrl, hipStream_t st);
 int lz_blocks(int n2);
 // Start block: column 0 = sum of the nwarm warm vectors (or SplitMix64 entries),
 // columns 1..b-1 SplitMix64 entries; masked sites zero.  Resets the control block.

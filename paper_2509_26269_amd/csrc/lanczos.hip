@@ -97,11 +97,11 @@ __device__ __forceinline__ bool lz_skip(const LzCtrl* ctrl, int tj) {
 // own wave in parallel; lane l takes the rows start + l, start + l + 64, ...
 // into two alternating partial sums (fixed order).
 template <class T>
-__global__ __launch_bounds__(NT) void k_lz_dots(int n2, const T* __restrict__ Q, int c, int tj,
+__global__ __launch_bounds__(NT) void k_lz_dots(int n2, const T* __restrict__ Q, int c, int tj, int self,
                                                 double* __restrict__ part, const LzCtrl* __restrict__ ctrl) {
     if (lz_skip(ctrl, tj)) return;
     const int col = blockIdx.y * (NT / 64) + (threadIdx.x >> 6);
-    if (col >= c) return;
+    if (col >= c + self) return;  // self = 1: also |w|^2 before the projection (slot c)
     const int per = lz_rows_per_block(n2, gridDim.x);
     const int r0 = blockIdx.x * per, r1 = min(n2, r0 + per);
     const int lane = threadIdx.x & 63;
@@ -121,13 +121,17 @@ __global__ __launch_bounds__(NT) void k_lz_dots(int n2, const T* __restrict__ Q,
 // h_q = sum_b part[b][q] for q < c (one wavefront per column).  With tj >= 0,
 // pass 0 sets column tj of T to h and pass 1 adds h to it.
 __global__ __launch_bounds__(NT) void k_lz_reduce(const double* __restrict__ part, int nblk, int c, int tj, int pass,
-                                                  LzCtrl* __restrict__ ctrl) {
+                                                  int self, LzCtrl* __restrict__ ctrl) {
     if (lz_skip(ctrl, tj)) return;
     const int lane = threadIdx.x & 63;
-    for (int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); q < c; q += gridDim.x * (NT / 64)) {
+    for (int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); q < c + self; q += gridDim.x * (NT / 64)) {
         double s = 0.0;
         for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * LZP + q];
         s = wave_sum(s);
+        if (q == c) {  // |w|^2 before the projection
+            if (lane == 0) ctrl->w0sq = s;
+            continue;
+        }
         if (lane == 0) {
             ctrl->h[q] = s;
             if (tj >= 0) {
@@ -166,10 +170,10 @@ __global__ __launch_bounds__(NT) void k_lz_update(int n2, T* __restrict__ Q, int
 
 // beta = |w| from the partials (one workgroup).  tj >= 0: one HVP counted,
 // T[c][tj] = beta, and a negligible beta ends the cycle after column tj.
-// tj < 0 (start or residual block): a vanishing column means no independent
-// direction is left (MOTO_BREAKDOWN).
+// tj < 0 (start or residual block): a column that the projection reduces to
+// rounding noise means no independent direction is left (MOTO_BREAKDOWN).
 __global__ __launch_bounds__(NT) void k_lz_beta(const double* __restrict__ part, int nblk, int c, int tj,
-                                                LzCtrl* __restrict__ ctrl) {
+                                                double rel_dep, LzCtrl* __restrict__ ctrl) {
     if (lz_skip(ctrl, tj)) return;
     __shared__ double red[NT / 64];
     double s = 0.0;
@@ -186,7 +190,10 @@ __global__ __launch_bounds__(NT) void k_lz_beta(const double* __restrict__ part,
         return;
     }
     if (tj < 0) {
-        if (!(beta > 1e-30)) {
+        // dependent: what is left after the projection is rounding of the
+        // column's own size (relative rel_dep: about 1e3 units of the basis
+        // precision)
+        if (!(beta > rel_dep * sqrt(ctrl->w0sq))) {
             ctrl->status = MOTO_BREAKDOWN;
             ctrl->done = 1;
         }
@@ -234,7 +241,8 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
     for2(m, m, [&](int r, int c) { A[r * LD + c] = 0.5 * (ctrl->T[r * LZ_LDT + c] + ctrl->T[c * LZ_LDT + r]); });
     wsync();
     symeig_wg<LD>(A, Z, m);
-    for (int i = lane; i < m; i += WL) ev[i] = A[i * LD + i];
+    // NaN ranks as +inf, so that the ranks below always form a permutation
+    for (int i = lane; i < m; i += WL) ev[i] = A[i * LD + i] == A[i * LD + i] ? A[i * LD + i] : INFINITY;
     wsync();
     for (int i = lane; i < m; i += WL) {
         const double li = ev[i];
@@ -367,16 +375,19 @@ hipError_t launch_lz_init(bool f64, int N, int b, void* Q, const double* m, cons
 
 hipError_t launch_lz_orth(bool f64, int n2, void* Q, int c, int tj, double* part, int nblk, LzCtrl* ctrl,
                           hipStream_t st) {
-    const int rb = (c + NT / 64 - 1) / (NT / 64);
-    const int cg = rb < 1 ? 1 : rb;  // column groups of the dot kernel (one column per wave)
     for (int pass = 0; pass < 2; ++pass) {
+        // the start and residual columns (tj < 0) also measure their own
+        // norm in the first pass, the scale of the dependence test
+        const int self = (tj < 0 && pass == 0) ? 1 : 0;
+        const int rb = (c + self + NT / 64 - 1) / (NT / 64);
+        const int cg = rb < 1 ? 1 : rb;  // column groups of the dot kernel (one column per wave)
         if (f64)
-            hipLaunchKernelGGL(k_lz_dots<double>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const double*)Q, c, tj, part,
-                               ctrl);
+            hipLaunchKernelGGL(k_lz_dots<double>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const double*)Q, c, tj, self,
+                               part, ctrl);
         else
-            hipLaunchKernelGGL(k_lz_dots<float>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const float*)Q, c, tj, part,
-                               ctrl);
-        hipLaunchKernelGGL(k_lz_reduce, dim3(cg), dim3(NT), 0, st, part, nblk, c, tj, pass, ctrl);
+            hipLaunchKernelGGL(k_lz_dots<float>, dim3(nblk, cg), dim3(NT), 0, st, n2, (const float*)Q, c, tj, self,
+                               part, ctrl);
+        hipLaunchKernelGGL(k_lz_reduce, dim3(cg), dim3(NT), 0, st, part, nblk, c, tj, pass, self, ctrl);
         if (f64)
             hipLaunchKernelGGL(k_lz_update<double>, dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, c, tj, pass, part,
                                ctrl);
@@ -384,7 +395,7 @@ hipError_t launch_lz_orth(bool f64, int n2, void* Q, int c, int tj, double* part
             hipLaunchKernelGGL(k_lz_update<float>, dim3(nblk), dim3(NT), 0, st, n2, (float*)Q, c, tj, pass, part,
                                ctrl);
     }
-    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(NT), 0, st, part, nblk, c, tj, ctrl);
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(NT), 0, st, part, nblk, c, tj, f64 ? 1e-12 : 1e-4, ctrl);
     if (f64)
         hipLaunchKernelGGL(k_lz_scale<double>, dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, c, tj, ctrl);
     else

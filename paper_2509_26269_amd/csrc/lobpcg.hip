@@ -24,6 +24,7 @@
 // of independent solves on lattices of one geometry (EigArgs::P, strides
 // s_ms, part_ms, g_ms); the dense per-member steps then run as P
 // workgroups side by side, so a population costs about one solve's latency.
+#include <algorithm>
 #include <type_traits>
 
 #include "dense_wg.hpp"
@@ -107,6 +108,38 @@ __global__ void k_eig_init(EigArgs a, T* __restrict__ S, const double* __restric
         S[(size_t)j * a.n2 + s] = on ? va : T(0);
         S[(size_t)j * a.n2 + N + s] = on ? vb : T(0);
     }
+}
+
+// --------------------------------------------------------------------------
+// Non-finite input (a NaN or infinite spin component or Weingarten scalar)
+// ends the solve before its first step: status MOTO_NAN, eigenvalues and
+// residuals NaN.  Launched after the control block is reset; every wave that
+// finds such a site writes the same values.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void mark_nan(EigCtrl* c) {
+    c->status = MOTO_NAN;
+    c->done = 1;
+    for (int j = 0; j < MAXB; ++j) {
+        c->lam[j] = __builtin_nan("");
+        c->resid[j] = __builtin_nan("");
+    }
+}
+__device__ __forceinline__ void mark_nan(LzCtrl* c) {
+    c->status = MOTO_NAN;
+    c->done = 1;
+    mark_nan(&c->out);
+}
+
+template <class C>
+__global__ __launch_bounds__(NT) void k_check_finite(const double* __restrict__ m, const double* __restrict__ c,
+                                                     int N, C* __restrict__ ctrl) {
+    const int y = blockIdx.y;
+    m += (size_t)y * 3 * N;
+    c += (size_t)y * N;
+    bool bad = false;
+    for (int s = blockIdx.x * NT + threadIdx.x; s < N; s += gridDim.x * NT)
+        bad = bad || !(isfinite(m[s]) && isfinite(m[N + s]) && isfinite(m[2 * N + s]) && isfinite(c[s]));
+    if (__any(bad) && (threadIdx.x & 63) == 0) mark_nan(ctrl + y);
 }
 
 // --------------------------------------------------------------------------
@@ -636,6 +669,18 @@ hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m,
     else
         hipLaunchKernelGGL(k_eig_init<float>, grid, dim3(NT), 0, st, a, (float*)S, m, Vwarm, nwarm,
                            (const float*)Xsave, use_save, mask, N, seed, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* m, const double* c, int N, int P, EigCtrl* ctrl, hipStream_t st) {
+    const int nb = std::min((N + NT - 1) / NT, 1024);
+    hipLaunchKernelGGL(k_check_finite<EigCtrl>, dim3(nb, P), dim3(NT), 0, st, m, c, N, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* m, const double* c, int N, LzCtrl* ctrl, hipStream_t st) {
+    const int nb = std::min((N + NT - 1) / NT, 1024);
+    hipLaunchKernelGGL(k_check_finite<LzCtrl>, dim3(nb, 1), dim3(NT), 0, st, m, c, N, ctrl);
     return hipGetLastError();
 }
 
