@@ -143,6 +143,26 @@ moto_status moto_energy_grad(moto_plan p, moto_dtype dt, int32_t batch, const vo
                              const uint8_t *mask, double *E, void *grad, void *c, void *F,
                              double *dE_dtheta, void *ws, size_t ws_bytes, moto_stream stream);
 
+/* Allocation-free variant of moto_energy_grad, for callers that cannot
+ * allocate or pass a workspace: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, outputs and
+ * results (bit for bit) as moto_energy_grad, minus the workspace: its
+ * per-tile partial sums go to a static device array of
+ * MOTO_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds until
+ * the process ends (its address is looked up on the first call on each
+ * device).  Calls that need more, moto_energy_grad_workspace(p, batch) >
+ * MOTO_NOALLOC_SCRATCH_BYTES (about 95 000 tiles of 32 x 8 sites: e.g. 1024
+ * lattices of 128 x 128, or one of 2048 x 2048), return MOTO_EWORKSPACE
+ * before any launch.  No device or host memory is allocated.  All calls on
+ * one GPU share that array: calls that overlap in time on one GPU (two
+ * streams, two host threads) race and must be ordered by the caller.
+ * Nothing needs clearing between calls (every partial is written before it
+ * is read). */
+#define MOTO_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+moto_status moto_energy_grad_noalloc(moto_plan p, moto_dtype dt, int32_t batch, const void *m,
+                                     const uint8_t *mask, double *E, void *grad, void *c, void *F,
+                                     double *dE_dtheta, moto_stream stream);
+
 /* ---------------------------------------------------------------------
  * Tangent Hessian-vector product, the operator of the inner layer (Methods,
  * "HVP operator mode"): W_j = M H(m) M V_j for n_vec vectors per lattice.

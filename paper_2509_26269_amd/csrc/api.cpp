@@ -239,17 +239,34 @@ size_t moto_energy_grad_workspace(moto_plan p, int32_t batch) {
     return energy_ws(p, batch);
 }
 
+namespace {
+// energy/gradient kernels with their per-tile partials in `part` (at least
+// energy_ws(p, batch) bytes), then the fixed-order reduction of E and dE/dtheta
+moto_status energy_grad_into(moto_plan p, moto_dtype dt, int batch, const void* m, const uint8_t* mask, double* E,
+                             void* grad, void* c, void* F, double* dE_dtheta, double* part, hipStream_t st) {
+    HIP_TRY(launch_energy_grad(p->g, p->k, dt == MOTO_F64, batch, m, mask, grad, c, F, part, st));
+    if (E || dE_dtheta) HIP_TRY(launch_reduce_partials(part, batch, p->g.tiles, p->ns, E, dE_dtheta, st));
+    return MOTO_OK;
+}
+}  // namespace
+
 moto_status moto_energy_grad(moto_plan p, moto_dtype dt, int32_t batch, const void* m, const uint8_t* mask,
                              double* E, void* grad, void* c, void* F, double* dE_dtheta, void* ws,
                              size_t ws_bytes, moto_stream stream) {
     if (!p || !m || batch < 1 || !hvp_ok(dt)) return MOTO_EINVAL;
     if (p->k.gen && dE_dtheta) return MOTO_EUNSUPPORTED;
-    const bool need_red = E || dE_dtheta;
     if (!ws || ws_bytes < energy_ws(p, batch)) return MOTO_EWORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(launch_energy_grad(p->g, p->k, dt == MOTO_F64, batch, m, mask, grad, c, F, (double*)ws, st));
-    if (need_red) HIP_TRY(launch_reduce_partials((double*)ws, batch, p->g.tiles, p->ns, E, dE_dtheta, st));
-    return MOTO_OK;
+    return energy_grad_into(p, dt, batch, m, mask, E, grad, c, F, dE_dtheta, (double*)ws, (hipStream_t)stream);
+}
+
+moto_status moto_energy_grad_noalloc(moto_plan p, moto_dtype dt, int32_t batch, const void* m, const uint8_t* mask,
+                                     double* E, void* grad, void* c, void* F, double* dE_dtheta, moto_stream stream) {
+    if (!p || !m || batch < 1 || !hvp_ok(dt)) return MOTO_EINVAL;
+    if (p->k.gen && dE_dtheta) return MOTO_EUNSUPPORTED;
+    if (energy_ws(p, batch) > ENERGY_SCRATCH_BYTES) return MOTO_EWORKSPACE;
+    double* part = nullptr;
+    HIP_TRY(energy_scratch(&part));
+    return energy_grad_into(p, dt, batch, m, mask, E, grad, c, F, dE_dtheta, part, (hipStream_t)stream);
 }
 
 moto_status moto_tangent_hvp(moto_plan p, moto_dtype dt, moto_layout layout, int32_t batch, const void* m,

@@ -98,6 +98,10 @@ hipError_t launch_param_grad_apply(const Geo& g, int ns, bool f64, int batch, co
                                   void* out, hipStream_t st);
 hipError_t launch_reduce_partials(const double* part, int batch, int tiles, int ns, double* E, double* dth,
                                   hipStream_t st);
+// Device address of this GPU's copy of the energy scratch array (looked up once
+// per device with that device current); ENERGY_SCRATCH_BYTES long.
+constexpr size_t ENERGY_SCRATCH_BYTES = MOTO_NOALLOC_SCRATCH_BYTES;
+hipError_t energy_scratch(double** out);
 // variant: frame-layout kernel variant (-1 = default choice), see hvp.hip;
 // vbs: elements from one lattice's vector block to the next (0 = nvec
 // vectors back to back)

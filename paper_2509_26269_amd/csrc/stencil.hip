@@ -4,6 +4,8 @@
 // Every kernel stages a (TX+4) x (TY+4) tile of 3-vectors in LDS (periodic
 // wrap at the halo) and evaluates the three-shell stencil of the spin
 // Hamiltonian (Methods, Eq. param-hamiltonian) at one site per thread.
+#include <mutex>
+
 #include "kernels.hpp"
 #include "tile_ops.hpp"
 
@@ -349,6 +351,36 @@ hipError_t launch_hessian_apply(const Geo& g, const CoefD& kd, bool f64, int bat
 hipError_t launch_topo_charge(const Geo& g, int batch, const double* m, double* part, hipStream_t st) {
     hipLaunchKernelGGL(k_topo_charge, dim3(batch * g.tiles), dim3(NT), 0, st, g, m, part);
     return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Scratch of the allocation-free energy/gradient entry point: the per-tile
+// partial sums live in this file-scope array, one copy per GPU for the life
+// of the process.  Host code must not use the array's name as an address (on
+// the host it is only a stand-in); energy_scratch() looks up each device's
+// copy once, with that device current, and hands out that pointer.
+// --------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[ENERGY_SCRATCH_BYTES / sizeof(double)];
+
+hipError_t energy_scratch(double** out) {
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static double* ptr[MAXDEV] = {};
+    *out = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        ptr[dev] = (double*)p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace moto

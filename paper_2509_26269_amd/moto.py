@@ -115,6 +115,7 @@ def lib():
         "moto_n_params": (_i32, [_vp]),
         "moto_energy_grad_workspace": (_sz, [_vp, _i32]),
         "moto_energy_grad": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "moto_energy_grad_noalloc": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "moto_tangent_hvp": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
         "moto_hessian_apply": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
         "moto_tangent_hvp_variants": (_i32, []),
@@ -272,6 +273,29 @@ def moto_energy_grad(plan: Plan, m: torch.Tensor, mask: Optional[torch.Tensor] =
     _check(lib().moto_energy_grad(plan.handle, _dt(m), batch, _ptr(m), _ptr(mask), _ptr(E), _ptr(g), _ptr(c),
                                   _ptr(F), _ptr(dth), _ptr(ws), nb, _stream(stream)), "moto_energy_grad")
     return E, g, c, F, dth
+
+
+def moto_energy_grad_noalloc(plan: Plan, m: torch.Tensor, mask: Optional[torch.Tensor] = None,
+                             want_grad: bool = True, want_c: bool = True, want_F: bool = True,
+                             want_dtheta: bool = False, out=None, stream=None):
+    """moto_energy_grad without a workspace (the library's static per-GPU
+    scratch).  `out` = (E, grad, c, F, dE/dtheta) preallocated by the caller
+    (entries may be None), so that the call itself allocates nothing."""
+    batch = m.numel() // (3 * plan.N)
+    if out is None:
+        dev = m.device
+        out = (torch.empty(batch, dtype=torch.float64, device=dev),
+               torch.empty_like(m) if want_grad else None,
+               torch.empty(m.shape[:-2] + (plan.N,), dtype=m.dtype, device=dev) if want_c else None,
+               torch.empty_like(m) if want_F else None,
+               torch.empty(batch, plan.n_params(), dtype=torch.float64, device=dev) if want_dtheta else None)
+    E, g, c, F, dth = out
+    _check(lib().moto_energy_grad_noalloc(plan.handle, _dt(m), batch, _ptr(m), _ptr(mask), _ptr(E), _ptr(g),
+                                          _ptr(c), _ptr(F), _ptr(dth), _stream(stream)), "moto_energy_grad_noalloc")
+    return E, g, c, F, dth
+
+
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 def moto_tangent_hvp(plan: Plan, m: torch.Tensor, c: torch.Tensor, V: torch.Tensor, layout: int = MOTO_FRAME,
