@@ -50,7 +50,10 @@
  *   moto_tangent_hvp, moto_hessian_apply and moto_reflected_step do not
  *   synchronise; the iterative drivers (moto_min_modes, moto_descend,
  *   moto_saddle_search, moto_saddle_search_batched) synchronise with the
- *   stream at their convergence checks and report through host structs.
+ *   stream at their convergence checks and report through host structs,
+ *   except moto_min_modes and moto_descend with the MOTO_ASYNC flag, which
+ *   queue every iteration up to the cap, report to device memory and can be
+ *   captured into a HIP graph.
  *   Return value: MOTO_OK or a negative error detected before any launch
  *   (outputs untouched) or from the HIP runtime (MOTO_EHIP).  A plan holds
  *   pinned host memory for convergence read-back: use one plan from one host
@@ -123,6 +126,9 @@ const char *moto_status_string(moto_status s);
 /* Rigorous bound on ||H||: 4 sum_delta (|J_delta| + |D_delta|) + 4|K| + |B|;
  * all relative tolerances below are multiples of it. */
 double moto_hessian_norm_bound(moto_plan p);
+/* Replays of the eigen-solvers' captured iteration graphs made with this plan
+ * so far (diagnostic: 0 means every chunk ran as plain launches). */
+int64_t moto_plan_graph_replays(moto_plan p);
 /* Number of Hamiltonian parameters theta = (J_0..J_{ns-1}, D_0..D_{ns-1}, K, Bx, By, Bz). */
 int32_t moto_n_params(moto_plan p);
 
@@ -225,8 +231,9 @@ moto_status moto_param_grad_apply(moto_plan p, moto_dtype dt, int32_t batch, con
  *          opts.warm == 1; output sign rule: the entry of largest magnitude
  *          (first in [3][N] order) is positive
  *   resid  [k] FP64 residual norms (or NULL)
- *   info   host: outcome (MOTO_CONVERGED / NOT_CONVERGED / NAN / BREAKDOWN),
- *          iterations, HVP columns applied
+ *   info   host (device with MOTO_ASYNC): outcome (MOTO_CONVERGED /
+ *          NOT_CONVERGED / NAN / BREAKDOWN), iterations, HVP columns applied
+ *          (or NULL).  NaN or infinite spins end the solve at once with NAN.
  * opts.warm == 2 reuses the full block left in ws by the previous call on
  * the same workspace (transported to the new tangent spaces).
  * Workspace: moto_min_modes_workspace(p, hvp, k, guard) bytes. */
@@ -238,8 +245,21 @@ typedef struct {
     int32_t check_every; /* iterations between host convergence checks (default 8) */
     uint64_t seed;       /* start-block seed (SplitMix64 counter generator) */
     int32_t use_graph;   /* 1: replay the iteration chunk as a captured HIP graph (default) */
-    int32_t reserved;
+    int32_t flags;       /* 0 (default) or MOTO_ASYNC */
 } moto_eig_opts;
+
+/* MOTO_ASYNC (moto_eig_opts.flags of moto_min_modes and
+ * moto_min_modes_population; moto_descend_opts.flags of moto_descend): the
+ * call does no host synchronisation and writes its outcome to DEVICE memory
+ * (moto_info / moto_descend_result pointers are then device pointers, or
+ * NULL).  Every iteration up to the cap is queued: the kernels of iterations
+ * after convergence return at once (the device done flag), so the results
+ * equal those of the synchronous call bit for bit.  The call is then
+ * stream-ordered and may be captured into a HIP graph by the caller (no
+ * allocation, no memset node, no host read-back); when the stream is being
+ * captured the library queues plain launches instead of replaying its own
+ * iteration graph. */
+#define MOTO_ASYNC 1
 
 typedef struct {
     int32_t status;
@@ -320,7 +340,8 @@ moto_status moto_reflected_step(moto_plan p, double *m, const double *F, const d
  * max_iter steps; finally one k = 1 eigen-solve at the minimum.
  *   m   [3][N] FP64: saddle in, relaxed state out
  *   v1  [3][N] FP64 unit min mode at the saddle
- *   res host: energy, topological charge (Berg-Luescher), ||F||, lambda_1. */
+ *   res host (device with MOTO_ASYNC): energy, topological charge
+ *       (Berg-Luescher), ||F||, lambda_1. */
 typedef struct {
     double eta;          /* default 0.1 rad */
     double tau_F;        /* default 1e-6 */
@@ -328,6 +349,8 @@ typedef struct {
     int32_t check_every; /* steps between host checks (default 16) */
     moto_step_opts step;
     moto_eig_opts eig;   /* final lambda_1 solve */
+    int32_t flags;       /* 0 (default) or MOTO_ASYNC (res is then a device pointer) */
+    int32_t reserved;
 } moto_descend_opts;
 
 typedef struct {

@@ -41,6 +41,7 @@ struct moto_plan_s {
     // private stream the graphs are captured on (capture is not possible on
     // the legacy default stream a caller may pass); replays use the caller's
     hipStream_t cap_stream;
+    long long graph_replays;  // replays of captured iteration chunks (diagnostic)
     // shell table of a Hamiltonian with more than three shells (k.gen points here)
     GenShells gen;
 };
@@ -148,6 +149,17 @@ bool shell_table(int ns, GenShells* t) {
 }
 
 // Read back n bytes of device memory through the plan's pinned buffer.
+// true while the caller's stream is being captured into a graph (the library
+// then queues plain launches: a replay of its own graph cannot be captured)
+bool stream_capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
 moto_status readback(moto_plan p, const void* dev, size_t n, void* host, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(p->pinned, dev, n, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -211,6 +223,7 @@ moto_status moto_plan_create(const moto_hamiltonian* h, moto_plan* out) {
     p->n_tune = 0;
     p->next_graph = 0;
     p->cap_stream = nullptr;
+    p->graph_replays = 0;
     for (auto& ge : p->graphs) ge.valid = 0;
     if (hipHostMalloc((void**)&p->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
         delete p;
@@ -238,6 +251,8 @@ size_t moto_energy_grad_workspace(moto_plan p, int32_t batch) {
     if (!p || batch < 1) return 0;
     return energy_ws(p, batch);
 }
+
+int64_t moto_plan_graph_replays(moto_plan p) { return p ? p->graph_replays : -1; }
 
 namespace {
 // energy/gradient kernels with their per-tile partials in `part` (at least
@@ -388,6 +403,7 @@ void moto_default_eig_opts(moto_dtype hvp, moto_eig_opts* o) {
     o->check_every = 8;
     o->seed = 0x2509262690ull;
     o->use_graph = 1;
+    o->flags = 0;
 }
 
 size_t moto_min_modes_workspace(moto_plan p, moto_dtype hvp, int32_t k, int32_t guard) {
@@ -443,6 +459,7 @@ static moto_status min_modes_pop_impl(moto_plan p, moto_dtype hvp, int P, const 
                                       moto_info* info, char* ws, size_t ws_bytes, hipStream_t st,
                                       const double* c64_in) {
     const int guard = resolve_guard(k, o->guard);
+    const bool async = (o->flags & MOTO_ASYNC) != 0;
     const EigLayout L = eig_layout(p, hvp, k, guard, P);
     if (L.mb > MAXB || L.mb > L.n2) return MOTO_EINVAL;
     if (ws_bytes < L.total) return MOTO_EWORKSPACE;
@@ -531,7 +548,7 @@ static moto_status min_modes_pop_impl(moto_plan p, moto_dtype hvp, int P, const 
     // private stream and replayed on the caller's; any capture failure falls
     // back to plain launches
     hipGraphExec_t gexec = nullptr;
-    if (o->use_graph) {
+    if (o->use_graph && !stream_capturing(st)) {
         long long key[8];
         double tolbits = a.tol_abs;
         std::memcpy(&key[0], &tolbits, sizeof(double));
@@ -550,17 +567,24 @@ static moto_status min_modes_pop_impl(moto_plan p, moto_dtype hvp, int P, const 
     }
     const int* done_dev = P > 1 ? all_done : &ctrl->done;
     for (int chunk = 0; chunk < max_chunks; ++chunk) {
-        int hdr[1];
-        moto_status rs = readback(p, done_dev, sizeof(hdr), hdr, st);
-        if (rs != MOTO_OK) return rs;
-        if (hdr[0]) break;
-        if (gexec)
+        if (!async) {
+            int hdr[1];
+            moto_status rs = readback(p, done_dev, sizeof(hdr), hdr, st);
+            if (rs != MOTO_OK) return rs;
+            if (hdr[0]) break;
+        }
+        if (gexec) {
             HIP_TRY(hipGraphLaunch(gexec, st));
-        else
+            p->graph_replays += 1;
+        } else {
             HIP_TRY(chunk_launches(st));
+        }
     }
     HIP_TRY(launch_eig_output(f64, a, S, m, N, V, part, ctrl, evals, resid, ws + L.Xsave, st));
-    if (info) {
+    if (async) {
+        // outcome straight into the caller's device array; no synchronisation
+        if (info) HIP_TRY(launch_eig_gather_info(P, ctrl, info, st));
+    } else if (info) {
         // status, iterations and HVP columns of every member, gathered and
         // read back at once (P <= MOTO_MAX_POPULATION fits the pinned buffer)
         HIP_TRY(launch_eig_gather_info(P, ctrl, (moto_info*)(ws + L.info), st));
@@ -587,7 +611,7 @@ moto_status moto_min_modes(moto_plan p, moto_dtype hvp, const double* m, const u
         o = *opts;
     else
         moto_default_eig_opts(hvp, &o);
-    if (o.max_iter < 0 || !(o.tol >= 0.0) || o.warm < 0 || o.warm > 2) return MOTO_EINVAL;
+    if (o.max_iter < 0 || !(o.tol >= 0.0) || o.warm < 0 || o.warm > 2 || (o.flags & ~MOTO_ASYNC)) return MOTO_EINVAL;
     if (!ws) return MOTO_EWORKSPACE;
     return min_modes_impl(p, hvp, m, mask, k, &o, evals, V, resid, info, (char*)ws, ws_bytes,
                           (hipStream_t)stream, nullptr);
@@ -608,7 +632,7 @@ moto_status moto_min_modes_population(moto_plan p, moto_dtype hvp, int32_t P, co
         o = *opts;
     else
         moto_default_eig_opts(hvp, &o);
-    if (o.max_iter < 0 || !(o.tol >= 0.0) || o.warm < 0 || o.warm > 2) return MOTO_EINVAL;
+    if (o.max_iter < 0 || !(o.tol >= 0.0) || o.warm < 0 || o.warm > 2 || (o.flags & ~MOTO_ASYNC)) return MOTO_EINVAL;
     if (!ws) return MOTO_EWORKSPACE;
     return min_modes_pop_impl(p, hvp, P, m, mask, k, &o, evals, V, resid, info, (char*)ws, ws_bytes,
                               (hipStream_t)stream, nullptr);
@@ -757,8 +781,10 @@ moto_status moto_min_modes_lanczos(moto_plan p, moto_dtype hvp, const double* m,
     for (int c = 0; c <= o.max_restarts + 1; ++c) {
         if (c == 0)
             HIP_TRY(cycle(0, st));
-        else if (gexec && hdr[5] == keep)
+        else if (gexec && hdr[5] == keep) {
             HIP_TRY(hipGraphLaunch(gexec, st));
+            p->graph_replays += 1;
+        }
         else
             HIP_TRY(cycle(hdr[5], st));  // a breakdown kept fewer Ritz vectors than `keep`
         HIP_TRY(launch_lz_rr_restart(f64, L.n2, b, Q, k, keep, tol_abs, o.max_restarts, o.m_max, L.nblk, mask, N,
@@ -839,6 +865,8 @@ void moto_default_descend_opts(moto_dtype hvp, moto_descend_opts* o) {
     o->check_every = 16;
     moto_default_step_opts(&o->step);
     moto_default_eig_opts(hvp, &o->eig);
+    o->flags = 0;
+    o->reserved = 0;
 }
 
 // Descent / search workspace: [energy partials][F 3N][out 2][state][eig ws][V k_max 3N][evals]
@@ -888,7 +916,8 @@ moto_status moto_descend(moto_plan p, moto_dtype hvp, double* m, const double* v
         o = *opts;
     else
         moto_default_descend_opts(hvp, &o);
-    if (!(o.eta > 0.0) || o.max_iter < 0) return MOTO_EINVAL;
+    if (!(o.eta > 0.0) || o.max_iter < 0 || (o.flags & ~MOTO_ASYNC)) return MOTO_EINVAL;
+    const bool async = (o.flags & MOTO_ASYNC) != 0;
     o.step.tau_F = o.tau_F;
     StepArgs a;
     if (!fill_step_args(p, &o.step, 0, &a)) return MOTO_EINVAL;
@@ -900,19 +929,22 @@ moto_status moto_descend(moto_plan p, moto_dtype hvp, double* m, const double* v
     double* F = (double*)(w + L.F);
     double* out = (double*)(w + L.out);
     double* part = (double*)(w + L.epart);
-    HIP_TRY(hipMemsetAsync(w + L.state, 0, step_state_bytes(N, o.step.mem), st));
-    HIP_TRY(hipMemsetAsync(out, 0, sizeof(double) * 2, st));
+    HIP_TRY(launch_zero(w + L.state, step_state_bytes(N, o.step.mem), st));
+    HIP_TRY(launch_zero(out, sizeof(double) * 4, st));
     HIP_TRY(launch_seed_rotate(N, m, v1, sign * o.eta, part, st));
     const int every = o.check_every > 0 ? o.check_every : 16;
     int it = 0;
     double ho[2] = {0.0, 0.0};
     while (it < o.max_iter) {
-        const int n = std::min(every, o.max_iter - it);
+        // the step kernels return at once after the stop test has passed, so
+        // the steps queued past it (all of them with MOTO_ASYNC) change nothing
+        const int n = async ? o.max_iter : std::min(every, o.max_iter - it);
         for (int q = 0; q < n; ++q) {
             HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, nullptr, nullptr, nullptr, F, part, st));
             HIP_TRY(launch_step(a, m, F, nullptr, w + L.state, out, st));
         }
         it += n;
+        if (async) break;
         moto_status rs = readback(p, out, sizeof(ho), ho, st);
         if (rs != MOTO_OK) return rs;
         if (ho[1] != 0.0 || !std::isfinite(ho[0])) break;
@@ -921,17 +953,22 @@ moto_status moto_descend(moto_plan p, moto_dtype hvp, double* m, const double* v
     double* E = (double*)(w + L.ev);
     HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, nullptr, nullptr, nullptr, F, part, st));
     HIP_TRY(launch_reduce_partials(part, 1, p->g.tiles, p->ns, E, nullptr, st));
-    // residual force norm after the last step: one more stop test with a zero-step state
+    // lambda_1 at the relaxed state
     moto_eig_opts eo = o.eig;
     eo.warm = 0;
+    eo.flags = async ? MOTO_ASYNC : 0;
     double lam = 0.0;
     moto_info inf;
-    moto_status rs = min_modes_impl(p, hvp, m, nullptr, 1, &eo, E + 1, (double*)(w + L.V), nullptr, &inf,
-                                    w + L.eig, ws_bytes - L.eig, st, nullptr);
+    moto_status rs = min_modes_impl(p, hvp, m, nullptr, 1, &eo, E + 1, (double*)(w + L.V), nullptr,
+                                    async ? nullptr : &inf, w + L.eig, ws_bytes - L.eig, st, nullptr);
     if (rs != MOTO_OK) return rs;
     HIP_TRY(launch_topo_charge(p->g, 1, m, part, st));
     double Qd[1];
     HIP_TRY(launch_reduce_partials(part, 1, p->g.tiles, p->ns, (double*)(w + L.out) + 2, nullptr, st));
+    if (async) {
+        HIP_TRY(launch_descend_result(w + L.state, N, o.step.mem, out, E, out + 2, (moto_descend_result*)res, st));
+        return MOTO_OK;
+    }
     double hv[4];
     rs = readback(p, w + L.ev, 2 * sizeof(double), hv, st);
     if (rs != MOTO_OK) return rs;
@@ -1019,6 +1056,7 @@ moto_status moto_saddle_search(moto_plan p, moto_dtype hvp, double* m, const uin
         HIP_TRY(launch_energy_grad(p->g, p->k, true, 1, m, mask, nullptr, nullptr, F, part, st));
         moto_eig_opts eo = o.eig;
         eo.warm = it == 0 ? 0 : 2;
+        eo.flags = 0;  // the driver reads the outcome on the host
         moto_info inf;
         moto_status rs = min_modes_impl(p, hvp, m, mask, o.k, &eo, ev, V, nullptr, &inf, w + L.eig,
                                         ws_bytes - L.eig, st, nullptr);
@@ -1044,6 +1082,7 @@ moto_status moto_saddle_search(moto_plan p, moto_dtype hvp, double* m, const uin
     moto_eig_opts eo = o.eig;
     eo.warm = 0;
     eo.seed = o.eig.seed + 1;
+    eo.flags = 0;
     moto_info inf;
     moto_status rs = min_modes_impl(p, hvp, m, mask, kc, &eo, ev, V, nullptr, &inf, w + L.eig, ws_bytes - L.eig,
                                     st, nullptr);
@@ -1183,6 +1222,7 @@ moto_status moto_saddle_search_population(moto_plan p, moto_dtype hvp, int32_t P
         HIP_TRY(launch_energy_grad(p->g, p->k, true, P, m, mask, nullptr, nullptr, F, part, st));
         moto_eig_opts eo = o.eig;
         eo.warm = it == 0 ? 0 : 2;
+        eo.flags = 0;  // the driver reads the outcome on the host
         moto_status rs = min_modes_pop_impl(p, hvp, P, m, mask, o.k, &eo, ev, V, nullptr, inf.data(), eigw,
                                             eig_bytes, st, nullptr);
         if (rs != MOTO_OK) return rs;
@@ -1217,6 +1257,7 @@ moto_status moto_saddle_search_population(moto_plan p, moto_dtype hvp, int32_t P
     moto_eig_opts eo = o.eig;
     eo.warm = 0;
     eo.seed = o.eig.seed + 1;
+    eo.flags = 0;
     moto_status rs = min_modes_pop_impl(p, hvp, P, m, mask, kc, &eo, ev, V, nullptr, inf.data(), eigw, eig_bytes, st,
                                         nullptr);
     if (rs != MOTO_OK) return rs;
@@ -1488,7 +1529,9 @@ moto_status moto_explorer_objectives(moto_plan p, moto_dtype hvp, int32_t P, con
     // l1 distances to S u A
     HIP_TRY(launch_l1(3LL * N, P, n_archive, x_out, archive, (double*)(w + L.l1), Db, st));
     // the k lowest modes of every candidate, in lock step
-    moto_status rs = min_modes_pop_impl(p, hvp, P, x_out, mrep, k, &o.eig, ev, Vb, nullptr, nullptr, w + L.eig,
+    moto_eig_opts eo = o.eig;
+    eo.flags = 0;
+    moto_status rs = min_modes_pop_impl(p, hvp, P, x_out, mrep, k, &eo, ev, Vb, nullptr, nullptr, w + L.eig,
                                         L.mask - L.eig, st, c);
     if (rs != MOTO_OK) return rs;
     const EigLayout EL = eig_layout(p, hvp, k, resolve_guard(k, o.eig.guard), P);

@@ -257,6 +257,12 @@ hipError_t launch_seed_rotate(int N, double* m, const double* v1, double scale_s
                               hipStream_t st);
 hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t st);
 hipError_t launch_mask_zero(double* v, const uint8_t* mask, int N, int ncomp, hipStream_t st);
+// zero `bytes` (a multiple of 16) at a 16-byte aligned device address (a
+// kernel, not a memset node: the drivers stay graph-capturable)
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// moto_descend_result from device values (MOTO_ASYNC descent)
+hipError_t launch_descend_result(void* state, int N, int mem, const double* out, const double* Eo, const double* Q,
+                                 moto_descend_result* res, hipStream_t st);
 
 // ---- batched.hip ----
 struct BatchArgs {

@@ -520,6 +520,45 @@ __global__ void k_mask_zero(double* __restrict__ v, const uint8_t* __restrict__ 
     for (int c = 0; c < ncomp; ++c) v[(size_t)c * N + s] = 0.0;
 }
 
+// zero fill of a byte range in 16-byte words (buffers are 256-byte aligned);
+// a kernel rather than a memset so that the drivers stay graph-capturable
+__global__ __launch_bounds__(NT) void k_zero(uint4* __restrict__ p, size_t n16) {
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n16; i += (size_t)gridDim.x * NT) p[i] = z;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+    if (bytes % 16 != 0 || ((uintptr_t)p & 15) != 0) return hipErrorInvalidValue;
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    const size_t nb = (n16 + NT - 1) / NT;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)(nb < 1024 ? nb : 1024)), dim3(NT), 0, st, (uint4*)p, n16);
+    return hipGetLastError();
+}
+
+// The descent's outcome assembled on the device (MOTO_ASYNC): stop flag and
+// ||F|| from the step output, steps taken from the step state, energy and
+// lambda_1 (Eo[0], Eo[1]) and the charge Q.
+__global__ void k_descend_result(StepPtrs P, const double* __restrict__ out, const double* __restrict__ Eo,
+                                 const double* __restrict__ Q, moto_descend_result* __restrict__ res) {
+    if (threadIdx.x != 0) return;
+    moto_descend_result r;
+    r.converged = out[1] != 0.0 ? 1 : 0;
+    r.iters = P.hdr->iters;
+    r.E = Eo[0];
+    r.Q = Q[0];
+    r.fnorm = out[0];
+    r.lambda1 = Eo[1];
+    *res = r;
+}
+
+hipError_t launch_descend_result(void* state, int N, int mem, const double* out, const double* Eo, const double* Q,
+                                 moto_descend_result* res, hipStream_t st) {
+    StepPtrs P = step_ptrs(state, N, mem, nullptr);
+    hipLaunchKernelGGL(k_descend_result, dim3(1), dim3(64), 0, st, P, out, Eo, Q, res);
+    return hipGetLastError();
+}
+
 hipError_t launch_mask_zero(double* v, const uint8_t* mask, int N, int ncomp, hipStream_t st) {
     hipLaunchKernelGGL(k_mask_zero, dim3((N + NT - 1) / NT), dim3(NT), 0, st, v, mask, N, ncomp);
     return hipGetLastError();

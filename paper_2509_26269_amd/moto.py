@@ -22,6 +22,7 @@ MOTO_F32, MOTO_F64 = 0, 1
 MOTO_AMBIENT, MOTO_FRAME = 0, 1
 MAX_SHELLS = 36
 
+MOTO_ASYNC = 1  # option flag: no host synchronisation, outcome in device memory
 SADDLE = CONVERGED = 0
 NOT_CONVERGED, DEGENERATE, HIGHER_INDEX, NAN, BREAKDOWN = 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "SADDLE/CONVERGED", 1: "NOT_CONVERGED", 2: "DEGENERATE", 3: "HIGHER_INDEX", 4: "NAN",
@@ -41,7 +42,7 @@ class _Ham(ctypes.Structure):
 class EigOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("guard", ctypes.c_int32),
                 ("warm", ctypes.c_int32), ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class LanczosOpts(ctypes.Structure):
@@ -61,7 +62,8 @@ class StepOpts(ctypes.Structure):
 
 class DescendOpts(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("tau_F", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("step", StepOpts), ("eig", EigOpts)]
+                ("check_every", ctypes.c_int32), ("step", StepOpts), ("eig", EigOpts),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class DescendResult(ctypes.Structure):
@@ -112,6 +114,7 @@ def lib():
         "moto_plan_destroy": (_i32, [_vp]),
         "moto_status_string": (ctypes.c_char_p, [_i32]),
         "moto_hessian_norm_bound": (ctypes.c_double, [_vp]),
+        "moto_plan_graph_replays": (ctypes.c_int64, [_vp]),
         "moto_n_params": (_i32, [_vp]),
         "moto_energy_grad_workspace": (_sz, [_vp, _i32]),
         "moto_energy_grad": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -127,7 +130,7 @@ def lib():
         "moto_param_grad_apply": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
         "moto_min_modes_workspace": (_sz, [_vp, _i32, _i32, _i32]),
         "moto_min_modes": (_i32, [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(EigOpts), _vp, _vp, _vp,
-                                  ctypes.POINTER(Info), _vp, _sz, _vp]),
+                                  _vp, _vp, _sz, _vp]),
         "moto_default_lanczos_opts": (None, [_i32, ctypes.POINTER(LanczosOpts)]),
         "moto_min_modes_lanczos_workspace": (_sz, [_vp, _i32, _i32]),
         "moto_min_modes_lanczos": (_i32, [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(LanczosOpts), _vp, _vp, _vp,
@@ -139,7 +142,7 @@ def lib():
         "moto_reflected_step": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(StepOpts), _vp, _vp, _vp]),
         "moto_descend_workspace": (_sz, [_vp, _i32, ctypes.POINTER(DescendOpts)]),
         "moto_descend": (_i32, [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(DescendOpts),
-                                ctypes.POINTER(DescendResult), _vp, _sz, _vp]),
+                                _vp, _vp, _sz, _vp]),
         "moto_saddle_search_workspace": (_sz, [_vp, _i32, ctypes.POINTER(SearchOpts)]),
         "moto_saddle_search": (_i32, [_vp, _i32, _vp, _vp, ctypes.POINTER(SearchOpts), ctypes.POINTER(SearchResult),
                                       _vp, _vp, _vp, _sz, _vp]),
@@ -258,6 +261,11 @@ class Plan:
 
 
 # ---------------------------------------------------------------------------
+def graph_replays(plan: Plan) -> int:
+    """Replays of the eigen-solvers' own iteration graphs made with this plan."""
+    return int(lib().moto_plan_graph_replays(plan.handle))
+
+
 def moto_energy_grad(plan: Plan, m: torch.Tensor, mask: Optional[torch.Tensor] = None, want_grad: bool = True,
                      want_c: bool = True, want_F: bool = True, want_dtheta: bool = False, stream=None):
     """E [batch] (FP64), grad, c, F (dtype of m), dE/dtheta [batch][n_params] (FP64)."""
@@ -462,7 +470,11 @@ class EigWorkspace:
 
 def moto_min_modes(plan: Plan, m: torch.Tensor, k: int, hvp: int = MOTO_F64, mask: Optional[torch.Tensor] = None,
                    opts: Optional[EigOpts] = None, V0: Optional[torch.Tensor] = None,
-                   ws: Optional[EigWorkspace] = None, stream=None) -> MinModes:
+                   ws: Optional[EigWorkspace] = None, info_dev: Optional[torch.Tensor] = None,
+                   stream=None) -> MinModes:
+    """With opts.flags = MOTO_ASYNC the call does not synchronise: the outcome
+    (moto_info: status, iterations, HVP columns) goes to the 16-byte device
+    tensor info_dev (or nowhere), and status/iters/n_hvp of the result are None."""
     o = opts if opts is not None else eig_opts(hvp)
     dev = m.device
     V = torch.zeros(k, 3, plan.N, dtype=torch.float64, device=dev) if V0 is None else V0.clone().contiguous()
@@ -472,9 +484,16 @@ def moto_min_modes(plan: Plan, m: torch.Tensor, k: int, hvp: int = MOTO_F64, mas
     resid = torch.empty(k, dtype=torch.float64, device=dev)
     if ws is None:
         ws = EigWorkspace(plan, hvp, k, o.guard, dev)
+    if o.flags & MOTO_ASYNC:
+        if info_dev is not None and info_dev.numel() * info_dev.element_size() < ctypes.sizeof(Info):
+            raise MotoError("info_dev must hold one moto_info (16 bytes)")
+        _check(lib().moto_min_modes(plan.handle, hvp, _ptr(m), _ptr(mask), k, ctypes.byref(o), _ptr(evals), _ptr(V),
+                                    _ptr(resid), _ptr(info_dev), _ptr(ws.buf), ws.nbytes, _stream(stream)),
+               "moto_min_modes")
+        return MinModes(evals, V, resid, None, None, None)
     info = Info()
     _check(lib().moto_min_modes(plan.handle, hvp, _ptr(m), _ptr(mask), k, ctypes.byref(o), _ptr(evals), _ptr(V),
-                                _ptr(resid), ctypes.byref(info), _ptr(ws.buf), ws.nbytes, _stream(stream)),
+                                _ptr(resid), ctypes.addressof(info), _ptr(ws.buf), ws.nbytes, _stream(stream)),
            "moto_min_modes")
     return MinModes(evals, V, resid, info.status, info.iters, info.n_hvp)
 
@@ -513,6 +532,8 @@ def moto_min_modes_population(plan: Plan, m: torch.Tensor, k: int, hvp: int = MO
     if V0 is not None and V0.numel() != P * k * 3 * plan.N:
         raise MotoError("V0 must be [P, k, 3, N]")
     o = opts if opts is not None else eig_opts(hvp)
+    if o.flags & MOTO_ASYNC:
+        raise MotoError("moto_min_modes_population: this binding reads the outcome on the host (no MOTO_ASYNC)")
     dev = m.device
     V = torch.zeros(P, k, 3, plan.N, dtype=torch.float64, device=dev) if V0 is None else V0.clone().contiguous()
     if V0 is not None and o.warm == 0:
@@ -550,13 +571,22 @@ def moto_reflected_step(plan: Plan, m: torch.Tensor, F: torch.Tensor, V: Optiona
 
 
 def moto_descend(plan: Plan, m: torch.Tensor, v1: torch.Tensor, sign: int, hvp: int = MOTO_F64,
-                 opts: Optional[DescendOpts] = None, stream=None) -> DescendResult:
+                 opts: Optional[DescendOpts] = None, res_dev: Optional[torch.Tensor] = None,
+                 stream=None) -> Optional[DescendResult]:
+    """With opts.flags = MOTO_ASYNC the result struct goes to the device
+    tensor res_dev (sizeof(DescendResult) bytes) and None is returned."""
     o = opts if opts is not None else descend_opts(hvp)
     nb = int(lib().moto_descend_workspace(plan.handle, hvp, ctypes.byref(o)))
     ws = _ws(nb, m.device)
+    if o.flags & MOTO_ASYNC:
+        if res_dev is None or res_dev.numel() * res_dev.element_size() < ctypes.sizeof(DescendResult):
+            raise MotoError("res_dev must hold one moto_descend_result")
+        _check(lib().moto_descend(plan.handle, hvp, _ptr(m), _ptr(v1), int(sign), ctypes.byref(o), _ptr(res_dev),
+                                  _ptr(ws), nb, _stream(stream)), "moto_descend")
+        return None
     res = DescendResult()
-    _check(lib().moto_descend(plan.handle, hvp, _ptr(m), _ptr(v1), int(sign), ctypes.byref(o), ctypes.byref(res),
-                              _ptr(ws), nb, _stream(stream)), "moto_descend")
+    _check(lib().moto_descend(plan.handle, hvp, _ptr(m), _ptr(v1), int(sign), ctypes.byref(o),
+                              ctypes.addressof(res), _ptr(ws), nb, _stream(stream)), "moto_descend")
     return res
 
 
