@@ -489,14 +489,41 @@ moto_status moto_saddle_search_population(moto_plan p, moto_dtype hvp, int32_t P
  *   h      host: Hamiltonian (Lx, Ly ignored)
  *   L      host [n] lattice sides
  *   m_all  device FP64: the n starts back to back, [3][L_b^2] each; final points out
+ *   mask_all device uint8 [sum_b L_b^2] active sites of every lattice, back
+ *          to back (or NULL: all active): the climb, its eigen-solves and the
+ *          certification then work in the masked tangent subspace
+ *          (Algorithm 1: the minimum mode of the masked tangent Hessian;
+ *          Methods: masked perturbation x0 + P_Omega delta), and the spins
+ *          of inactive sites stay fixed
  *   res    device [n] results (status, iterations, HVP columns, E, ||F_mmf||, lambda_1, lambda_2)
  * The call uploads the small descriptor arrays (synchronising once before
  * the launch) and returns after queueing the launch.
  * Workspace: moto_saddle_search_batched_workspace(n, L, opts) bytes. */
+#define MOTO_TILE_32x8 0  /* tile shapes of the lattice loops: 32 x 8 output sites */
+#define MOTO_TILE_16x16 1 /* 16 x 16 */
+#define MOTO_TILE_64x4 2  /* 64 x 4 */
 size_t moto_saddle_search_batched_workspace(int32_t n, const int32_t *L /* host */, const moto_search_opts *o);
+/*   tiles  host [n] tile shape of each lattice (MOTO_TILE_*), e.g. from
+ *          moto_saddle_search_batched_autotune; NULL: 32 x 8 everywhere */
 moto_status moto_saddle_search_batched(const moto_hamiltonian *h, int32_t n, const int32_t *L /* host */,
-                                       double *m_all, const moto_search_opts *opts /* host */,
-                                       moto_search_result *res, void *ws, size_t ws_bytes, moto_stream stream);
+                                       double *m_all, const uint8_t *mask_all, const int32_t *tiles /* host */,
+                                       const moto_search_opts *opts /* host */, moto_search_result *res, void *ws,
+                                       size_t ws_bytes, moto_stream stream);
+
+/* Autotuner of the batching form's tile shapes (systems; the paper runs its
+ * searches one by one): the lattices are grouped by side into buckets 8
+ * apart; for each bucket up to 4 members run 2 outer steps of the batched
+ * search from copies of their starts (m_all and mask_all are not changed)
+ * with each tile shape, timed on the stream with events, and the fastest
+ * shape is written to tiles[] (host [n]) for every member of the bucket.
+ * Synchronises with the stream.  Same arguments as the batched search
+ * otherwise.  Workspace: moto_saddle_search_batched_autotune_workspace. */
+size_t moto_saddle_search_batched_autotune_workspace(int32_t n, const int32_t *L /* host */,
+                                                     const moto_search_opts *o);
+moto_status moto_saddle_search_batched_autotune(const moto_hamiltonian *h, int32_t n, const int32_t *L /* host */,
+                                                const double *m_all, const uint8_t *mask_all,
+                                                const moto_search_opts *opts /* host */, int32_t *tiles /* host */,
+                                                void *ws, size_t ws_bytes, moto_stream stream);
 
 /* ---------------------------------------------------------------------
  * Explorer objectives (Methods, "Multi-objective initial-configuration

@@ -1322,13 +1322,15 @@ static moto_status check_ham(const moto_hamiltonian* h, bool need_size) {
 }
 
 struct BatchHostLayout {
-    size_t Ls, order, moff, woff, res0, total;
+    size_t Ls, tiles, order, moff, woff, res0, total;
     std::vector<long long> m_off, ws_off;
 };
 
 static bool batch_layout_host(int32_t n, const int32_t* L, int mem, BatchHostLayout* o) {
     size_t p = 0;
     o->Ls = p;
+    p += al(sizeof(int) * (size_t)n);
+    o->tiles = p;
     p += al(sizeof(int) * (size_t)n);
     o->order = p;
     p += al(sizeof(int) * (size_t)n);
@@ -1364,9 +1366,12 @@ size_t moto_saddle_search_batched_workspace(int32_t n, const int32_t* L, const m
     return bl.total;
 }
 
-moto_status moto_saddle_search_batched(const moto_hamiltonian* h, int32_t n, const int32_t* L, double* m_all,
-                                       const moto_search_opts* opts, moto_search_result* res, void* ws,
-                                       size_t ws_bytes, moto_stream stream) {
+// the batched launch with explicit tile shapes; ev0 / ev1 (optional) are
+// recorded around the kernel alone
+static moto_status batched_impl(const moto_hamiltonian* h, int32_t n, const int32_t* L, double* m_all,
+                                const uint8_t* mask_all, const int32_t* tiles, const moto_search_opts* opts,
+                                moto_search_result* res, void* ws, size_t ws_bytes, hipStream_t st,
+                                hipEvent_t ev0, hipEvent_t ev1) {
     moto_status cs = check_ham(h, false);
     if (cs != MOTO_OK) return cs;
     if (n < 1 || !L || !m_all || !res) return MOTO_EINVAL;
@@ -1378,6 +1383,12 @@ moto_status moto_saddle_search_batched(const moto_hamiltonian* h, int32_t n, con
     if (o.k < 1 || o.k > 2 || o.k_cert > 2 || o.k_reflect != 1 || o.max_outer < 0 || o.step.rule != 0 ||
         o.step.mem < 1 || o.step.mem > 16 || !(o.step.theta_max > 0.0) || o.eig.max_iter < 0)
         return MOTO_EINVAL;
+    std::vector<int> tl(n, MOTO_TILE_32x8);
+    if (tiles)
+        for (int i = 0; i < n; ++i) {
+            if (tiles[i] < MOTO_TILE_32x8 || tiles[i] > MOTO_TILE_64x4) return MOTO_EINVAL;
+            tl[i] = tiles[i];
+        }
     BatchHostLayout bl;
     if (!batch_layout_host(n, L, o.step.mem, &bl)) return MOTO_EINVAL;
     if (!ws || ws_bytes < bl.total) return MOTO_EWORKSPACE;
@@ -1386,8 +1397,8 @@ moto_status moto_saddle_search_batched(const moto_hamiltonian* h, int32_t n, con
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return L[a] > L[b]; });
     char* w = (char*)ws;
-    hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(w + bl.Ls, L, sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + bl.tiles, tl.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + bl.order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + bl.moff, bl.m_off.data(), sizeof(long long) * n, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + bl.woff, bl.ws_off.data(), sizeof(long long) * n, hipMemcpyHostToDevice, st));
@@ -1419,10 +1430,123 @@ moto_status moto_saddle_search_batched(const moto_hamiltonian* h, int32_t n, con
     a.eig_max_iter = o.eig.max_iter;
     a.n = n;
     a.seed = o.eig.seed;
-    HIP_TRY(launch_batched_search(a, m_all, (const int*)(w + bl.Ls), (const int*)(w + bl.order),
-                                  (const long long*)(w + bl.moff), (const long long*)(w + bl.woff), w + bl.res0, res, n,
-                                  st));
+    if (ev0) HIP_TRY(hipEventRecord(ev0, st));
+    HIP_TRY(launch_batched_search(a, m_all, mask_all, (const int*)(w + bl.Ls), (const int*)(w + bl.tiles),
+                                  (const int*)(w + bl.order), (const long long*)(w + bl.moff),
+                                  (const long long*)(w + bl.woff), w + bl.res0, res, n, st));
+    if (ev1) HIP_TRY(hipEventRecord(ev1, st));
     return MOTO_OK;
+}
+
+moto_status moto_saddle_search_batched(const moto_hamiltonian* h, int32_t n, const int32_t* L, double* m_all,
+                                       const uint8_t* mask_all, const int32_t* tiles, const moto_search_opts* opts,
+                                       moto_search_result* res, void* ws, size_t ws_bytes, moto_stream stream) {
+    return batched_impl(h, n, L, m_all, mask_all, tiles, opts, res, ws, ws_bytes, (hipStream_t)stream, nullptr,
+                        nullptr);
+}
+
+// Autotuner of the batched searches' tile shapes, per lattice-size bucket
+// (sides 8 apart): up to BATCH_TUNE_SAMPLE members of each bucket run
+// BATCH_TUNE_STEPS outer steps from copies of their starts with every shape;
+// the fastest kernel time wins for the whole bucket.
+namespace {
+constexpr int BATCH_TUNE_SAMPLE = 4;
+constexpr int BATCH_TUNE_STEPS = 2;
+constexpr int BATCH_TUNE_BUCKET = 8;
+size_t batch_tune_extra(int32_t n, const int32_t* L) {
+    size_t m = 0, k = 0;
+    for (int i = 0; i < n; ++i) {
+        m += 3ull * L[i] * L[i];
+        k += (size_t)L[i] * L[i];
+    }
+    return al(sizeof(double) * m) + al(k) + al(sizeof(moto_search_result) * (size_t)n);
+}
+}  // namespace
+
+size_t moto_saddle_search_batched_autotune_workspace(int32_t n, const int32_t* L, const moto_search_opts* o) {
+    const size_t b = moto_saddle_search_batched_workspace(n, L, o);
+    return b == 0 ? 0 : b + batch_tune_extra(n, L);
+}
+
+moto_status moto_saddle_search_batched_autotune(const moto_hamiltonian* h, int32_t n, const int32_t* L,
+                                                const double* m_all, const uint8_t* mask_all,
+                                                const moto_search_opts* opts, int32_t* tiles, void* ws,
+                                                size_t ws_bytes, moto_stream stream) {
+    if (!h || n < 1 || !L || !m_all || !tiles) return MOTO_EINVAL;
+    const size_t base = moto_saddle_search_batched_workspace(n, L, opts);
+    if (base == 0) return MOTO_EINVAL;
+    if (!ws || ws_bytes < base + batch_tune_extra(n, L)) return MOTO_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    moto_search_opts o;
+    if (opts)
+        o = *opts;
+    else
+        moto_default_search_opts(MOTO_F32, &o);
+    o.max_outer = BATCH_TUNE_STEPS;
+    std::vector<long long> off(n);
+    long long acc = 0;
+    for (int i = 0; i < n; ++i) {
+        off[i] = acc;
+        acc += 3LL * L[i] * L[i];
+    }
+    char* w = (char*)ws;
+    double* mcopy = (double*)(w + base);
+    uint8_t* kcopy = (uint8_t*)(w + base + al(sizeof(double) * (size_t)acc));
+    moto_search_result* rcopy = (moto_search_result*)(w + base + al(sizeof(double) * (size_t)acc) + al((size_t)acc / 3));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MOTO_EHIP;
+    }
+    moto_status rs = MOTO_OK;
+    for (int i = 0; i < n; ++i) tiles[i] = MOTO_TILE_32x8;
+    int maxb = 0;
+    for (int i = 0; i < n; ++i) maxb = std::max(maxb, L[i] / BATCH_TUNE_BUCKET);
+    for (int bk = 0; bk <= maxb && rs == MOTO_OK; ++bk) {
+        std::vector<int> mem;
+        for (int i = 0; i < n; ++i)
+            if (L[i] / BATCH_TUNE_BUCKET == bk) mem.push_back(i);
+        if (mem.empty()) continue;
+        const int ns = std::min((int)mem.size(), BATCH_TUNE_SAMPLE);
+        std::vector<int32_t> Ls(ns), tl(ns);
+        for (int q = 0; q < ns; ++q) Ls[q] = L[mem[q]];
+        float best = 0.0f;
+        int best_tile = MOTO_TILE_32x8;
+        for (int t = MOTO_TILE_32x8; t <= MOTO_TILE_64x4 && rs == MOTO_OK; ++t) {
+            // fresh copies of the sampled starts (the search moves them)
+            long long o2 = 0;
+            for (int q = 0; q < ns; ++q) {
+                const size_t nn = 3ull * Ls[q] * Ls[q];
+                if (hipMemcpyAsync(mcopy + o2, m_all + off[mem[q]], sizeof(double) * nn, hipMemcpyDeviceToDevice,
+                                   st) != hipSuccess ||
+                    (mask_all && hipMemcpyAsync(kcopy + o2 / 3, mask_all + off[mem[q]] / 3, nn / 3,
+                                                hipMemcpyDeviceToDevice, st) != hipSuccess)) {
+                    rs = MOTO_EHIP;
+                    break;
+                }
+                o2 += (long long)nn;
+            }
+            if (rs != MOTO_OK) break;
+            for (int q = 0; q < ns; ++q) tl[q] = t;
+            rs = batched_impl(h, ns, Ls.data(), mcopy, mask_all ? kcopy : nullptr, tl.data(), &o, rcopy, ws, base, st,
+                              e0, e1);
+            if (rs != MOTO_OK) break;
+            float ms = 0.0f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rs = MOTO_EHIP;
+                break;
+            }
+            if (t == MOTO_TILE_32x8 || ms < best) {
+                best = ms;
+                best_tile = t;
+            }
+        }
+        for (int i : mem) tiles[i] = best_tile;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rs;
 }
 
 // ---------------------------------------------------------------------------

@@ -110,21 +110,49 @@ struct BSearch {
     Geo g;
     int N, n2;
     double* m;
+    const uint8_t* mask;  // active sites of this lattice (null: all)
+    int tile;             // tile shape of its lattice loops: BATCH_TILE_32x8 / 16x16 / 64x4
     double *F, *c64, *V, *Sm, *Ym, *G, *Gp, *dp, *d;
     float *m32, *c32, *S, *HS, *Xs;
     EigCtrl* ctrl;
     double* Gsm;
 };
 
+constexpr int BRCH = 64;  // rows per staged chunk of the Gram reductions
+
+// LDS of the tile loops for one tile shape (TXV x 256 / TXV)
+template <int TXV>
+struct BTiles {
+    HvpLDS<float, true, TXV> hv;
+    TileLDS<double, TXV> te;
+};
+
 struct BShared {
-    HvpLDS<float, true> hv;
-    TileLDS<double> te;
+    union {  // one search uses one tile shape at a time
+        BTiles<32> t32;
+        BTiles<16> t16;
+        BTiles<64> t64;
+    };
     double red[4 * 160];
+    float st[2][BNS][BRCH];  // staged rows of two sets of basis columns
+    double sy[BMEM], alph[BMEM];  // L-BFGS pair curvatures and two-loop coefficients
     double Cl[BNS * BMB], Cpl[BNS * BMB], lam[BMB], Bw[2 * BMB * BMB], Tw[BMB * BMB];
 };
 
-// energy/force at m (FP64): F and c; returns E
-__device__ double b_energy(const BArgs& a, const BSearch& s, BShared& sh, bool want_F) {
+template <int TXV>
+__device__ __forceinline__ BTiles<TXV>& b_tiles(BShared& sh) {
+    if constexpr (TXV == 32)
+        return sh.t32;
+    else if constexpr (TXV == 16)
+        return sh.t16;
+    else
+        return sh.t64;
+}
+
+// energy/force at m (FP64): F and c; returns E.  Tiles of TXV x 256 / TXV.
+template <int TXV>
+__device__ __forceinline__ double b_energy_t(const BArgs& a, const BSearch& s, BShared& sh, bool want_F) {
+    using SHP = TileShape<TXV>;
     Coef<double> k;
     for (int q = 0; q < 3; ++q) k.cJ[q] = a.k.cJ[q];
     k.cD = a.k.cD;
@@ -133,64 +161,84 @@ __device__ double b_energy(const BArgs& a, const BSearch& s, BShared& sh, bool w
     double v[NPART];
 #pragma unroll
     for (int q = 0; q < NPART; ++q) v[q] = 0.0;
-    for (int t = 0; t < s.g.tiles; ++t) {
-        const int tx0 = (t % s.g.tiles_x) * TX, ty0 = (t / s.g.tiles_x) * TY;
-        energy_tile<double>(sh.te, s.g, k, s.m, nullptr, nullptr, s.c64, want_F ? s.F : nullptr, tx0, ty0, v);
+    const int ntx = (s.g.Lx + SHP::X - 1) / SHP::X, nty = (s.g.Ly + SHP::Y - 1) / SHP::Y;
+    for (int t = 0; t < ntx * nty; ++t) {
+        const int tx0 = (t % ntx) * SHP::X, ty0 = (t / ntx) * SHP::Y;
+        energy_tile<double, TXV>(b_tiles<TXV>(sh).te, s.g, k, s.m, s.mask, nullptr, s.c64, want_F ? s.F : nullptr,
+                                 tx0, ty0, v);
     }
     double e[1] = {v[0]};
     wg_sum<1>(e, sh.red);
     return e[0];
 }
 
-__device__ void b_hvp(const BArgs& a, const BSearch& s, BShared& sh, const float* W, float* HW) {
+__device__ __forceinline__ double b_energy(const BArgs& a, const BSearch& s, BShared& sh, bool want_F) {
+    if (s.tile == BATCH_TILE_16x16) return b_energy_t<16>(a, s, sh, want_F);
+    if (s.tile == BATCH_TILE_64x4) return b_energy_t<64>(a, s, sh, want_F);
+    return b_energy_t<32>(a, s, sh, want_F);
+}
+
+template <int TXV>
+__device__ __forceinline__ void b_hvp_t(const BArgs& a, const BSearch& s, BShared& sh, const float* W, float* HW) {
+    using SHP = TileShape<TXV>;
     Coef<float> k;
     for (int q = 0; q < 3; ++q) k.cJ[q] = (float)a.k.cJ[q];
     k.cD = (float)a.k.cD;
     k.cK = (float)a.k.cK;
     for (int q = 0; q < 3; ++q) k.B[q] = (float)a.k.B[q];
-    for (int t = 0; t < s.g.tiles; ++t) {
-        const int tx0 = (t % s.g.tiles_x) * TX, ty0 = (t / s.g.tiles_x) * TY;
-        tangent_hvp_tile<float, true>(sh.hv, s.g, k, s.m32, s.c32, nullptr, BMB, W, HW, tx0, ty0);
+    const int ntx = (s.g.Lx + SHP::X - 1) / SHP::X, nty = (s.g.Ly + SHP::Y - 1) / SHP::Y;
+    for (int t = 0; t < ntx * nty; ++t) {
+        const int tx0 = (t % ntx) * SHP::X, ty0 = (t / ntx) * SHP::Y;
+        tangent_hvp_tile<float, true, TXV>(b_tiles<TXV>(sh).hv, s.g, k, s.m32, s.c32, s.mask, BMB, W, HW, tx0,
+                                           ty0);
     }
     __syncthreads();
 }
 
+__device__ __forceinline__ void b_hvp(const BArgs& a, const BSearch& s, BShared& sh, const float* W, float* HW) {
+    if (s.tile == BATCH_TILE_16x16)
+        b_hvp_t<16>(a, s, sh, W, HW);
+    else if (s.tile == BATCH_TILE_64x4)
+        b_hvp_t<64>(a, s, sh, W, HW);
+    else
+        b_hvp_t<32>(a, s, sh, W, HW);
+}
+
 // orthonormalise X (target 0) or W against [X P] (target 1), in place
-__device__ void b_orth(const BArgs& a, const BSearch& s, BShared& sh, int target) {
+__device__ __forceinline__ void b_orth(const BArgs& a, const BSearch& s, BShared& sh, int target) {
     const int np = s.ctrl->np;
     const int nq = target == 1 ? BMB + np : 0;
     const int t0 = target == 1 ? BMB : 0;
     const int nrow = nq + BMB;
-    constexpr int NE = (2 * BMB + BMB) * BMB;  // 48 max
-    double acc[NE];
-#pragma unroll
-    for (int q = 0; q < NE; ++q) acc[q] = 0.0;
-    for (int r = threadIdx.x; r < s.n2; r += NT) {
-        float col[3 * BMB];
-#pragma unroll
-        for (int c = 0; c < 3 * BMB; ++c) {
-            if (c < nq) {
-                const int qc = c < BMB ? c : 2 * BMB + (c - BMB);
-                col[c] = s.S[(size_t)qc * s.n2 + r];
-            } else if (c < nrow) {
-                col[c] = s.S[(size_t)(t0 + c - nq) * s.n2 + r];
-            }
+    // Gram entries e = j * nrow + i (staged column i . target column j), one
+    // per thread, summed over staged chunks of rows in a fixed order
+    const int E = nrow * BMB;
+    double acc = 0.0;
+    int ei = 0, ej = 0;
+    if (threadIdx.x < E) {
+        ej = threadIdx.x / nrow;
+        ei = threadIdx.x - ej * nrow;
+    }
+    for (int r0 = 0; r0 < s.n2; r0 += BRCH) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < nrow * BRCH; idx += NT) {
+            const int c = idx / BRCH, rr = idx - c * BRCH, r = r0 + rr;
+            const int col = c < nq ? (c < BMB ? c : 2 * BMB + (c - BMB)) : t0 + (c - nq);
+            sh.st[0][c][rr] = r < s.n2 ? s.S[(size_t)col * s.n2 + r] : 0.0f;
         }
-#pragma unroll
-        for (int j = 0; j < BMB; ++j)
-#pragma unroll
-            for (int i = 0; i < 3 * BMB; ++i)
-                if (i < nrow) acc[j * 3 * BMB + i] += (double)col[i] * (double)col[nq + j];
+        __syncthreads();
+        if (threadIdx.x < E) {
+            const float* x = sh.st[0][ei];
+            const float* y = sh.st[0][nq + ej];
+            double d0 = 0.0, d1 = 0.0;
+            for (int rr = 0; rr < BRCH; rr += 2) {
+                d0 += (double)x[rr] * (double)y[rr];
+                d1 += (double)x[rr + 1] * (double)y[rr + 1];
+            }
+            acc += d0 + d1;
+        }
     }
-    wg_sum<NE>(acc, sh.red);
-    if (threadIdx.x == 0) {
-        // static indices only: a runtime index would move acc to scratch
-#pragma unroll
-        for (int j = 0; j < BMB; ++j)
-#pragma unroll
-            for (int i = 0; i < 3 * BMB; ++i)
-                if (i < nrow) s.Gsm[j * nrow + i] = acc[j * 3 * BMB + i];
-    }
+    if (threadIdx.x < E) s.Gsm[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x < WL) orth_small_body<BLD + 1>(BMB, nq, a.drop, s.Gsm, s.ctrl->Bw, s.ctrl->Tw);
     __syncthreads();
@@ -224,58 +272,49 @@ __device__ void b_orth(const BArgs& a, const BSearch& s, BShared& sh, int target
     __syncthreads();
 }
 
-// Rows [I0, I1) of the upper triangle of X^T Y (Y = HS for pass 0, S for
-// pass 1) into Gsm, FP64 accumulation.  Row blocks keep the accumulators
-// within registers.
-template <int I0, int I1>
-__device__ void b_gram_rows(const BSearch& s, BShared& sh, int ns, int pass) {
-    constexpr int NE = (I1 - I0) * (2 * BNS - I0 - I1 + 1) / 2;
-    const int Eh = ns * (ns + 1) / 2;
-    double acc[NE];
-#pragma unroll
-    for (int q = 0; q < NE; ++q) acc[q] = 0.0;
-    for (int r = threadIdx.x; r < s.n2; r += NT) {
-        float x[BNS], y[BNS];
-#pragma unroll
-        for (int c = 0; c < BNS; ++c) {
-            x[c] = 0.0f;
-            y[c] = 0.0f;
-            if (c < ns) {
-                if (c >= I0 && c < I1) x[c] = s.S[(size_t)c * s.n2 + r];
-                y[c] = pass == 0 ? s.HS[(size_t)c * s.n2 + r] : s.S[(size_t)c * s.n2 + r];
-            }
+// Rayleigh-Ritz Grams (upper triangles of S^T HS then S^T S) into Gsm: one
+// entry per thread, FP64 sums over staged chunks of rows in a fixed order
+__device__ __forceinline__ void b_gram(const BArgs& a, const BSearch& s, BShared& sh, int ns) {
+    (void)a;
+    const int Eh = ns * (ns + 1) / 2, E = 2 * Eh;
+    int ei = 0, ej = 0, ew = 0;
+    if (threadIdx.x < E) {
+        ew = threadIdx.x >= Eh;
+        int p = threadIdx.x - ew * Eh, i = 0;
+        while (p >= ns - i) {
+            p -= ns - i;
+            ++i;
         }
-        int e = 0;
-#pragma unroll
-        for (int i = I0; i < I1; ++i)
-#pragma unroll
-            for (int j = i; j < BNS; ++j) acc[e++] += (double)x[i] * (double)y[j];
+        ei = i;
+        ej = i + p;
     }
-    wg_sum<NE>(acc, sh.red);
-    if (threadIdx.x == 0) {
-        int e = 0;
-#pragma unroll
-        for (int i = I0; i < I1; ++i)
-#pragma unroll
-            for (int j = i; j < BNS; ++j) {
-                if (i < ns && j < ns) s.Gsm[pass * Eh + i * ns - i * (i - 1) / 2 + (j - i)] = acc[e];
-                ++e;
+    double acc = 0.0;
+    for (int r0 = 0; r0 < s.n2; r0 += BRCH) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < ns * BRCH; idx += NT) {
+            const int c = idx / BRCH, rr = idx - c * BRCH, r = r0 + rr;
+            const bool in = r < s.n2;
+            sh.st[0][c][rr] = in ? s.S[(size_t)c * s.n2 + r] : 0.0f;
+            sh.st[1][c][rr] = in ? s.HS[(size_t)c * s.n2 + r] : 0.0f;
+        }
+        __syncthreads();
+        if (threadIdx.x < E) {
+            const float* x = sh.st[0][ei];
+            const float* y = ew ? sh.st[0][ej] : sh.st[1][ej];
+            double d0 = 0.0, d1 = 0.0;
+            for (int rr = 0; rr < BRCH; rr += 2) {
+                d0 += (double)x[rr] * (double)y[rr];
+                d1 += (double)x[rr + 1] * (double)y[rr + 1];
             }
+            acc += d0 + d1;
+        }
     }
+    if (threadIdx.x < E) s.Gsm[threadIdx.x] = acc;
     __syncthreads();
 }
 
-// Rayleigh-Ritz Grams (upper triangles of S^T HS then S^T S) into Gsm
-__device__ void b_gram(const BArgs& a, const BSearch& s, BShared& sh, int ns) {
-    (void)a;
-    for (int pass = 0; pass < 2; ++pass) {
-        b_gram_rows<0, 4>(s, sh, ns, pass);
-        if (ns > 4) b_gram_rows<4, BNS>(s, sh, ns, pass);
-    }
-}
-
 // X <- S C, HX <- HS C, P <- S Cp, HP <- HS Cp, W <- HX - X Lam; residual norms
-__device__ void b_update(const BArgs& a, const BSearch& s, BShared& sh, int ns, int kk, bool first) {
+__device__ __forceinline__ void b_update(const BArgs& a, const BSearch& s, BShared& sh, int ns, int kk, bool first) {
     for (int i = threadIdx.x; i < ns * BMB; i += NT) {
         sh.Cl[i] = s.ctrl->C[i];
         sh.Cpl[i] = s.ctrl->Cp[i];
@@ -356,7 +395,7 @@ __device__ void b_update(const BArgs& a, const BSearch& s, BShared& sh, int ns, 
 
 // k smallest eigenpairs at m; warm: start from the saved block.  Leaves the
 // first kk vectors (ambient FP64, unit) in s.V and the block in s.Xs.
-__device__ void b_eig(const BArgs& a, const BSearch& s, BShared& sh, int kk, bool warm, unsigned long long seed) {
+__device__ __forceinline__ void b_eig(const BArgs& a, const BSearch& s, BShared& sh, int kk, bool warm, unsigned long long seed) {
     const int N = s.N;
     if (threadIdx.x == 0) {
         s.ctrl->done = 0;
@@ -386,8 +425,9 @@ __device__ void b_eig(const BArgs& a, const BSearch& s, BShared& sh, int kk, boo
                 va = (float)splitmix_uniform(seed, (uint64_t)j * 2 * N + i);
                 vb = (float)splitmix_uniform(seed, (uint64_t)j * 2 * N + N + i);
             }
-            s.S[(size_t)j * s.n2 + i] = va;
-            s.S[(size_t)j * s.n2 + N + i] = vb;
+            const bool on = s.mask == nullptr || s.mask[i] != 0;
+            s.S[(size_t)j * s.n2 + i] = on ? va : 0.0f;
+            s.S[(size_t)j * s.n2 + N + i] = on ? vb : 0.0f;
         }
     }
     __syncthreads();
@@ -414,8 +454,10 @@ __device__ void b_eig(const BArgs& a, const BSearch& s, BShared& sh, int kk, boo
     for (int i = threadIdx.x; i < N; i += NT) {
         float e1[3], e2[3];
         onb(s.m32[i], s.m32[N + i], s.m32[2 * N + i], e1, e2);
+#pragma unroll
         for (int j = 0; j < BMB; ++j) {
             const float va = s.S[(size_t)j * s.n2 + i], vb = s.S[(size_t)j * s.n2 + N + i];
+#pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float amb = va * e1[c] + vb * e2[c];
                 s.Xs[(size_t)j * 3 * N + c * N + i] = amb;
@@ -427,7 +469,9 @@ __device__ void b_eig(const BArgs& a, const BSearch& s, BShared& sh, int kk, boo
         }
     }
     wg_sum<BMB>(nr, sh.red);
-    for (int j = 0; j < kk; ++j) {
+#pragma unroll
+    for (int j = 0; j < BMB; ++j) {
+        if (j >= kk) break;
         const double sc = nr[j] > 0.0 ? 1.0 / sqrt(nr[j]) : 0.0;
         for (int i = threadIdx.x; i < 3 * N; i += NT) s.V[(size_t)j * 3 * N + i] *= sc;
     }
@@ -440,23 +484,27 @@ struct LbfgsHdr {
     int count, head, have_prev;
 };
 
-__device__ double b_dot(const double* x, const double* y, int n3, double* red) {
+__device__ __forceinline__ double b_dot(const double* x, const double* y, int n3, double* red) {
     double v[1] = {0.0};
     for (int i = threadIdx.x; i < n3; i += NT) v[0] += x[i] * y[i];
     wg_sum<1>(v, red);
     return v[0];
 }
 
-__device__ double b_step(const BArgs& a, const BSearch& s, BShared& sh, LbfgsHdr& h, int k_reflect, bool* stopped) {
+__device__ __forceinline__ double b_step(const BArgs& a, const BSearch& s, BShared& sh, LbfgsHdr& h, int k_reflect, bool* stopped) {
     const int N = s.N, n3 = 3 * N;
     double fr[2] = {0.0, 0.0};
     for (int i = threadIdx.x; i < n3; i += NT)
-        for (int r = 0; r < k_reflect; ++r) fr[r] += s.F[i] * s.V[(size_t)r * n3 + i];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+            if (r < k_reflect) fr[r] += s.F[i] * s.V[(size_t)r * n3 + i];
     wg_sum<2>(fr, sh.red);
     double fn[1] = {0.0};
     for (int i = threadIdx.x; i < n3; i += NT) {
         double v = s.F[i];
-        for (int r = 0; r < k_reflect; ++r) v -= 2.0 * fr[r] * s.V[(size_t)r * n3 + i];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+            if (r < k_reflect) v -= 2.0 * fr[r] * s.V[(size_t)r * n3 + i];
         s.G[i] = -v;
         fn[0] += v * v;
     }
@@ -506,21 +554,27 @@ __device__ double b_step(const BArgs& a, const BSearch& s, BShared& sh, LbfgsHdr
     h.count = c_new;
     h.head = h_new;
     // two-loop recursion on q = G (stored in d)
-    double sy[BMEM], alph[BMEM];
+    // (per-pair scalars in LDS: a register array indexed by the runtime pair
+    // index would live in scratch memory)
+    double* sy = sh.sy;
+    double* alph = sh.alph;
     int newest = -1;
     for (int j = 0; j < h.count; ++j) {
         const int ph = (h.head + j) % a.mem;
-        sy[j] = b_dot(s.Sm + (size_t)ph * n3, s.Ym + (size_t)ph * n3, n3, sh.red);
-        if (sy[j] > a.sy_min) newest = j;
+        const double v = b_dot(s.Sm + (size_t)ph * n3, s.Ym + (size_t)ph * n3, n3, sh.red);
+        if (threadIdx.x == 0) sy[j] = v;
+        if (v > a.sy_min) newest = j;
     }
+    __syncthreads();
     for (int i = threadIdx.x; i < n3; i += NT) s.d[i] = s.G[i];
     __syncthreads();
     for (int j = h.count - 1; j >= 0; --j) {
         if (!(sy[j] > a.sy_min)) continue;
         const int ph = (h.head + j) % a.mem;
-        alph[j] = b_dot(s.Sm + (size_t)ph * n3, s.d, n3, sh.red) / sy[j];
+        const double al = b_dot(s.Sm + (size_t)ph * n3, s.d, n3, sh.red) / sy[j];
+        if (threadIdx.x == 0) alph[j] = al;
         const double* Yj = s.Ym + (size_t)ph * n3;
-        for (int i = threadIdx.x; i < n3; i += NT) s.d[i] -= alph[j] * Yj[i];
+        for (int i = threadIdx.x; i < n3; i += NT) s.d[i] -= al * Yj[i];
         __syncthreads();
     }
     double gamma = a.alpha0;
@@ -585,8 +639,10 @@ __device__ double b_step(const BArgs& a, const BSearch& s, BShared& sh, LbfgsHdr
     return fnorm;
 }
 
-__global__ __launch_bounds__(NT) void k_batched_search(BArgs a, double* __restrict__ m_all,
-                                                       const int* __restrict__ Ls, const int* __restrict__ order,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_batched_search(BArgs a, double* __restrict__ m_all,
+                                                       const uint8_t* __restrict__ mask_all,
+                                                       const int* __restrict__ Ls, const int* __restrict__ tiles,
+                                                       const int* __restrict__ order,
                                                        const long long* __restrict__ m_off,
                                                        const long long* __restrict__ ws_off, char* __restrict__ ws,
                                                        moto_search_result* __restrict__ res) {
@@ -599,6 +655,8 @@ __global__ __launch_bounds__(NT) void k_batched_search(BArgs a, double* __restri
         s.N = L * L;
         s.n2 = 2 * s.N;
         s.m = m_all + m_off[idx];
+        s.mask = mask_all ? mask_all + m_off[idx] / 3 : nullptr;
+        s.tile = tiles[idx];
         char* base = ws + ws_off[idx];
         const BLayout o = batch_layout(s.N, a.mem);
         s.F = (double*)(base + o.F);
@@ -678,10 +736,12 @@ __global__ __launch_bounds__(NT) void k_batched_search(BArgs a, double* __restri
     }
 }
 
-hipError_t launch_batched_search(const BatchArgs& a, double* m_all, const int* Ls, const int* order,
-                                 const long long* m_off, const long long* ws_off, char* ws, moto_search_result* res,
-                                 int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_batched_search, dim3(grid), dim3(NT), 0, st, a, m_all, Ls, order, m_off, ws_off, ws, res);
+hipError_t launch_batched_search(const BatchArgs& a, double* m_all, const uint8_t* mask_all, const int* Ls,
+                                 const int* tiles, const int* order, const long long* m_off,
+                                 const long long* ws_off, char* ws, moto_search_result* res, int grid,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_batched_search, dim3(grid), dim3(NT), 0, st, a, m_all, mask_all, Ls, tiles, order, m_off,
+                       ws_off, ws, res);
     return hipGetLastError();
 }
 

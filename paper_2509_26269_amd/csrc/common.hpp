@@ -72,10 +72,19 @@ __device__ __forceinline__ void onb(T nx, T ny, T nz, T e1[3], T e2[3]) {
     e2[2] = -ny;
 }
 
+// Tile shapes: TXV x (NT / TXV) output sites, one per thread of a 256-thread
+// workgroup (32 x 8 by default; the batched searches also use 16 x 16 and
+// 64 x 4).
+template <int TXV>
+struct TileShape {
+    static constexpr int X = TXV, Y = NT / TXV;
+    static constexpr int LX = X + 2 * HALO, LY = Y + 2 * HALO, SITES = LX * LY;
+};
+
 // Staged tile: three component planes of (TY+4) x (TX+4) values.
-template <class T>
+template <class T, int TXV = TX>
 struct TileLDS {
-    T u[3][LYH][LXH];
+    T u[3][TileShape<TXV>::LY][TileShape<TXV>::LX];
 };
 
 // (A u) at tile-local centre (cx, cy) of the staged planes.  Offsets of the
@@ -86,8 +95,8 @@ struct TileLDS {
 // Interfacial DMI through the pair differences of the three NN directions
 // dhat = (1,0), (1/2, sqrt3/2), (-1/2, sqrt3/2):
 //   (z x dhat) x v = dhat v_z - z (dhat . v).
-template <class T>
-__device__ __forceinline__ void apply_A_tile(const TileLDS<T>& t, int cx, int cy, const Coef<T>& k,
+template <class T, int TXV>
+__device__ __forceinline__ void apply_A_tile(const TileLDS<T, TXV>& t, int cx, int cy, const Coef<T>& k,
                                              T out[3]) {
     const T h = T(0.5);
     const T r3 = T(0.86602540378443864676);
@@ -114,8 +123,8 @@ __device__ __forceinline__ void apply_A_tile(const TileLDS<T>& t, int cx, int cy
 //   Q_s = sum_{delta in shell s} (z x dhat) x u_{i+delta}
 // Shell 2 pairs: (1,1) dhat (sqrt3/2, 1/2); (-1,2) (0, 1); (-2,1) (-sqrt3/2, 1/2).
 // Shell 3 pairs: (2,0) (1, 0); (0,2) (1/2, sqrt3/2); (-2,2) (-1/2, sqrt3/2).
-template <class T>
-__device__ __forceinline__ void pair_dmi(const TileLDS<T>& t, int cx, int cy, int ax, int ay, T dhx,
+template <class T, int TXV>
+__device__ __forceinline__ void pair_dmi(const TileLDS<T, TXV>& t, int cx, int cy, int ax, int ay, T dhx,
                                          T dhy, T q[3]) {
     const T dx = t.u[0][cy + ay][cx + ax] - t.u[0][cy - ay][cx - ax];
     const T dy = t.u[1][cy + ay][cx + ax] - t.u[1][cy - ay][cx - ax];
@@ -125,8 +134,8 @@ __device__ __forceinline__ void pair_dmi(const TileLDS<T>& t, int cx, int cy, in
     q[2] -= dhx * dx + dhy * dy;
 }
 
-template <class T>
-__device__ __forceinline__ void shell_sums(const TileLDS<T>& t, int cx, int cy, T S[3][3], T Q[3][3]) {
+template <class T, int TXV>
+__device__ __forceinline__ void shell_sums(const TileLDS<T, TXV>& t, int cx, int cy, T S[3][3], T Q[3][3]) {
 #define U(c, dx, dy) t.u[c][cy + (dy)][cx + (dx)]
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

@@ -272,8 +272,11 @@ struct BatchArgs {
     unsigned long long seed;
 };
 size_t batch_search_bytes(int N, int mem);
-hipError_t launch_batched_search(const BatchArgs& a, double* m_all, const int* Ls, const int* order,
-                                 const long long* m_off, const long long* ws_off, char* ws, moto_search_result* res,
-                                 int grid, hipStream_t st);
+// tile shapes of the batched searches' lattice loops
+constexpr int BATCH_TILE_32x8 = MOTO_TILE_32x8, BATCH_TILE_16x16 = MOTO_TILE_16x16, BATCH_TILE_64x4 = MOTO_TILE_64x4;
+hipError_t launch_batched_search(const BatchArgs& a, double* m_all, const uint8_t* mask_all, const int* Ls,
+                                 const int* tiles, const int* order, const long long* m_off,
+                                 const long long* ws_off, char* ws, moto_search_result* res, int grid,
+                                 hipStream_t st);
 
 }  // namespace moto

@@ -40,6 +40,7 @@ constexpr int OENT = MAXS * MAXB;                    // orthonormalisation Gram 
 constexpr int OQ = (OENT + NT - 1) / NT;
 constexpr int PSTRIDE = GENT;                        // doubles per block partial row
 constexpr int RED_BLOCKS = 64;                       // workgroups of the partial-row reduction
+typedef double mf_d4 __attribute__((ext_vector_type(4)));  // accumulator of a 16x16x4 FP64 product
 
 // FP64 dot product of two staged chunks (RCH rows) with four interleaved
 // partial sums, so the chain of dependent adds is RCH / 4 long; the order is
@@ -365,6 +366,108 @@ __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* _
     }
 }
 
+// The Rayleigh-Ritz Grams on the matrix cores (FP32 blocks): a wave takes
+// 16-row slices of the basis; lane l = n + 16 g loads rows r0 + 4 g .. + 3 of
+// column 16 I + n of S and of HS (one 16-byte run per column and lane group)
+// and feeds element q of them to the q-th of four v_mfma_f64_16x16x4f64
+// products per column-tile pair (I <= J): as A (= S^T, 16 x 4) and as B
+// (= HS or S, 4 x 16) the rows of one slice then pair up the same way, so
+// each product adds rows r0 + 4 g + q, g = 0..3, to the 16 x 16 tile
+// (I, J).  FP32 values widened to FP64, FP64 products and sums.  The four
+// waves of a workgroup add their tiles in LDS in a fixed order and the
+// workgroup writes the upper triangles in k_gram's partial-row layout.
+// --------------------------------------------------------------------------
+constexpr int GT = (MAXS + 15) / 16;  // 16-column tiles of the basis
+
+__global__ __launch_bounds__(NT) void k_gram_mfma(EigArgs a, int ns_fixed, const float* __restrict__ S,
+                                                  const float* __restrict__ HS, double* __restrict__ part,
+                                                  const EigCtrl* __restrict__ ctrl) {
+    S += blockIdx.y * a.s_ms;
+    HS += blockIdx.y * a.s_ms;
+    part += blockIdx.y * a.part_ms;
+    ctrl += blockIdx.y;
+    if (ctrl->done) return;
+    // tile pairs (I, J), I <= J < GT, in the order (0,0) (0,1) (0,2) (1,1) (1,2) (2,2)
+    constexpr int NPR = GT * (GT + 1) / 2;
+    __shared__ double acc_l[2][NPR][256];
+    const int ns = sol_ns(a, ctrl, ns_fixed);
+    const int nt = (ns + 15) >> 4;
+    const int n2 = a.n2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, lg = lane >> 4;
+    mf_d4 ga[NPR], gb[NPR];
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) {
+        ga[q] = mf_d4{0.0, 0.0, 0.0, 0.0};
+        gb[q] = ga[q];
+    }
+    const int nslices = (n2 + 15) >> 4;
+    const int nw = gridDim.x * (NT / 64);
+    for (int sl = blockIdx.x * (NT / 64) + wv; sl < nslices; sl += nw) {
+        const int rb = sl * 16 + 4 * lg;  // first of this lane group's four rows
+        float sv[GT][4], hv[GT][4];
+#pragma unroll
+        for (int I = 0; I < GT; ++I) {
+            const int col = 16 * I + ln;
+            const bool cin = I < nt && col < ns;
+            if (cin && rb + 4 <= n2) {
+                const float2 s01 = *(const float2*)(S + (size_t)col * n2 + rb);
+                const float2 s23 = *(const float2*)(S + (size_t)col * n2 + rb + 2);
+                const float2 h01 = *(const float2*)(HS + (size_t)col * n2 + rb);
+                const float2 h23 = *(const float2*)(HS + (size_t)col * n2 + rb + 2);
+                sv[I][0] = s01.x, sv[I][1] = s01.y, sv[I][2] = s23.x, sv[I][3] = s23.y;
+                hv[I][0] = h01.x, hv[I][1] = h01.y, hv[I][2] = h23.x, hv[I][3] = h23.y;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool in = cin && rb + q < n2;
+                    sv[I][q] = in ? S[(size_t)col * n2 + rb + q] : 0.0f;
+                    hv[I][q] = in ? HS[(size_t)col * n2 + rb + q] : 0.0f;
+                }
+            }
+        }
+        int pr = 0;
+#pragma unroll
+        for (int I = 0; I < GT; ++I)
+#pragma unroll
+            for (int J = I; J < GT; ++J, ++pr) {
+                if (J < nt) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double a = sv[I][q];
+                        ga[pr] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)hv[J][q], ga[pr], 0, 0, 0);
+                        gb[pr] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)sv[J][q], gb[pr], 0, 0, 0);
+                    }
+                }
+            }
+    }
+    // waves 0..3 add their tiles into LDS one after another (fixed order)
+    for (int w = 0; w < NT / 64; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int pr = 0; pr < NPR; ++pr)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = (lg + 4 * q) * 16 + ln;  // tile row lg + 4 q, column ln
+                    acc_l[0][pr][e] = w == 0 ? ga[pr][q] : acc_l[0][pr][e] + ga[pr][q];
+                    acc_l[1][pr][e] = w == 0 ? gb[pr][q] : acc_l[1][pr][e] + gb[pr][q];
+                }
+        }
+        __syncthreads();
+    }
+    // upper triangles: entry (i, j), i <= j < ns, from tile (i / 16, j / 16)
+    const int Eh = ns * (ns + 1) / 2;
+    for (int e = threadIdx.x; e < Eh; e += NT) {
+        int i, j;
+        tri_index(e, ns, i, j);
+        const int I = i >> 4, J = j >> 4;
+        const int pr = I * GT - I * (I - 1) / 2 + (J - I);
+        const int t = (i & 15) * 16 + (j & 15);
+        part[(size_t)blockIdx.x * PSTRIDE + e] = acc_l[0][pr][t];
+        part[(size_t)blockIdx.x * PSTRIDE + Eh + e] = acc_l[1][pr][t];
+    }
+}
+
 // Rayleigh-Ritz step (one wavefront, FP64): see rr_body.
 __global__ __launch_bounds__(WL) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ Gtri,
                                            EigCtrl* __restrict__ ctrl) {
@@ -460,6 +563,121 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
     if (threadIdx.x < mb) {
         const int j = threadIdx.x;
         part[(size_t)blockIdx.x * MAXB + j] = red[j * 4] + red[j * 4 + 1] + red[j * 4 + 2] + red[j * 4 + 3];
+    }
+}
+
+// --------------------------------------------------------------------------
+// The same block update on the matrix cores (FP32 blocks, wider blocks):
+// 16-row tiles of S and HS times the ns x ncol coefficient matrix [C | Cp]
+// (ncol = 2 mb, or mb at the start), as v_mfma_f64_16x16x4f64 products: the
+// FP32 block values are widened to FP64, products and sums are FP64, so the
+// arithmetic is that of k_update in another summation order.  Each wave owns
+// whole 16-row tiles (it reads every input column of its rows before it
+// writes any output); one LDS load of a coefficient fragment serves a whole
+// 16 x 16 x 4 product instead of one multiply-add.
+// Lane layout of the 16x16x4 FP64 product (A 16 x 4, B 4 x 16, D 16 x 16):
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[l / 16 + 4 i][l % 16] in accumulator element i.  Here A = a 16 x 4
+// slice of the block (rows r0.., columns 4t..), B = rows 4t.. of [C | Cp].
+// Residual partials |W_j|^2 per workgroup, as k_update writes them.
+// --------------------------------------------------------------------------
+// block widths from which FP32 updates run on the matrix cores
+constexpr int UPDATE_MFMA_MIN_MB = 5;
+constexpr int UKS = MAXS / 4;  // k-steps of 4 basis columns
+
+__global__ __launch_bounds__(NT) void k_update_mfma(EigArgs a, int ns_fixed, float* __restrict__ S,
+                                                    float* __restrict__ HS, double* __restrict__ part,
+                                                    const EigCtrl* __restrict__ ctrl) {
+    S += blockIdx.y * a.s_ms;
+    HS += blockIdx.y * a.s_ms;
+    part += blockIdx.y * a.part_ms;
+    ctrl += blockIdx.y;
+    if (ctrl->done) return;
+    __shared__ double red[MAXB][NT / 64];
+    const int ns = sol_ns(a, ctrl, ns_fixed);
+    const int mb = a.mb, n2 = a.n2;
+    const bool has_p = ns > mb;
+    const int ncol = has_p ? 2 * mb : mb;
+    const bool two = ncol > 16;  // a second 16-column tile of outputs
+    const int ks = (ns + 3) >> 2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, lg = lane >> 4;
+    // [C | Cp] in LDS, zero-padded to UKS * 4 rows and 32 columns: each
+    // product reads its B fragment with one LDS load (keeping the fragments
+    // in registers would cost 48 VGPRs and half the occupancy)
+    __shared__ double cc[UKS * 4][32];
+    for (int e = threadIdx.x; e < UKS * 4 * 32; e += NT) {
+        const int i = e >> 5, j = e & 31;
+        double v = 0.0;
+        if (i < ns && j < ncol) v = j < mb ? ctrl->C[i + ns * j] : ctrl->Cp[i + ns * (j - mb)];
+        cc[i][j] = v;
+    }
+    double lamj[2], rs[2] = {0.0, 0.0};
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int j = 16 * nt + ln;
+        lamj[nt] = j < mb ? ctrl->lam[j] : 0.0;
+    }
+    __syncthreads();
+    const int ntiles = (n2 + 15) >> 4;
+    const int nw = gridDim.x * (NT / 64);
+    for (int tile = blockIdx.x * (NT / 64) + wv; tile < ntiles; tile += nw) {
+        const int r0 = tile * 16;
+        const int ra = r0 + ln;
+        mf_d4 xs0 = {0.0, 0.0, 0.0, 0.0}, xs1 = xs0, xh0 = xs0, xh1 = xs0;
+#pragma unroll
+        for (int t = 0; t < UKS; ++t) {
+            if (t < ks) {
+                const int i = 4 * t + lg;
+                const bool in = i < ns && ra < n2;
+                const double as = in ? (double)S[(size_t)i * n2 + ra] : 0.0;
+                const double ah = in ? (double)HS[(size_t)i * n2 + ra] : 0.0;
+                const double b0 = cc[i][ln];
+                xs0 = __builtin_amdgcn_mfma_f64_16x16x4f64(as, b0, xs0, 0, 0, 0);
+                xh0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ah, b0, xh0, 0, 0, 0);
+                if (two) {
+                    const double b1 = cc[i][16 + ln];
+                    xs1 = __builtin_amdgcn_mfma_f64_16x16x4f64(as, b1, xs1, 0, 0, 0);
+                    xh1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ah, b1, xh1, 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int j = 16 * nt + ln;
+            if (nt == 1 && !two) break;
+            const mf_d4 xs = nt == 0 ? xs0 : xs1;
+            const mf_d4 xh = nt == 0 ? xh0 : xh1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = r0 + lg + 4 * q;
+                if (row >= n2) continue;
+                if (j < mb) {
+                    S[(size_t)j * n2 + row] = (float)xs[q];
+                    HS[(size_t)j * n2 + row] = (float)xh[q];
+                    const float w = (float)(xh[q] - lamj[nt] * xs[q]);
+                    S[(size_t)(mb + j) * n2 + row] = w;
+                    rs[nt] += (double)w * (double)w;
+                } else if (j < ncol) {
+                    S[(size_t)(mb + j) * n2 + row] = (float)xs[q];  // P column j - mb
+                    HS[(size_t)(mb + j) * n2 + row] = (float)xh[q];
+                }
+            }
+        }
+    }
+    // |W_j|^2: the four lane groups of column j, then the waves (fixed order)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        double v = rs[nt];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        const int j = 16 * nt + ln;
+        if (lg == 0 && j < mb) red[j][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < mb) {
+        const int j = threadIdx.x;
+        part[(size_t)blockIdx.x * MAXB + j] = (red[j][0] + red[j][1]) + (red[j][2] + red[j][3]);
     }
 }
 
@@ -710,7 +928,10 @@ hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* 
 
 hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const void* HS, double* part, int nblk,
                        double* G, const EigCtrl* ctrl, hipStream_t st) {
-    if (f64)
+    if (!f64 && a.mb >= UPDATE_MFMA_MIN_MB)
+        hipLaunchKernelGGL(k_gram_mfma, dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (const float*)S, (const float*)HS,
+                           part, ctrl);
+    else if (f64)
         hipLaunchKernelGGL(k_gram<double>, dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (const double*)S,
                            (const double*)HS, part, ctrl);
     else
@@ -727,6 +948,10 @@ hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, h
 
 hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, double* part, int nblk,
                          EigCtrl* ctrl, hipStream_t st) {
+    if (!f64 && a.mb >= UPDATE_MFMA_MIN_MB) {
+        hipLaunchKernelGGL(k_update_mfma, dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (float*)S, (float*)HS, part, ctrl);
+        return hipGetLastError();
+    }
     if (f64)
         go_mb(a.mb, [&](auto mbc) {
             hipLaunchKernelGGL((k_update<double, decltype(mbc)::value>), dim3(nblk, a.P), dim3(NT), 0, st, a, ns,

@@ -2,7 +2,8 @@
 // one-launch-per-step kernels (one tile per workgroup) and the persistent
 // batched search (one workgroup looping over the tiles of its lattice).
 //
-// A tile is TX x TY output sites; the workgroup stages the (TX+4) x (TY+4)
+// A tile is TX x TY output sites (TileShape; 32 x 8 unless a caller picks
+// another shape); the workgroup stages the (TX+4) x (TY+4)
 // neighbourhood in LDS with periodic wrap and evaluates the three-shell
 // stencil of the spin Hamiltonian (Methods, Eq. param-hamiltonian) at one
 // site per thread.
@@ -12,10 +13,12 @@
 
 namespace moto {
 
-template <class T>
-__device__ __forceinline__ void stage_tile(TileLDS<T>& t, const Geo& g, const T* __restrict__ mb, int tx0, int ty0) {
-    for (int i = threadIdx.x; i < TILE_SITES; i += NT) {
-        const int lx = i % LXH, ly = i / LXH;
+template <class T, int TXV>
+__device__ __forceinline__ void stage_tile(TileLDS<T, TXV>& t, const Geo& g, const T* __restrict__ mb, int tx0,
+                                           int ty0) {
+    using SH = TileShape<TXV>;
+    for (int i = threadIdx.x; i < SH::SITES; i += NT) {
+        const int lx = i % SH::LX, ly = i / SH::LX;
         const int x = wrapi(tx0 + lx - HALO, g.Lx), y = wrapi(ty0 + ly - HALO, g.Ly);
         const int s = x + g.Lx * y;
         t.u[0][ly][lx] = mb[s];
@@ -28,15 +31,15 @@ __device__ __forceinline__ void stage_tile(TileLDS<T>& t, const Geo& g, const T*
 //   [e_i, -m.S_0, -m.S_1, -m.S_2, m.Q_0, m.Q_1, m.Q_2, -m_z^2, -m_x, -m_y, -m_z]
 // with e_i = 1/2 m_i.(A m)_i - B.m_i.  Pointers are of the lattice (batch
 // offset applied); grad, c, F, mask may be null.  Ends with a barrier.
-template <class T>
-__device__ __forceinline__ void energy_tile(TileLDS<T>& t, const Geo& g, const Coef<T>& k, const T* __restrict__ mb,
+template <class T, int TXV>
+__device__ __forceinline__ void energy_tile(TileLDS<T, TXV>& t, const Geo& g, const Coef<T>& k, const T* __restrict__ mb,
                                             const uint8_t* __restrict__ mk, T* __restrict__ gb,
                                             T* __restrict__ cb, T* __restrict__ fb, int tx0, int ty0,
                                             double (&v)[NPART]) {
     __syncthreads();
     stage_tile(t, g, mb, tx0, ty0);
     __syncthreads();
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int lx = threadIdx.x % TXV, ly = threadIdx.x / TXV;
     const int x = tx0 + lx, y = ty0 + ly;
     if (x < g.Lx && y < g.Ly) {
         const int cx = lx + HALO, cy = ly + HALO;
@@ -75,11 +78,11 @@ __device__ __forceinline__ void energy_tile(TileLDS<T>& t, const Geo& g, const C
 }
 
 // LDS of the tangent HVP: staged vector planes, frames (or spins), activity.
-template <class T, bool FRAME>
+template <class T, bool FRAME, int TXV = TX>
 struct HvpLDS {
-    TileLDS<T> t;
-    T fr[FRAME ? 6 : 3][LYH][LXH];
-    uint8_t act[LYH][LXH];
+    TileLDS<T, TXV> t;
+    T fr[FRAME ? 6 : 3][TileShape<TXV>::LY][TileShape<TXV>::LX];
+    uint8_t act[TileShape<TXV>::LY][TileShape<TXV>::LX];
 };
 
 // Tangent Hessian-vector product on one tile (Methods, HVP operator mode):
@@ -89,15 +92,16 @@ struct HvpLDS {
 //   e2.(A u) - c b) (P_i drops out against the tangent basis).
 //   AMBIENT: V, W = [nvec][3][N]; output P_i (A u)_i - c_i u_i.
 // Pointers are of the lattice (batch offset applied).
-template <class T, bool FRAME>
-__device__ __forceinline__ void tangent_hvp_tile(HvpLDS<T, FRAME>& sh, const Geo& g, const Coef<T>& k,
+template <class T, bool FRAME, int TXV>
+__device__ __forceinline__ void tangent_hvp_tile(HvpLDS<T, FRAME, TXV>& sh, const Geo& g, const Coef<T>& k,
                                                  const T* __restrict__ mb, const T* __restrict__ cb,
                                                  const uint8_t* __restrict__ mk, int nvec, const T* __restrict__ Vb,
                                                  T* __restrict__ Wb, int tx0, int ty0) {
     constexpr int DV = FRAME ? 2 : 3;
+    using SH = TileShape<TXV>;
     __syncthreads();
-    for (int i = threadIdx.x; i < TILE_SITES; i += NT) {
-        const int lx = i % LXH, ly = i / LXH;
+    for (int i = threadIdx.x; i < SH::SITES; i += NT) {
+        const int lx = i % SH::LX, ly = i / SH::LX;
         const int x = wrapi(tx0 + lx - HALO, g.Lx), y = wrapi(ty0 + ly - HALO, g.Ly);
         const int s = x + g.Lx * y;
         const T mx = mb[s], my = mb[g.N + s], mz = mb[2 * g.N + s];
@@ -117,7 +121,7 @@ __device__ __forceinline__ void tangent_hvp_tile(HvpLDS<T, FRAME>& sh, const Geo
         }
         sh.act[ly][lx] = mk ? (mk[s] != 0) : 1;
     }
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int lx = threadIdx.x % TXV, ly = threadIdx.x / TXV;
     const int x = tx0 + lx, y = ty0 + ly;
     const bool valid = x < g.Lx && y < g.Ly;
     const int cx = lx + HALO, cy = ly + HALO;
@@ -127,8 +131,8 @@ __device__ __forceinline__ void tangent_hvp_tile(HvpLDS<T, FRAME>& sh, const Geo
     for (int j = 0; j < nvec; ++j) {
         __syncthreads();
         const T* vj = Vb + j * vstride;
-        for (int i = threadIdx.x; i < TILE_SITES; i += NT) {
-            const int lx2 = i % LXH, ly2 = i / LXH;
+        for (int i = threadIdx.x; i < SH::SITES; i += NT) {
+            const int lx2 = i % SH::LX, ly2 = i / SH::LX;
             const int x2 = wrapi(tx0 + lx2 - HALO, g.Lx), y2 = wrapi(ty0 + ly2 - HALO, g.Ly);
             const int s = x2 + g.Lx * y2;
             const bool on = sh.act[ly2][lx2];

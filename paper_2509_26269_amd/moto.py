@@ -164,7 +164,13 @@ def lib():
     sig.update({
         "moto_saddle_search_batched_workspace": (_sz, [_i32, ctypes.POINTER(ctypes.c_int32),
                                                        ctypes.POINTER(SearchOpts)]),
-        "moto_saddle_search_batched": (_i32, [ctypes.POINTER(_Ham), _i32, ctypes.POINTER(ctypes.c_int32), _vp,
+        "moto_saddle_search_batched_autotune_workspace": (_sz, [_i32, ctypes.POINTER(ctypes.c_int32),
+                                                                 ctypes.POINTER(SearchOpts)]),
+        "moto_saddle_search_batched_autotune": (_i32, [ctypes.POINTER(_Ham), _i32, ctypes.POINTER(ctypes.c_int32), _vp,
+                                                       _vp, ctypes.POINTER(SearchOpts),
+                                                       ctypes.POINTER(ctypes.c_int32), _vp, _sz, _vp]),
+        "moto_saddle_search_batched": (_i32, [ctypes.POINTER(_Ham), _i32, ctypes.POINTER(ctypes.c_int32), _vp, _vp,
+                                              ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(SearchOpts), _vp, _vp, _sz, _vp]),
     })
     optional = {}
@@ -630,20 +636,10 @@ def moto_saddle_search(plan: Plan, m: torch.Tensor, hvp: int = MOTO_F64, mask: O
     return res, ev, V
 
 
-def moto_saddle_search_batched(params, Ls: Sequence[int], m_all: torch.Tensor, opts: Optional[SearchOpts] = None,
-                               stream=None):
-    """Saddle searches on square lattices of sides Ls in one persistent launch
-    (FP32 HVP, FP64 state).  m_all holds the starts back to back
-    ([3][L_b^2] each, FP64) and is updated in place.  Returns a list of
-    SearchResult (one per lattice, input order)."""
-    o = opts if opts is not None else search_opts(MOTO_F32)
-    n = len(Ls)
-    Larr = (ctypes.c_int32 * n)(*[int(v) for v in Ls])
-    nb = int(lib().moto_saddle_search_batched_workspace(n, Larr, ctypes.byref(o)))
-    if nb == 0:
-        raise MotoError("moto_saddle_search_batched_workspace: invalid sizes or options")
-    ws = _ws(nb, m_all.device)
-    res = torch.empty(n * ctypes.sizeof(SearchResult), dtype=torch.uint8, device=m_all.device)
+TILE_32x8, TILE_16x16, TILE_64x4 = 0, 1, 2
+
+
+def _batch_ham(params) -> "_Ham":
     h = _Ham()
     h.Lx, h.Ly = 1, 1
     h.n_shells = max(len(params.J), len(params.D), 1)
@@ -654,7 +650,51 @@ def moto_saddle_search_batched(params, Ls: Sequence[int], m_all: torch.Tensor, o
     h.K = float(params.K)
     for a in range(3):
         h.B[a] = float(params.B[a])
-    _check(lib().moto_saddle_search_batched(ctypes.byref(h), n, Larr, _ptr(m_all), ctypes.byref(o), _ptr(res),
+    return h
+
+
+def moto_saddle_search_batched_autotune(params, Ls: Sequence[int], m_all: torch.Tensor,
+                                        opts: Optional[SearchOpts] = None, mask_all: Optional[torch.Tensor] = None,
+                                        stream=None):
+    """Tile shape per lattice (MOTO_TILE_*) chosen by timing short batched runs
+    per lattice-size bucket; m_all and mask_all are left unchanged."""
+    o = opts if opts is not None else search_opts(MOTO_F32)
+    n = len(Ls)
+    Larr = (ctypes.c_int32 * n)(*[int(v) for v in Ls])
+    nb = int(lib().moto_saddle_search_batched_autotune_workspace(n, Larr, ctypes.byref(o)))
+    if nb == 0:
+        raise MotoError("moto_saddle_search_batched_autotune_workspace: invalid sizes or options")
+    ws = _ws(nb, m_all.device)
+    tiles = (ctypes.c_int32 * n)()
+    h = _batch_ham(params)
+    _check(lib().moto_saddle_search_batched_autotune(ctypes.byref(h), n, Larr, _ptr(m_all), _ptr(mask_all),
+                                                     ctypes.byref(o), tiles, _ptr(ws), nb, _stream(stream)),
+           "moto_saddle_search_batched_autotune")
+    return list(tiles)
+
+
+def moto_saddle_search_batched(params, Ls: Sequence[int], m_all: torch.Tensor, opts: Optional[SearchOpts] = None,
+                               mask_all: Optional[torch.Tensor] = None, tiles: Optional[Sequence[int]] = None,
+                               stream=None):
+    """Saddle searches on square lattices of sides Ls in one persistent launch
+    (FP32 HVP, FP64 state).  m_all holds the starts back to back
+    ([3][L_b^2] each, FP64) and is updated in place; tiles: tile shape per
+    lattice (None: 32 x 8).  Returns a list of SearchResult (one per lattice,
+    input order)."""
+    o = opts if opts is not None else search_opts(MOTO_F32)
+    n = len(Ls)
+    Larr = (ctypes.c_int32 * n)(*[int(v) for v in Ls])
+    tarr = None if tiles is None else (ctypes.c_int32 * n)(*[int(v) for v in tiles])
+    nb = int(lib().moto_saddle_search_batched_workspace(n, Larr, ctypes.byref(o)))
+    if nb == 0:
+        raise MotoError("moto_saddle_search_batched_workspace: invalid sizes or options")
+    ws = _ws(nb, m_all.device)
+    res = torch.empty(n * ctypes.sizeof(SearchResult), dtype=torch.uint8, device=m_all.device)
+    h = _batch_ham(params)
+    if mask_all is not None and (mask_all.dtype != torch.uint8 or mask_all.numel() != sum(int(v) ** 2 for v in Ls)):
+        raise MotoError("mask_all must be uint8 with one entry per site of every lattice")
+    _check(lib().moto_saddle_search_batched(ctypes.byref(h), n, Larr, _ptr(m_all), _ptr(mask_all), tarr,
+                                            ctypes.byref(o), _ptr(res),
                                             _ptr(ws), nb, _stream(stream)), "moto_saddle_search_batched")
     raw = bytes(res.cpu().numpy())
     sz = ctypes.sizeof(SearchResult)

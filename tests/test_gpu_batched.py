@@ -1,8 +1,13 @@
 """Batching form: each member of a ragged batch of saddle searches run in one
 persistent launch reaches the same outcome as the same search run alone
-through moto_saddle_search (and, for the 16x16 collapse start, as the FP64
-oracle).  FP32 HVP with FP64 state: same status; for saddles |dE| <= 1e-6 |E|
-and max per-site angle <= 1e-2 rad."""
+through moto_saddle_search, and as the FP64 oracle's climb from the same
+start (the 16x16 collapse start of the nearest-neighbour model; four
+three-shell members on uneven 16x16 / 20x20 lattices whose oracle climbs
+are stored in tests/golden/ragged_search_reference.txt).  FP32 HVP with FP64
+state: same status; for saddles |dE| <= 1e-6 |E| and max per-site angle
+<= 1e-2 rad."""
+import os
+
 import numpy as np
 import pytest
 
@@ -123,3 +128,116 @@ def test_batched_full_size_ragged_256():
         ro = O.min_modes(h, finals[i], 2, tol=1e-8, max_iter=800)
         assert ro.converged
         assert abs(res[i].lambda1 - ro.evals[0]) <= 1e-4 * h.h_est(), (i, L, res[i].lambda1, ro.evals[0])
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+RAGGED_REF = os.path.join(HERE, "golden", "ragged_search_reference.txt")
+
+
+def _ragged_reference():
+    rows, lines = [], [ln for ln in open(RAGGED_REF) if not ln.startswith("#")]
+    for head, spins in zip(lines[0::2], lines[1::2]):
+        L, kind, R, seed, status, iters, E, l1, l2 = head.split()
+        L = int(L)
+        m = np.array([float(x) for x in spins.split()]).reshape(3, L * L)
+        rows.append(dict(L=L, kind=kind, R=float(R), seed=int(seed), status=int(status), E=float(E),
+                         l1=float(l1), l2=float(l2), m=m))
+    return rows
+
+
+def test_batched_ragged_three_shell_members_match_the_oracle():
+    """Four three-shell searches on uneven lattices (16, 20, 20, 16) in one
+    persistent launch against the FP64 oracle's climbs from the same starts:
+    two different first-order saddles on 20x20, one on 16x16, and a
+    degenerate end point (antiskyrmion start).  Same end point (energy,
+    largest per-site angle, lambda_1) and the same verdict at the
+    certification threshold of an FP32 HVP (tau_lam = 1e-4 h_est, applied to
+    the oracle's eigenvalues): the first 20x20 saddle has lambda_2 = 2.1e-4,
+    above the FP64 threshold 3.4e-5 (the oracle's SADDLE) but below the FP32
+    one 3.4e-3, so both report it DEGENERATE at FP32 precision."""
+    M = _M()
+    ref = _ragged_reference()
+    assert [r["status"] for r in ref] == [0, 0, 0, 2]
+    Ls = [r["L"] for r in ref]
+    starts = [S.three_shell_start(r["L"], seed=r["seed"], kind=r["kind"], R=r["R"]) for r in ref]
+    p = S.ham_3shell(Ls[0])
+    opts = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, max_outer=1500, eig={"tol": 1e-5, "max_iter": 200})
+    mall = _pack(starts)
+    res = M.moto_saddle_search_batched(p, Ls, mall, opts)
+    finals = _unpack(mall, Ls)
+    expect = []
+    for i, r in enumerate(ref):
+        hest = O.Ham(**p.with_size(r["L"], r["L"]).asdict()).h_est()
+        want = O.certify(np.array([r["l1"], r["l2"]]), 1e-4 * hest)
+        expect.append(want)
+        assert res[i].status == want, (i, M.STATUS_NAMES[res[i].status], want)
+        assert res[i].iters < 1500
+        assert abs(res[i].E - r["E"]) <= 1e-6 * abs(r["E"]), (i, res[i].E, r["E"])
+        if r["status"] == 0:
+            assert O.max_site_angle(finals[i], r["m"]) <= 1e-2, i
+            assert abs(res[i].lambda1 - r["l1"]) <= 1e-4 * hest, (i, res[i].lambda1, r["l1"])
+    # the two 20x20 saddles are distinct saddles; the verdicts at FP32
+    # precision: the soft second mode of the first falls under the threshold
+    assert abs(ref[1]["E"] - ref[2]["E"]) > 1.0
+    assert expect == [0, 2, 0, 2]
+
+
+def test_batched_masked_searches_stay_in_the_mask():
+    """Masked climbs in one launch (disc of radius 6 around the texture on
+    24x24 and 32x32): the spins outside the disc never move, and a member
+    that ends SADDLE has lambda_1 < 0 < lambda_2 of the masked operator as the
+    oracle computes it at the returned state."""
+    M = _M()
+    Ls = [24, 32]
+    p = S.ham_3shell(Ls[0])
+    starts = [S.three_shell_start(L, seed=3 + i, kind="skyrmion", R=1.2) for i, L in enumerate(Ls)]
+    masks = [S.random_mask_disc(L, L, 6.0) for L in Ls]
+    opts = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, max_outer=1500, eig={"tol": 1e-5, "max_iter": 200})
+    mall = _pack(starts)
+    mask_all = torch.as_tensor(np.concatenate([mk.astype(np.uint8) for mk in masks]), device="cuda")
+    res = M.moto_saddle_search_batched(p, Ls, mall, opts, mask_all=mask_all)
+    finals = _unpack(mall, Ls)
+    for i, L in enumerate(Ls):
+        off = masks[i] == 0
+        assert np.array_equal(finals[i][:, off], starts[i][:, off]), i
+        assert np.allclose(np.linalg.norm(finals[i], axis=0), 1.0, atol=1e-12)
+        h = O.Ham(**p.with_size(L, L).asdict())
+        if res[i].status == M.SADDLE:
+            ro = O.min_modes(h, finals[i], 2, tol=1e-9, mask=masks[i], max_iter=2000)
+            assert ro.evals[0] < 0 < ro.evals[1], ro.evals
+            assert abs(res[i].lambda1 - ro.evals[0]) <= 1e-4 * h.h_est()
+            assert abs(res[i].lambda2 - ro.evals[1]) <= 1e-4 * h.h_est()
+
+
+def test_batched_tile_shapes_agree_and_autotuner_leaves_starts():
+    """The three tile shapes of the lattice loops (32x8, 16x16, 64x4) change
+    only the order of the energy sum: the climbs are bit-identical (spins,
+    status, iterations, lambda) and the energies agree to rounding.  The
+    autotuner returns a valid shape per lattice, one per size bucket, and
+    leaves the starts untouched."""
+    M = _M()
+    Ls = [24, 33, 40]
+    p = S.ham_3shell(Ls[0])
+    starts = [S.three_shell_start(L, seed=30 + i, kind="skyrmion", R=1.2) for i, L in enumerate(Ls)]
+    opts = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, max_outer=40, eig={"tol": 1e-5, "max_iter": 200})
+    outs = []
+    for t in (M.TILE_32x8, M.TILE_16x16, M.TILE_64x4):
+        mall = _pack(starts)
+        res = M.moto_saddle_search_batched(p, Ls, mall, opts, tiles=[t] * len(Ls))
+        outs.append((mall.clone(), res))
+    m0, r0 = outs[0]
+    for mt, rt in outs[1:]:
+        assert torch.equal(mt, m0)
+        for a, b in zip(rt, r0):
+            assert (a.status, a.iters, a.n_hvp, a.lambda1, a.lambda2) == (b.status, b.iters, b.n_hvp, b.lambda1,
+                                                                             b.lambda2)
+            assert abs(a.E - b.E) <= 1e-12 * abs(b.E)
+    mall = _pack(starts)
+    before = mall.clone()
+    tiles = M.moto_saddle_search_batched_autotune(p, Ls, mall, opts)
+    torch.cuda.synchronize()
+    assert torch.equal(mall, before)
+    assert len(tiles) == 3 and all(t in (M.TILE_32x8, M.TILE_16x16, M.TILE_64x4) for t in tiles)
+    res = M.moto_saddle_search_batched(p, Ls, mall, opts, tiles=tiles)
+    assert torch.equal(mall, m0)
+    assert [r.status for r in res] == [r.status for r in r0]
