@@ -243,7 +243,11 @@ def main():
     ap.add_argument("--searches", type=int, default=2, help="one-at-a-time GPU searches timed")
     ap.add_argument("--batched", type=int, default=64, help="searches on 128x128 in the batched (one-launch) leg")
     ap.add_argument("--ragged", type=int, default=256, help="searches on uneven 32..96 lattices, one launch")
-    ap.add_argument("--max-outer", type=int, default=300, help="outer-iteration cap of every search leg")
+    ap.add_argument("--max-outer", type=int, default=300, help="outer-iteration cap of the unmasked search legs")
+    ap.add_argument("--max-outer-masked", type=int, default=600,
+                    help="outer-iteration cap of the masked search legs")
+    ap.add_argument("--ragged-single", type=int, default=8,
+                    help="masked ragged searches also run one at a time (same starts, same tau_F)")
     ap.add_argument("--large", type=int, default=1, help="512x512 k=8 solve and the k=2 size sweep (0: skip)")
     ap.add_argument("--shells35", type=int, default=64,
                     help="lattices in the 35-shell (Pd/Fe/Ir(111)) HVP leg (0: skip)")
@@ -361,6 +365,11 @@ def main():
             r = M.moto_min_modes(plan, m1, 4, M.MOTO_F32, opts=o, ws=ws)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
+        # the same solve with the library's default options (guard 2, cap 200)
+        rd = M.moto_min_modes(plan, m1, 4, M.MOTO_F32)
+        torch.cuda.synchronize()
+        extra["min_modes_128_k4_default_opts"] = {"iters": rd.iters, "status": M.STATUS_NAMES[rd.status],
+                                                  "lambda": [round(float(x), 6) for x in rd.evals.cpu()]}
         extra["min_modes_128_k4_ms"] = round(1e3 * float(np.median(times)), 3)
         extra["min_modes_128_k4_iters"] = r.iters
         extra["min_modes_128_k4_n_hvp"] = int(r.n_hvp)
@@ -472,7 +481,19 @@ def main():
             "status": M.STATUS_NAMES[r2.status], "workspace_bytes": ws2.nbytes,
             "dense_hessian_bytes": (2 * L2 * L2) ** 2 * 8,
             "lambda": [round(float(x), 6) for x in r2.evals.cpu()]}
-        del m2, ws2
+        # the band Lanczos on the same state (depth 64): the magnon band
+        # bottom that LOBPCG does not resolve within its cap
+        wsl2 = M.LanczosWorkspace(plan2, M.MOTO_F32, 64)
+        ol2 = M.lanczos_opts(M.MOTO_F32, tol=1e-5, m_max=64, max_restarts=400)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rl2 = M.moto_min_modes_lanczos(plan2, m2, 8, M.MOTO_F32, opts=ol2, ws=wsl2)
+        torch.cuda.synchronize()
+        extra["min_modes_512_two_skyrmions_k8_lanczos64"] = {
+            "ms": round(1e3 * (time.perf_counter() - t0), 2), "restarts": rl2.iters, "n_hvp": int(rl2.n_hvp),
+            "status": M.STATUS_NAMES[rl2.status], "workspace_bytes": wsl2.nbytes,
+            "lambda": [round(float(x), 6) for x in rl2.evals.cpu()]}
+        del m2, ws2, wsl2
         # time and workspace of the k = 2 solve against the lattice size
         # (the paper's Fig. 2b-c axes), uniform and skyrmion states
         scal = {}
@@ -610,23 +631,46 @@ def main():
         extra["search_opts"] = {"tau_F": 1e-5, "k": 2, "k_cert": 2, "max_outer": args.max_outer,
                                 "eig_tol_rel": 1e-5, "eig_max_iter": 200, "hvp": "f32", "rule": "lbfgs(8)"}
 
-        def batched_leg(name, Ls, starts, hp):
-            mall = torch.as_tensor(np.concatenate([x.reshape(-1) for x in starts]), device="cuda")
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = M.moto_saddle_search_batched(hp, list(Ls), mall, so)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
+        som = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, k_cert=2, max_outer=args.max_outer_masked,
+                            eig={"tol": 1e-5, "max_iter": 200})
+
+        def summary(res, el, cap):
             hist = {}
             for r in res:
                 hist[M.STATUS_NAMES[r.status]] = hist.get(M.STATUS_NAMES[r.status], 0) + 1
             its = int(sum(r.iters for r in res))
-            extra[name] = {"searches": len(Ls), "wall_s": round(el, 3),
-                           "searches_per_s": round(len(Ls) / el, 4),
-                           "outer_iters_per_s": round(its / el, 1),
-                           "mean_outer_iters": round(its / len(Ls), 1),
-                           "hvp_columns_per_outer": round(sum(r.n_hvp for r in res) / max(its, 1), 1),
-                           "status": hist}
+            return {"searches": len(res), "wall_s": round(el, 3),
+                    "searches_per_s": round(len(res) / el, 4),
+                    "certified_saddles_per_s": round(sum(1 for r in res if r.status == M.SADDLE) / el, 4),
+                    "outer_iters_per_s": round(its / el, 1),
+                    "mean_outer_iters": round(its / len(res), 1),
+                    "max_outer_iters": int(max(r.iters for r in res)),
+                    "outer_cap": cap, "ended_at_cap": int(sum(1 for r in res if r.iters >= cap)),
+                    "hvp_columns_per_outer": round(sum(r.n_hvp for r in res) / max(its, 1), 1),
+                    "status": hist}
+
+        def batched_leg(name, Ls, starts, hp, opts, cap, masks=None, tune=False):
+            mall = torch.as_tensor(np.concatenate([x.reshape(-1) for x in starts]), device="cuda")
+            mk = None if masks is None else torch.as_tensor(np.concatenate(masks), device="cuda")
+            tiles, t_tune = None, 0.0
+            if tune:
+                t0 = time.perf_counter()
+                tiles = M.moto_saddle_search_batched_autotune(hp, list(Ls), mall, opts, mask_all=mk)
+                t_tune = time.perf_counter() - t0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = M.moto_saddle_search_batched(hp, list(Ls), mall, opts, mask_all=mk, tiles=tiles)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            extra[name] = summary(res, el, cap)
+            if tune:
+                names = {M.TILE_32x8: "32x8", M.TILE_16x16: "16x16", M.TILE_64x4: "64x4"}
+                by = {}
+                for L_, t_ in zip(Ls, tiles):
+                    by.setdefault(names[t_], []).append(int(L_))
+                extra[name]["autotune_s"] = round(t_tune, 3)
+                extra[name]["tiles_by_side"] = {k_: [min(v_), max(v_), len(v_)] for k_, v_ in by.items()}
+            return res
 
         spec = S.fixed_size_spec(max(args.batched, args.searches), L, seed=128)
         if args.batched > 0:
@@ -643,14 +687,7 @@ def main():
             for r in resp:
                 hist[M.STATUS_NAMES[r.status]] = hist.get(M.STATUS_NAMES[r.status], 0) + 1
             its = int(sum(r.iters for r in resp))
-            extra["population_128"] = {"searches": len(resp), "wall_s": round(el, 3),
-                                       "searches_per_s": round(len(resp) / el, 4),
-                                       "certified_saddles_per_s": round(
-                                           sum(1 for r in resp if r.status == M.SADDLE) / el, 4),
-                                       "outer_iters_per_s": round(its / el, 1),
-                                       "mean_outer_iters": round(its / len(resp), 1),
-                                       "hvp_columns_per_outer": round(sum(r.n_hvp for r in resp) / max(its, 1), 1),
-                                       "status": hist}
+            extra["population_128"] = summary(resp, el, args.max_outer)
             # The same starts with the climb confined to a disc of radius 8
             # around the core (the masked subspace Omega): outside it the
             # texture stays fixed, which pins the two soft translation modes
@@ -660,34 +697,61 @@ def main():
                   file=sys.stderr, flush=True)
             disc = S.random_mask_disc(L, L, 8.0)
             mmask = torch.as_tensor(np.stack([disc] * args.batched), device="cuda")
+            mpop = torch.as_tensor(np.stack([S.batch_member(spec, i) for i in range(args.batched)]), device="cuda")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            resm, _, _ = M.moto_saddle_search_population(plan, mpop, M.MOTO_F32, mask=mmask, opts=so)
+            resm, _, _ = M.moto_saddle_search_population(plan, mpop, M.MOTO_F32, mask=mmask, opts=som)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
-            histm = {}
-            for r in resm:
-                histm[M.STATUS_NAMES[r.status]] = histm.get(M.STATUS_NAMES[r.status], 0) + 1
-            itm = int(sum(r.iters for r in resm))
-            nsad = sum(1 for r in resm if r.status == M.SADDLE)
-            extra["population_128_masked_disc8"] = {
-                "searches": len(resm), "wall_s": round(el, 3),
-                "searches_per_s": round(len(resm) / el, 4),
-                "certified_saddles_per_s": round(nsad / el, 4),
-                "outer_iters_per_s": round(itm / el, 1),
-                "mean_outer_iters": round(itm / len(resm), 1),
-                "masked_sites": int(disc.sum()),
-                "status": histm}
+            extra["population_128_masked_disc8"] = summary(resm, el, args.max_outer_masked)
+            extra["population_128_masked_disc8"]["masked_sites"] = int(disc.sum())
             del mpop, mmask
-            print(f"[bench] {args.batched} saddle searches on {L}x{L} in one persistent launch", file=sys.stderr,
-                  flush=True)
-            batched_leg("batched_128", [L] * args.batched, [S.batch_member(spec, i) for i in range(args.batched)], p)
+            if args.searches > 0:
+                # the same masked starts one at a time through moto_saddle_search
+                print(f"[bench] {args.searches} masked saddle searches on {L}x{L} one at a time", file=sys.stderr,
+                      flush=True)
+                dmask = torch.as_tensor(disc, device="cuda")
+                r1s = []
+                t0 = time.perf_counter()
+                for i in range(args.searches):
+                    md = torch.as_tensor(S.batch_member(spec, i), device="cuda")
+                    r1, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, mask=dmask, opts=som)
+                    r1s.append(r1)
+                    print(f"[bench]   search {i}: {M.STATUS_NAMES[r1.status]} iters={r1.iters}", file=sys.stderr,
+                          flush=True)
+                torch.cuda.synchronize()
+                extra["one_at_a_time_128_masked_disc8"] = summary(r1s, time.perf_counter() - t0,
+                                                                  args.max_outer_masked)
         if args.ragged > 0:
             rs = S.ragged_batch_spec(256, seed=26269)
             n = min(args.ragged, 256)
             print(f"[bench] {n} saddle searches on uneven 32..96 lattices in one persistent launch",
                   file=sys.stderr, flush=True)
-            batched_leg("batched_ragged_32_96", rs.L[:n], [S.batch_member(rs, i) for i in range(n)], p)
+            batched_leg("batched_ragged_32_96", rs.L[:n], [S.batch_member(rs, i) for i in range(n)], p, so,
+                        args.max_outer)
+            # the same starts with the climb confined to a disc of radius 10
+            # around the lattice centre (the textures' cores), tile shapes from
+            # the autotuner
+            masks = [S.random_mask_disc(Lb, Lb, 10.0).astype(np.uint8) for Lb in rs.L[:n]]
+            print(f"[bench] {n} masked saddle searches on uneven lattices, autotuned tiles, one persistent launch",
+                  file=sys.stderr, flush=True)
+            batched_leg("batched_ragged_32_96_masked_disc10", rs.L[:n], [S.batch_member(rs, i) for i in range(n)], p,
+                        som, args.max_outer_masked, masks=masks, tune=True)
+            ns1 = min(args.ragged_single, n)
+            if ns1 > 0:
+                print(f"[bench] {ns1} of them one at a time", file=sys.stderr, flush=True)
+                r1s = []
+                t0 = time.perf_counter()
+                for i in range(ns1):
+                    Lb = rs.L[i]
+                    pl = M.Plan.from_params(p.with_size(Lb, Lb))
+                    md = torch.as_tensor(S.batch_member(rs, i), device="cuda")
+                    r1, _, _ = M.moto_saddle_search(pl, md, M.MOTO_F32, mask=torch.as_tensor(masks[i], device="cuda"),
+                                                    opts=som)
+                    r1s.append(r1)
+                torch.cuda.synchronize()
+                extra["one_at_a_time_ragged_masked_disc10_first%d" % ns1] = summary(r1s, time.perf_counter() - t0,
+                                                                                    args.max_outer_masked)
         def one_at_a_time(name, rule):
             sor = M.search_opts(M.MOTO_F32, tau_F=1e-5, k=2, k_cert=2, max_outer=args.max_outer,
                                 eig={"tol": 1e-5, "max_iter": 200}, step={"rule": rule})

@@ -41,6 +41,8 @@ constexpr int OQ = (OENT + NT - 1) / NT;
 constexpr int PSTRIDE = GENT;                        // doubles per block partial row
 constexpr int RED_BLOCKS = 64;                       // workgroups of the partial-row reduction
 typedef double mf_d4 __attribute__((ext_vector_type(4)));  // accumulator of a 16x16x4 FP64 product
+constexpr int UKS = MAXS / 4;                        // k-steps of 4 basis columns
+constexpr int UPDATE_MFMA_MIN_MB = 5;                // block widths whose FP32 row kernels run on the matrix cores
 
 // FP64 dot product of two staged chunks (RCH rows) with four interleaved
 // partial sums, so the chain of dependent adds is RCH / 4 long; the order is
@@ -208,6 +210,130 @@ __global__ __launch_bounds__(NT) void k_orth_gram(EigArgs a, int target, const T
     for (int q = 0; q < OQ; ++q) {
         const int e = threadIdx.x + q * NT;
         if (e < E) part[(size_t)blockIdx.x * PSTRIDE + e] = acc[q];
+    }
+}
+
+// The orthonormalisation Gram and transform on the matrix cores (FP32 blocks,
+// the same lane layout as the Rayleigh-Ritz products below).  Gram: staged
+// columns [Q Y] (nrow = nq + mb, up to three 16-column tiles) against the
+// target block Y (one tile), 16-row slices per wave, four products per tile
+// and slice; partial rows in k_orth_gram's layout (entry j * nrow + i).
+__global__ __launch_bounds__(NT) void k_orth_gram_mfma(EigArgs a, int target, const float* __restrict__ S,
+                                                       double* __restrict__ part,
+                                                       const EigCtrl* __restrict__ ctrl) {
+    S += blockIdx.y * a.s_ms;
+    part += blockIdx.y * a.part_ms;
+    ctrl += blockIdx.y;
+    if (ctrl->done) return;
+    constexpr int TT = (MAXS + 15) / 16;
+    __shared__ OrthCols oc;
+    __shared__ double acc_l[TT][256];
+    if (threadIdx.x == 0) orth_cols(a, target, ctrl, oc);
+    __syncthreads();
+    const int mb = a.mb, nq = oc.nq, nrow = nq + mb, n2 = a.n2;
+    const int nt = (nrow + 15) >> 4;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, lg = lane >> 4;
+    // physical column of staged column 16 I + ln, and of target column ln
+    int pc[TT];
+#pragma unroll
+    for (int I = 0; I < TT; ++I) {
+        const int c = 16 * I + ln;
+        pc[I] = c >= nrow ? -1 : c < nq ? oc.qcol[c] : oc.t0 + (c - nq);
+    }
+    const int tc = ln < mb ? oc.t0 + ln : -1;
+    mf_d4 g[TT];
+#pragma unroll
+    for (int I = 0; I < TT; ++I) g[I] = mf_d4{0.0, 0.0, 0.0, 0.0};
+    const int nslices = (n2 + 15) >> 4;
+    const int nw = gridDim.x * (NT / 64);
+    for (int sl = blockIdx.x * (NT / 64) + wv; sl < nslices; sl += nw) {
+        const int rb = sl * 16 + 4 * lg;
+        float sv[TT][4], tv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tv[q] = (tc >= 0 && rb + q < n2) ? S[(size_t)tc * n2 + rb + q] : 0.0f;
+#pragma unroll
+        for (int I = 0; I < TT; ++I)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                sv[I][q] = (I < nt && pc[I] >= 0 && rb + q < n2) ? S[(size_t)pc[I] * n2 + rb + q] : 0.0f;
+#pragma unroll
+        for (int I = 0; I < TT; ++I) {
+            if (I < nt) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    g[I] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)sv[I][q], (double)tv[q], g[I], 0, 0, 0);
+            }
+        }
+    }
+    for (int w = 0; w < NT / 64; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int I = 0; I < TT; ++I)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = (lg + 4 * q) * 16 + ln;  // tile row lg + 4 q, column ln
+                    acc_l[I][e] = w == 0 ? g[I][q] : acc_l[I][e] + g[I][q];
+                }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nrow * mb; e += NT) {
+        const int j = e / nrow, i = e - j * nrow;
+        part[(size_t)blockIdx.x * PSTRIDE + e] = acc_l[i >> 4][(i & 15) * 16 + j];
+    }
+}
+
+// Y <- (Y - Q B) Tw = [Q Y] [-B Tw; Tw] as 16-row tiles times that
+// nrow x mb coefficient matrix (formed in LDS), in place: each wave reads
+// all staged columns of its rows before it writes the new Y.
+__global__ __launch_bounds__(NT) void k_orth_apply_mfma(EigArgs a, int target, float* __restrict__ S,
+                                                        const EigCtrl* __restrict__ ctrl) {
+    S += blockIdx.y * a.s_ms;
+    ctrl += blockIdx.y;
+    if (ctrl->done) return;
+    __shared__ OrthCols oc;
+    __shared__ double cc[MAXS][16];
+    if (threadIdx.x == 0) orth_cols(a, target, ctrl, oc);
+    __syncthreads();
+    const int mb = a.mb, nq = oc.nq, nrow = nq + mb, n2 = a.n2;
+    for (int e = threadIdx.x; e < MAXS * 16; e += NT) {
+        const int i = e >> 4, j = e & 15;
+        double v = 0.0;
+        if (i < nrow && j < mb) {
+            if (i < nq) {
+                for (int l = 0; l < mb; ++l) v -= ctrl->Bw[i + 2 * MAXB * l] * ctrl->Tw[l + mb * j];
+            } else {
+                v = ctrl->Tw[(i - nq) + mb * j];
+            }
+        }
+        cc[i][j] = v;
+    }
+    __syncthreads();
+    const int ks = (nrow + 3) >> 2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, lg = lane >> 4;
+    const int ntiles = (n2 + 15) >> 4;
+    const int nw = gridDim.x * (NT / 64);
+    for (int tile = blockIdx.x * (NT / 64) + wv; tile < ntiles; tile += nw) {
+        const int r0 = tile * 16, ra = r0 + ln;
+        mf_d4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < UKS; ++t) {
+            if (t < ks) {
+                const int i = 4 * t + lg;
+                const int col = i >= nrow ? -1 : i < nq ? oc.qcol[i] : oc.t0 + (i - nq);
+                const double av = (col >= 0 && ra < n2) ? (double)S[(size_t)col * n2 + ra] : 0.0;
+                y = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cc[i][ln], y, 0, 0, 0);
+            }
+        }
+        if (ln < mb) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = r0 + lg + 4 * q;
+                if (row < n2) S[(size_t)(oc.t0 + ln) * n2 + row] = (float)y[q];
+            }
+        }
     }
 }
 
@@ -581,9 +707,6 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
 // slice of the block (rows r0.., columns 4t..), B = rows 4t.. of [C | Cp].
 // Residual partials |W_j|^2 per workgroup, as k_update writes them.
 // --------------------------------------------------------------------------
-// block widths from which FP32 updates run on the matrix cores
-constexpr int UPDATE_MFMA_MIN_MB = 5;
-constexpr int UKS = MAXS / 4;  // k-steps of 4 basis columns
 
 __global__ __launch_bounds__(NT) void k_update_mfma(EigArgs a, int ns_fixed, float* __restrict__ S,
                                                     float* __restrict__ HS, double* __restrict__ part,
@@ -904,7 +1027,11 @@ hipError_t launch_check_finite(const double* m, const double* c, int N, LzCtrl* 
 
 hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* part, int nblk, double* G,
                        EigCtrl* ctrl, hipStream_t st) {
-    if (f64)
+    const bool mf = !f64 && a.mb >= UPDATE_MFMA_MIN_MB;
+    if (mf)
+        hipLaunchKernelGGL(k_orth_gram_mfma, dim3(nblk, a.P), dim3(NT), 0, st, a, target, (const float*)S, part,
+                           ctrl);
+    else if (f64)
         hipLaunchKernelGGL(k_orth_gram<double>, dim3(nblk, a.P), dim3(NT), 0, st, a, target, (const double*)S, part,
                            ctrl);
     else
@@ -913,6 +1040,10 @@ hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* 
     hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS, a.P), dim3(NT), 0, st, a, part, nblk, 0, target, G, ctrl);
     hipLaunchKernelGGL(k_orth_small, dim3(1, a.P), dim3(WL), 0, st, a, target, G, ctrl);
     const int nb = update_blocks(a.n2);
+    if (mf) {
+        hipLaunchKernelGGL(k_orth_apply_mfma, dim3(nb, a.P), dim3(NT), 0, st, a, target, (float*)S, ctrl);
+        return hipGetLastError();
+    }
     if (f64)
         go_mb(a.mb, [&](auto mbc) {
             hipLaunchKernelGGL((k_orth_apply<double, decltype(mbc)::value>), dim3(nb, a.P), dim3(NT), 0, st, a, target,

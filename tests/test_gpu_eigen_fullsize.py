@@ -8,6 +8,13 @@ oracle's operator within the stopping tolerance.  This rules out a solver
 that meets its residual test on a set of pairs that are not the k smallest
 (a skipped eigenvalue).
 
+At 512x512 (the two-skyrmion state, tests/golden/eig512_reference.txt,
+written by make_eig512_reference.py from the oracle alone): block LOBPCG
+k = 4 (the four internal modes) and band Lanczos k = 8, whose upper four
+eigenvalues are the bottom of the magnon band, about 1e-4 apart; there each
+returned eigenvalue must also lie within half the distance to its reference
+neighbours of its own reference value.
+
 Bars (parity criteria): |d lambda| <= 1e-5 max(|lambda|, h_est), and in
 FP64 also 1e-5 |lambda| for |lambda| >= 1e-3 h_est."""
 import os
@@ -24,6 +31,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 REF = os.path.join(HERE, "golden", "eig128_reference.txt")
+REF512 = os.path.join(HERE, "golden", "eig512_reference.txt")
 K = 4
 
 
@@ -33,9 +41,9 @@ def _M():
     return M
 
 
-def _reference():
+def _reference(path=REF):
     out = {}
-    for line in open(REF):
+    for line in open(path):
         if line.startswith("#") or not line.strip():
             continue
         name, *vals = line.split()
@@ -51,16 +59,16 @@ def _state(name):
     return S.three_shell_start(128, seed=0, kind="skyrmion")
 
 
-def _check(r, ref, h, m, hvp, tol):
+def _check(r, ref, h, m, hvp, tol, k=K):
     M = _M()
     hest = h.h_est()
     assert r.status == M.CONVERGED, (r.status, r.iters)
     ev = r.evals.double().cpu().numpy()
     assert np.all(np.diff(ev) >= -1e-6 * hest), ev
-    P.check_eigs(ev, ref[:K], hest, hvp == "f64", "eigenvalues")
+    P.check_eigs(ev, ref[:k], hest, hvp == "f64", "eigenvalues")
     V = r.V.double().cpu().numpy()
     _, _, c, _ = O.energy_grad(h, m)
-    for j in range(K):
+    for j in range(k):
         assert abs(np.linalg.norm(V[j]) - 1.0) < 1e-6
         res = np.linalg.norm(O.tangent_hvp(h, m, c, V[j]) - ev[j] * V[j])
         # the solver's own residual, measured in its precision, plus the
@@ -98,6 +106,49 @@ def test_lanczos_k4_128_equals_oracle_reference(name, hvp):
     _check(r, _reference()[name], h, m, hvp, tol)
 
 
+def _closest_is_own(ev, ref):
+    """Each eigenvalue lies closer to its own reference value than half the
+    distance to the neighbouring reference values (no skipped or doubled
+    level inside a cluster)."""
+    for j, x in enumerate(ev):
+        lo = ref[j] - ref[j - 1] if j > 0 else np.inf
+        hi = ref[j + 1] - ref[j]
+        assert abs(x - ref[j]) < 0.5 * min(lo, hi), (j, x, ref[j - 1 if j else 0:j + 2])
+
+
+@pytest.mark.parametrize("hvp", ["f32", "f64"])
+def test_lobpcg_k4_512_two_skyrmions_equals_oracle_reference(hvp):
+    M = _M()
+    p = S.ham_3shell(512)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m = S.two_skyrmions(512)
+    dt = M.MOTO_F64 if hvp == "f64" else M.MOTO_F32
+    tol = 1e-8 if hvp == "f64" else 1e-5
+    r = M.moto_min_modes(plan, torch.as_tensor(m, device="cuda"), 4, dt,
+                         opts=M.eig_opts(dt, tol=tol, max_iter=2000 if hvp == "f64" else 600))
+    ref = _reference(REF512)["two_skyrmions"]
+    _check(r, ref, h, m, hvp, tol)
+    _closest_is_own(r.evals.double().cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("hvp", ["f32", "f64"])
+def test_lanczos_k8_512_two_skyrmions_equals_oracle_reference(hvp):
+    M = _M()
+    p = S.ham_3shell(512)
+    h = O.Ham(**p.asdict())
+    plan = M.Plan.from_params(p)
+    m = S.two_skyrmions(512)
+    dt = M.MOTO_F64 if hvp == "f64" else M.MOTO_F32
+    tol = 1e-8 if hvp == "f64" else 1e-5
+    ws = M.LanczosWorkspace(plan, dt, 64)
+    r = M.moto_min_modes_lanczos(plan, torch.as_tensor(m, device="cuda"), 8, dt,
+                                 opts=M.lanczos_opts(dt, tol=tol, m_max=64, max_restarts=1500), ws=ws)
+    ref = _reference(REF512)["two_skyrmions"]
+    _check(r, ref, h, m, hvp, tol, k=8)
+    _closest_is_own(r.evals.double().cpu().numpy(), ref)
+
+
 def test_reference_file_is_consistent():
     """The stored reference: six ascending eigenvalues per state, the norm
     bound of the three-shell Hamiltonian in the header."""
@@ -108,3 +159,8 @@ def test_reference_file_is_consistent():
     h = O.Ham(**S.ham_3shell(128).asdict())
     head = open(REF).readline()
     assert repr(h.h_est()) in head
+    ref512 = _reference(REF512)
+    assert set(ref512) == {"two_skyrmions"}
+    v = ref512["two_skyrmions"]
+    assert len(v) == 10 and np.all(np.diff(v) > 0) and v[0] > 0
+    assert repr(O.Ham(**S.ham_3shell(512).asdict()).h_est()) in open(REF512).readline()
