@@ -431,23 +431,20 @@ __device__ __forceinline__ void b_eig(const BArgs& a, const BSearch& s, BShared&
         }
     }
     __syncthreads();
-    b_orth(a, s, sh, 0);
-    b_orth(a, s, sh, 0);
-    b_hvp(a, s, sh, s.S, s.HS);
-    b_gram(a, s, sh, BMB);
-    if (threadIdx.x < WL) rr_body<BLD + 1>(BMB, BMB, a.drop, s.Gsm, s.ctrl);
-    __syncthreads();
-    b_update(a, s, sh, BMB, kk, true);
-    for (int it = 0; it <= a.eig_max_iter + 1; ++it) {
-        if (s.ctrl->done) break;
-        b_orth(a, s, sh, 1);
-        b_orth(a, s, sh, 1);
-        b_hvp(a, s, sh, s.S + (size_t)BMB * s.n2, s.HS + (size_t)BMB * s.n2);
-        const int ns = 2 * BMB + s.ctrl->np;
+    // pass -1 orthonormalises and projects the start block alone; each later
+    // pass the residual block W against [X P] (one copy of each step's code)
+    for (int it = -1; it <= a.eig_max_iter + 1; ++it) {
+        const bool first = it < 0;
+        if (!first && s.ctrl->done) break;
+        b_orth(a, s, sh, first ? 0 : 1);
+        b_orth(a, s, sh, first ? 0 : 1);
+        const size_t off = first ? 0 : (size_t)BMB * s.n2;
+        b_hvp(a, s, sh, s.S + off, s.HS + off);
+        const int ns = first ? BMB : 2 * BMB + s.ctrl->np;
         b_gram(a, s, sh, ns);
         if (threadIdx.x < WL) rr_body<BLD + 1>(BMB, ns, a.drop, s.Gsm, s.ctrl);
         __syncthreads();
-        b_update(a, s, sh, ns, kk, false);
+        b_update(a, s, sh, ns, kk, first);
     }
     // output: ambient block (saved) and the first kk unit vectors
     double nr[BMB] = {0.0, 0.0, 0.0, 0.0};

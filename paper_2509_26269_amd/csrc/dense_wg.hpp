@@ -1,8 +1,11 @@
 // dense_wg.hpp -- small dense FP64 steps of the inner layer, each executed by
-// one wavefront: the symmetric eigen-solve (Householder tridiagonalisation
-// and implicit QL), the orthonormalising transform of a projected block, and
-// the Rayleigh-Ritz step with the orthogonal complement for P.  LD is the largest basis size handled (the
-// leading dimension of the LDS matrices); LD / 3 is the largest block width.
+// one wavefront: the symmetric eigen-solves (the lowest eigenpairs by
+// Householder reduction, multisection and inverse iteration; a complete
+// decomposition by Householder reduction and implicit QL), the
+// orthonormalising transform of a projected block, and the Rayleigh-Ritz step
+// with the orthogonal complement for P.  LD is the largest basis size handled
+// (the leading dimension of the LDS matrices); LD / 3 is the largest block
+// width.
 #pragma once
 
 #include "kernels.hpp"
@@ -30,8 +33,10 @@ __device__ __forceinline__ void wsync() {
 __device__ __forceinline__ int wlane() { return threadIdx.x & (WL - 1); }
 
 // --------------------------------------------------------------------------
-// Symmetric eigen-decomposition on one wavefront, the solver of every small
-// dense step: Householder reduction to tridiagonal form with the reflections
+// Complete symmetric eigen-decomposition on one wavefront (the general
+// Gram path of the Rayleigh-Ritz step, which needs every eigenpair; the
+// other dense steps need only the lowest ones and use symeig_low below):
+// Householder reduction to tridiagonal form with the reflections
 // accumulated (lane r owns row r of the matrix and of Z), then the implicit
 // QL iteration with Wilkinson shifts on the tridiagonal, its plane rotations
 // applied to the columns of Z (Golub & Van Loan, Sections 8.3.1 and 8.3.5).
@@ -39,8 +44,9 @@ __device__ __forceinline__ int wlane() { return threadIdx.x & (WL - 1); }
 // so control flow stays uniform.  On return
 // diag(A) holds the eigenvalues (in no particular order) and column j of Z
 // the eigenvector of A[j][j]; the off-diagonal part of A is left undefined.
-// About n^2 short serial steps instead of a cyclic Jacobi's ~ 6 n rounds of
-// n^2/2 rotations, which is what a single wavefront is limited by.
+// About n^2 short serial steps: one wavefront issues an instruction every
+// ~4.6 cycles and waits ~7 for a dependent FP64 result, so the serial
+// rotation chain, not arithmetic, sets its time.
 // --------------------------------------------------------------------------
 // value of v held by lane i (i uniform across the wave)
 __device__ __forceinline__ double rdlane(double v, int i) {
@@ -189,6 +195,418 @@ __device__ void symeig_wg(double* A, double* Z, int n) {
 }
 
 // --------------------------------------------------------------------------
+// The lowest nw eigenpairs of a symmetric n x n matrix on one wavefront, with
+// every stage spread over the lanes instead of one serial sweep:
+//  1. Householder reduction to tridiagonal T (lane r keeps row r of the
+//     matrix in registers; the reflectors are stored, not accumulated);
+//  2. eigenvalues by multisection of T's Sturm sequence: a group of lanes per
+//     eigenvalue, each lane counting the eigenvalues below its own point with
+//     the three-term recurrence of the leading minors det(T_i - x I), on T
+//     scaled by a power of two to norm < 1 (so no overflow; rescaled against
+//     underflow); the counts of the group pick the sub-interval;
+//  3. eigenvectors of T by two steps of inverse iteration (a lane per
+//     eigenvalue, Gaussian elimination with partial pivoting, counter-based
+//     start vectors), then modified Gram-Schmidt inside each cluster of
+//     eigenvalues closer than 1e-3 ||T|| (the clustering rule of LAPACK's
+//     stein);
+//  4. back-transformation by the stored reflectors (a lane per vector).
+// (Golub & Van Loan, Sections 8.3.1, 8.4.1 and 8.2.2.)  A (leading
+// dimension lda) is destroyed: its storage holds the reflectors, which needs
+// (n - 2) NM <= lda^2.  On return w[j] and column j of Z (leading dimension
+// ldz) hold the j-th smallest eigenpair, j < min(nw, n), ascending.  A
+// non-finite entry of A gives NaN eigenpairs.  sb: LDS scratch of
+// symeig_low_doubles(NM, NWS) doubles; eigenvectors are solved NWS at a time.
+// --------------------------------------------------------------------------
+constexpr int symeig_low_doubles(int nm, int nws) { return 3 * nm * nws + 5 * nm + WL; }
+
+// 1/x to FP64 accuracy: the hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// a double moved across lanes by a DPP pattern (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the wavefront, the same value on every lane, without an LDS round
+// trip: partners at xor 1 and xor 2 inside quads, then mirrored lanes inside
+// half-rows and rows (each row of 16 then holds its total on every lane),
+// then the four row totals added in a fixed order.
+__device__ __forceinline__ double wsum_dpp(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+}
+
+__device__ __forceinline__ double wmax_dpp(double v) {
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    return fmax(fmax(rdlane(v, 0), rdlane(v, 16)), fmax(rdlane(v, 32), rdlane(v, 48)));
+}
+
+// number of eigenvalues of the scaled tridiagonal below x: sign changes of
+// 1, p_0, ..., p_(n-1) with p_i = (dh_i - x) p_(i-1) - e2s_i p_(i-2)
+// (e2s_i: squared off-diagonal between i - 1 and i, e2s_0 = 0); an exact zero
+// takes the sign opposite to its predecessor (a tiny negative pivot).  The
+// coefficients come from LDS sixteen at a time.
+template <int NM>
+__device__ __forceinline__ int sturm_below(const double* dh, const double* e2s, int n, double x) {
+    double pp = 0.0, p = 1.0;
+    int cnt = 0;
+#pragma unroll
+    for (int c0 = 0; c0 < NM; c0 += 16) {
+        if (c0 < n) {
+            // the first 32 coefficients may stay in registers across calls;
+            // later chunks are reloaded (bounds the register footprint)
+            if (c0 >= 32) asm volatile("" ::: "memory");
+            double dc[16], ec[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                dc[q] = dh[c0 + q];
+                ec[q] = e2s[c0 + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                if (c0 + q < n) {
+                    double pn = fma(dc[q] - x, p, -(ec[q] * pp));
+                    pn = pn == 0.0 ? -p * 0x1p-52 : pn;
+                    cnt += (pn < 0.0) != (p < 0.0);
+                    pp = p;
+                    p = pn;
+                    if ((q & 3) == 3) {
+                        const double f = fmax(fabs(p), fabs(pp)) < 0x1p-600 ? 0x1p600 : 1.0;
+                        p *= f;
+                        pp *= f;
+                    }
+                }
+            }
+        }
+    }
+    return cnt;
+}
+
+template <int NM, int NWS>
+__device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int ldz, int n, int nw, double* w,
+                                              double* sb) {
+    const int lane = wlane();
+    double* U0 = sb;  // per eigenvector slot: inverse pivots, then the two superdiagonals of U
+    double* U1 = U0 + NM * NWS;
+    double* U2 = U1 + NM * NWS;
+    double* dh = U2 + NM * NWS;
+    double* eh = dh + NM;
+    double* e2s = eh + NM;
+    double* bc = e2s + NM;
+    double* hw = bc + NM;
+    double* lamh = hw + NM;
+    // ---- 1. tridiagonalisation, lane r holding row r ----
+    double a[NM];
+    bool fin = true;
+#pragma unroll
+    for (int c = 0; c < NM; ++c) {
+        a[c] = (lane < n && c < n) ? A[lane * lda + c] : 0.0;
+        fin = fin && (fabs(a[c]) <= 1.7976931348623157e308);
+    }
+    if (__ballot(!fin) != 0ull) {
+        const int nv = nw < n ? nw : n;
+        if (lane < nv) {
+            w[lane] = NAN;
+            for (int r = 0; r < n; ++r) Z[r * ldz + lane] = NAN;
+        }
+        wsync();
+        return;
+    }
+    wsync();  // A's storage takes the reflectors from here on: row k at V + k NM
+    double* V = A;
+    for (int k = 0; k + 2 < n; ++k) {
+        if (lane == k) {
+#pragma unroll
+            for (int c = 0; c < NM; ++c) bc[c] = a[c];
+        }
+        wsync();
+        const double x = (lane > k && lane < n) ? bc[lane] : 0.0;
+        const double x0 = bc[k + 1];
+        const double x2 = wsum_dpp(x * x);
+        double v = 0.0, alpha = 0.0;
+        if (x2 > 0.0) {
+            const double nx = sqrt(x2);
+            alpha = x0 >= 0.0 ? -nx : nx;
+            // |x - alpha e|^2 = 2 (|x|^2 - alpha x0) > 0
+            v = (x - (lane == k + 1 ? alpha : 0.0)) * rsqrt_nr(2.0 * (x2 - alpha * x0));
+        }
+        if (lane < NM) V[k * NM + lane] = v;
+        if (lane == 0) eh[k] = alpha;
+        wsync();
+        if (x2 > 0.0) {
+            // A <- H A H = A - 2 (v w^T + w v^T), p = A v, w = p - (v.p) v;
+            // columns <= k (v is zero there) are never read again and skipped
+            const double* vk = V + k * NM;
+            double pa[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c0 = 0; c0 < NM; c0 += 8)
+                if (c0 + 8 > k + 1) {
+                    asm volatile("" ::: "memory");
+#pragma unroll
+                    for (int c = c0; c < c0 + 8; ++c) pa[c & 3] = fma(a[c], vk[c], pa[c & 3]);
+                }
+            const double p = (pa[0] + pa[1]) + (pa[2] + pa[3]);
+            const double wv = p - wsum_dpp(p * v) * v;
+            if (lane < NM) hw[lane] = wv;
+            wsync();
+#pragma unroll
+            for (int c0 = 0; c0 < NM; c0 += 8)
+                if (c0 + 8 > k + 1) {
+                    // one chunk of broadcast operands live at a time (the
+                    // scheduler would otherwise hoist all 2 NM of them)
+                    asm volatile("" ::: "memory");
+#pragma unroll
+                    for (int c = c0; c < c0 + 8; ++c) a[c] -= 2.0 * (v * hw[c] + wv * vk[c]);
+                }
+        }
+        wsync();
+    }
+    double dr = 0.0, sub = 0.0;
+#pragma unroll
+    for (int c = 0; c < NM; ++c) {
+        dr = c == lane ? a[c] : dr;
+        sub = c + 1 == lane ? a[c] : sub;
+    }
+    if (n >= 2 && lane == n - 1) eh[n - 2] = sub;  // the last subdiagonal entry
+    wsync();
+    const double er = lane + 1 < n ? eh[lane] : 0.0;
+    const double el = (lane >= 1 && lane < n) ? eh[lane - 1] : 0.0;
+    // power-of-two scale above the Gershgorin bound: ||T / s|| < 1
+    const double gb = wmax_dpp(lane < n ? fabs(dr) + fabs(er) + fabs(el) : 0.0);
+    int ex = 0;
+    (void)frexp(gb, &ex);
+    const double s = gb > 0.0 ? ldexp(1.0, ex) : 1.0, is = 1.0 / s;
+    wsync();
+    if (lane < NM) {
+        dh[lane] = lane < n ? dr * is : 0.0;
+        eh[lane] = er * is;
+        e2s[lane] = (el * is) * (el * is);
+    }
+    wsync();
+    // ---- 2. multisection: g lanes per eigenvalue, g + 1 sub-intervals per round ----
+    if (nw > n) nw = n;
+    int g = 1;
+    while (2 * g * nw <= WL && g < 16) g *= 2;
+    const int rounds = g == 1 ? 56 : g == 2 ? 36 : g == 4 ? 25 : g == 8 ? 19 : 15;  // (g+1)^-rounds < 2^-55
+    const int jg = lane / g, t = lane - jg * g;
+    const int jw = jg < nw ? jg : nw - 1;
+    const double ig1 = 1.0 / (double)(g + 1);
+    const unsigned long long gm = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << (jg * g);
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < rounds; ++it) {
+        const double wd = hi - lo;
+        const int c = sturm_below<NM>(dh, e2s, n, lo + wd * ((double)(t + 1) * ig1));
+        const int ts = __popcll(__ballot(c <= jw) & gm) - 1;  // last point with <= j eigenvalues below
+        const double nlo = ts < 0 ? lo : lo + wd * ((double)(ts + 1) * ig1);
+        const double nhi = ts + 1 >= g ? hi : lo + wd * ((double)(ts + 2) * ig1);
+        lo = nlo;
+        hi = nhi;
+    }
+    if (t == 0 && jg < nw) lamh[jg] = 0.5 * (lo + hi);
+    wsync();
+    // ---- 3. inverse iteration, NWS eigenvalues at a time; vector j in column j of Z ----
+    constexpr double pmin = 0x1p-52;
+    for (int j0 = 0; j0 < nw; j0 += NWS) {
+        const int sl = lane - j0;
+        if (sl >= 0 && sl < NWS && lane < nw) {
+            const double lm = lamh[lane];
+            const uint64_t seed = 0x5EED0000ull + (uint64_t)lane;
+            double scale = 1.0;
+            for (int itn = 0; itn < 2; ++itn) {
+                auto rhs = [&](int i) {
+                    return itn == 0 ? 2.0 * splitmix_uniform(seed, (uint64_t)i) - 1.0 : Z[i * ldz + lane] * scale;
+                };
+                // forward elimination with row interchanges; the current row
+                // (r0, r1) sits at columns (i, i + 1), right-hand side cr
+                double r0 = dh[0] - lm, r1 = eh[0], cr = rhs(0);
+                for (int c0 = 0; c0 + 1 < n; c0 += 8) {
+                    double sd[8], nd[8], ne[8], bn[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int i = c0 + q;
+                        const bool ok = i + 1 < n;
+                        sd[q] = ok ? eh[i] : 0.0;
+                        nd[q] = ok ? dh[i + 1] : 0.0;
+                        ne[q] = ok ? eh[i + 1] : 0.0;
+                        bn[q] = ok ? rhs(i + 1) : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int i = c0 + q;
+                        if (i + 1 < n) {
+                            const double d1 = nd[q] - lm;
+                            const bool sw = fabs(sd[q]) > fabs(r0) && fabs(sd[q]) > pmin;
+                            const double iv = rcp_nr(sw ? sd[q] : (fabs(r0) > pmin ? r0 : pmin));
+                            const double m = (sw ? r0 : sd[q]) * iv;
+                            U0[i * NWS + sl] = iv;
+                            U1[i * NWS + sl] = sw ? d1 : r1;
+                            U2[i * NWS + sl] = sw ? ne[q] : 0.0;
+                            Z[i * ldz + lane] = sw ? bn[q] : cr;
+                            const double n0 = sw ? r1 - m * d1 : d1 - m * r1;
+                            const double n1 = sw ? -m * ne[q] : ne[q];
+                            cr = sw ? cr - m * bn[q] : bn[q] - m * cr;
+                            r0 = n0;
+                            r1 = n1;
+                        }
+                    }
+                }
+                U0[(n - 1) * NWS + sl] = rcp_nr(fabs(r0) > pmin ? r0 : pmin);
+                U1[(n - 1) * NWS + sl] = 0.0;
+                U2[(n - 1) * NWS + sl] = 0.0;
+                Z[(n - 1) * ldz + lane] = cr;
+                // back substitution, eight rows per LDS round trip
+                double x1 = 0.0, x2 = 0.0, ss = 0.0;
+                for (int c1 = n - 1; c1 >= 0; c1 -= 8) {
+                    double u0[8], u1[8], u2[8], yy[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int i = c1 - q;
+                        const bool ok = i >= 0;
+                        u0[q] = ok ? U0[i * NWS + sl] : 0.0;
+                        u1[q] = ok ? U1[i * NWS + sl] : 0.0;
+                        u2[q] = ok ? U2[i * NWS + sl] : 0.0;
+                        yy[q] = ok ? Z[i * ldz + lane] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int i = c1 - q;
+                        if (i >= 0) {
+                            const double xi = (yy[q] - u1[q] * x1 - u2[q] * x2) * u0[q];
+                            Z[i * ldz + lane] = xi;
+                            ss = fma(xi, xi, ss);
+                            x2 = x1;
+                            x1 = xi;
+                        }
+                    }
+                }
+                scale = rsqrt_nr(ss);
+            }
+            for (int i = 0; i < n; ++i) Z[i * ldz + lane] *= scale;
+        }
+        wsync();
+    }
+    // ---- modified Gram-Schmidt inside clusters (consecutive gaps <= 1e-3 of
+    // the scaled norm), the own column in registers ----
+    double y[NM];
+#pragma unroll
+    for (int c = 0; c < NM; ++c) y[c] = (lane < nw && c < n) ? Z[c * ldz + lane] : 0.0;
+    const bool brk = lane < nw && (lane == 0 || lamh[lane] - lamh[lane - 1] > 1e-3);
+    const unsigned long long bm = __ballot(brk) | (nw < WL ? (~0ull << nw) : 0ull);
+    auto normalize = [&]() {
+        double q4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NM; ++c) q4[c & 3] = fma(y[c], y[c], q4[c & 3]);
+        const double sc = rsqrt_nr((q4[0] + q4[1]) + (q4[2] + q4[3]));
+#pragma unroll
+        for (int c = 0; c < NM; ++c) y[c] *= sc;
+    };
+    for (int i = 0; i + 1 < nw; ++i) {
+        if ((bm >> (i + 1)) & 1ull) continue;  // nothing after i in its cluster
+        if (lane == i) {
+            if (!brk) normalize();
+#pragma unroll
+            for (int c = 0; c < NM; ++c) bc[c] = y[c];
+        }
+        wsync();
+        const unsigned long long between =
+            lane > i ? ((~0ull << (i + 1)) & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull))) : 0ull;
+        if (lane > i && lane < nw && (bm & between) == 0ull) {
+            double q4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < NM; ++c) {
+                if ((c & 7) == 0) asm volatile("" ::: "memory");
+                q4[c & 3] = fma(bc[c], y[c], q4[c & 3]);
+            }
+            const double cf = (q4[0] + q4[1]) + (q4[2] + q4[3]);
+#pragma unroll
+            for (int c = 0; c < NM; ++c) {
+                if ((c & 7) == 0) asm volatile("" ::: "memory");
+                y[c] = fma(-cf, bc[c], y[c]);
+            }
+        }
+        wsync();
+    }
+    if (lane > 0 && lane < nw && !brk) normalize();
+    // ---- 4. back-transformation: z = H_0 H_1 ... H_(n-3) y ----
+    for (int k = n - 3; k >= 0; --k) {
+        const double* vk = V + k * NM;
+        double q4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c0 = 0; c0 < NM; c0 += 8)
+            if (c0 + 8 > k + 1) {
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int c = c0; c < c0 + 8; ++c) q4[c & 3] = fma(y[c], vk[c], q4[c & 3]);
+            }
+        const double dt = 2.0 * ((q4[0] + q4[1]) + (q4[2] + q4[3]));
+#pragma unroll
+        for (int c0 = 0; c0 < NM; c0 += 8)
+            if (c0 + 8 > k + 1) {
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int c = c0; c < c0 + 8; ++c) y[c] = fma(-dt, vk[c], y[c]);
+            }
+    }
+    if (lane < nw) {
+#pragma unroll
+        for (int c = 0; c < NM; ++c)
+            if (c < n) Z[c * ldz + lane] = y[c];
+        w[lane] = lamh[lane] * s;
+    }
+    wsync();
+}
+
+// Dispatch on the register-array bound NM >= n, in buckets of 16 up to NMAX
+// (default: the largest the leading dimension LD allows; callers whose n is
+// known to be small pass a smaller NMAX and get one bucket).  The LDS scratch
+// is shared by the buckets.  Same contract as symeig_low_nm with
+// lda = ldz = LD.
+template <int LD, int NWS, int NMAX = ((LD - 1 + 15) / 16) * 16>
+__device__ __forceinline__ void symeig_low(double* A, double* Z, int n, int nw, double* w) {
+    static_assert(NMAX % 16 == 0 && NMAX <= WL, "one lane per row, buckets of 16");
+    __shared__ double sb[symeig_low_doubles(NMAX, NWS)];
+    if (n <= 0 || nw <= 0) return;
+    if constexpr (NMAX == 16) {
+        symeig_low_nm<16, NWS>(A, LD, Z, LD, n, nw, w, sb);
+    } else if constexpr (NMAX == 32) {
+        if (n <= 16)
+            symeig_low_nm<16, NWS>(A, LD, Z, LD, n, nw, w, sb);
+        else
+            symeig_low_nm<32, NWS>(A, LD, Z, LD, n, nw, w, sb);
+    } else if constexpr (NMAX == 48) {
+        if (n <= 16)
+            symeig_low_nm<16, NWS>(A, LD, Z, LD, n, nw, w, sb);
+        else if (n <= 32)
+            symeig_low_nm<32, NWS>(A, LD, Z, LD, n, nw, w, sb);
+        else
+            symeig_low_nm<48, NWS>(A, LD, Z, LD, n, nw, w, sb);
+    } else {
+        if (n <= 16)
+            symeig_low_nm<16, NWS>(A, LD, Z, LD, n, nw, w, sb);
+        else if (n <= 32)
+            symeig_low_nm<32, NWS>(A, LD, Z, LD, n, nw, w, sb);
+        else if (n <= 48)
+            symeig_low_nm<48, NWS>(A, LD, Z, LD, n, nw, w, sb);
+        else
+            symeig_low_nm<64, NWS>(A, LD, Z, LD, n, nw, w, sb);
+    }
+}
+
+// --------------------------------------------------------------------------
 // Visit (a, b), a < na, b < nb, in lane-strided order of a * nb + b, with
 // one integer division per call instead of one per element.
 template <class F>
@@ -218,15 +636,129 @@ __device__ __forceinline__ void for2(int na, int nb, F&& f) {
 // columns whose projected norm is negligible get a zero transform.
 // --------------------------------------------------------------------------
 template <int LD>
+__device__ void orth_small_body(int mb, int nq, double drop, const double* G, double* Bw, double* Tw);
+
+// --------------------------------------------------------------------------
+// D = A B on one wavefront with FP64 16x16x4 matrix-core products.  Elements
+// are read through fa(i, k) (i < M, k < K) and fb(k, j) (j < N <= 64) at
+// clamped in-range indices (zero outside), so every lane issues the same
+// loads; a 16-row band of D is accumulated over all its column tiles at once
+// (up to four independent product chains) and handed to fd(i, j, value).
+// Lane l of one product supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+// receives D[l / 16 + 4 q][l % 16] in element q.  Call with the whole wave.
+// --------------------------------------------------------------------------
+typedef double wd4 __attribute__((ext_vector_type(4)));
+
+template <class FA, class FB, class FD>
+__device__ __forceinline__ void wave_gemm(int M, int N, int K, FA&& fa, FB&& fb, FD&& fd) {
+    const int lane = wlane(), lr = lane & 15, lk = lane >> 4;
+    const int tn = (N + 15) >> 4;
+    for (int r0 = 0; r0 < M; r0 += 16) {
+        wd4 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = wd4{0.0, 0.0, 0.0, 0.0};
+        const int ar = r0 + lr;
+        const int arc = ar < M ? ar : M - 1;
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + lk;
+            const int kc = k < K ? k : K - 1;
+            const double av = fa(arc, kc);
+            const double a = (ar < M && k < K) ? av : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < tn) {
+                    const int c = q * 16 + lr;
+                    const double bv = fb(kc, c < N ? c : N - 1);
+                    const double b = (k < K && c < N) ? bv : 0.0;
+                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < tn) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = r0 + lk + 4 * i, c = q * 16 + lr;
+                    if (r < M && c < N) fd(r, c, acc[q][i]);
+                }
+            }
+        }
+    }
+    wsync();
+}
+
+// Lanes i < n with pred(i) set, in increasing order, into list[]; returns
+// their count (n <= 64).
+template <class P>
+__device__ __forceinline__ int wave_compact(int n, P&& pred, int* list) {
+    const int lane = wlane();
+    const bool on = lane < n && pred(lane);
+    const unsigned long long m = __ballot(on);
+    if (on) list[__popcll(m & ((1ull << lane) - 1ull))] = lane;
+    wsync();
+    return __popcll(m);
+}
+
+// --------------------------------------------------------------------------
+// Inverse Cholesky factor on one wavefront, the fast path of the small
+// orthonormalising transforms: for a symmetric positive definite n x n
+// matrix M with unit diagonal (n <= 16, in A with leading dimension LD),
+// M = R^T R and Z <- R^-1 (upper triangular), so that Y R^-1 has orthonormal
+// columns when M = Y^T Y.  Returns false, leaving Z undefined, as soon as a
+// pivot is not above tau (M is then too close to singular for this path and
+// the caller falls back to the eigen-decomposition with rank dropping).  A is
+// overwritten by the factor.  (Golub & Van Loan, Section 4.2.)
+// --------------------------------------------------------------------------
+template <int LD>
+__device__ __forceinline__ bool chol_inv_wg(double* A, double* Z, int n, double tau) {
+    const int lane = wlane();
+    for (int j = 0; j < n; ++j) {
+        const double d = A[j * LD + j];
+        if (!(d > tau)) return false;
+        const double id = 1.0 / d;
+        // trailing update with the unscaled column j, then its scaling
+        for2(n - j - 1, n - j - 1, [&](int a, int b) {
+            const int i = j + 1 + a, k = j + 1 + b;
+            A[i * LD + k] -= A[i * LD + j] * A[k * LD + j] * id;
+        });
+        wsync();
+        const double r = sqrt(d), ir = 1.0 / r;
+        if (lane > j && lane < n) A[lane * LD + j] *= ir;
+        if (lane == j) A[j * LD + j] = r;
+        wsync();
+    }
+    // lane q: column q of L^-1 by forward substitution (L = R^T in the lower
+    // triangle of A); R^-1 = (L^-1)^T, so that column is row q of R^-1
+    if (lane < n) {
+        double x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i < n) {
+                double v = i == lane ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 0; k < i; ++k) v -= A[i * LD + k] * x[k];
+                x[i] = i < lane ? 0.0 : v / A[i * LD + i];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < n) Z[lane * LD + c] = x[c];
+    }
+    wsync();
+    return true;
+}
+
+template <int LD>
 __device__ void orth_small_body(int mb, int nq, double drop, const double* G, double* Bw, double* Tw) {
     // G is read many times below: it is first copied to LDS
     constexpr int MBL = LD / 3;
     __shared__ double A[MBL * LD];
     __shared__ double Z[MBL * LD];
-    __shared__ double dsc[MBL], th[MBL];
+    __shared__ double dsc[MBL], th[MBL], thv[MBL];
     __shared__ int keep[MBL];
-    __shared__ int nkeep;
     __shared__ double Gl[LD * MBL];
+    __shared__ double Mq[MBL * MBL];
     const int tid = wlane();
     const int nrow = nq + mb;
     for (int i = tid; i < nrow * mb; i += WL) Gl[i] = G[i];
@@ -235,63 +767,57 @@ __device__ void orth_small_body(int mb, int nq, double drop, const double* G, do
     for2(mb, nq, [&](int j, int r) {
         Bw[r + 2 * MAXB * j] = G[j * nrow + r];
     });
-    for2(mb, mb, [&](int c, int r) {
-        double v = G[c * nrow + nq + r];
-        for (int l = 0; l < nq; ++l) v -= G[r * nrow + l] * G[c * nrow + l];
-        A[r * LD + c] = v;
-    });
-    wsync();
-    for (int j = tid; j < mb; j += WL) {
-        const double full = G[j * nrow + nq + j];
-        const double proj = A[j * LD + j];
-        dsc[j] = (proj > drop * full && proj > 0.0) ? 1.0 / sqrt(proj) : 0.0;
+    // M = Y^T Y - B^T B with B = Q^T Y (B[l][c] = G[c nrow + l]); B^T B kept
+    wave_gemm(mb, mb, nq, [&](int r, int l) { return G[r * nrow + l]; }, [&](int l, int c) { return G[c * nrow + l]; },
+              [&](int r, int c, double v) {
+                  Mq[r * MBL + c] = v;
+                  A[r * LD + c] = G[c * nrow + nq + r] - v;
+              });
+    if (tid < mb) {
+        const double full = G[tid * nrow + nq + tid];
+        const double proj = A[tid * LD + tid];
+        dsc[tid] = (proj > drop * full && proj > 0.0) ? 1.0 / sqrt(proj) : 0.0;
     }
     wsync();
+    double emax = 0.0;
     for2(mb, mb, [&](int c, int r) {
-        A[r * LD + c] *= dsc[r] * dsc[c];
+        const double v = A[r * LD + c] * dsc[r] * dsc[c];
+        A[r * LD + c] = v;
+        if (r != c) emax = fmax(emax, fabs(v));
     });
     wsync();
     // a block that is already orthonormal (the second pass) has D M D = I + E
     // at rounding level: (I + E)^(-1/2) = I - E/2 + 3/8 E^2 replaces the
     // eigen-decomposition (Z holds that transform, th = 1)
-    double emax = 0.0;
-    for2(mb, mb, [&](int c, int r) {
-        if (r != c) emax = fmax(emax, fabs(A[r * LD + c]));
-    });
-    emax = wave_max(emax);
-    if (emax < 1e-5) {
-        auto E = [&](int i, int j) { return i == j ? (dsc[i] > 0.0 ? A[i * LD + i] - 1.0 : 0.0) : A[i * LD + j]; };
-        for2(mb, mb, [&](int i, int j) {
-            double v = 0.0;
-            for (int l = 0; l < mb; ++l) v += E(i, l) * E(l, j);
-            Z[i * LD + j] = (i == j ? 1.0 : 0.0) - 0.5 * E(i, j) + 0.375 * v;
-        });
-        if (tid == 0) {
-            int r = 0;
-            for (int i = 0; i < mb; ++i)
-                if (dsc[i] > 0.0) {
-                    keep[r] = i;
-                    th[r] = 1.0;
-                    ++r;
-                }
-            nkeep = r;
+    int nkeep;
+    if (wmax_dpp(emax) < 1e-5) {
+        if (tid < mb) A[tid * LD + tid] = dsc[tid] > 0.0 ? A[tid * LD + tid] - 1.0 : 0.0;  // E in place
+        nkeep = wave_compact(mb, [&](int i) { return dsc[i] > 0.0; }, keep);
+        if (tid < nkeep) th[tid] = 1.0;
+        wave_gemm(mb, mb, mb, [&](int i, int l) { return A[i * LD + l]; }, [&](int l, int j) { return A[l * LD + j]; },
+                  [&](int i, int j, double v) {
+                      Z[i * LD + j] = (i == j ? 1.0 : 0.0) - 0.5 * A[i * LD + j] + 0.375 * v;
+                  });
+    } else if (chol_inv_wg<LD>(A, Z, mb, 1e-6)) {
+        // well conditioned: T = D R^-1 spans the same space (Rayleigh-Ritz
+        // does not depend on which orthonormal basis of it is taken)
+        nkeep = mb;
+        if (tid < mb) {
+            keep[tid] = tid;
+            th[tid] = 1.0;
         }
+        wsync();
     } else {
-        symeig_wg<LD>(A, Z, mb);
-        if (tid == 0) {
-            int r = 0;
-            for (int i = 0; i < mb; ++i) {
-                const double t = A[i * LD + i];
-                if (t > drop) {
-                    keep[r] = i;
-                    th[r] = t;
-                    ++r;
-                }
-            }
-            nkeep = r;
-        }
+        // rebuild D M D (the factorisation overwrote it) and drop directions
+        for2(mb, mb, [&](int c, int r) {
+            A[r * LD + c] = (G[c * nrow + nq + r] - Mq[r * MBL + c]) * dsc[r] * dsc[c];
+        });
+        wsync();
+        symeig_low<LD, MBL, 16>(A, Z, mb, mb, thv);
+        nkeep = wave_compact(mb, [&](int i) { return thv[i] > drop; }, keep);
+        if (tid < nkeep) th[tid] = thv[keep[tid]];
+        wsync();
     }
-    wsync();
     for2(mb, mb, [&](int c, int row) {
         Tw[row + mb * c] = c < nkeep ? dsc[row] * Z[row * LD + keep[c]] / sqrt(th[c]) : 0.0;
     });
@@ -307,18 +833,19 @@ __device__ void orth_small_body(int mb, int nq, double drop, const double* G, do
 //   C_wp = C with its X rows zeroed, made G_B-orthogonal to C (twice) and
 //   G_B-orthonormalised with rank dropping -> Cp  (P_new = S Cp).
 // Gtri: upper triangles (row-major) of S^T HS, then of S^T S.
-// Writes C, Cp, lam, rank of the control block `out`.
+// Writes C, Cp, lam, rank of the control block `out`.  The matrix products
+// run on the matrix cores (wave_gemm), the eigenproblems in symeig_low.
 // --------------------------------------------------------------------------
 template <int LD>
-__device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl* out) {
+__device__ __forceinline__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl* out) {
+    static_assert(LD - 1 <= WL, "one lane per basis column");
     constexpr int MBL = LD / 3;
     __shared__ double A[LD * LD];
     __shared__ double Z[LD * LD];
     __shared__ double Tm[LD * LD];
     __shared__ double dsc[LD], th[LD], ev[LD];
     __shared__ double h1[MBL * MBL];
-    __shared__ int keep[LD], order[LD];
-    __shared__ int rank_s;
+    __shared__ int keep[LD];
     __shared__ double GAf[LD * LD], GBf[LD * LD];
     const int tid = wlane();
     const int Eh = ns * (ns + 1) / 2;
@@ -333,15 +860,17 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
     wsync();
     auto GA = [&](int i, int j) { return GAf[i * LD + j]; };
     auto GB = [&](int i, int j) { return GBf[i * LD + j]; };
-    double gbmax = 0.0;
-    for (int i = 0; i < ns; ++i) gbmax = fmax(gbmax, GB(i, i));
-    for (int i = tid; i < ns; i += WL) {
-        const double gii = GB(i, i);
-        dsc[i] = gii > 1e-24 * gbmax ? 1.0 / sqrt(gii) : 0.0;
+    const double gbmax = wmax_dpp(tid < ns ? GB(tid, tid) : 0.0);
+    if (tid < ns) {
+        const double gii = GB(tid, tid);
+        dsc[tid] = gii > 1e-24 * gbmax ? 1.0 / sqrt(gii) : 0.0;
     }
     wsync();
+    double emax = 0.0;
     for2(ns, ns, [&](int r, int c) {
-        A[r * LD + c] = dsc[r] * GB(r, c) * dsc[c];
+        const double v = dsc[r] * GB(r, c) * dsc[c];
+        A[r * LD + c] = v;
+        if (r != c) emax = fmax(emax, fabs(v));
     });
     wsync();
     // The basis is orthonormal by construction, so D G_B D = I + E with E
@@ -349,69 +878,35 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
     // 3/8 E^2) to FP64 accuracy, with the zero columns (dropped earlier) left
     // out.  Otherwise the general path: an eigen-decomposition with rank
     // dropping.
-    double emax = 0.0;
-    for2(ns, ns, [&](int r, int c) {
-        if (r != c) emax = fmax(emax, fabs(A[r * LD + c]));
-    });
-    emax = wave_max(emax);
-    const bool near_id = emax < 1e-5;
+    const bool near_id = wmax_dpp(emax) < 1e-5;
+    int r;
     if (near_id) {
-        auto E = [&](int i, int j) { return i == j ? (dsc[i] > 0.0 ? A[i * LD + i] - 1.0 : 0.0) : A[i * LD + j]; };
-        for2(ns, ns, [&](int i, int j) {  // Z <- E^2
-            double v = 0.0;
-            for (int l = 0; l < ns; ++l) v += E(i, l) * E(l, j);
-            Z[i * LD + j] = v;
-        });
-        if (tid == 0) {
-            int r = 0;
-            for (int i = 0; i < ns; ++i)
-                if (dsc[i] > 0.0) keep[r++] = i;
-            rank_s = r;
-        }
-        wsync();
-        const int r = rank_s;
+        // E in place of D G_B D (zero on the dropped columns)
+        if (tid < ns) A[tid * LD + tid] = dsc[tid] > 0.0 ? A[tid * LD + tid] - 1.0 : 0.0;
+        r = wave_compact(ns, [&](int i) { return dsc[i] > 0.0; }, keep);
+        wave_gemm(ns, ns, ns, [&](int i, int l) { return A[i * LD + l]; }, [&](int l, int j) { return A[l * LD + j]; },
+                  [&](int i, int j, double v) { Z[i * LD + j] = v; });  // Z <- E^2
         for2(ns, r, [&](int row, int c) {  // T (ns x r)
             const int k = keep[c];
-            const double t0 = (row == k ? 1.0 : 0.0) - 0.5 * E(row, k) + 0.375 * Z[row * LD + k];
+            const double t0 = (row == k ? 1.0 : 0.0) - 0.5 * A[row * LD + k] + 0.375 * Z[row * LD + k];
             Tm[row * LD + c] = dsc[row] * t0;
         });
         wsync();
     } else {
         symeig_wg<LD>(A, Z, ns);
-        if (tid == 0) {
-            double tmax = 0.0;
-            for (int i = 0; i < ns; ++i) tmax = fmax(tmax, A[i * LD + i]);
-            int r = 0;
-            for (int i = 0; i < ns; ++i) {
-                const double t = A[i * LD + i];
-                if (t > drop * tmax) {
-                    keep[r] = i;
-                    th[r] = t;
-                    ++r;
-                }
-            }
-            rank_s = r;
-        }
+        const double tmax = wmax_dpp(tid < ns ? A[tid * LD + tid] : -INFINITY);
+        r = wave_compact(ns, [&](int i) { return A[i * LD + i] > drop * tmax; }, keep);
+        if (tid < r) th[tid] = A[keep[tid] * LD + keep[tid]];
         wsync();
-        const int r = rank_s;
         for2(ns, r, [&](int row, int c) {  // T (ns x r)
             Tm[row * LD + c] = dsc[row] * Z[row * LD + keep[c]] / sqrt(th[c]);
         });
         wsync();
     }
-    const int r = rank_s;
-    for2(ns, r, [&](int row, int c) {  // Z <- G_A T
-        double s = 0.0;
-        for (int l = 0; l < ns; ++l) s += GA(row, l) * Tm[l * LD + c];
-        Z[row * LD + c] = s;
-    });
-    wsync();
-    for2(r, r, [&](int row, int c) {  // A <- T^T Z
-        double s = 0.0;
-        for (int l = 0; l < ns; ++l) s += Tm[l * LD + row] * Z[l * LD + c];
-        A[row * LD + c] = s;
-    });
-    wsync();
+    wave_gemm(ns, r, ns, GA, [&](int l, int c) { return Tm[l * LD + c]; },
+              [&](int i, int c, double v) { Z[i * LD + c] = v; });  // Z <- G_A T
+    wave_gemm(r, r, ns, [&](int i, int l) { return Tm[l * LD + i]; }, [&](int l, int c) { return Z[l * LD + c]; },
+              [&](int i, int c, double v) { A[i * LD + c] = v; });  // A <- T^T Z
     for2(r, r, [&](int row, int c) {
         if (row < c) {
             const double v = 0.5 * (A[row * LD + c] + A[c * LD + row]);
@@ -420,29 +915,20 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
         }
     });
     wsync();
-    symeig_wg<LD>(A, Z, r);
-    // NaN ranks as +inf, so that the ranks below always form a permutation
-    for (int i = tid; i < r; i += WL) ev[i] = A[i * LD + i] == A[i * LD + i] ? A[i * LD + i] : INFINITY;
-    wsync();
-    for (int i = tid; i < r; i += WL) {
-        const double li = ev[i];
-        int rk = 0;
-        for (int j = 0; j < r; ++j) rk += (ev[j] < li) || (ev[j] == li && j < i);
-        order[rk] = i;
-    }
-    wsync();
+    // the mb lowest eigenpairs, ascending (column j of Z)
     const int mcol = r < mb ? r : mb;
-    // C = T Y[:, order[0..mb)] -> A region (ld MBL) and out->C
-    for2(mb, ns, [&](int j, int row) {
-        double s = 0.0;
-        if (j < mcol) {
-            const int yc = order[j];
-            for (int l = 0; l < r; ++l) s += Tm[row * LD + l] * Z[l * LD + yc];
-        }
-        A[row * MBL + j] = s;
-        out->C[row + ns * j] = s;
+    symeig_low<LD, MBL>(A, Z, r, mcol, ev);
+    // C = T Y[:, 0..mb) -> A region (ld MBL) and out->C (zero beyond the rank)
+    wave_gemm(ns, mcol, r, [&](int row, int l) { return Tm[row * LD + l]; }, [&](int l, int j) { return Z[l * LD + j]; },
+              [&](int row, int j, double v) {
+                  A[row * MBL + j] = v;
+                  out->C[row + ns * j] = v;
+              });
+    for2(mb - mcol, ns, [&](int j, int row) {
+        A[row * MBL + mcol + j] = 0.0;
+        out->C[row + ns * (mcol + j)] = 0.0;
     });
-    for (int j = tid; j < mb; j += WL) out->lam[j] = j < mcol ? ev[order[j]] : 0.0;
+    if (tid < mb) out->lam[tid] = tid < mcol ? ev[tid] : 0.0;
     if (tid == 0) out->rank = r;
     wsync();
     // ---- P complement: Cwp in the Tm region (ld MBL) ----
@@ -450,72 +936,52 @@ __device__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl
         Tm[row * MBL + j] = row < mb ? 0.0 : A[row * MBL + j];
     });
     wsync();
+    auto Cw = [&](int l, int j) { return Tm[l * MBL + j]; };
     for (int pass = 0; pass < 2; ++pass) {
-        for2(mb, ns, [&](int j, int row) {  // Z <- G_B Cwp
-            double s = 0.0;
-            for (int l = 0; l < ns; ++l) s += GB(row, l) * Tm[l * MBL + j];
-            Z[row * MBL + j] = s;
-        });
-        wsync();
-        for2(mb, mb, [&](int j, int p) {  // h1 <- C^T G_B Cwp
-            double s = 0.0;
-            for (int l = 0; l < ns; ++l) s += A[l * MBL + p] * Z[l * MBL + j];
-            h1[p + MBL * j] = s;
-        });
-        wsync();
-        for2(mb, ns, [&](int j, int row) {  // Cwp <- Cwp - C h1
-            double s = Tm[row * MBL + j];
-            for (int p = 0; p < mb; ++p) s -= A[row * MBL + p] * h1[p + MBL * j];
-            Tm[row * MBL + j] = s;
-        });
-        wsync();
+        wave_gemm(ns, mb, ns, GB, Cw, [&](int row, int j, double v) { Z[row * MBL + j] = v; });  // Z <- G_B Cwp
+        wave_gemm(mb, mb, ns, [&](int p, int l) { return A[l * MBL + p]; }, [&](int l, int j) { return Z[l * MBL + j]; },
+                  [&](int p, int j, double v) { h1[p + MBL * j] = v; });  // h1 <- C^T G_B Cwp
+        wave_gemm(ns, mb, mb, [&](int row, int p) { return A[row * MBL + p]; },
+                  [&](int p, int j) { return h1[p + MBL * j]; },
+                  [&](int row, int j, double v) { Tm[row * MBL + j] -= v; });  // Cwp <- Cwp - C h1
     }
     // Mp = Cwp^T G_B Cwp
-    for2(mb, ns, [&](int j, int row) {
-        double s = 0.0;
-        for (int l = 0; l < ns; ++l) s += GB(row, l) * Tm[l * MBL + j];
-        A[row * MBL + j] = s;
-    });
-    wsync();
-    for2(mb, mb, [&](int j, int p) {
-        double s = 0.0;
-        for (int l = 0; l < ns; ++l) s += Tm[l * MBL + p] * A[l * MBL + j];
-        h1[p + MBL * j] = s;
-    });
-    wsync();
-    for (int j = tid; j < mb; j += WL) {
-        const double d = h1[j + MBL * j];
-        dsc[j] = d > 1e-24 ? 1.0 / sqrt(d) : 0.0;
+    wave_gemm(ns, mb, ns, GB, Cw, [&](int row, int j, double v) { A[row * MBL + j] = v; });
+    wave_gemm(mb, mb, ns, [&](int p, int l) { return Tm[l * MBL + p]; }, [&](int l, int j) { return A[l * MBL + j]; },
+              [&](int p, int j, double v) { h1[p + MBL * j] = v; });
+    if (tid < mb) {
+        const double d = h1[tid + MBL * tid];
+        dsc[tid] = d > 1e-24 ? 1.0 / sqrt(d) : 0.0;
     }
     wsync();
     for2(mb, mb, [&](int j, int p) {
         Z[p * LD + j] = dsc[p] * h1[p + MBL * j] * dsc[j];
     });
     wsync();
-    symeig_wg<LD>(Z, A, mb);
-    if (tid == 0) {
-        int rr = 0;
-        for (int i = 0; i < mb; ++i) {
-            const double t = Z[i * LD + i];
-            if (t > drop) {
-                keep[rr] = i;
-                th[rr] = t;
-                ++rr;
-            }
+    int rp;
+    if (chol_inv_wg<LD>(Z, A, mb, 1e-6)) {
+        // well conditioned: Cp = Cwp D R^-1 (any orthonormal basis of the span)
+        rp = mb;
+        if (tid < mb) {
+            keep[tid] = tid;
+            th[tid] = 1.0;
         }
-        rank_s = rr;
+        wsync();
+    } else {
+        for2(mb, mb, [&](int j, int p) {
+            Z[p * LD + j] = dsc[p] * h1[p + MBL * j] * dsc[j];
+        });
+        wsync();
+        symeig_low<LD, MBL, 16>(Z, A, mb, mb, ev);
+        rp = wave_compact(mb, [&](int i) { return ev[i] > drop; }, keep);
+        if (tid < rp) th[tid] = 1.0 / sqrt(ev[keep[tid]]);
+        wsync();
     }
-    wsync();
-    const int rp = rank_s;
-    for2(mb, ns, [&](int j, int row) {  // Cp = Cwp D Zp_keep theta^-1/2
-        double s = 0.0;
-        if (j < rp) {
-            const int zc = keep[j];
-            for (int l = 0; l < mb; ++l) s += Tm[row * MBL + l] * dsc[l] * A[l * LD + zc];
-            s /= sqrt(th[j]);
-        }
-        out->Cp[row + ns * j] = s;
-    });
+    // Cp = Cwp D Zp_keep theta^-1/2 (zero beyond the kept rank)
+    wave_gemm(ns, rp, mb, [&](int row, int l) { return Tm[row * MBL + l] * dsc[l]; },
+              [&](int l, int j) { return A[l * LD + keep[j]]; },
+              [&](int row, int j, double v) { out->Cp[row + ns * j] = v * th[j]; });
+    for2(mb - rp, ns, [&](int j, int row) { out->Cp[row + ns * (rp + j)] = 0.0; });
     wsync();
 }
 

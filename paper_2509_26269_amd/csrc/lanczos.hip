@@ -226,7 +226,6 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
     constexpr int LD = LZ_MAXM + 1;
     __shared__ double A[LD * LD], Z[LD * LD];
     __shared__ double ev[LZ_MAXM];
-    __shared__ int order[LZ_MAXM];
     const int lane = wlane();
     if (ctrl->done) {  // stopped inside the cycle (NaN, no direction left)
         if (lane == 0) {
@@ -240,28 +239,18 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
     const int b = ctrl->blk;
     for2(m, m, [&](int r, int c) { A[r * LD + c] = 0.5 * (ctrl->T[r * LZ_LDT + c] + ctrl->T[c * LZ_LDT + r]); });
     wsync();
-    symeig_wg<LD>(A, Z, m);
-    // NaN ranks as +inf, so that the ranks below always form a permutation
-    for (int i = lane; i < m; i += WL) ev[i] = A[i * LD + i] == A[i * LD + i] ? A[i * LD + i] : INFINITY;
-    wsync();
-    for (int i = lane; i < m; i += WL) {
-        const double li = ev[i];
-        int rk = 0;
-        for (int q = 0; q < m; ++q) rk += (ev[q] < li) || (ev[q] == li && q < i);
-        order[rk] = i;
-    }
-    wsync();
+    // the kk lowest Ritz pairs, ascending (column i of Z)
     const int kk = keep < m ? keep : m;
-    for2(kk, m, [&](int i, int r) { ctrl->Y[i * LZ_MAXM + r] = Z[r * LD + order[i]]; });
+    symeig_low<LD, 32>(A, Z, m, kk, ev);
+    for2(kk, m, [&](int i, int r) { ctrl->Y[i * LZ_MAXM + r] = Z[r * LD + i]; });
     for (int i = lane; i < kk; i += WL) {
-        const int zi = order[i];
         double r2 = 0.0;
         for (int l = 0; l < b; ++l) {
             double t = 0.0;
-            for (int c = 0; c < m; ++c) t += ctrl->T[(m + l) * LZ_LDT + c] * Z[c * LD + zi];
+            for (int c = 0; c < m; ++c) t += ctrl->T[(m + l) * LZ_LDT + c] * Z[c * LD + i];
             r2 += t * t;
         }
-        const double th = ev[zi];
+        const double th = ev[i];
         const double rn = sqrt(r2);
         ctrl->theta[i] = th;
         ctrl->resid[i] = rn;
