@@ -204,7 +204,7 @@ __device__ void symeig_wg(double* A, double* Z, int n) {
 //     the three-term recurrence of the leading minors det(T_i - x I), on T
 //     scaled by a power of two to norm < 1 (so no overflow; rescaled against
 //     underflow); the counts of the group pick the sub-interval;
-//  3. eigenvectors of T by two steps of inverse iteration (a lane per
+//  3. eigenvectors of T by one step of inverse iteration (a lane per
 //     eigenvalue, Gaussian elimination with partial pivoting, counter-based
 //     start vectors), then modified Gram-Schmidt inside each cluster of
 //     eigenvalues closer than 1e-3 ||T|| (the clustering rule of LAPACK's
@@ -355,7 +355,7 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
 #pragma unroll
             for (int c0 = 0; c0 < NM; c0 += 8)
                 if (c0 + 8 > k + 1) {
-                    asm volatile("" ::: "memory");
+                    if constexpr (NM > 32) asm volatile("" ::: "memory");
 #pragma unroll
                     for (int c = c0; c < c0 + 8; ++c) pa[c & 3] = fma(a[c], vk[c], pa[c & 3]);
                 }
@@ -368,7 +368,7 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
                 if (c0 + 8 > k + 1) {
                     // one chunk of broadcast operands live at a time (the
                     // scheduler would otherwise hoist all 2 NM of them)
-                    asm volatile("" ::: "memory");
+                    if constexpr (NM > 32) asm volatile("" ::: "memory");
 #pragma unroll
                     for (int c = c0; c < c0 + 8; ++c) a[c] -= 2.0 * (v * hw[c] + wv * vk[c]);
                 }
@@ -426,10 +426,11 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
             const double lm = lamh[lane];
             const uint64_t seed = 0x5EED0000ull + (uint64_t)lane;
             double scale = 1.0;
-            for (int itn = 0; itn < 2; ++itn) {
-                auto rhs = [&](int i) {
-                    return itn == 0 ? 2.0 * splitmix_uniform(seed, (uint64_t)i) - 1.0 : Z[i * ldz + lane] * scale;
-                };
+            // one solve: lambda is exact to rounding, so the wanted component
+            // grows by ~1 / (eps ||T||) and any other by 1 / gap; what is left
+            // inside a cluster is removed below
+            {
+                auto rhs = [&](int i) { return 2.0 * splitmix_uniform(seed, (uint64_t)i) - 1.0; };
                 // forward elimination with row interchanges; the current row
                 // (r0, r1) sits at columns (i, i + 1), right-hand side cr
                 double r0 = dh[0] - lm, r1 = eh[0], cr = rhs(0);
@@ -528,13 +529,13 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
             double q4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int c = 0; c < NM; ++c) {
-                if ((c & 7) == 0) asm volatile("" ::: "memory");
+                if (NM > 32 && (c & 7) == 0) asm volatile("" ::: "memory");
                 q4[c & 3] = fma(bc[c], y[c], q4[c & 3]);
             }
             const double cf = (q4[0] + q4[1]) + (q4[2] + q4[3]);
 #pragma unroll
             for (int c = 0; c < NM; ++c) {
-                if ((c & 7) == 0) asm volatile("" ::: "memory");
+                if (NM > 32 && (c & 7) == 0) asm volatile("" ::: "memory");
                 y[c] = fma(-cf, bc[c], y[c]);
             }
         }
@@ -548,7 +549,7 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
 #pragma unroll
         for (int c0 = 0; c0 < NM; c0 += 8)
             if (c0 + 8 > k + 1) {
-                asm volatile("" ::: "memory");
+                if constexpr (NM > 32) asm volatile("" ::: "memory");
 #pragma unroll
                 for (int c = c0; c < c0 + 8; ++c) q4[c & 3] = fma(y[c], vk[c], q4[c & 3]);
             }
@@ -556,7 +557,7 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
 #pragma unroll
         for (int c0 = 0; c0 < NM; c0 += 8)
             if (c0 + 8 > k + 1) {
-                asm volatile("" ::: "memory");
+                if constexpr (NM > 32) asm volatile("" ::: "memory");
 #pragma unroll
                 for (int c = c0; c < c0 + 8; ++c) y[c] = fma(-dt, vk[c], y[c]);
             }
