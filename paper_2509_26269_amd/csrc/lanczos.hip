@@ -286,48 +286,69 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
 
 // After k_lz_rr: Q[:, 0..kk) = Q[:, 0..m) Y (rows in place); when going on,
 // Q[:, kk + l] = Q[:, m + l] (l < b; after a breakdown the dependent last
-// column becomes fresh SplitMix64 entries) and T = diag(theta).  Destination
-// columns never exceed their sources, so the copies run in increasing l.
-template <class T, int MM>
+// column becomes fresh SplitMix64 entries) and T = diag(theta).  The product
+// runs on the matrix cores: a wave takes 16 rows at a time, reads all m
+// basis columns of them into FP64 16x16x4 products against Y (in LDS,
+// zero-padded to 64 x 64) and writes its rows only after that, so the update
+// is in place; the residual columns of the same rows move last.  Lane l of a
+// product supplies Q[4 t + l / 16][row l % 16] and Y[4 t + l / 16][col l % 16]
+// and receives row l / 16 + 4 q of the tile.
+typedef double lz_d4 __attribute__((ext_vector_type(4)));
+
+template <class T>
 __global__ __launch_bounds__(NT) void k_lz_restart(int n2, T* __restrict__ Q, const uint8_t* __restrict__ mask,
                                                    int N, uint64_t seed, LzCtrl* __restrict__ ctrl) {
-    __shared__ double Y[MM * MM];
+    __shared__ double Yt[LZ_MAXM][LZ_MAXM];  // Yt[c][i]: component c of Ritz vector i
     if (ctrl->status == MOTO_NAN || ctrl->status == MOTO_BREAKDOWN) return;
     const int m = ctrl->m_eff, kk = ctrl->nkeep, b = ctrl->blk;
     const bool brk = ctrl->brk != 0;
-    for (int i = threadIdx.x; i < kk * m; i += NT) Y[i] = ctrl->Y[(i / m) * LZ_MAXM + (i % m)];
+    for (int e = threadIdx.x; e < LZ_MAXM * LZ_MAXM; e += NT) {
+        const int c = e / LZ_MAXM, i = e - c * LZ_MAXM;
+        Yt[c][i] = (c < m && i < kk) ? ctrl->Y[i * LZ_MAXM + c] : 0.0;
+    }
     __syncthreads();
     const bool go_on = ctrl->done == 0;
     const uint64_t fseed = seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(ctrl->restarts + 1));
-    for (int r = blockIdx.x * NT + threadIdx.x; r < n2; r += gridDim.x * NT) {
-        T q[MM];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, lg = lane >> 4;
+    const int ks = (m + 3) >> 2, nt = (kk + 15) >> 4;
+    const int ntiles = (n2 + 15) >> 4, nwv = gridDim.x * (NT / 64);
+    for (int tile = blockIdx.x * (NT / 64) + wv; tile < ntiles; tile += nwv) {
+        const int r0 = tile * 16, ra = r0 + ln;
+        lz_d4 acc[4];
 #pragma unroll
-        for (int c = 0; c < MM; ++c)
-            if (c < m) q[c] = Q[(size_t)c * n2 + r];
-        for (int i = 0; i < kk; ++i) {
-            double s = 0.0;
+        for (int q = 0; q < 4; ++q) acc[q] = lz_d4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < ks; ++t) {
+            const int c = 4 * t + lg;
+            const double av = (c < m && ra < n2) ? (double)Q[(size_t)c * n2 + ra] : 0.0;
 #pragma unroll
-            for (int c = 0; c < MM; ++c)
-                if (c < m) s += (double)q[c] * Y[i * m + c];
-            Q[(size_t)i * n2 + r] = (T)s;
+            for (int q = 0; q < 4; ++q)
+                if (q < nt) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yt[c][16 * q + ln], acc[q], 0, 0, 0);
         }
-        if (go_on) {
-            for (int l = 0; l < b; ++l) {
-                T v;
-                if (brk && l == b - 1) {
-                    const int site = r < N ? r : r - N;
-                    v = (mask == nullptr || mask[site] != 0) ? (T)splitmix_uniform(fseed, (uint64_t)r) : T(0);
-                } else {
-                    v = Q[(size_t)(m + l) * n2 + r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < nt) {
+                const int col = 16 * q + ln;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = r0 + lg + 4 * e;
+                    if (row < n2 && col < kk) Q[(size_t)col * n2 + row] = (T)acc[q][e];
                 }
-                Q[(size_t)(kk + l) * n2 + r] = v;
             }
+        }
+        if (go_on && lg < b && ra < n2) {
+            T v;
+            if (brk && lg == b - 1) {
+                const int site = ra < N ? ra : ra - N;
+                v = (mask == nullptr || mask[site] != 0) ? (T)splitmix_uniform(fseed, (uint64_t)ra) : T(0);
+            } else {
+                v = Q[(size_t)(m + lg) * n2 + ra];
+            }
+            Q[(size_t)(kk + lg) * n2 + ra] = v;
         }
     }
 }
 
-// The restarted projected matrix: the kept Ritz values on the diagonal; the
-// couplings to the residual block are filled by the steps of the next cycle.
 // A launch of its own, after every block of k_lz_restart has read m_eff and brk.
 __global__ __launch_bounds__(NT) void k_lz_restart_ctrl(LzCtrl* __restrict__ ctrl) {
     if (ctrl->done) return;
@@ -397,19 +418,11 @@ hipError_t launch_lz_rr_restart(bool f64, int n2, int b, void* Q, int k, int kee
                                 hipStream_t st) {
     (void)b;
     hipLaunchKernelGGL(k_lz_rr, dim3(1), dim3(WL), 0, st, k, keep, tol_abs, max_restarts, ctrl);
-    auto go = [&](auto mmc) {
-        constexpr int MM = decltype(mmc)::value;
-        if (f64)
-            hipLaunchKernelGGL((k_lz_restart<double, MM>), dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, mask, N, seed,
-                               ctrl);
-        else
-            hipLaunchKernelGGL((k_lz_restart<float, MM>), dim3(nblk), dim3(NT), 0, st, n2, (float*)Q, mask, N, seed,
-                               ctrl);
-    };
-    if (m_max <= 32)
-        go(std::integral_constant<int, 32>{});
+    (void)m_max;
+    if (f64)
+        hipLaunchKernelGGL(k_lz_restart<double>, dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, mask, N, seed, ctrl);
     else
-        go(std::integral_constant<int, LZ_MAXM>{});
+        hipLaunchKernelGGL(k_lz_restart<float>, dim3(nblk), dim3(NT), 0, st, n2, (float*)Q, mask, N, seed, ctrl);
     hipLaunchKernelGGL(k_lz_restart_ctrl, dim3(1), dim3(NT), 0, st, ctrl);
     return hipGetLastError();
 }
