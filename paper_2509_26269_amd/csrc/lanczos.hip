@@ -16,8 +16,8 @@
 // space long after the first has met the stopping rule; a block of b
 // directions brings such a pair in together.
 // Q lives in one [m_max + b][2N] array; w is written straight into its
-// column.  At the end of a cycle one wavefront diagonalises T (FP64,
-// Householder tridiagonalisation and implicit QL), tests the residuals and
+// column.  At the end of a cycle one wavefront takes the `keep` lowest
+// eigenpairs of T (FP64, symeig_low), tests the residuals and
 // either stops or restarts from the `keep` lowest Ritz vectors plus the
 // residual block (Wu & Simon 2000), which is re-orthonormalised before the
 // next cycle; the steps of that cycle fill the couplings of T.  A breakdown
