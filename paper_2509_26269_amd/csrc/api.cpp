@@ -1233,15 +1233,20 @@ moto_status moto_saddle_search_population(moto_plan p, moto_dtype hvp, int32_t P
             if (inf[y].status == MOTO_NAN) {
                 nanm[y] = 1;
                 done[y] = 1;
+                // its state stops it: the population step below leaves it alone
+                HIP_TRY(launch_step_stop(w + L.state, (int)N, a.mem, L.state_b, y, st));
                 continue;
             }
-            StepArgs ay = a;
-            if (it == o.max_outer) ay.tau_F = INFINITY;  // last iterate: ||F_mmf|| without moving
-            HIP_TRY(launch_step(ay, m + (size_t)y * N3, F + (size_t)y * N3, V + (size_t)y * o.k * N3,
-                                w + L.state + L.state_b * (size_t)y, out + 2 * (size_t)y, st));
             ++active;
         }
         if (active == 0) break;
+        {
+            // every member in one set of launches; members that met tau_F or
+            // failed are stopped in their step state and left alone
+            StepArgs ay = a;
+            if (it == o.max_outer) ay.tau_F = INFINITY;  // last iterate: ||F_mmf|| without moving
+            HIP_TRY(launch_step_population(ay, P, o.k, m, F, V, w + L.state, L.state_b, out, st));
+        }
         rs = readback(p, out, sizeof(double) * 2 * (size_t)P, ho.data(), st);
         if (rs != MOTO_OK) return rs;
         int left = 0;

@@ -253,6 +253,9 @@ struct StepArgs {
 size_t step_state_bytes(int N, int mem);
 hipError_t launch_step(const StepArgs& a, double* m, const double* F, const double* V, void* state, double* out,
                        hipStream_t st);
+hipError_t launch_step_population(const StepArgs& a, int P, int k, double* m, const double* F, const double* V,
+                                  void* state, size_t state_bytes, double* out, hipStream_t st);
+hipError_t launch_step_stop(void* state, int N, int mem, size_t state_bytes, int y, hipStream_t st);
 hipError_t launch_seed_rotate(int N, double* m, const double* v1, double scale_sign_eta, double* part,
                               hipStream_t st);
 hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t st);

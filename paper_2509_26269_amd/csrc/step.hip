@@ -107,9 +107,35 @@ __device__ __forceinline__ Ring ring_next(const StepHdr* h, int mem, int rule) {
     return r;
 }
 
+// Members of a population stepped by one launch: member y = blockIdx.y owns
+// the step state at + y sb bytes, spins and forces at + y m3 doubles and its
+// modes at + y v3 doubles (all zero for a single search).
+struct StepBatch {
+    long long sb = 0, m3 = 0, v3 = 0;
+};
+
+__device__ __forceinline__ StepPtrs member_ptrs(StepPtrs P, const StepBatch& B) {
+    const long long off = (long long)blockIdx.y * B.sb;
+    auto sh = [&](auto* q) { return reinterpret_cast<decltype(q)>(reinterpret_cast<char*>(q) + off); };
+    P.hdr = sh(P.hdr);
+    P.S = sh(P.S);
+    P.Y = sh(P.Y);
+    P.G = sh(P.G);
+    P.Gp = sh(P.Gp);
+    P.dp = sh(P.dp);
+    P.d = sh(P.d);
+    P.pgram = sh(P.pgram);
+    P.pdot = sh(P.pdot);
+    P.pmax = sh(P.pmax);
+    return P;
+}
+
 // (1) per-block partial dots F . v_r
 __global__ __launch_bounds__(NT) void k_step_dots(StepArgs a, const double* __restrict__ F,
-                                                  const double* __restrict__ V, StepPtrs P) {
+                                                  const double* __restrict__ V, StepPtrs P, StepBatch B) {
+    P = member_ptrs(P, B);
+    F += blockIdx.y * B.m3;
+    V += blockIdx.y * B.v3;
     if (P.hdr->stopped) return;
     __shared__ double red[MAXR * (NT / 64)];
     double v[MAXR] = {0, 0, 0, 0};
@@ -129,7 +155,11 @@ __global__ __launch_bounds__(NT) void k_step_dots(StepArgs a, const double* __re
 // Gram partials of {S_0..S_{c-1}, Y_0..Y_{c-1}, G} and ||F_mmf||^2.
 __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __restrict__ m,
                                                   const double* __restrict__ F, const double* __restrict__ V,
-                                                  StepPtrs P) {
+                                                  StepPtrs P, StepBatch B) {
+    P = member_ptrs(P, B);
+    m += blockIdx.y * B.m3;
+    F += blockIdx.y * B.m3;
+    V += blockIdx.y * B.v3;
     const StepHdr* h = P.hdr;
     if (h->stopped) return;
     __shared__ double fr[MAXR];
@@ -259,7 +289,8 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
 // (3) reduce the Gram (one wavefront per entry, fixed-order sums), then one
 // thread: stop test, two-loop recursion in coefficient space, reset test;
 // writes the direction coefficients.
-__global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P) {
+__global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P, StepBatch B) {
+    P = member_ptrs(P, B);
     StepHdr* h = P.hdr;
     if (h->stopped) return;
     __shared__ double gs[SNE + 1];
@@ -275,9 +306,14 @@ __global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P) {
         s = wave_sum(s);
         if (lane == 0) gs[ee] = s;
     }
+    // the serial control below runs on one thread; its arrays live in LDS
+    // (as per-thread arrays indexed at run time they would sit in scratch,
+    // a global-memory round trip per access)
+    __shared__ double Gm[SNV][SNV];
+    __shared__ double coef[SNV], q[SNV], alph[SMEM], rho[SMEM];
+    __shared__ bool valid[SMEM];
     __syncthreads();
     if (threadIdx.x != 0) return;
-    double Gm[SNV][SNV];
     for (int e = 0; e < ne; ++e) {
         int p = e, i = 0;
         while (p >= nv - i) {
@@ -296,8 +332,7 @@ __global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P) {
         return;
     }
     const int iG = 2 * c;
-    double coef[SNV];
-    for (int q = 0; q < nv; ++q) coef[q] = 0.0;
+    for (int i = 0; i < nv; ++i) coef[i] = 0.0;
     bool reset = (a.rule == 1);
     if (a.rule == 2) {
         // nonlinear CG (Fletcher-Reeves) on G with one stored pair: S_0 is
@@ -312,8 +347,6 @@ __global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P) {
             if (-GG + bs * Gm[0][iG] < 0.0) coef[0] = a.alpha0 * bs;
         }
     } else if (a.rule == 0) {
-        double q[SNV], alph[SMEM], rho[SMEM];
-        bool valid[SMEM];
         for (int i = 0; i < nv; ++i) q[i] = 0.0;
         q[iG] = 1.0;
         int newest = -1;
@@ -347,16 +380,19 @@ __global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P) {
         if (!(dG < 0.0)) reset = true;
     }
     if (reset) {
-        for (int q = 0; q < nv; ++q) coef[q] = 0.0;
+        for (int i = 0; i < nv; ++i) coef[i] = 0.0;
         coef[iG] = -a.alpha0;
         if (a.rule == 0) h->count = 0;
     }
-    for (int q = 0; q < SNV; ++q) h->coef[q] = q < nv ? coef[q] : 0.0;
+    for (int i = 0; i < SNV; ++i) h->coef[i] = i < nv ? coef[i] : 0.0;
     h->cu = c;
 }
 
 // (4) direction d = P(sum coef . vectors) and per-block max |d_i|
-__global__ __launch_bounds__(NT) void k_step_dir(StepArgs a, const double* __restrict__ m, StepPtrs P) {
+__global__ __launch_bounds__(NT) void k_step_dir(StepArgs a, const double* __restrict__ m, StepPtrs P,
+                                                 StepBatch B) {
+    P = member_ptrs(P, B);
+    m += blockIdx.y * B.m3;
     const StepHdr* h = P.hdr;
     if (h->stopped) return;
     __shared__ double red[NT / 64];
@@ -392,7 +428,10 @@ __global__ __launch_bounds__(NT) void k_step_dir(StepArgs a, const double* __res
 
 // (5) rotation cap and exponential-map rotation of every spin; d -> d_prev,
 // G -> G_prev.
-__global__ __launch_bounds__(NT) void k_step_rot(StepArgs a, double* __restrict__ m, StepPtrs P, int nblk_dir) {
+__global__ __launch_bounds__(NT) void k_step_rot(StepArgs a, double* __restrict__ m, StepPtrs P, int nblk_dir,
+                                                 StepBatch B) {
+    P = member_ptrs(P, B);
+    m += blockIdx.y * B.m3;
     const StepHdr* h = P.hdr;
     if (h->stopped) return;
     __shared__ double scale_s;
@@ -428,8 +467,10 @@ __global__ __launch_bounds__(NT) void k_step_rot(StepArgs a, double* __restrict_
     }
 }
 
-__global__ void k_step_finish(StepPtrs P, double* __restrict__ out) {
+__global__ void k_step_finish(StepPtrs P, double* __restrict__ out, StepBatch B) {
     if (threadIdx.x != 0) return;
+    P = member_ptrs(P, B);
+    out += 2 * blockIdx.y;
     StepHdr* h = P.hdr;
     out[0] = h->fnorm;
     out[1] = h->stopped ? 1.0 : 0.0;
@@ -439,16 +480,44 @@ __global__ void k_step_finish(StepPtrs P, double* __restrict__ out) {
     }
 }
 
-hipError_t launch_step(const StepArgs& a, double* m, const double* F, const double* V, void* state, double* out,
-                       hipStream_t st) {
+static hipError_t launch_step_members(const StepArgs& a, double* m, const double* F, const double* V, void* state,
+                                      double* out, int members, const StepBatch& B, hipStream_t st) {
     StepPtrs P = step_ptrs(state, a.N, a.mem, nullptr);
     const int nb = P.nblk;
-    if (a.k_reflect > 0) hipLaunchKernelGGL(k_step_dots, dim3(nb), dim3(NT), 0, st, a, F, V, P);
-    hipLaunchKernelGGL(k_step_gram, dim3(nb), dim3(NT), 0, st, a, m, F, V, P);
-    hipLaunchKernelGGL(k_step_ctrl, dim3(1), dim3(NT), 0, st, a, P);
-    hipLaunchKernelGGL(k_step_dir, dim3(nb), dim3(NT), 0, st, a, m, P);
-    hipLaunchKernelGGL(k_step_rot, dim3(nb), dim3(NT), 0, st, a, m, P, nb);
-    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64), 0, st, P, out);
+    if (a.k_reflect > 0) hipLaunchKernelGGL(k_step_dots, dim3(nb, members), dim3(NT), 0, st, a, F, V, P, B);
+    hipLaunchKernelGGL(k_step_gram, dim3(nb, members), dim3(NT), 0, st, a, m, F, V, P, B);
+    hipLaunchKernelGGL(k_step_ctrl, dim3(1, members), dim3(NT), 0, st, a, P, B);
+    hipLaunchKernelGGL(k_step_dir, dim3(nb, members), dim3(NT), 0, st, a, m, P, B);
+    hipLaunchKernelGGL(k_step_rot, dim3(nb, members), dim3(NT), 0, st, a, m, P, nb, B);
+    hipLaunchKernelGGL(k_step_finish, dim3(1, members), dim3(64), 0, st, P, out, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const StepArgs& a, double* m, const double* F, const double* V, void* state, double* out,
+                       hipStream_t st) {
+    return launch_step_members(a, m, F, V, state, out, 1, StepBatch{}, st);
+}
+
+// One step of P members in one set of launches (member y: spins and forces at
+// + y 3N, modes at + y k 3N, step state at + y state_bytes, output at + 2y);
+// members whose state says stopped are left alone.
+hipError_t launch_step_population(const StepArgs& a, int P, int k, double* m, const double* F, const double* V,
+                                  void* state, size_t state_bytes, double* out, hipStream_t st) {
+    StepBatch B;
+    B.sb = (long long)state_bytes;
+    B.m3 = 3LL * a.N;
+    B.v3 = (long long)k * 3LL * a.N;
+    return launch_step_members(a, m, F, V, state, out, P, B, st);
+}
+
+__global__ void k_step_stop(StepHdr* h) {
+    if (threadIdx.x == 0) h->stopped = 1;
+}
+
+// Marks member y's step state stopped (a member whose eigen-solve failed).
+hipError_t launch_step_stop(void* state, int N, int mem, size_t state_bytes, int y, hipStream_t st) {
+    StepPtrs P = step_ptrs((char*)state + state_bytes * (size_t)y, N, mem, nullptr);
+    hipLaunchKernelGGL(k_step_stop, dim3(1), dim3(64), 0, st, P.hdr);
     return hipGetLastError();
 }
 
