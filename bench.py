@@ -241,6 +241,8 @@ def main():
     ap.add_argument("--nvec", type=int, default=4)
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--searches", type=int, default=2, help="one-at-a-time GPU searches timed")
+    ap.add_argument("--searches-masked", type=int, default=8,
+                    help="of the masked 128x128 starts, how many also run one at a time")
     ap.add_argument("--batched", type=int, default=64, help="searches on 128x128 in the batched (one-launch) leg")
     ap.add_argument("--ragged", type=int, default=256, help="searches on uneven 32..96 lattices, one launch")
     ap.add_argument("--max-outer", type=int, default=300, help="outer-iteration cap of the unmasked search legs")
@@ -706,14 +708,15 @@ def main():
             extra["population_128_masked_disc8"] = summary(resm, el, args.max_outer_masked)
             extra["population_128_masked_disc8"]["masked_sites"] = int(disc.sum())
             del mpop, mmask
-            if args.searches > 0:
-                # the same masked starts one at a time through moto_saddle_search
-                print(f"[bench] {args.searches} masked saddle searches on {L}x{L} one at a time", file=sys.stderr,
+            nsm = min(args.searches_masked, args.batched)
+            if nsm > 0:
+                # the first of the same masked starts one at a time through moto_saddle_search
+                print(f"[bench] {nsm} masked saddle searches on {L}x{L} one at a time", file=sys.stderr,
                       flush=True)
                 dmask = torch.as_tensor(disc, device="cuda")
                 r1s = []
                 t0 = time.perf_counter()
-                for i in range(args.searches):
+                for i in range(nsm):
                     md = torch.as_tensor(S.batch_member(spec, i), device="cuda")
                     r1, _, _ = M.moto_saddle_search(plan, md, M.MOTO_F32, mask=dmask, opts=som)
                     r1s.append(r1)

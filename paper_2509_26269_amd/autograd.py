@@ -15,6 +15,8 @@ Every value comes from the HIP kernels; this module only marshals tensors.
 """
 from __future__ import annotations
 
+from collections import OrderedDict
+
 import torch
 
 from . import moto as M
@@ -25,10 +27,28 @@ def _split_theta(theta: torch.Tensor, ns: int):
     return t[:ns], t[ns:2 * ns], t[2 * ns], tuple(t[2 * ns + 1:2 * ns + 4])
 
 
+_PLANS: "OrderedDict[tuple, M.Plan]" = OrderedDict()
+_PLAN_CACHE = 8
+
+
 def _plan(Lx: int, Ly: int, theta: torch.Tensor) -> M.Plan:
+    """The plan of (Lx, Ly, theta), reused across forward and backward calls
+    (a plan holds shell tables and a pinned read-back buffer); the least
+    recently used of more than eight is closed."""
     ns = (theta.numel() - 4) // 2
     J, D, K, B = _split_theta(theta, ns)
-    return M.Plan(Lx, Ly, J, D, K, B)
+    key = (Lx, Ly, tuple(J), tuple(D), K, B)
+    plan = _PLANS.get(key)
+    if plan is None:
+        plan = M.Plan(Lx, Ly, J, D, K, B)
+        _PLANS[key] = plan
+        while len(_PLANS) > _PLAN_CACHE:
+            _, old = _PLANS.popitem(last=False)
+            torch.cuda.synchronize()  # nothing queued may still use it
+            old.close()
+    else:
+        _PLANS.move_to_end(key)
+    return plan
 
 
 def _batch(m: torch.Tensor, N: int) -> int:

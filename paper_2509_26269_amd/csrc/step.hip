@@ -313,8 +313,8 @@ __global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P, StepBa
     __shared__ double coef[SNV], q[SNV], alph[SMEM], rho[SMEM];
     __shared__ bool valid[SMEM];
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int e = 0; e < ne; ++e) {
+    // the Gram as a full matrix (every thread decodes its own entries)
+    for (int e = threadIdx.x; e < ne; e += NT) {
         int p = e, i = 0;
         while (p >= nv - i) {
             p -= nv - i;
@@ -323,6 +323,8 @@ __global__ __launch_bounds__(NT) void k_step_ctrl(StepArgs a, StepPtrs P, StepBa
         Gm[i][i + p] = gs[e];
         Gm[i + p][i] = gs[e];
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const double fn = sqrt(gs[SNE]);
     h->fnorm = fn;
     h->count = c;
