@@ -290,9 +290,10 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
 // runs on the matrix cores: a wave takes 16 rows at a time, reads all m
 // basis columns of them into FP64 16x16x4 products against Y (in LDS,
 // zero-padded to 64 x 64) and writes its rows only after that, so the update
-// is in place; the residual columns of the same rows move last.  Lane l of a
-// product supplies Q[4 t + l / 16][row l % 16] and Y[4 t + l / 16][col l % 16]
-// and receives row l / 16 + 4 q of the tile.
+// is in place; the residual columns of the same rows move last.  The
+// product is formed transposed (Y^T Q^T): lane l supplies Y[4 t + l / 16]
+// [col l % 16] and Q[4 t + l / 16][row l % 16] and receives row l % 16 of
+// column l / 16 + 4 e, so every store writes 16 consecutive rows.
 typedef double lz_d4 __attribute__((ext_vector_type(4)));
 
 template <class T>
@@ -323,16 +324,19 @@ __global__ __launch_bounds__(NT) void k_lz_restart(int n2, T* __restrict__ Q, co
             const double av = (c < m && ra < n2) ? (double)Q[(size_t)c * n2 + ra] : 0.0;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (q < nt) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Yt[c][16 * q + ln], acc[q], 0, 0, 0);
+                if (q < nt) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Yt[c][16 * q + ln], av, acc[q], 0, 0, 0);
         }
+        // transposed product: lane (ln, lg) holds row r0 + ln of columns
+        // 16 q + lg + 4 e (16 consecutive rows per store)
+        if (ra < n2) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (q < nt) {
-                const int col = 16 * q + ln;
+            for (int q = 0; q < 4; ++q) {
+                if (q < nt) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = r0 + lg + 4 * e;
-                    if (row < n2 && col < kk) Q[(size_t)col * n2 + row] = (T)acc[q][e];
+                    for (int e = 0; e < 4; ++e) {
+                        const int col = 16 * q + lg + 4 * e;
+                        if (col < kk) Q[(size_t)col * n2 + ra] = (T)acc[q][e];
+                    }
                 }
             }
         }

@@ -324,14 +324,16 @@ __global__ __launch_bounds__(NT) void k_orth_apply_mfma(EigArgs a, int target, f
                 const int i = 4 * t + lg;
                 const int col = i >= nrow ? -1 : i < nq ? oc.qcol[i] : oc.t0 + (i - nq);
                 const double av = (col >= 0 && ra < n2) ? (double)S[(size_t)col * n2 + ra] : 0.0;
-                y = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cc[i][ln], y, 0, 0, 0);
+                y = __builtin_amdgcn_mfma_f64_16x16x4f64(cc[i][ln], av, y, 0, 0, 0);
             }
         }
-        if (ln < mb) {
+        // transposed product: lane (ln, lg) holds row r0 + ln of target
+        // columns lg + 4 q (16 consecutive rows per store)
+        if (ra < n2) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row = r0 + lg + 4 * q;
-                if (row < n2) S[(size_t)(oc.t0 + ln) * n2 + row] = (float)y[q];
+                const int col = lg + 4 * q;
+                if (col < mb) S[(size_t)(oc.t0 + col) * n2 + ra] = (float)y[q];
             }
         }
     }
