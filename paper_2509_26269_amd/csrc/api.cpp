@@ -531,7 +531,7 @@ static moto_status min_modes_pop_impl(moto_plan p, moto_dtype hvp, int P, const 
     auto chunk_launches = [&](hipStream_t s) -> hipError_t {
         for (int it = 0; it < every; ++it) {
             for (int pass = 0; pass < 2; ++pass) {
-                hipError_t e = launch_orth(f64, a, 1, S, part, L.nblk_g, G, ctrl, s);
+                hipError_t e = launch_orth(f64, a, 1 + pass, S, part, L.nblk_g, G, ctrl, s);
                 if (e != hipSuccess) return e;
             }
             hipError_t e = launch_tangent_hvp(p->g, p->k, f64, true, P, mT, cT, mask, L.mb, Wslot, HWslot, hv_done,

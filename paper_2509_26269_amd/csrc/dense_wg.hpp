@@ -637,7 +637,7 @@ __device__ __forceinline__ void for2(int na, int nb, F&& f) {
 // columns whose projected norm is negligible get a zero transform.
 // --------------------------------------------------------------------------
 template <int LD>
-__device__ void orth_small_body(int mb, int nq, double drop, const double* G, double* Bw, double* Tw);
+__device__ bool orth_small_body(int mb, int nq, double drop, const double* G, double* Bw, double* Tw);
 
 // --------------------------------------------------------------------------
 // D = A B on one wavefront with FP64 16x16x4 matrix-core products.  Elements
@@ -712,11 +712,13 @@ __device__ __forceinline__ int wave_compact(int n, P&& pred, int* list) {
 // overwritten by the factor.  (Golub & Van Loan, Section 4.2.)
 // --------------------------------------------------------------------------
 template <int LD>
-__device__ __forceinline__ bool chol_inv_wg(double* A, double* Z, int n, double tau) {
+__device__ __forceinline__ bool chol_inv_wg(double* A, double* Z, int n, double tau, double* minpiv = nullptr) {
     const int lane = wlane();
+    double dmin = INFINITY;
     for (int j = 0; j < n; ++j) {
         const double d = A[j * LD + j];
         if (!(d > tau)) return false;
+        dmin = fmin(dmin, d);
         const double id = 1.0 / d;
         // trailing update with the unscaled column j, then its scaling
         for2(n - j - 1, n - j - 1, [&](int a, int b) {
@@ -747,11 +749,12 @@ __device__ __forceinline__ bool chol_inv_wg(double* A, double* Z, int n, double 
             if (c < n) Z[lane * LD + c] = x[c];
     }
     wsync();
+    if (minpiv) *minpiv = dmin;
     return true;
 }
 
 template <int LD>
-__device__ void orth_small_body(int mb, int nq, double drop, const double* G, double* Bw, double* Tw) {
+__device__ bool orth_small_body(int mb, int nq, double drop, const double* G, double* Bw, double* Tw) {
     // G is read many times below: it is first copied to LDS
     constexpr int MBL = LD / 3;
     __shared__ double A[MBL * LD];
@@ -774,11 +777,14 @@ __device__ void orth_small_body(int mb, int nq, double drop, const double* G, do
                   Mq[r * MBL + c] = v;
                   A[r * LD + c] = G[c * nrow + nq + r] - v;
               });
+    double kept = 1.0;  // smallest fraction of a column's squared norm left by the projection
     if (tid < mb) {
         const double full = G[tid * nrow + nq + tid];
         const double proj = A[tid * LD + tid];
         dsc[tid] = (proj > drop * full && proj > 0.0) ? 1.0 / sqrt(proj) : 0.0;
+        kept = proj > 0.0 && full > 0.0 ? proj / full : 0.0;
     }
+    kept = -wmax_dpp(-kept);
     wsync();
     double emax = 0.0;
     for2(mb, mb, [&](int c, int r) {
@@ -791,6 +797,8 @@ __device__ void orth_small_body(int mb, int nq, double drop, const double* G, do
     // at rounding level: (I + E)^(-1/2) = I - E/2 + 3/8 E^2 replaces the
     // eigen-decomposition (Z holds that transform, th = 1)
     int nkeep;
+    double minpiv = 0.0;
+    bool settled = false;  // one pass suffices (see the Cholesky branch)
     if (wmax_dpp(emax) < 1e-5) {
         if (tid < mb) A[tid * LD + tid] = dsc[tid] > 0.0 ? A[tid * LD + tid] - 1.0 : 0.0;  // E in place
         nkeep = wave_compact(mb, [&](int i) { return dsc[i] > 0.0; }, keep);
@@ -799,10 +807,11 @@ __device__ void orth_small_body(int mb, int nq, double drop, const double* G, do
                   [&](int i, int j, double v) {
                       Z[i * LD + j] = (i == j ? 1.0 : 0.0) - 0.5 * A[i * LD + j] + 0.375 * v;
                   });
-    } else if (chol_inv_wg<LD>(A, Z, mb, 1e-6)) {
+    } else if (chol_inv_wg<LD>(A, Z, mb, 1e-6, &minpiv)) {
         // well conditioned: T = D R^-1 spans the same space (Rayleigh-Ritz
         // does not depend on which orthonormal basis of it is taken)
         nkeep = mb;
+        settled = minpiv > 0.1 && kept > 0.25;
         if (tid < mb) {
             keep[tid] = tid;
             th[tid] = 1.0;
@@ -823,6 +832,7 @@ __device__ void orth_small_body(int mb, int nq, double drop, const double* G, do
         Tw[row + mb * c] = c < nkeep ? dsc[row] * Z[row * LD + keep[c]] / sqrt(th[c]) : 0.0;
     });
     wsync();
+    return settled;
 }
 
 // --------------------------------------------------------------------------

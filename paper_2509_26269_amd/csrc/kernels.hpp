@@ -139,7 +139,7 @@ struct EigCtrl {
     int np;           // columns of P in the current basis (0 or mb)
     long long n_hvp;  // HVP columns applied
     int rank;         // basis rank kept by the last Rayleigh-Ritz
-    int pad;
+    int orth_skip;    // 1: the first orthonormalisation pass of W settled it (the second is a no-op)
     double lam[MAXB];
     double resid[MAXB];
     double C[MAXS * MAXB];       // Ritz coefficients of X, column-major [ns][mb]
@@ -220,7 +220,8 @@ hipError_t launch_eig_init(bool f64, const EigArgs& a, void* S, const double* m,
                            const void* Xsave, int use_save, const uint8_t* mask, int N, uint64_t seed,
                            EigCtrl* ctrl, hipStream_t st);
 // Orthonormalise the X block (target 0, start) or the W block against [X P]
-// and itself (target 1), in place.
+// and itself (target 1: first pass, target 2: second pass, a no-op when the
+// first was well conditioned), in place.
 hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* part, int nblk, double* G,
                        EigCtrl* ctrl, hipStream_t st);
 hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const void* HS, double* part, int nblk,

@@ -163,7 +163,7 @@ struct OrthCols {
 __device__ __forceinline__ void orth_cols(const EigArgs& a, int target, const EigCtrl* ctrl, OrthCols& oc) {
     oc.nq = 0;
     oc.t0 = target == 0 ? 0 : a.mb;
-    if (target == 1) {
+    if (target >= 1) {
         for (int i = 0; i < a.mb; ++i) oc.qcol[oc.nq++] = i;                    // X
         for (int i = 0; i < ctrl->np; ++i) oc.qcol[oc.nq++] = 2 * a.mb + i;     // P
     }
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(NT) void k_orth_gram(EigArgs a, int target, const T
     S += blockIdx.y * a.s_ms;
     part += blockIdx.y * a.part_ms;
     ctrl += blockIdx.y;
-    if (ctrl->done) return;
+    if (ctrl->done || (target == 2 && ctrl->orth_skip)) return;
     __shared__ OrthCols oc;
     __shared__ T ts[MAXS][RCH];
     if (threadIdx.x == 0) orth_cols(a, target, ctrl, oc);
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(NT) void k_orth_gram_mfma(EigArgs a, int target, co
     S += blockIdx.y * a.s_ms;
     part += blockIdx.y * a.part_ms;
     ctrl += blockIdx.y;
-    if (ctrl->done) return;
+    if (ctrl->done || (target == 2 && ctrl->orth_skip)) return;
     constexpr int TT = (MAXS + 15) / 16;
     __shared__ OrthCols oc;
     __shared__ double acc_l[TT][256];
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_orth_apply_mfma(EigArgs a, int target, f
                                                         const EigCtrl* __restrict__ ctrl) {
     S += blockIdx.y * a.s_ms;
     ctrl += blockIdx.y;
-    if (ctrl->done) return;
+    if (ctrl->done || (target == 2 && ctrl->orth_skip)) return;
     __shared__ OrthCols oc;
     __shared__ double cc[MAXS][16];
     if (threadIdx.x == 0) orth_cols(a, target, ctrl, oc);
@@ -350,10 +350,10 @@ __global__ __launch_bounds__(NT) void k_reduce_rows(EigArgs a, const double* __r
     part += blockIdx.y * a.part_ms;
     G += blockIdx.y * a.g_ms;
     ctrl += blockIdx.y;
-    if (ctrl->done) return;
+    if (ctrl->done || (kind == 0 && arg == 2 && ctrl->orth_skip)) return;
     int E;
     if (kind == 0) {
-        const int nq = arg == 1 ? a.mb + ctrl->np : 0;
+        const int nq = arg >= 1 ? a.mb + ctrl->np : 0;
         E = (nq + a.mb) * a.mb;
     } else {
         const int ns = sol_ns(a, ctrl, arg);
@@ -373,9 +373,15 @@ __global__ __launch_bounds__(WL) void k_orth_small(EigArgs a, int target, const 
                                                    EigCtrl* __restrict__ ctrl) {
     G += blockIdx.y * a.g_ms;
     ctrl += blockIdx.y;
-    if (ctrl->done) return;
-    const int nq = target == 1 ? a.mb + ctrl->np : 0;
-    orth_small_body<MAXS + 1>(a.mb, nq, a.drop, G, ctrl->Bw, ctrl->Tw);
+    if (ctrl->done || (target == 2 && ctrl->orth_skip)) return;
+    const int nq = target >= 1 ? a.mb + ctrl->np : 0;
+    const bool settled = orth_small_body<MAXS + 1>(a.mb, nq, a.drop, G, ctrl->Bw, ctrl->Tw);
+    // after a first pass that kept every column, lost at most half of each
+    // column's norm to the projection and met an inverse Cholesky factor with
+    // pivots above 0.1, the block is orthonormal and orthogonal to [X P] to a
+    // few FP32 roundings, which the Rayleigh-Ritz step's near-identity series
+    // absorbs: the second pass is not needed
+    if (target == 1 && wlane() == 0) ctrl->orth_skip = settled ? 1 : 0;
 }
 
 // MB: compile-time bound on the block width (mb <= MB), so that the per-row
@@ -385,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_orth_apply(EigArgs a, int target, T* __r
                                                    const EigCtrl* __restrict__ ctrl) {
     S += blockIdx.y * a.s_ms;
     ctrl += blockIdx.y;
-    if (ctrl->done) return;
+    if (ctrl->done || (target == 2 && ctrl->orth_skip)) return;
     __shared__ OrthCols oc;
     __shared__ double B[2 * MAXB * MAXB];
     __shared__ double Tw[MAXB * MAXB];
