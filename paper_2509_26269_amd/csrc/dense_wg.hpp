@@ -571,40 +571,41 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
     wsync();
 }
 
-// Dispatch on the register-array bound NM >= n, in buckets of 16 up to NMAX
-// (default: the largest the leading dimension LD allows; callers whose n is
-// known to be small pass a smaller NMAX and get one bucket).  The LDS scratch
-// is shared by the buckets.  Same contract as symeig_low_nm with
-// lda = ldz = LD.
+// Dispatch on the register-array bound NM >= n, in buckets of 8 above 16 (16,
+// 24, 32, 40, 48, 64) up to NMAX (default: the largest the leading dimension
+// LD allows; callers whose n is known to be small pass a smaller NMAX and get
+// fewer buckets).  The LDS scratch is shared by the buckets.  Same contract as
+// symeig_low_nm with lda = ldz = LD.
 template <int LD, int NWS, int NMAX = ((LD - 1 + 15) / 16) * 16>
 __device__ __forceinline__ void symeig_low(double* A, double* Z, int n, int nw, double* w) {
-    static_assert(NMAX % 16 == 0 && NMAX <= WL, "one lane per row, buckets of 16");
+    static_assert(NMAX % 16 == 0 && NMAX <= WL, "one lane per row, buckets of 16 at the top");
     __shared__ double sb[symeig_low_doubles(NMAX, NWS)];
     if (n <= 0 || nw <= 0) return;
-    if constexpr (NMAX == 16) {
+    if (n <= 16 || NMAX == 16) {
         symeig_low_nm<16, NWS>(A, LD, Z, LD, n, nw, w, sb);
-    } else if constexpr (NMAX == 32) {
-        if (n <= 16)
-            symeig_low_nm<16, NWS>(A, LD, Z, LD, n, nw, w, sb);
-        else
-            symeig_low_nm<32, NWS>(A, LD, Z, LD, n, nw, w, sb);
-    } else if constexpr (NMAX == 48) {
-        if (n <= 16)
-            symeig_low_nm<16, NWS>(A, LD, Z, LD, n, nw, w, sb);
-        else if (n <= 32)
-            symeig_low_nm<32, NWS>(A, LD, Z, LD, n, nw, w, sb);
-        else
-            symeig_low_nm<48, NWS>(A, LD, Z, LD, n, nw, w, sb);
-    } else {
-        if (n <= 16)
-            symeig_low_nm<16, NWS>(A, LD, Z, LD, n, nw, w, sb);
-        else if (n <= 32)
-            symeig_low_nm<32, NWS>(A, LD, Z, LD, n, nw, w, sb);
-        else if (n <= 48)
-            symeig_low_nm<48, NWS>(A, LD, Z, LD, n, nw, w, sb);
-        else
-            symeig_low_nm<64, NWS>(A, LD, Z, LD, n, nw, w, sb);
+        return;
     }
+    if constexpr (NMAX >= 32) {
+        if (n <= 24) {
+            symeig_low_nm<24, NWS>(A, LD, Z, LD, n, nw, w, sb);
+            return;
+        }
+        if (n <= 32 || NMAX == 32) {
+            symeig_low_nm<32, NWS>(A, LD, Z, LD, n, nw, w, sb);
+            return;
+        }
+    }
+    if constexpr (NMAX >= 48) {
+        if (n <= 40) {
+            symeig_low_nm<40, NWS>(A, LD, Z, LD, n, nw, w, sb);
+            return;
+        }
+        if (n <= 48 || NMAX == 48) {
+            symeig_low_nm<48, NWS>(A, LD, Z, LD, n, nw, w, sb);
+            return;
+        }
+    }
+    if constexpr (NMAX >= 64) symeig_low_nm<64, NWS>(A, LD, Z, LD, n, nw, w, sb);
 }
 
 // --------------------------------------------------------------------------
