@@ -642,49 +642,114 @@ __device__ bool orth_small_body(int mb, int nq, double drop, const double* G, do
 
 // --------------------------------------------------------------------------
 // D = A B on one wavefront with FP64 16x16x4 matrix-core products.  Elements
-// are read through fa(i, k) (i < M, k < K) and fb(k, j) (j < N <= 64) at
-// clamped in-range indices (zero outside), so every lane issues the same
-// loads; a 16-row band of D is accumulated over all its column tiles at once
-// (up to four independent product chains) and handed to fd(i, j, value).
-// Lane l of one product supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
-// receives D[l / 16 + 4 q][l % 16] in element q.  Call with the whole wave.
+// are read through fa(i, k) (i < M, k < K) and fb(k, j) (j < N) at clamped
+// in-range indices (zero outside), so every lane issues the same loads, and
+// handed to fd(i, j, value).  Lane l of one product supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] and receives D[l / 16 + 4 q][l % 16] in element q.
+// Call with the whole wave.
+//
+// A dependent FP64 product waits ~190 cycles for its accumulator while the
+// matrix pipe takes a new one every ~64, so the body keeps at least three
+// accumulation chains in flight: every 16 x 16 tile of D at once (TM x TN
+// chains, tile counts fixed at compile time so the accumulators stay in
+// their registers) and, when there are fewer than three tiles, the K range
+// split into interleaved phases summed at the end.
 // --------------------------------------------------------------------------
 typedef double wd4 __attribute__((ext_vector_type(4)));
 
-template <class FA, class FB, class FD>
-__device__ __forceinline__ void wave_gemm(int M, int N, int K, FA&& fa, FB&& fb, FD&& fd) {
+template <int TM, int TN, class FA, class FB, class FD>
+__device__ __forceinline__ void wave_gemm_tiles(int M, int N, int K, FA&& fa, FB&& fb, FD&& fd) {
+    constexpr int T = TM * TN;
+    constexpr int S = T >= 3 ? 1 : (T == 2 ? 2 : 3);
     const int lane = wlane(), lr = lane & 15, lk = lane >> 4;
-    const int tn = (N + 15) >> 4;
-    for (int r0 = 0; r0 < M; r0 += 16) {
-        wd4 acc[4];
+    int arow[TM], bcol[TN];
+    bool aok[TM], bok[TN];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = wd4{0.0, 0.0, 0.0, 0.0};
-        const int ar = r0 + lr;
-        const int arc = ar < M ? ar : M - 1;
-        for (int k0 = 0; k0 < K; k0 += 4) {
-            const int k = k0 + lk;
-            const int kc = k < K ? k : K - 1;
-            const double av = fa(arc, kc);
-            const double a = (ar < M && k < K) ? av : 0.0;
+    for (int t = 0; t < TM; ++t) {
+        const int r = 16 * t + lr;
+        aok[t] = r < M;
+        arow[t] = aok[t] ? r : M - 1;
+    }
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+        const int c = 16 * t + lr;
+        bok[t] = c < N;
+        bcol[t] = bok[t] ? c : N - 1;
+    }
+    wd4 acc[S][TM][TN];
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[p][i][j] = wd4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4 * S) {
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+            const int k = k0 + 4 * p + lk;
+            const bool kok = k < K;
+            const int kc = kok ? k : K - 1;
+            double a[TM], b[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const double v = fa(arow[i], kc);
+                a[i] = (aok[i] && kok) ? v : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const double v = fb(kc, bcol[j]);
+                b[j] = (bok[j] && kok) ? v : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[p][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[p][i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            wd4 d = acc[0][i][j];
+#pragma unroll
+            for (int p = 1; p < S; ++p) d += acc[p][i][j];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (q < tn) {
-                    const int c = q * 16 + lr;
-                    const double bv = fb(kc, c < N ? c : N - 1);
-                    const double b = (k < K && c < N) ? bv : 0.0;
-                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
-                }
+                const int r = 16 * i + lk + 4 * q, c = 16 * j + lr;
+                if (r < M && c < N) fd(r, c, d[q]);
             }
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (q < tn) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = r0 + lk + 4 * i, c = q * 16 + lr;
-                    if (r < M && c < N) fd(r, c, acc[q][i]);
-                }
-            }
+}
+
+// Entry: TMX and TNX bound the tile counts of D (M <= 16 TMX, N <= 16 TNX).
+// A product with TMX = TNX runs on a square tile grid of side
+// max(ceil(M / 16), ceil(N / 16)), one with TNX = 1 (or TMX = 1) on a
+// column (row) of tiles; only those shapes are compiled.
+template <int TMX, int TNX, class FA, class FB, class FD>
+__device__ __forceinline__ void wave_gemm(int M, int N, int K, FA&& fa, FB&& fb, FD&& fd) {
+    static_assert(TMX >= 1 && TNX >= 1 && TMX <= 4 && TNX <= 4 && (TMX == TNX || TMX == 1 || TNX == 1),
+                  "square, column or row tile grids");
+    if (M > 0 && N > 0) {
+        const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+        if constexpr (TMX == 1 && TNX == 1) {
+            wave_gemm_tiles<1, 1>(M, N, K, fa, fb, fd);
+        } else if constexpr (TNX == 1) {
+            if (tm <= 1) wave_gemm_tiles<1, 1>(M, N, K, fa, fb, fd);
+            else if (TMX == 2 || tm == 2) wave_gemm_tiles<(TMX < 2 ? TMX : 2), 1>(M, N, K, fa, fb, fd);
+            else if (TMX == 3 || tm == 3) wave_gemm_tiles<(TMX < 3 ? TMX : 3), 1>(M, N, K, fa, fb, fd);
+            else wave_gemm_tiles<TMX, 1>(M, N, K, fa, fb, fd);
+        } else if constexpr (TMX == 1) {
+            if (tn <= 1) wave_gemm_tiles<1, 1>(M, N, K, fa, fb, fd);
+            else if (TNX == 2 || tn == 2) wave_gemm_tiles<1, (TNX < 2 ? TNX : 2)>(M, N, K, fa, fb, fd);
+            else if (TNX == 3 || tn == 3) wave_gemm_tiles<1, (TNX < 3 ? TNX : 3)>(M, N, K, fa, fb, fd);
+            else wave_gemm_tiles<1, TNX>(M, N, K, fa, fb, fd);
+        } else {
+            const int t = tm > tn ? tm : tn;
+            if (t <= 1) wave_gemm_tiles<1, 1>(M, N, K, fa, fb, fd);
+            else if (TMX == 2 || t == 2) wave_gemm_tiles<2, 2>(M, N, K, fa, fb, fd);
+            else if (TMX == 3 || t == 3) wave_gemm_tiles<(TMX < 3 ? TMX : 3), (TMX < 3 ? TMX : 3)>(M, N, K, fa, fb, fd);
+            else wave_gemm_tiles<TMX, TMX>(M, N, K, fa, fb, fd);
         }
     }
     wsync();
@@ -773,7 +838,7 @@ __device__ bool orth_small_body(int mb, int nq, double drop, const double* G, do
         Bw[r + 2 * MAXB * j] = G[j * nrow + r];
     });
     // M = Y^T Y - B^T B with B = Q^T Y (B[l][c] = G[c nrow + l]); B^T B kept
-    wave_gemm(mb, mb, nq, [&](int r, int l) { return G[r * nrow + l]; }, [&](int l, int c) { return G[c * nrow + l]; },
+    wave_gemm<1, 1>(mb, mb, nq, [&](int r, int l) { return G[r * nrow + l]; }, [&](int l, int c) { return G[c * nrow + l]; },
               [&](int r, int c, double v) {
                   Mq[r * MBL + c] = v;
                   A[r * LD + c] = G[c * nrow + nq + r] - v;
@@ -804,7 +869,7 @@ __device__ bool orth_small_body(int mb, int nq, double drop, const double* G, do
         if (tid < mb) A[tid * LD + tid] = dsc[tid] > 0.0 ? A[tid * LD + tid] - 1.0 : 0.0;  // E in place
         nkeep = wave_compact(mb, [&](int i) { return dsc[i] > 0.0; }, keep);
         if (tid < nkeep) th[tid] = 1.0;
-        wave_gemm(mb, mb, mb, [&](int i, int l) { return A[i * LD + l]; }, [&](int l, int j) { return A[l * LD + j]; },
+        wave_gemm<1, 1>(mb, mb, mb, [&](int i, int l) { return A[i * LD + l]; }, [&](int l, int j) { return A[l * LD + j]; },
                   [&](int i, int j, double v) {
                       Z[i * LD + j] = (i == j ? 1.0 : 0.0) - 0.5 * A[i * LD + j] + 0.375 * v;
                   });
@@ -852,6 +917,8 @@ template <int LD>
 __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl* out) {
     static_assert(LD - 1 <= WL, "one lane per basis column");
     constexpr int MBL = LD / 3;
+    static_assert(MBL <= 16, "block width within one tile");
+    constexpr int TX = (LD - 1 + 15) / 16;  // tiles along the basis
     __shared__ double A[LD * LD];
     __shared__ double Z[LD * LD];
     __shared__ double Tm[LD * LD];
@@ -896,7 +963,7 @@ __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const doubl
         // E in place of D G_B D (zero on the dropped columns)
         if (tid < ns) A[tid * LD + tid] = dsc[tid] > 0.0 ? A[tid * LD + tid] - 1.0 : 0.0;
         r = wave_compact(ns, [&](int i) { return dsc[i] > 0.0; }, keep);
-        wave_gemm(ns, ns, ns, [&](int i, int l) { return A[i * LD + l]; }, [&](int l, int j) { return A[l * LD + j]; },
+        wave_gemm<TX, TX>(ns, ns, ns, [&](int i, int l) { return A[i * LD + l]; }, [&](int l, int j) { return A[l * LD + j]; },
                   [&](int i, int j, double v) { Z[i * LD + j] = v; });  // Z <- E^2
         for2(ns, r, [&](int row, int c) {  // T (ns x r)
             const int k = keep[c];
@@ -915,9 +982,9 @@ __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const doubl
         });
         wsync();
     }
-    wave_gemm(ns, r, ns, GA, [&](int l, int c) { return Tm[l * LD + c]; },
+    wave_gemm<TX, TX>(ns, r, ns, GA, [&](int l, int c) { return Tm[l * LD + c]; },
               [&](int i, int c, double v) { Z[i * LD + c] = v; });  // Z <- G_A T
-    wave_gemm(r, r, ns, [&](int i, int l) { return Tm[l * LD + i]; }, [&](int l, int c) { return Z[l * LD + c]; },
+    wave_gemm<TX, TX>(r, r, ns, [&](int i, int l) { return Tm[l * LD + i]; }, [&](int l, int c) { return Z[l * LD + c]; },
               [&](int i, int c, double v) { A[i * LD + c] = v; });  // A <- T^T Z
     for2(r, r, [&](int row, int c) {
         if (row < c) {
@@ -931,7 +998,7 @@ __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const doubl
     const int mcol = r < mb ? r : mb;
     symeig_low<LD, MBL>(A, Z, r, mcol, ev);
     // C = T Y[:, 0..mb) -> A region (ld MBL) and out->C (zero beyond the rank)
-    wave_gemm(ns, mcol, r, [&](int row, int l) { return Tm[row * LD + l]; }, [&](int l, int j) { return Z[l * LD + j]; },
+    wave_gemm<TX, 1>(ns, mcol, r, [&](int row, int l) { return Tm[row * LD + l]; }, [&](int l, int j) { return Z[l * LD + j]; },
               [&](int row, int j, double v) {
                   A[row * MBL + j] = v;
                   out->C[row + ns * j] = v;
@@ -950,16 +1017,16 @@ __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const doubl
     wsync();
     auto Cw = [&](int l, int j) { return Tm[l * MBL + j]; };
     for (int pass = 0; pass < 2; ++pass) {
-        wave_gemm(ns, mb, ns, GB, Cw, [&](int row, int j, double v) { Z[row * MBL + j] = v; });  // Z <- G_B Cwp
-        wave_gemm(mb, mb, ns, [&](int p, int l) { return A[l * MBL + p]; }, [&](int l, int j) { return Z[l * MBL + j]; },
+        wave_gemm<TX, 1>(ns, mb, ns, GB, Cw, [&](int row, int j, double v) { Z[row * MBL + j] = v; });  // Z <- G_B Cwp
+        wave_gemm<1, 1>(mb, mb, ns, [&](int p, int l) { return A[l * MBL + p]; }, [&](int l, int j) { return Z[l * MBL + j]; },
                   [&](int p, int j, double v) { h1[p + MBL * j] = v; });  // h1 <- C^T G_B Cwp
-        wave_gemm(ns, mb, mb, [&](int row, int p) { return A[row * MBL + p]; },
+        wave_gemm<TX, 1>(ns, mb, mb, [&](int row, int p) { return A[row * MBL + p]; },
                   [&](int p, int j) { return h1[p + MBL * j]; },
                   [&](int row, int j, double v) { Tm[row * MBL + j] -= v; });  // Cwp <- Cwp - C h1
     }
     // Mp = Cwp^T G_B Cwp
-    wave_gemm(ns, mb, ns, GB, Cw, [&](int row, int j, double v) { A[row * MBL + j] = v; });
-    wave_gemm(mb, mb, ns, [&](int p, int l) { return Tm[l * MBL + p]; }, [&](int l, int j) { return A[l * MBL + j]; },
+    wave_gemm<TX, 1>(ns, mb, ns, GB, Cw, [&](int row, int j, double v) { A[row * MBL + j] = v; });
+    wave_gemm<1, 1>(mb, mb, ns, [&](int p, int l) { return Tm[l * MBL + p]; }, [&](int l, int j) { return A[l * MBL + j]; },
               [&](int p, int j, double v) { h1[p + MBL * j] = v; });
     if (tid < mb) {
         const double d = h1[tid + MBL * tid];
@@ -990,7 +1057,7 @@ __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const doubl
         wsync();
     }
     // Cp = Cwp D Zp_keep theta^-1/2 (zero beyond the kept rank)
-    wave_gemm(ns, rp, mb, [&](int row, int l) { return Tm[row * MBL + l] * dsc[l]; },
+    wave_gemm<TX, 1>(ns, rp, mb, [&](int row, int l) { return Tm[row * MBL + l] * dsc[l]; },
               [&](int l, int j) { return A[l * LD + keep[j]]; },
               [&](int row, int j, double v) { out->Cp[row + ns * j] = v * th[j]; });
     for2(mb - rp, ns, [&](int j, int row) { out->Cp[row + ns * (rp + j)] = 0.0; });
