@@ -259,7 +259,9 @@ __device__ __forceinline__ double wmax_dpp(double v) {
 // 1, p_0, ..., p_(n-1) with p_i = (dh_i - x) p_(i-1) - e2s_i p_(i-2)
 // (e2s_i: squared off-diagonal between i - 1 and i, e2s_0 = 0); an exact zero
 // takes the sign opposite to its predecessor (a tiny negative pivot).  The
-// coefficients come from LDS sixteen at a time.
+// coefficients come from LDS sixteen at a time.  Entries n .. NM-1 are
+// padding (dh = 4, e2s = 0: p_i = (4 - x) p_(i-1) keeps the sign for
+// |x| <= 1), so the steps of a chunk need no per-step test of i < n.
 template <int NM>
 __device__ __forceinline__ int sturm_below(const double* dh, const double* e2s, int n, double x) {
     double pp = 0.0, p = 1.0;
@@ -270,15 +272,16 @@ __device__ __forceinline__ int sturm_below(const double* dh, const double* e2s, 
             // the first 32 coefficients may stay in registers across calls;
             // later chunks are reloaded (bounds the register footprint)
             if (c0 >= 32) asm volatile("" ::: "memory");
-            double dc[16], ec[16];
+            constexpr int QN = 16;
+            double dc[QN], ec[QN];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                dc[q] = dh[c0 + q];
-                ec[q] = e2s[c0 + q];
+            for (int q = 0; q < QN; ++q) {
+                dc[q] = c0 + q < NM ? dh[c0 + q] : 4.0;
+                ec[q] = c0 + q < NM ? e2s[c0 + q] : 0.0;
             }
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                if (c0 + q < n) {
+            for (int q = 0; q < QN; ++q) {
+                if (c0 + q < NM) {
                     double pn = fma(dc[q] - x, p, -(ec[q] * pp));
                     pn = pn == 0.0 ? -p * 0x1p-52 : pn;
                     cnt += (pn < 0.0) != (p < 0.0);
@@ -294,6 +297,60 @@ __device__ __forceinline__ int sturm_below(const double* dh, const double* e2s, 
         }
     }
     return cnt;
+}
+
+// z = H_0 H_1 ... H_(n-3) y for the nw vectors in the columns of Z (leading
+// dimension ldz), L lanes per vector (L * nw <= 64): lane t of the group of
+// vector j holds rows t, t + L, ... in registers, and each reflection's dot
+// product is summed over the group by DPP moves (quads, then half-rows).  The
+// reflector rows V + k NM are zero outside k + 1 .. n - 1.
+template <int NM, int L>
+__device__ __forceinline__ void back_reflect_split(const double* V, double* Z, int ldz, int n, int nw) {
+    static_assert(L == 4 || L == 8, "quad or half-row groups");
+    constexpr int R = (NM + L - 1) / L;
+    const int lane = wlane(), j = lane / L, t = lane - j * L;
+    const bool act = j < nw;
+    double y[R], vn[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int r = t + L * i;
+        y[i] = (act && r < n) ? Z[r * ldz + j] : 0.0;
+    }
+    if (n >= 3) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = t + L * i;
+            vn[i] = r < NM ? V[(n - 3) * NM + r] : 0.0;
+        }
+    }
+    for (int k = n - 3; k >= 0; --k) {
+        double vc[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) vc[i] = vn[i];
+        if (k > 0) {  // the next reflector's rows load while this one is applied
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = t + L * i;
+                vn[i] = r < NM ? V[(k - 1) * NM + r] : 0.0;
+            }
+        }
+        double d = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) d = fma(y[i], vc[i], d);
+        d += dpp_f64<0xB1>(d);  // quad_perm [1, 0, 3, 2]
+        d += dpp_f64<0x4E>(d);  // quad_perm [2, 3, 0, 1]
+        if constexpr (L == 8) d += dpp_f64<0x141>(d);  // row_half_mirror: the other quad
+        d *= 2.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) y[i] = fma(-d, vc[i], y[i]);
+    }
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = t + L * i;
+            if (r < n) Z[r * ldz + j] = y[i];
+        }
+    }
 }
 
 template <int NM, int NWS>
@@ -392,7 +449,7 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
     const double s = gb > 0.0 ? ldexp(1.0, ex) : 1.0, is = 1.0 / s;
     wsync();
     if (lane < NM) {
-        dh[lane] = lane < n ? dr * is : 0.0;
+        dh[lane] = lane < n ? dr * is : 4.0;  // padding for sturm_below
         eh[lane] = er * is;
         e2s[lane] = (el * is) * (el * is);
     }
@@ -543,6 +600,22 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
     }
     if (lane > 0 && lane < nw && !brk) normalize();
     // ---- 4. back-transformation: z = H_0 H_1 ... H_(n-3) y ----
+    if (nw <= 16) {
+        // up to 16 vectors: through LDS to L lanes per vector
+        if (lane < nw) {
+#pragma unroll
+            for (int c = 0; c < NM; ++c)
+                if (c < n) Z[c * ldz + lane] = y[c];
+        }
+        wsync();
+        if (nw <= 8)
+            back_reflect_split<NM, 8>(V, Z, ldz, n, nw);
+        else
+            back_reflect_split<NM, 4>(V, Z, ldz, n, nw);
+        if (lane < nw) w[lane] = lamh[lane] * s;
+        wsync();
+        return;
+    }
     for (int k = n - 3; k >= 0; --k) {
         const double* vk = V + k * NM;
         double q4[4] = {0.0, 0.0, 0.0, 0.0};
