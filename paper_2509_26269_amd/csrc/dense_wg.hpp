@@ -216,8 +216,13 @@ __device__ void symeig_wg(double* A, double* Z, int n) {
 // ldz) hold the j-th smallest eigenpair, j < min(nw, n), ascending.  A
 // non-finite entry of A gives NaN eigenpairs.  sb: LDS scratch of
 // symeig_low_doubles(NM, NWS) doubles; eigenvectors are solved NWS at a time.
+// With NWV > 1 all NWV waves of the workgroup (threads 0 .. 64 NWV - 1) call
+// it: the multisection then counts at 64 NWV points per round (fewer rounds),
+// everything else runs on wave 0, and the waves meet at two workgroup
+// barriers; on return only wave 0 has finished the eigenvectors (the others
+// return after the multisection).
 // --------------------------------------------------------------------------
-constexpr int symeig_low_doubles(int nm, int nws) { return 3 * nm * nws + 5 * nm + WL; }
+constexpr int symeig_low_doubles(int nm, int nws) { return 3 * nm * nws + 5 * nm + WL + 2; }
 
 // 1/x to FP64 accuracy: the hardware estimate refined by two Newton steps
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -353,9 +358,51 @@ __device__ __forceinline__ void back_reflect_split(const double* V, double* Z, i
     }
 }
 
-template <int NM, int NWS>
+// Multisection for the lowest nw eigenvalues of the scaled tridiagonal (dh,
+// e2s as for sturm_below, spectrum inside (-1, 1)): g lanes per eigenvalue,
+// a group inside one wave, each round cutting the bracket into g + 1 parts
+// by the counts of the group; lamh[j] <- midpoint of the final bracket of the
+// j-th smallest.  With NWV > 1 the NWV waves of the workgroup call it
+// together and share the eigenvalues (more lanes per eigenvalue, fewer
+// rounds).
+template <int NM, int NWV>
+__device__ __forceinline__ void multisect(const double* dh, const double* e2s, int n, int nw, double* lamh) {
+    const int lane = wlane();
+    const int gt = NWV > 1 ? (int)threadIdx.x : lane;
+    int g = 1;
+    while (2 * g * nw <= WL * NWV && g < (NWV > 1 ? 32 : 16)) g *= 2;
+    // (g + 1)^-rounds < 2^-55
+    const int rounds = g == 1 ? 56 : g == 2 ? 36 : g == 4 ? 25 : g == 8 ? 19 : (NWV == 1 || g == 16) ? 15 : 12;
+    const int jg = gt / g, t = gt - jg * g;
+    const int jw = jg < nw ? jg : nw - 1;
+    const double ig1 = 1.0 / (double)(g + 1);
+    const unsigned long long gm = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << (NWV > 1 ? lane - t : jg * g);
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < rounds; ++it) {
+        const double wd = hi - lo;
+        const int c = sturm_below<NM>(dh, e2s, n, lo + wd * ((double)(t + 1) * ig1));
+        const int ts = __popcll(__ballot(c <= jw) & gm) - 1;  // last point with <= j eigenvalues below
+        const double nlo = ts < 0 ? lo : lo + wd * ((double)(ts + 1) * ig1);
+        const double nhi = ts + 1 >= g ? hi : lo + wd * ((double)(ts + 2) * ig1);
+        lo = nlo;
+        hi = nhi;
+    }
+    if (t == 0 && jg < nw) lamh[jg] = 0.5 * (lo + hi);
+}
+
+// all waves of a workgroup (NWV > 1), else the one calling wave
+template <int NWV>
+__device__ __forceinline__ void waves_sync() {
+    if constexpr (NWV > 1)
+        __syncthreads();
+    else
+        wsync();
+}
+
+template <int NM, int NWS, int NWV = 1>
 __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int ldz, int n, int nw, double* w,
                                               double* sb) {
+    static_assert(NWV == 1 || NWV == 2 || NWV == 4, "one, two or four waves");
     const int lane = wlane();
     double* U0 = sb;  // per eigenvector slot: inverse pivots, then the two superdiagonals of U
     double* U1 = U0 + NM * NWS;
@@ -366,6 +413,16 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
     double* bc = e2s + NM;
     double* hw = bc + NM;
     double* lamh = hw + NM;
+    if constexpr (NWV > 1) {
+        // waves 1 .. NWV-1: only the multisection (after wave 0's reduction)
+        if (threadIdx.x >= WL) {
+            __syncthreads();
+            if (lamh[WL] != 0.0) return;  // non-finite input
+            multisect<NM, NWV>(dh, e2s, n, nw < n ? nw : n, lamh);
+            __syncthreads();
+            return;
+        }
+    }
     // ---- 1. tridiagonalisation, lane r holding row r ----
     double a[NM];
     bool fin = true;
@@ -381,6 +438,10 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
             for (int r = 0; r < n; ++r) Z[r * ldz + lane] = NAN;
         }
         wsync();
+        if constexpr (NWV > 1) {
+            if (lane == 0) lamh[WL] = 1.0;
+            __syncthreads();
+        }
         return;
     }
     wsync();  // A's storage takes the reflectors from here on: row k at V + k NM
@@ -454,27 +515,14 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
         e2s[lane] = (el * is) * (el * is);
     }
     wsync();
-    // ---- 2. multisection: g lanes per eigenvalue, g + 1 sub-intervals per round ----
-    if (nw > n) nw = n;
-    int g = 1;
-    while (2 * g * nw <= WL && g < 16) g *= 2;
-    const int rounds = g == 1 ? 56 : g == 2 ? 36 : g == 4 ? 25 : g == 8 ? 19 : 15;  // (g+1)^-rounds < 2^-55
-    const int jg = lane / g, t = lane - jg * g;
-    const int jw = jg < nw ? jg : nw - 1;
-    const double ig1 = 1.0 / (double)(g + 1);
-    const unsigned long long gm = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << (jg * g);
-    double lo = -1.0, hi = 1.0;
-    for (int it = 0; it < rounds; ++it) {
-        const double wd = hi - lo;
-        const int c = sturm_below<NM>(dh, e2s, n, lo + wd * ((double)(t + 1) * ig1));
-        const int ts = __popcll(__ballot(c <= jw) & gm) - 1;  // last point with <= j eigenvalues below
-        const double nlo = ts < 0 ? lo : lo + wd * ((double)(ts + 1) * ig1);
-        const double nhi = ts + 1 >= g ? hi : lo + wd * ((double)(ts + 2) * ig1);
-        lo = nlo;
-        hi = nhi;
+    if constexpr (NWV > 1) {
+        if (lane == 0) lamh[WL] = 0.0;
+        __syncthreads();
     }
-    if (t == 0 && jg < nw) lamh[jg] = 0.5 * (lo + hi);
-    wsync();
+    // ---- 2. multisection ----
+    if (nw > n) nw = n;
+    multisect<NM, NWV>(dh, e2s, n, nw, lamh);
+    waves_sync<NWV>();
     // ---- 3. inverse iteration, NWS eigenvalues at a time; vector j in column j of Z ----
     constexpr double pmin = 0x1p-52;
     for (int j0 = 0; j0 < nw; j0 += NWS) {
@@ -649,36 +697,36 @@ __device__ __forceinline__ void symeig_low_nm(double* A, int lda, double* Z, int
 // LD allows; callers whose n is known to be small pass a smaller NMAX and get
 // fewer buckets).  The LDS scratch is shared by the buckets.  Same contract as
 // symeig_low_nm with lda = ldz = LD.
-template <int LD, int NWS, int NMAX = ((LD - 1 + 15) / 16) * 16>
+template <int LD, int NWS, int NMAX = ((LD - 1 + 15) / 16) * 16, int NWV = 1>
 __device__ __forceinline__ void symeig_low(double* A, double* Z, int n, int nw, double* w) {
     static_assert(NMAX % 16 == 0 && NMAX <= WL, "one lane per row, buckets of 16 at the top");
     __shared__ double sb[symeig_low_doubles(NMAX, NWS)];
     if (n <= 0 || nw <= 0) return;
     if (n <= 16 || NMAX == 16) {
-        symeig_low_nm<16, NWS>(A, LD, Z, LD, n, nw, w, sb);
+        symeig_low_nm<16, NWS, NWV>(A, LD, Z, LD, n, nw, w, sb);
         return;
     }
     if constexpr (NMAX >= 32) {
         if (n <= 24) {
-            symeig_low_nm<24, NWS>(A, LD, Z, LD, n, nw, w, sb);
+            symeig_low_nm<24, NWS, NWV>(A, LD, Z, LD, n, nw, w, sb);
             return;
         }
         if (n <= 32 || NMAX == 32) {
-            symeig_low_nm<32, NWS>(A, LD, Z, LD, n, nw, w, sb);
+            symeig_low_nm<32, NWS, NWV>(A, LD, Z, LD, n, nw, w, sb);
             return;
         }
     }
     if constexpr (NMAX >= 48) {
         if (n <= 40) {
-            symeig_low_nm<40, NWS>(A, LD, Z, LD, n, nw, w, sb);
+            symeig_low_nm<40, NWS, NWV>(A, LD, Z, LD, n, nw, w, sb);
             return;
         }
         if (n <= 48 || NMAX == 48) {
-            symeig_low_nm<48, NWS>(A, LD, Z, LD, n, nw, w, sb);
+            symeig_low_nm<48, NWS, NWV>(A, LD, Z, LD, n, nw, w, sb);
             return;
         }
     }
-    if constexpr (NMAX >= 64) symeig_low_nm<64, NWS>(A, LD, Z, LD, n, nw, w, sb);
+    if constexpr (NMAX >= 64) symeig_low_nm<64, NWS, NWV>(A, LD, Z, LD, n, nw, w, sb);
 }
 
 // --------------------------------------------------------------------------
@@ -986,7 +1034,7 @@ __device__ bool orth_small_body(int mb, int nq, double drop, const double* G, do
 // Writes C, Cp, lam, rank of the control block `out`.  The matrix products
 // run on the matrix cores (wave_gemm), the eigenproblems in symeig_low.
 // --------------------------------------------------------------------------
-template <int LD>
+template <int LD, int NWV = 1>
 __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const double* Gtri, EigCtrl* out) {
     static_assert(LD - 1 <= WL, "one lane per basis column");
     constexpr int MBL = LD / 3;
@@ -999,77 +1047,92 @@ __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const doubl
     __shared__ double h1[MBL * MBL];
     __shared__ int keep[LD];
     __shared__ double GAf[LD * LD], GBf[LD * LD];
+    __shared__ int shr[2];
     const int tid = wlane();
-    const int Eh = ns * (ns + 1) / 2;
-    // both Grams as full symmetric matrices in LDS: the dense steps below
-    // read them many times, and a global read costs far more than an LDS one
-    for2(ns, ns, [&](int i, int j) {
-        const int r = i < j ? i : j, c = i < j ? j : i;
-        const int e = r * ns - r * (r - 1) / 2 + (c - r);
-        GAf[i * LD + j] = Gtri[e];
-        GBf[i * LD + j] = Gtri[Eh + e];
-    });
-    wsync();
+    const int wave = NWV > 1 ? (int)(threadIdx.x / WL) : 0;
     auto GA = [&](int i, int j) { return GAf[i * LD + j]; };
     auto GB = [&](int i, int j) { return GBf[i * LD + j]; };
-    const double gbmax = wmax_dpp(tid < ns ? GB(tid, tid) : 0.0);
-    if (tid < ns) {
-        const double gii = GB(tid, tid);
-        dsc[tid] = gii > 1e-24 * gbmax ? 1.0 / sqrt(gii) : 0.0;
-    }
-    wsync();
-    double emax = 0.0;
-    for2(ns, ns, [&](int r, int c) {
-        const double v = dsc[r] * GB(r, c) * dsc[c];
-        A[r * LD + c] = v;
-        if (r != c) emax = fmax(emax, fabs(v));
-    });
-    wsync();
-    // The basis is orthonormal by construction, so D G_B D = I + E with E
-    // at the level of FP32 rounding: then T = D (I + E)^(-1/2) = D (I - E/2 +
-    // 3/8 E^2) to FP64 accuracy, with the zero columns (dropped earlier) left
-    // out.  Otherwise the general path: an eigen-decomposition with rank
-    // dropping.
-    const bool near_id = wmax_dpp(emax) < 1e-5;
-    int r;
-    if (near_id) {
-        // E in place of D G_B D (zero on the dropped columns)
-        if (tid < ns) A[tid * LD + tid] = dsc[tid] > 0.0 ? A[tid * LD + tid] - 1.0 : 0.0;
-        r = wave_compact(ns, [&](int i) { return dsc[i] > 0.0; }, keep);
-        wave_gemm<TX, TX>(ns, ns, ns, [&](int i, int l) { return A[i * LD + l]; }, [&](int l, int j) { return A[l * LD + j]; },
-                  [&](int i, int j, double v) { Z[i * LD + j] = v; });  // Z <- E^2
-        for2(ns, r, [&](int row, int c) {  // T (ns x r)
-            const int k = keep[c];
-            const double t0 = (row == k ? 1.0 : 0.0) - 0.5 * A[row * LD + k] + 0.375 * Z[row * LD + k];
-            Tm[row * LD + c] = dsc[row] * t0;
+    int r = 0, mcol = 0;
+    if (wave == 0) {
+        const int Eh = ns * (ns + 1) / 2;
+        // both Grams as full symmetric matrices in LDS: the dense steps below
+        // read them many times, and a global read costs far more than an LDS one
+        for2(ns, ns, [&](int i, int j) {
+            const int lo = i < j ? i : j, hi = i < j ? j : i;
+            const int e = lo * ns - lo * (lo - 1) / 2 + (hi - lo);
+            GAf[i * LD + j] = Gtri[e];
+            GBf[i * LD + j] = Gtri[Eh + e];
         });
         wsync();
-    } else {
-        symeig_wg<LD>(A, Z, ns);
-        const double tmax = wmax_dpp(tid < ns ? A[tid * LD + tid] : -INFINITY);
-        r = wave_compact(ns, [&](int i) { return A[i * LD + i] > drop * tmax; }, keep);
-        if (tid < r) th[tid] = A[keep[tid] * LD + keep[tid]];
-        wsync();
-        for2(ns, r, [&](int row, int c) {  // T (ns x r)
-            Tm[row * LD + c] = dsc[row] * Z[row * LD + keep[c]] / sqrt(th[c]);
-        });
-        wsync();
-    }
-    wave_gemm<TX, TX>(ns, r, ns, GA, [&](int l, int c) { return Tm[l * LD + c]; },
-              [&](int i, int c, double v) { Z[i * LD + c] = v; });  // Z <- G_A T
-    wave_gemm<TX, TX>(r, r, ns, [&](int i, int l) { return Tm[l * LD + i]; }, [&](int l, int c) { return Z[l * LD + c]; },
-              [&](int i, int c, double v) { A[i * LD + c] = v; });  // A <- T^T Z
-    for2(r, r, [&](int row, int c) {
-        if (row < c) {
-            const double v = 0.5 * (A[row * LD + c] + A[c * LD + row]);
-            A[row * LD + c] = v;
-            A[c * LD + row] = v;
+        const double gbmax = wmax_dpp(tid < ns ? GB(tid, tid) : 0.0);
+        if (tid < ns) {
+            const double gii = GB(tid, tid);
+            dsc[tid] = gii > 1e-24 * gbmax ? 1.0 / sqrt(gii) : 0.0;
         }
-    });
-    wsync();
-    // the mb lowest eigenpairs, ascending (column j of Z)
-    const int mcol = r < mb ? r : mb;
-    symeig_low<LD, MBL>(A, Z, r, mcol, ev);
+        wsync();
+        double emax = 0.0;
+        for2(ns, ns, [&](int r, int c) {
+            const double v = dsc[r] * GB(r, c) * dsc[c];
+            A[r * LD + c] = v;
+            if (r != c) emax = fmax(emax, fabs(v));
+        });
+        wsync();
+        // The basis is orthonormal by construction, so D G_B D = I + E with E
+        // at the level of FP32 rounding: then T = D (I + E)^(-1/2) = D (I - E/2 +
+        // 3/8 E^2) to FP64 accuracy, with the zero columns (dropped earlier) left
+        // out.  Otherwise the general path: an eigen-decomposition with rank
+        // dropping.
+        const bool near_id = wmax_dpp(emax) < 1e-5;
+        if (near_id) {
+            // E in place of D G_B D (zero on the dropped columns)
+            if (tid < ns) A[tid * LD + tid] = dsc[tid] > 0.0 ? A[tid * LD + tid] - 1.0 : 0.0;
+            r = wave_compact(ns, [&](int i) { return dsc[i] > 0.0; }, keep);
+            wave_gemm<TX, TX>(ns, ns, ns, [&](int i, int l) { return A[i * LD + l]; }, [&](int l, int j) { return A[l * LD + j]; },
+                      [&](int i, int j, double v) { Z[i * LD + j] = v; });  // Z <- E^2
+            for2(ns, r, [&](int row, int c) {  // T (ns x r)
+                const int k = keep[c];
+                const double t0 = (row == k ? 1.0 : 0.0) - 0.5 * A[row * LD + k] + 0.375 * Z[row * LD + k];
+                Tm[row * LD + c] = dsc[row] * t0;
+            });
+            wsync();
+        } else {
+            symeig_wg<LD>(A, Z, ns);
+            const double tmax = wmax_dpp(tid < ns ? A[tid * LD + tid] : -INFINITY);
+            r = wave_compact(ns, [&](int i) { return A[i * LD + i] > drop * tmax; }, keep);
+            if (tid < r) th[tid] = A[keep[tid] * LD + keep[tid]];
+            wsync();
+            for2(ns, r, [&](int row, int c) {  // T (ns x r)
+                Tm[row * LD + c] = dsc[row] * Z[row * LD + keep[c]] / sqrt(th[c]);
+            });
+            wsync();
+        }
+        wave_gemm<TX, TX>(ns, r, ns, GA, [&](int l, int c) { return Tm[l * LD + c]; },
+                  [&](int i, int c, double v) { Z[i * LD + c] = v; });  // Z <- G_A T
+        wave_gemm<TX, TX>(r, r, ns, [&](int i, int l) { return Tm[l * LD + i]; }, [&](int l, int c) { return Z[l * LD + c]; },
+                  [&](int i, int c, double v) { A[i * LD + c] = v; });  // A <- T^T Z
+        for2(r, r, [&](int row, int c) {
+            if (row < c) {
+                const double v = 0.5 * (A[row * LD + c] + A[c * LD + row]);
+                A[row * LD + c] = v;
+                A[c * LD + row] = v;
+            }
+        });
+        wsync();
+        mcol = r < mb ? r : mb;
+        if (NWV > 1 && tid == 0) {
+            shr[0] = r;
+            shr[1] = mcol;
+        }
+    }  // wave 0
+    if constexpr (NWV > 1) {
+        __syncthreads();
+        r = shr[0];
+        mcol = shr[1];
+    }
+    // the mb lowest eigenpairs, ascending (column j of Z); with NWV > 1 every
+    // wave takes part in the multisection, the rest is wave 0's
+    symeig_low<LD, MBL, ((LD - 1 + 15) / 16) * 16, NWV>(A, Z, r, mcol, ev);
+    if (wave != 0) return;
     // C = T Y[:, 0..mb) -> A region (ld MBL) and out->C (zero beyond the rank)
     wave_gemm<TX, 1>(ns, mcol, r, [&](int row, int l) { return Tm[row * LD + l]; }, [&](int l, int j) { return Z[l * LD + j]; },
               [&](int row, int j, double v) {

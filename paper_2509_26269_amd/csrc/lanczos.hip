@@ -221,14 +221,16 @@ __global__ __launch_bounds__(NT) void k_lz_scale(int n2, T* __restrict__ Q, int 
 
 // Rayleigh-Ritz on T[0..m) (one wavefront): eigenpairs in ascending order,
 // residual norms |T[m..m+b)[0..m) y_i|, stop test.
-__global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, int max_restarts,
-                                              LzCtrl* __restrict__ ctrl) {
+constexpr int LZ_RR_WAVES = 4;  // waves of the multisection (the rest runs on wave 0)
+__global__ __launch_bounds__(LZ_RR_WAVES * WL) void k_lz_rr(int k, int keep, double tol_abs, int max_restarts,
+                                                            LzCtrl* __restrict__ ctrl) {
     constexpr int LD = LZ_MAXM + 1;
     __shared__ double A[LD * LD], Z[LD * LD];
     __shared__ double ev[LZ_MAXM];
     const int lane = wlane();
+    const bool w0 = threadIdx.x < WL;
     if (ctrl->done) {  // stopped inside the cycle (NaN, no direction left)
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             ctrl->out.status = ctrl->status;
             ctrl->out.iters = ctrl->restarts;
             ctrl->out.n_hvp = ctrl->n_hvp;
@@ -237,11 +239,12 @@ __global__ __launch_bounds__(WL) void k_lz_rr(int k, int keep, double tol_abs, i
     }
     const int m = ctrl->m_eff;
     const int b = ctrl->blk;
-    for2(m, m, [&](int r, int c) { A[r * LD + c] = 0.5 * (ctrl->T[r * LZ_LDT + c] + ctrl->T[c * LZ_LDT + r]); });
-    wsync();
+    if (w0) for2(m, m, [&](int r, int c) { A[r * LD + c] = 0.5 * (ctrl->T[r * LZ_LDT + c] + ctrl->T[c * LZ_LDT + r]); });
+    __syncthreads();
     // the kk lowest Ritz pairs, ascending (column i of Z)
     const int kk = keep < m ? keep : m;
-    symeig_low<LD, 32>(A, Z, m, kk, ev);
+    symeig_low<LD, 32, ((LD - 1 + 15) / 16) * 16, LZ_RR_WAVES>(A, Z, m, kk, ev);
+    if (!w0) return;
     for2(kk, m, [&](int i, int r) { ctrl->Y[i * LZ_MAXM + r] = Z[r * LD + i]; });
     for (int i = lane; i < kk; i += WL) {
         double r2 = 0.0;
@@ -421,7 +424,7 @@ hipError_t launch_lz_rr_restart(bool f64, int n2, int b, void* Q, int k, int kee
                                 int m_max, int nblk, const uint8_t* mask, int N, uint64_t seed, LzCtrl* ctrl,
                                 hipStream_t st) {
     (void)b;
-    hipLaunchKernelGGL(k_lz_rr, dim3(1), dim3(WL), 0, st, k, keep, tol_abs, max_restarts, ctrl);
+    hipLaunchKernelGGL(k_lz_rr, dim3(1), dim3(LZ_RR_WAVES * WL), 0, st, k, keep, tol_abs, max_restarts, ctrl);
     (void)m_max;
     if (f64)
         hipLaunchKernelGGL(k_lz_restart<double>, dim3(nblk), dim3(NT), 0, st, n2, (double*)Q, mask, N, seed, ctrl);

@@ -602,13 +602,15 @@ __global__ __launch_bounds__(NT) void k_gram_mfma(EigArgs a, int ns_fixed, const
     }
 }
 
-// Rayleigh-Ritz step (one wavefront, FP64): see rr_body.
-__global__ __launch_bounds__(WL) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ Gtri,
-                                           EigCtrl* __restrict__ ctrl) {
+// Rayleigh-Ritz step (FP64): see rr_body.  Wave 0 does the dense steps; the
+// RR_WAVES waves together do the multisection of the eigen-solve.
+constexpr int RR_WAVES = 4;
+__global__ __launch_bounds__(RR_WAVES * WL) void k_rr(EigArgs a, int ns_fixed, const double* __restrict__ Gtri,
+                                                      EigCtrl* __restrict__ ctrl) {
     Gtri += blockIdx.y * a.g_ms;
     ctrl += blockIdx.y;
     if (ctrl->done) return;
-    rr_body<MAXS + 1>(a.mb, sol_ns(a, ctrl, ns_fixed), a.drop, Gtri, ctrl);
+    rr_body<MAXS + 1, RR_WAVES>(a.mb, sol_ns(a, ctrl, ns_fixed), a.drop, Gtri, ctrl);
 }
 
 // --------------------------------------------------------------------------
@@ -1081,7 +1083,7 @@ hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const 
 }
 
 hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, hipStream_t st) {
-    hipLaunchKernelGGL(k_rr, dim3(1, a.P), dim3(WL), 0, st, a, ns, G, ctrl);
+    hipLaunchKernelGGL(k_rr, dim3(1, a.P), dim3(RR_WAVES * WL), 0, st, a, ns, G, ctrl);
     return hipGetLastError();
 }
 
