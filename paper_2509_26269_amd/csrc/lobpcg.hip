@@ -994,8 +994,15 @@ int gram_blocks(int n2) {
     return nch < cap ? nch : cap;
 }
 
-int update_blocks(int n2) {
-    const int nb = (n2 + NT - 1) / NT;
+// workgroups of the row-update kernels: one row per thread for the vector
+// kernels; for the matrix-core kernels one 16-row tile per wave (64 rows per
+// workgroup), so that a small lattice still keeps every compute unit busy
+// (each wave would otherwise wait out the load latency of several tiles in
+// turn); at most 1024, with grid-stride loops beyond
+int update_blocks(int n2, bool f64, int mb) {
+    const bool mfma = !f64 && mb >= UPDATE_MFMA_MIN_MB;
+    const int rows = mfma ? (NT / 64) * 16 : NT;
+    const int nb = (n2 + rows - 1) / rows;
     return nb < 1024 ? nb : 1024;
 }
 
@@ -1049,7 +1056,7 @@ hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* 
                            ctrl);
     hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS, a.P), dim3(NT), 0, st, a, part, nblk, 0, target, G, ctrl);
     hipLaunchKernelGGL(k_orth_small, dim3(1, a.P), dim3(WL), 0, st, a, target, G, ctrl);
-    const int nb = update_blocks(a.n2);
+    const int nb = update_blocks(a.n2, f64, a.mb);
     if (mf) {
         hipLaunchKernelGGL(k_orth_apply_mfma, dim3(nb, a.P), dim3(NT), 0, st, a, target, (float*)S, ctrl);
         return hipGetLastError();
