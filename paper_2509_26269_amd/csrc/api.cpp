@@ -23,7 +23,6 @@ struct moto_plan_s {
     double hest;
     int ns;
     int64_t* pinned;  // host read-back buffer (hipHostMalloc)
-    hipEvent_t flag_ev[2];  // read-backs of the done flag between iteration chunks
     // autotuned frame-layout HVP variants, keyed by (dtype, batch, n_vec)
     struct Tune {
         int dt, batch, nvec, variant;
@@ -175,29 +174,6 @@ moto_status readback(moto_plan p, const void* dev, size_t n, void* host, hipStre
     return MOTO_OK;
 }
 
-// Up to max_chunks iteration chunks (launch_chunk() queues one), stopping
-// once the device flag done_dev is set.  One chunk stays in flight ahead of
-// the flag's read-back: the flag copied after chunk c is read while chunk
-// c + 1 runs, so the GPU does not idle through each host round trip; a chunk
-// queued after the solve has finished runs its kernels as early exits.  The
-// two flag copies use the last 8 bytes of the pinned buffer.
-template <class F>
-moto_status run_chunks(moto_plan p, const int* done_dev, int max_chunks, F&& launch_chunk, hipStream_t st) {
-    for (auto& e : p->flag_ev)
-        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    volatile int32_t* hf = (volatile int32_t*)((char*)p->pinned + 4096 - 2 * sizeof(int32_t));
-    for (int c = 0; c < max_chunks; ++c) {
-        HIP_TRY(launch_chunk());
-        HIP_TRY(hipMemcpyAsync((void*)&hf[c & 1], done_dev, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipEventRecord(p->flag_ev[c & 1], st));
-        if (c >= 1) {
-            HIP_TRY(hipEventSynchronize(p->flag_ev[(c - 1) & 1]));
-            if (hf[(c - 1) & 1]) break;
-        }
-    }
-    return MOTO_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -251,7 +227,6 @@ moto_status moto_plan_create(const moto_hamiltonian* h, moto_plan* out) {
     p->hest = 4.0 * (sj + sd) + 4.0 * std::fabs(h->K) +
               std::sqrt(h->B[0] * h->B[0] + h->B[1] * h->B[1] + h->B[2] * h->B[2]);
     p->pinned = nullptr;
-    p->flag_ev[0] = p->flag_ev[1] = nullptr;
     p->n_tune = 0;
     p->next_graph = 0;
     p->cap_stream = nullptr;
@@ -270,8 +245,6 @@ moto_status moto_plan_destroy(moto_plan p) {
     for (auto& ge : p->graphs)
         if (ge.valid) (void)hipGraphExecDestroy(ge.exec);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    for (auto& e : p->flag_ev)
-        if (e) (void)hipEventDestroy(e);
     if (p->pinned) (void)hipHostFree(p->pinned);
     delete p;
     return MOTO_OK;
@@ -605,11 +578,17 @@ static moto_status min_modes_pop_impl(moto_plan p, moto_dtype hvp, int P, const 
         p->graph_replays += 1;
         return hipGraphLaunch(gexec, st);
     };
-    if (async) {
-        for (int chunk = 0; chunk < max_chunks; ++chunk) HIP_TRY(one_chunk());
-    } else {
-        moto_status rs = run_chunks(p, done_dev, max_chunks, one_chunk, st);
-        if (rs != MOTO_OK) return rs;
+    // with host synchronisation the done flag is read before each chunk (a
+    // read-back queued behind a running chunk, to overlap the round trip,
+    // measured slower: the chunk's kernels then start with gaps)
+    for (int chunk = 0; chunk < max_chunks; ++chunk) {
+        if (!async) {
+            int hdr[1];
+            moto_status rs = readback(p, done_dev, sizeof(hdr), hdr, st);
+            if (rs != MOTO_OK) return rs;
+            if (hdr[0]) break;
+        }
+        HIP_TRY(one_chunk());
     }
     HIP_TRY(launch_eig_output(f64, a, S, m, N, V, part, ctrl, evals, resid, ws + L.Xsave, st));
     if (async) {
