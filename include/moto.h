@@ -240,7 +240,7 @@ moto_status moto_param_grad_apply(moto_plan p, moto_dtype dt, int32_t batch, con
 typedef struct {
     double tol;          /* relative residual tolerance (default 1e-5 F32, 1e-10 F64) */
     int32_t max_iter;    /* default 200 */
-    int32_t guard;       /* extra block vectors; <0 = max(2, k) for k <= 4, else max(4, ceil(k/2)), at most 16 - k */
+    int32_t guard;       /* extra block vectors; <0 = 2 for k <= 2, 2k for k = 3, 4, else max(4, ceil(k/2)), at most 16 - k */
     int32_t warm;        /* 0 random start, 1 V holds k start vectors, 2 reuse block */
     int32_t check_every; /* iterations between host convergence checks (default 8) */
     uint64_t seed;       /* start-block seed (SplitMix64 counter generator) */
