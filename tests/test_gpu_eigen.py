@@ -79,6 +79,36 @@ def test_min_modes_three_shell_64_random_texture(hvp):
     _check_pairs(_np(r.evals), _np(r.V), w[:4], ro.V[:4], h.h_est(), hvp == "f32", gaps)
 
 
+@pytest.fixture(scope="module")
+def three_shell_16_reference():
+    p = S.ham_3shell(16)
+    h = O.Ham(**p.asdict())
+    m = S.three_shell_start(16, seed=3, kind="skyrmion")
+    return p, h, m, O.min_modes(h, m, 6, tol=1e-11, max_iter=600)
+
+
+@pytest.mark.parametrize("hvp", ["f64", "f32"])
+@pytest.mark.parametrize("guard", [2, 4, 6, 8, 12])
+def test_min_modes_every_basis_size_matches_oracle(three_shell_16_reference, hvp, guard):
+    """k = 4 with guards 2 .. 12: Rayleigh-Ritz bases of 18, 24, 30, 36 and 48
+    columns, so the lowest-eigenpair solver runs in each of its register
+    buckets (24, 32, 40, 48 rows), its multisection with 8 .. 16 wanted pairs
+    on four waves, and the matrix-core products on square tile grids of side
+    2 and 3 and column grids of 2 and 3 tiles; block widths 6 .. 16 (the FP32
+    row kernels on the matrix cores from width 5)."""
+    M = _M()
+    p, h, m, ro = three_shell_16_reference
+    plan = M.Plan.from_params(p)
+    dt = M.MOTO_F64 if hvp == "f64" else M.MOTO_F32
+    tol = 1e-10 if hvp == "f64" else 1e-5
+    r = M.moto_min_modes(plan, _dev(m), 4, dt, opts=M.eig_opts(dt, tol=tol, max_iter=400, guard=guard))
+    assert r.status == M.CONVERGED, (r.status, r.iters, _np(r.resid))
+    w = ro.evals
+    gaps = [min(abs(w[j] - w[i]) for i in range(len(w)) if i != j) >= 1e-3 * h.h_est() for j in range(4)]
+    _check_pairs(_np(r.evals), _np(r.V), w[:4], ro.V[:4], h.h_est(), hvp == "f32", gaps)
+    assert np.all(_np(r.resid) <= tol * h.h_est())
+
+
 @pytest.mark.parametrize("hvp", ["f64", "f32"])
 def test_min_modes_fm_closed_form_128(hvp):
     """Full-size 128x128 three-shell lattice, uniform state: the k = 4 lowest
