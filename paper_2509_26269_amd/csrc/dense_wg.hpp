@@ -1053,17 +1053,25 @@ __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const doubl
     auto GA = [&](int i, int j) { return GAf[i * LD + j]; };
     auto GB = [&](int i, int j) { return GBf[i * LD + j]; };
     int r = 0, mcol = 0;
-    if (wave == 0) {
+    {
+        // both Grams as full symmetric matrices in LDS (every wave takes a
+        // share): the dense steps below read them many times, and a global
+        // read costs far more than an LDS one
         const int Eh = ns * (ns + 1) / 2;
-        // both Grams as full symmetric matrices in LDS: the dense steps below
-        // read them many times, and a global read costs far more than an LDS one
-        for2(ns, ns, [&](int i, int j) {
+        auto put = [&](int i, int j) {
             const int lo = i < j ? i : j, hi = i < j ? j : i;
             const int e = lo * ns - lo * (lo - 1) / 2 + (hi - lo);
             GAf[i * LD + j] = Gtri[e];
             GBf[i * LD + j] = Gtri[Eh + e];
-        });
-        wsync();
+        };
+        if constexpr (NWV > 1) {
+            for (int q = (int)threadIdx.x; q < ns * ns; q += NWV * WL) put(q / ns, q % ns);
+        } else {
+            for2(ns, ns, put);
+        }
+        waves_sync<NWV>();
+    }
+    if (wave == 0) {
         const double gbmax = wmax_dpp(tid < ns ? GB(tid, tid) : 0.0);
         if (tid < ns) {
             const double gii = GB(tid, tid);
@@ -1108,16 +1116,32 @@ __device__ __forceinline__ void rr_body(int mb, int ns, double drop, const doubl
         }
         wave_gemm<TX, TX>(ns, r, ns, GA, [&](int l, int c) { return Tm[l * LD + c]; },
                   [&](int i, int c, double v) { Z[i * LD + c] = v; });  // Z <- G_A T
-        wave_gemm<TX, TX>(r, r, ns, [&](int i, int l) { return Tm[l * LD + i]; }, [&](int l, int c) { return Z[l * LD + c]; },
-                  [&](int i, int c, double v) { A[i * LD + c] = v; });  // A <- T^T Z
-        for2(r, r, [&](int row, int c) {
-            if (row < c) {
-                const double v = 0.5 * (A[row * LD + c] + A[c * LD + row]);
-                A[row * LD + c] = v;
-                A[c * LD + row] = v;
-            }
-        });
-        wsync();
+        // A <- T^T Z, made exactly symmetric: its upper triangle mirrored as
+        // it is stored (the one-wave form keeps a separate averaging pass:
+        // the persistent search kernel that inlines it sits at the register
+        // limit, and the mirrored store moves part of it to scratch)
+        auto TtZ = [&](auto&& store) {
+            wave_gemm<TX, TX>(r, r, ns, [&](int i, int l) { return Tm[l * LD + i]; },
+                              [&](int l, int c) { return Z[l * LD + c]; }, store);
+        };
+        if constexpr (NWV > 1) {
+            TtZ([&](int i, int c, double v) {
+                if (i <= c) {
+                    A[i * LD + c] = v;
+                    A[c * LD + i] = v;
+                }
+            });
+        } else {
+            TtZ([&](int i, int c, double v) { A[i * LD + c] = v; });
+            for2(r, r, [&](int row, int c) {
+                if (row < c) {
+                    const double v = 0.5 * (A[row * LD + c] + A[c * LD + row]);
+                    A[row * LD + c] = v;
+                    A[c * LD + row] = v;
+                }
+            });
+            wsync();
+        }
         mcol = r < mb ? r : mb;
         if (NWV > 1 && tid == 0) {
             shr[0] = r;
