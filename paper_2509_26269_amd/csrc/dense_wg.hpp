@@ -952,6 +952,7 @@ __device__ bool orth_small_body(int mb, int nq, double drop, const double* G, do
     __shared__ double Mq[MBL * MBL];
     const int tid = wlane();
     const int nrow = nq + mb;
+#pragma unroll 8  // several global loads in flight per lane
     for (int i = tid; i < nrow * mb; i += WL) Gl[i] = G[i];
     wsync();
     G = Gl;

@@ -363,6 +363,7 @@ __global__ __launch_bounds__(NT) void k_reduce_rows(EigArgs a, const double* __r
     const int nw = gridDim.x * (NT / 64);
     for (int e = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); e < E; e += nw) {
         double s = 0.0;
+#pragma unroll 4  // several loads in flight per lane
         for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * PSTRIDE + e];
         s = wave_sum(s);
         if (lane == 0) G[e] = s;
@@ -825,6 +826,7 @@ __global__ __launch_bounds__(NT) void k_eig_control(EigArgs a, const double* __r
     const int lane = threadIdx.x & 63;
     for (int j = threadIdx.x >> 6; j < a.mb; j += NT / 64) {
         double s = 0.0;
+#pragma unroll 8  // several loads in flight per lane
         for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * MAXB + j];
         s = wave_sum(s);
         if (lane == 0) rsq[j] = s;
