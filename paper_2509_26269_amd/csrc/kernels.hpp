@@ -160,6 +160,11 @@ struct EigArgs {
     // + y part_ms doubles, Grams at + y g_ms doubles and control block y.
     int P = 1;
     long long s_ms = 0, part_ms = 0, g_ms = 0;
+    // masked solve: site activity (member y at mask + y mask_ms) of the
+    // Nsite sites; row r of a block column belongs to site r mod Nsite
+    const uint8_t* mask = nullptr;
+    int Nsite = 0;
+    long long mask_ms = 0;
 };
 
 // ---- lanczos.hip ----
@@ -231,6 +236,7 @@ hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, h
 hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, double* part, int nblk,
                          EigCtrl* ctrl, hipStream_t st);
 int update_blocks(int n2, bool f64, int mb);  // row-update workgroups (same rule as the launchers)
+bool rows_on_matrix_cores(bool f64, int mb);  // FP32 block widths from 5
 hipError_t launch_eig_control(const EigArgs& a, const double* part, int nblk, EigCtrl* ctrl, int first,
                               hipStream_t st);
 hipError_t launch_eig_gather_info(int P, const EigCtrl* ctrl, moto_info* out, hipStream_t st);

@@ -154,6 +154,27 @@ __global__ __launch_bounds__(NT) void k_check_finite(const double* __restrict__ 
 // Columns whose projected norm is negligible are zeroed (and so dropped by
 // the Rayleigh-Ritz rank test).
 // --------------------------------------------------------------------------
+// Masked solves: the rows of inactive sites are zero in every column that
+// is ever read (the start block is masked and the HVP is M H M), so the
+// vector row kernels skip them: a Gram gains nothing from them, and an
+// update or transform leaves them as they are (a column slot written only by
+// those kernels may then hold stale values there, which no kernel reads: the
+// Gram kernels stage such rows as zeros, the HVP masks its input).  The
+// matrix-core row kernels, used from block width 5, process every row.
+__device__ __forceinline__ const uint8_t* member_mask(const EigArgs& a) {
+    return a.mask ? a.mask + blockIdx.y * a.mask_ms : nullptr;
+}
+__device__ __forceinline__ bool row_active(const uint8_t* mk, int nsite, int r) {
+    return mk == nullptr || mk[r < nsite ? r : r - nsite] != 0;
+}
+// whole-workgroup test: does the RCH-row chunk at r0 hold an active row
+// (also the barrier before the chunk is staged)
+__device__ __forceinline__ bool chunk_active(const uint8_t* mk, int nsite, int n2, int r0, int rch) {
+    bool any = false;
+    for (int rr = threadIdx.x; rr < rch; rr += NT) any = any || (r0 + rr < n2 && row_active(mk, nsite, r0 + rr));
+    return __syncthreads_or(any) != 0;
+}
+
 struct OrthCols {
     int nq;       // projection columns
     int qcol[MAXS];
@@ -169,7 +190,7 @@ __device__ __forceinline__ void orth_cols(const EigArgs& a, int target, const Ei
     }
 }
 
-template <class T>
+template <class T, bool MSK>
 __global__ __launch_bounds__(NT) void k_orth_gram(EigArgs a, int target, const T* __restrict__ S,
                                                   double* __restrict__ part, const EigCtrl* __restrict__ ctrl) {
     S += blockIdx.y * a.s_ms;
@@ -185,14 +206,20 @@ __global__ __launch_bounds__(NT) void k_orth_gram(EigArgs a, int target, const T
     double acc[OQ];
 #pragma unroll
     for (int q = 0; q < OQ; ++q) acc[q] = 0.0;
+    const uint8_t* mk = MSK ? member_mask(a) : nullptr;
     const int nchunks = (a.n2 + RCH - 1) / RCH;
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int r0 = ch * RCH;
-        __syncthreads();
+        if constexpr (MSK) {
+            if (!chunk_active(mk, a.Nsite, a.n2, r0, RCH)) continue;
+        } else {
+            __syncthreads();
+        }
         for (int idx = threadIdx.x; idx < nrow * RCH; idx += NT) {
             const int c = idx / RCH, rr = idx % RCH, r = r0 + rr;
             const int col = c < oc.nq ? oc.qcol[c] : oc.t0 + (c - oc.nq);
-            ts[c][rr] = r < a.n2 ? S[(size_t)col * a.n2 + r] : T(0);
+            const bool in = r < a.n2 && (!MSK || row_active(mk, a.Nsite, r));
+            ts[c][rr] = in ? S[(size_t)col * a.n2 + r] : T(0);
         }
         __syncthreads();
 #pragma unroll
@@ -387,7 +414,7 @@ __global__ __launch_bounds__(WL) void k_orth_small(EigArgs a, int target, const 
 
 // MB: compile-time bound on the block width (mb <= MB), so that the per-row
 // register arrays are sized for the actual block and never spill.
-template <class T, int MB>
+template <class T, int MB, bool MSK>
 __global__ __launch_bounds__(NT) void k_orth_apply(EigArgs a, int target, T* __restrict__ S,
                                                    const EigCtrl* __restrict__ ctrl) {
     S += blockIdx.y * a.s_ms;
@@ -401,7 +428,11 @@ __global__ __launch_bounds__(NT) void k_orth_apply(EigArgs a, int target, T* __r
     for (int i = threadIdx.x; i < MAXB * MAXB; i += NT) Tw[i] = ctrl->Tw[i];
     __syncthreads();
     const int mb = a.mb, nq = oc.nq;
+    const uint8_t* mk = MSK ? member_mask(a) : nullptr;
     for (int r = blockIdx.x * NT + threadIdx.x; r < a.n2; r += gridDim.x * NT) {
+        if constexpr (MSK) {
+            if (!row_active(mk, a.Nsite, r)) continue;
+        }
         // at the widest bucket, keep the compiler from hoisting the LDS
         // coefficients (B: 2 MB x MB, Tw: MB x MB doubles) out of the row
         // loop into registers: that runs at the register limit and spills
@@ -448,7 +479,7 @@ __device__ __forceinline__ void tri_index(int p, int ns, int& i, int& j) {
     j = ii + p;
 }
 
-template <class T>
+template <class T, bool MSK>
 __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* __restrict__ S,
                                              const T* __restrict__ HS, double* __restrict__ part,
                                              const EigCtrl* __restrict__ ctrl) {
@@ -474,15 +505,21 @@ __global__ __launch_bounds__(NT) void k_gram(EigArgs a, int ns_fixed, const T* _
     double acc[GQ];
 #pragma unroll
     for (int q = 0; q < GQ; ++q) acc[q] = 0.0;
+    const uint8_t* mk = MSK ? member_mask(a) : nullptr;
     const int nchunks = (a.n2 + RCH - 1) / RCH;
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int r0 = ch * RCH;
-        __syncthreads();
+        if constexpr (MSK) {
+            if (!chunk_active(mk, a.Nsite, a.n2, r0, RCH)) continue;
+        } else {
+            __syncthreads();
+        }
         for (int idx = threadIdx.x; idx < ns * RCH; idx += NT) {
             const int col = idx / RCH, rr = idx % RCH;
             const int r = r0 + rr;
-            ts[col][rr] = r < a.n2 ? S[(size_t)col * a.n2 + r] : T(0);
-            th[col][rr] = r < a.n2 ? HS[(size_t)col * a.n2 + r] : T(0);
+            const bool in = r < a.n2 && (!MSK || row_active(mk, a.Nsite, r));
+            ts[col][rr] = in ? S[(size_t)col * a.n2 + r] : T(0);
+            th[col][rr] = in ? HS[(size_t)col * a.n2 + r] : T(0);
         }
         __syncthreads();
 #pragma unroll
@@ -620,7 +657,7 @@ __global__ __launch_bounds__(RR_WAVES * WL) void k_rr(EigArgs a, int ns_fixed, c
 // and per-block partial sums of |W_j|^2.  At the start (ns == mb) P is left
 // alone.
 // --------------------------------------------------------------------------
-template <class T, int MB>
+template <class T, int MB, bool MSK>
 __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __restrict__ S, T* __restrict__ HS,
                                                double* __restrict__ part, const EigCtrl* __restrict__ ctrl) {
     S += blockIdx.y * a.s_ms;
@@ -644,7 +681,11 @@ __global__ __launch_bounds__(NT) void k_update(EigArgs a, int ns_fixed, T* __res
 #pragma unroll
     for (int j = 0; j < MB; ++j) rs[j] = 0.0;
     const bool has_p = ns > mb;
+    const uint8_t* mk = MSK ? member_mask(a) : nullptr;
     for (int r = blockIdx.x * NT + threadIdx.x; r < a.n2; r += gridDim.x * NT) {
+        if constexpr (MSK) {
+            if (!row_active(mk, a.Nsite, r)) continue;
+        }
         T sv[3 * MB];
 #pragma unroll
         for (int i = 0; i < 3 * MB; ++i)
@@ -1001,8 +1042,10 @@ int gram_blocks(int n2) {
 // workgroup), so that a small lattice still keeps every compute unit busy
 // (each wave would otherwise wait out the load latency of several tiles in
 // turn); at most 1024, with grid-stride loops beyond
+bool rows_on_matrix_cores(bool f64, int mb) { return !f64 && mb >= UPDATE_MFMA_MIN_MB; }
+
 int update_blocks(int n2, bool f64, int mb) {
-    const bool mfma = !f64 && mb >= UPDATE_MFMA_MIN_MB;
+    const bool mfma = rows_on_matrix_cores(f64, mb);
     const int rows = mfma ? (NT / 64) * 16 : NT;
     const int nb = (n2 + rows - 1) / rows;
     return nb < 1024 ? nb : 1024;
@@ -1044,18 +1087,32 @@ hipError_t launch_check_finite(const double* m, const double* c, int N, LzCtrl* 
     return hipGetLastError();
 }
 
+// dispatch on masking (the vector row kernels skip inactive rows only in
+// their masked instantiation)
+template <class F>
+static void go_mask(const EigArgs& a, F&& f) {
+    if (a.mask)
+        f(std::true_type{});
+    else
+        f(std::false_type{});
+}
+
 hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* part, int nblk, double* G,
                        EigCtrl* ctrl, hipStream_t st) {
-    const bool mf = !f64 && a.mb >= UPDATE_MFMA_MIN_MB;
+    const bool mf = rows_on_matrix_cores(f64, a.mb);
     if (mf)
         hipLaunchKernelGGL(k_orth_gram_mfma, dim3(nblk, a.P), dim3(NT), 0, st, a, target, (const float*)S, part,
                            ctrl);
-    else if (f64)
-        hipLaunchKernelGGL(k_orth_gram<double>, dim3(nblk, a.P), dim3(NT), 0, st, a, target, (const double*)S, part,
-                           ctrl);
     else
-        hipLaunchKernelGGL(k_orth_gram<float>, dim3(nblk, a.P), dim3(NT), 0, st, a, target, (const float*)S, part,
-                           ctrl);
+        go_mask(a, [&](auto mk) {
+            constexpr bool M = decltype(mk)::value;
+            if (f64)
+                hipLaunchKernelGGL((k_orth_gram<double, M>), dim3(nblk, a.P), dim3(NT), 0, st, a, target,
+                                   (const double*)S, part, ctrl);
+            else
+                hipLaunchKernelGGL((k_orth_gram<float, M>), dim3(nblk, a.P), dim3(NT), 0, st, a, target,
+                                   (const float*)S, part, ctrl);
+        });
     hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS, a.P), dim3(NT), 0, st, a, part, nblk, 0, target, G, ctrl);
     hipLaunchKernelGGL(k_orth_small, dim3(1, a.P), dim3(WL), 0, st, a, target, G, ctrl);
     const int nb = update_blocks(a.n2, f64, a.mb);
@@ -1063,30 +1120,36 @@ hipError_t launch_orth(bool f64, const EigArgs& a, int target, void* S, double* 
         hipLaunchKernelGGL(k_orth_apply_mfma, dim3(nb, a.P), dim3(NT), 0, st, a, target, (float*)S, ctrl);
         return hipGetLastError();
     }
-    if (f64)
+    go_mask(a, [&](auto mk) {
+        constexpr bool M = decltype(mk)::value;
         go_mb(a.mb, [&](auto mbc) {
-            hipLaunchKernelGGL((k_orth_apply<double, decltype(mbc)::value>), dim3(nb, a.P), dim3(NT), 0, st, a, target,
-                               (double*)S, ctrl);
+            constexpr int W = decltype(mbc)::value;
+            if (f64)
+                hipLaunchKernelGGL((k_orth_apply<double, W, M>), dim3(nb, a.P), dim3(NT), 0, st, a, target,
+                                   (double*)S, ctrl);
+            else
+                hipLaunchKernelGGL((k_orth_apply<float, W, M>), dim3(nb, a.P), dim3(NT), 0, st, a, target,
+                                   (float*)S, ctrl);
         });
-    else
-        go_mb(a.mb, [&](auto mbc) {
-            hipLaunchKernelGGL((k_orth_apply<float, decltype(mbc)::value>), dim3(nb, a.P), dim3(NT), 0, st, a, target,
-                               (float*)S, ctrl);
-        });
+    });
     return hipGetLastError();
 }
 
 hipError_t launch_gram(bool f64, const EigArgs& a, int ns, const void* S, const void* HS, double* part, int nblk,
                        double* G, const EigCtrl* ctrl, hipStream_t st) {
-    if (!f64 && a.mb >= UPDATE_MFMA_MIN_MB)
+    if (rows_on_matrix_cores(f64, a.mb))
         hipLaunchKernelGGL(k_gram_mfma, dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (const float*)S, (const float*)HS,
                            part, ctrl);
-    else if (f64)
-        hipLaunchKernelGGL(k_gram<double>, dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (const double*)S,
-                           (const double*)HS, part, ctrl);
     else
-        hipLaunchKernelGGL(k_gram<float>, dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (const float*)S, (const float*)HS,
-                           part, ctrl);
+        go_mask(a, [&](auto mk) {
+            constexpr bool M = decltype(mk)::value;
+            if (f64)
+                hipLaunchKernelGGL((k_gram<double, M>), dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (const double*)S,
+                                   (const double*)HS, part, ctrl);
+            else
+                hipLaunchKernelGGL((k_gram<float, M>), dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (const float*)S,
+                                   (const float*)HS, part, ctrl);
+        });
     hipLaunchKernelGGL(k_reduce_rows, dim3(RED_BLOCKS, a.P), dim3(NT), 0, st, a, part, nblk, 1, ns, G, ctrl);
     return hipGetLastError();
 }
@@ -1098,20 +1161,22 @@ hipError_t launch_rr(const EigArgs& a, int ns, const double* G, EigCtrl* ctrl, h
 
 hipError_t launch_update(bool f64, const EigArgs& a, int ns, void* S, void* HS, double* part, int nblk,
                          EigCtrl* ctrl, hipStream_t st) {
-    if (!f64 && a.mb >= UPDATE_MFMA_MIN_MB) {
+    if (rows_on_matrix_cores(f64, a.mb)) {
         hipLaunchKernelGGL(k_update_mfma, dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (float*)S, (float*)HS, part, ctrl);
         return hipGetLastError();
     }
-    if (f64)
+    go_mask(a, [&](auto mk) {
+        constexpr bool M = decltype(mk)::value;
         go_mb(a.mb, [&](auto mbc) {
-            hipLaunchKernelGGL((k_update<double, decltype(mbc)::value>), dim3(nblk, a.P), dim3(NT), 0, st, a, ns,
-                               (double*)S, (double*)HS, part, ctrl);
+            constexpr int W = decltype(mbc)::value;
+            if (f64)
+                hipLaunchKernelGGL((k_update<double, W, M>), dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (double*)S,
+                                   (double*)HS, part, ctrl);
+            else
+                hipLaunchKernelGGL((k_update<float, W, M>), dim3(nblk, a.P), dim3(NT), 0, st, a, ns, (float*)S,
+                                   (float*)HS, part, ctrl);
         });
-    else
-        go_mb(a.mb, [&](auto mbc) {
-            hipLaunchKernelGGL((k_update<float, decltype(mbc)::value>), dim3(nblk, a.P), dim3(NT), 0, st, a, ns,
-                               (float*)S, (float*)HS, part, ctrl);
-        });
+    });
     return hipGetLastError();
 }
 
