@@ -998,6 +998,7 @@ __global__ void k_eig_out2(EigArgs a, const double* __restrict__ part, int nblk,
     const int j = threadIdx.x;
     if (j >= a.k) return;
     double n = 0.0, mx = -1.0, mi = 1e300;
+#pragma unroll 8  // several loads in flight
     for (int b = 0; b < nblk; ++b) {
         const double* p = part + ((size_t)b * MAXB + j) * 3;
         n += p[0];

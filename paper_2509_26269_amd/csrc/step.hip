@@ -163,16 +163,25 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
     const StepHdr* h = P.hdr;
     if (h->stopped) return;
     __shared__ double fr[MAXR];
-    __shared__ double stage[SNV][3][SCH];
+    // rows padded by two doubles (16-byte aligned): the lanes of a wave read
+    // different vectors at the same site, all on one LDS bank otherwise
+    constexpr int SCHP = SCH + 2;
+    __shared__ double stage[SNV][3][SCHP];
     const Ring rg = ring_next(h, a.mem, a.rule);
     const int c = rg.c_new;
     const int nv = 2 * c + 1;
     const int ne = nv * (nv + 1) / 2;
-    if (threadIdx.x < MAXR) {
-        double s = 0.0;
-        if ((int)threadIdx.x < a.k_reflect)
-            for (int b = 0; b < P.nblk; ++b) s += P.pdot[(size_t)b * MAXR + threadIdx.x];
-        fr[threadIdx.x] = s;
+    // fr[r] = sum over the blocks' partials: wave r, lanes over the blocks
+    static_assert(MAXR <= NT / 64, "a wave per reflected mode");
+    {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        if (w < MAXR) {
+            double s = 0.0;
+            if (w < a.k_reflect)
+                for (int b = lane; b < P.nblk; b += 64) s += P.pdot[(size_t)b * MAXR + w];
+            s = wave_sum(s);
+            if (lane == 0) fr[w] = s;
+        }
     }
     // entries owned by this thread (upper triangle of the nv x nv Gram)
     constexpr int EQ = (SNE + NT - 1) / NT;
@@ -198,8 +207,12 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
     const size_t n3 = 3 * (size_t)a.N;
     const int nchunks = (a.N + SCH - 1) / SCH;
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int t = threadIdx.x;
-        if (t < SCH) {
+        // the four waves stage the same SCH sites: each forms the site's
+        // reflected force, gradient and new pair and transports every fourth
+        // stored pair (wave 0 also writes G, the gradient column and |F|^2)
+        static_assert(SCH == 64 && NT % SCH == 0, "one site per lane, whole waves");
+        const int t = threadIdx.x % SCH, wv = threadIdx.x / SCH;
+        {
             const int s = ch * SCH + t;
             if (s < a.N) {
                 const double mi[3] = {m[s], m[a.N + s], m[2 * a.N + s]};
@@ -208,10 +221,11 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
                     double v = F[cc * a.N + s];
                     for (int r = 0; r < a.k_reflect; ++r) v -= 2.0 * fr[r] * V[r * n3 + cc * a.N + s];
                     fm[cc] = v;
-                    fn2 += v * v;
+                    if (wv == 0) fn2 += v * v;
                 }
                 double g[3] = {-fm[0], -fm[1], -fm[2]};
-                for (int cc = 0; cc < 3; ++cc) P.G[cc * a.N + s] = g[cc];
+                if (wv == 0)
+                    for (int cc = 0; cc < 3; ++cc) P.G[cc * a.N + s] = g[cc];
                 // transport stored pairs / form the new one
                 double sn[3] = {0, 0, 0}, yn[3] = {0, 0, 0};
                 if (rg.slot >= 0) {
@@ -227,7 +241,7 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
                         yn[cc] = g[cc] - (gpv[cc] - mg * mi[cc]);
                     }
                 }
-                for (int j = 0; j < c; ++j) {
+                for (int j = wv; j < c; j += NT / SCH) {
                     const int ph = (rg.h_new + j) % a.mem;
                     double* Sj = P.S + ph * P.vstride;
                     double* Yj = P.Y + ph * P.vstride;
@@ -256,8 +270,9 @@ __global__ __launch_bounds__(NT) void k_step_gram(StepArgs a, const double* __re
                         stage[c + j][cc][t] = yv[cc];
                     }
                 }
-                for (int cc = 0; cc < 3; ++cc) stage[2 * c][cc][t] = g[cc];
-            } else {
+                if (wv == 0)
+                    for (int cc = 0; cc < 3; ++cc) stage[2 * c][cc][t] = g[cc];
+            } else if (wv == 0) {
                 for (int q = 0; q < nv; ++q)
                     for (int cc = 0; cc < 3; ++cc) stage[q][cc][t] = 0.0;
             }
@@ -437,10 +452,11 @@ __global__ __launch_bounds__(NT) void k_step_rot(StepArgs a, double* __restrict_
     const StepHdr* h = P.hdr;
     if (h->stopped) return;
     __shared__ double scale_s;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {  // largest per-site angle over the blocks' partials (wave 0)
         double mx = 0.0;
-        for (int b = 0; b < nblk_dir; ++b) mx = fmax(mx, P.pmax[b]);
-        scale_s = mx > a.theta_max ? a.theta_max / mx : 1.0;
+        for (int b = threadIdx.x; b < nblk_dir; b += 64) mx = fmax(mx, P.pmax[b]);
+        mx = wave_max(mx);
+        if (threadIdx.x == 0) scale_s = mx > a.theta_max ? a.theta_max / mx : 1.0;
     }
     __syncthreads();
     const double sc = scale_s;
@@ -538,10 +554,11 @@ __global__ __launch_bounds__(NT) void k_maxnorm(int N, const double* __restrict_
 __global__ __launch_bounds__(NT) void k_seed_rot(int N, double* __restrict__ m, const double* __restrict__ v,
                                                  double sse, const double* __restrict__ part, int nblk) {
     __shared__ double sc;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {  // largest partial (wave 0)
         double mx = 0.0;
-        for (int b = 0; b < nblk; ++b) mx = fmax(mx, part[b]);
-        sc = mx > 0.0 ? sse / mx : 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 64) mx = fmax(mx, part[b]);
+        mx = wave_max(mx);
+        if (threadIdx.x == 0) sc = mx > 0.0 ? sse / mx : 0.0;
     }
     __syncthreads();
     for (int s = blockIdx.x * NT + threadIdx.x; s < N; s += gridDim.x * NT) {
