@@ -126,6 +126,7 @@ __global__ __launch_bounds__(NT) void k_lz_reduce(const double* __restrict__ par
     const int lane = threadIdx.x & 63;
     for (int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); q < c + self; q += gridDim.x * (NT / 64)) {
         double s = 0.0;
+#pragma unroll 4  // several loads in flight per lane
         for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * LZP + q];
         s = wave_sum(s);
         if (q == c) {  // |w|^2 before the projection
@@ -177,6 +178,7 @@ __global__ __launch_bounds__(NT) void k_lz_beta(const double* __restrict__ part,
     if (lz_skip(ctrl, tj)) return;
     __shared__ double red[NT / 64];
     double s = 0.0;
+#pragma unroll 4
     for (int b = threadIdx.x; b < nblk; b += NT) s += part[(size_t)b * LZP + LZ_NCOL];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
