@@ -1,5 +1,6 @@
 // dense_wg.hpp -- small dense FP64 steps of the inner layer, each executed by
-// one wavefront: the symmetric eigen-solves (the lowest eigenpairs by
+// one wavefront (the multisection of the lowest-eigenpair solver optionally
+// by all waves of the workgroup): the symmetric eigen-solves (the lowest eigenpairs by
 // Householder reduction, multisection and inverse iteration; a complete
 // decomposition by Householder reduction and implicit QL), the
 // orthonormalising transform of a projected block, and the Rayleigh-Ritz step
@@ -195,8 +196,9 @@ __device__ void symeig_wg(double* A, double* Z, int n) {
 }
 
 // --------------------------------------------------------------------------
-// The lowest nw eigenpairs of a symmetric n x n matrix on one wavefront, with
-// every stage spread over the lanes instead of one serial sweep:
+// The lowest nw eigenpairs of a symmetric n x n matrix on one wavefront (the
+// multisection optionally on NWV waves, see below), with every stage spread
+// over the lanes instead of one serial sweep:
 //  1. Householder reduction to tridiagonal T (lane r keeps row r of the
 //     matrix in registers; the reflectors are stored, not accumulated);
 //  2. eigenvalues by multisection of T's Sturm sequence: a group of lanes per

@@ -16,7 +16,7 @@
 // space long after the first has met the stopping rule; a block of b
 // directions brings such a pair in together.
 // Q lives in one [m_max + b][2N] array; w is written straight into its
-// column.  At the end of a cycle one wavefront takes the `keep` lowest
+// column.  At the end of a cycle one workgroup takes the `keep` lowest
 // eigenpairs of T (FP64, symeig_low), tests the residuals and
 // either stops or restarts from the `keep` lowest Ritz vectors plus the
 // residual block (Wu & Simon 2000), which is re-orthonormalised before the
@@ -221,8 +221,9 @@ __global__ __launch_bounds__(NT) void k_lz_scale(int n2, T* __restrict__ Q, int 
     for (int r = blockIdx.x * NT + threadIdx.x; r < n2; r += gridDim.x * NT) q[r] = (T)((double)q[r] * inv);
 }
 
-// Rayleigh-Ritz on T[0..m) (one wavefront): eigenpairs in ascending order,
-// residual norms |T[m..m+b)[0..m) y_i|, stop test.
+// Rayleigh-Ritz on T[0..m) (wave 0; all waves in the eigen-solve's
+// multisection): eigenpairs in ascending order, residual norms
+// |T[m..m+b)[0..m) y_i|, stop test.
 constexpr int LZ_RR_WAVES = 4;  // waves of the multisection (the rest runs on wave 0)
 __global__ __launch_bounds__(LZ_RR_WAVES * WL) void k_lz_rr(int k, int keep, double tol_abs, int max_restarts,
                                                             LzCtrl* __restrict__ ctrl) {
